@@ -1,0 +1,127 @@
+"""Throughput of the batched AS-ICP solve on one MI355X.
+
+One step = one whole solve of the paper-scale workload: set-up (A0), 100
+iterations of Algorithm 1 for 3 preshapes x 256 particles against an
+8192-point object, the final evaluation and the selection.  Inputs are
+resident in HBM before the timed region.  Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "particle-iters/s & grasps/s at matched final cost: plain vs learned-seeded"
+PEAK_FP32_MFMA = 157.3e12  # MI355X dense fp32 matrix peak, FLOP/s
+FLOP_PER_PAIR = 6          # 3 multiply-adds of |r|^2 - 2 r.s per (query, object point) pair
+
+
+def cpu_baseline(pb, st, iters=1):
+    """The FP64 oracle, untuned, on a bounded sample: `iters` iteration(s) of
+    every particle of the same workload (evaluation + Stein update)."""
+    import numpy as np
+    import oracle
+    o = oracle.Oracle(pb, st)
+    th = pb.theta0.astype(np.float64)
+    t0 = time.perf_counter()
+    pc = cv = None
+    for k in range(iters):
+        r = o.step(k, th, pc, cv)
+        th, pc, cv = r["theta"], r["prev_cost"], r["converged"]
+    dt = time.perf_counter() - t0
+    return {"value": pb.k_tot * iters / dt, "unit": "particle-iters/s", "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": f"{iters} iteration(s) of all {pb.k_tot} particles of the same workload "
+                      f"(FP64, {dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--k-max", type=int, default=100)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (objects and groups are "
+              "independent and would shard across GPUs without communication)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2412_08346_amd as A
+    from paper_2412_08346_amd import synth
+
+    pb, st = synth.workload_paper_scale(k_max=args.k_max)
+    torch.cuda.set_device(0)
+    solver = A.Solver(pb, st, timing=True)
+    stream = torch.cuda.current_stream()
+    print(f"[bench] workload ready: Ktot={pb.k_tot} M={pb.R.shape[0]} N={pb.S.shape[0] // pb.n_pre} "
+          f"k_max={st.k_max}", file=sys.stderr, flush=True)
+    for w in range(args.warmup):
+        solver.reset()
+        solver.solve()
+        solver.result(per_particle=False)
+        print(f"[bench] warmup {w} done", file=sys.stderr, flush=True)
+    # timed region: one fresh context per step on the same device arrays and
+    # workspace (set-up + solve + selection), all on one stream
+    solver.close()
+    sp = stream.cuda_stream
+    ctxs = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        ctx = A.asicp_create(solver.problem, solver.config, solver._ws_ptr, solver.ws_bytes, sp)
+        A.asicp_solve(ctx, sp)
+        ctxs.append(ctx)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    nn_ms, nn_n = 0.0, 0
+    for ctx in ctxs:
+        ms, n = A.asicp_kernel_time(ctx)
+        nn_ms, nn_n = nn_ms + ms, nn_n + n
+    solver.ctx = ctxs[-1]
+    res = solver.result(per_particle=False)
+    for ctx in ctxs:
+        A.asicp_destroy(ctx)
+    solver.ctx = None
+    wall = t1 - t0
+    ms_per_step = 1e3 * wall / args.steps
+    p_iters = pb.k_tot * st.k_max * args.steps
+    pairs = sum(pb.K * int(np.diff(pb.s_off)[p]) * int(np.diff(pb.r_off)[o])
+                for o in range(pb.n_obj) for p in range(pb.n_pre))
+    avg_nn = nn_ms / max(nn_n, 1) / 1e3
+    achieved = FLOP_PER_PAIR * pairs / avg_nn
+    line = {
+        "metric": METRIC,
+        "value": p_iters / wall,
+        "unit": "particle-iters/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "grasps_per_s": pb.n_obj * args.steps / wall,
+        "config": {"workload": "paper-scale plain AS-ICP: 1 superquadric object of 8192 points, "
+                               "3 box-gripper preshapes x 4096 contact points, 128^3 SDF, 256 "
+                               f"Fibonacci particles per preshape, {st.k_max} iterations",
+                   "particles": pb.k_tot, "iterations": st.k_max, "object_points": int(pb.R.shape[0]),
+                   "contact_points_per_preshape": int(np.diff(pb.s_off)[0]), "preshapes": pb.n_pre},
+        "roofline": {"bound": "mfma", "kernel": "k_nn_forward", "achieved": achieved / 1e12,
+                     "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA,
+                     "traffic": None, "avg_launch_ms": avg_nn * 1e3, "launches": nn_n,
+                     "pairs_per_launch": pairs, "flop_per_pair": FLOP_PER_PAIR},
+        "best_cost": float(res["best_cost"][0]), "best_free": int(res["best_free"][0]),
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(pb, st)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

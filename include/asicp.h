@@ -1,0 +1,194 @@
+/*
+ * asicp.h -- C ABI of the MI355X (gfx950) batched Annealed Stein ICP grasp
+ * solver: "Grasping by Parallel Shape Matching" (arXiv 2412.08346).
+ *
+ * The solver takes the inputs of the paper's Algorithm 1 -- the gripper's
+ * contact (inner-surface) cloud S per preshape, the object cloud R, the
+ * collision cloud C, the gripper's signed distance field (built from the
+ * complete gripper cloud G), the initial particles Theta_0, k_stein and
+ * k_max (Sec. IV-A, Algorithm 1 inputs) -- and returns, per object, the pose
+ * theta that minimises the grasp loss among collision-free particles
+ * (Algorithm 1 return; Sec. V-A).  Every iteration of every particle runs in
+ * hand-written HIP kernels on the stream the caller passes.
+ *
+ * Conventions (all calls)
+ *   - Units are metres.  A pose theta is (tx, ty, tz, qw, qx, qy, qz): the
+ *     translation and a unit quaternion, scalar first (Sec. III-A).  A pose
+ *     maps gripper-frame points into the object frame: s' = R(q) s + t.
+ *   - Device arrays are float32 structure-of-arrays unless stated; "device"
+ *     means memory of the current HIP device, "host" ordinary CPU memory.
+ *   - Particle numbering: i = ((o * n_preshapes) + p) * K + j for object o,
+ *     preshape p, particle j < K.  A group (o, p) is one Stein population.
+ *   - Streams are passed as void* holding a hipStream_t (NULL = the null
+ *     stream).  create / step / solve only enqueue work; result synchronises.
+ *   - Status: ASICP_OK (0) or a negative code; on error asicp_last_error()
+ *     returns a message (thread-local, valid until the next call on the same
+ *     thread).  No C++ exception crosses this boundary.
+ *   - The library never allocates device memory: the caller provides one
+ *     workspace of asicp_workspace_bytes() bytes, aligned to 256 bytes.
+ *   - A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef ASICP_H
+#define ASICP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t asicp_status;
+#define ASICP_OK 0
+#define ASICP_E_INVALID (-1) /* bad argument; detected on the host, no device work done */
+#define ASICP_E_STATE (-2)   /* call not allowed in the context's current state           */
+#define ASICP_E_HIP (-3)     /* a HIP runtime call or kernel launch failed                 */
+#define ASICP_E_NUMERIC (-4) /* a pose, cost or gradient became NaN / Inf on the device    */
+
+/* Preconditioner A of the SGD-ICP update, eq. (3). */
+#define ASICP_PRECOND_GN_DIAG 0  /* 1/(1+lambda) on t, 3/(2(rho^2 + lambda |TCP|^2)) on rotation */
+#define ASICP_PRECOND_IDENTITY 1
+/* Annealing. */
+#define ASICP_SCHED_GEOMETRIC 0    /* gamma = 1, repulsion tau_k = T0 (T1/T0)^(k/(k_max-1))     */
+#define ASICP_SCHED_PAPER_CYCLIC 1 /* eq. (11): gamma = (mod(k, k_max/C)/(k_max/C))^p, tau = 1 */
+/* Combination of the translation RBF kernel (eq. 9) and the rotation kernel (eq. 10). */
+#define ASICP_KERNEL_PRODUCT 0
+#define ASICP_KERNEL_BLOCK 1
+/* RBF bandwidth h of eq. (9). */
+#define ASICP_BW_MEDIAN 0 /* lower median of |t_i - t_j|^2 over pairs / ln K, floored at h_min */
+#define ASICP_BW_FIXED 1
+/* Flags. */
+#define ASICP_FLAG_DEBUG 1u  /* record per-point forward and reverse NN indices (needs more workspace) */
+#define ASICP_FLAG_TIMING 2u /* record HIP events around every forward-NN launch                     */
+
+/* Signed distance grid of one preshape (Sec. IV-C): value at node (i, j, k)
+ * is the signed distance of origin + cell * (i, j, k) to the complete
+ * gripper, negative inside.  A point collides when it lies inside the node box
+ * and its trilinear interpolant is strictly negative. */
+typedef struct {
+  const float* values; /* device, [nz][ny][nx], x fastest; borrowed */
+  int32_t nx, ny, nz;  /* >= 2 each */
+  float origin[3];
+  float cell;          /* > 0 */
+} asicp_sdf;
+
+/* One batch: n_objects objects x n_preshapes preshapes x K particles.  All
+ * device pointers are borrowed: the caller keeps them alive and unmodified
+ * until asicp_destroy.  Host arrays are read during asicp_create only. */
+typedef struct {
+  int32_t n_objects;           /* >= 1                                               */
+  int32_t n_preshapes;         /* >= 1                                               */
+  int32_t particles_per_group; /* K, 1 .. 1024                                       */
+  const float* rx;             /* device, object clouds R concatenated (SoA)         */
+  const float* ry;
+  const float* rz;
+  const int32_t* r_off;        /* host [n_objects+1]; every object has >= 1 point    */
+  const float* cx;             /* device, collision clouds C concatenated (SoA);     */
+  const float* cy;             /*   may alias rx/ry/rz; an object may have 0 points  */
+  const float* cz;
+  const int32_t* c_off;        /* host [n_objects+1]                                 */
+  const float* sx;             /* device, contact clouds S concatenated, gripper     */
+  const float* sy;             /*   frame                                            */
+  const float* sz;
+  const int32_t* s_off;        /* host [n_preshapes+1]; every preshape >= 1 point    */
+  const asicp_sdf* sdf;        /* host [n_preshapes]                                 */
+  const float* theta0;         /* device [7][Ktot] initial particles                 */
+  const float* prev_cost;      /* device [Ktot] or NULL: resume state (cost of the   */
+  const int32_t* converged;    /*   previous iteration, converged flags)             */
+  int32_t k_start;             /* first iteration to run (0 .. k_max)                */
+} asicp_problem;
+
+/* Iteration settings.  Table I of the paper: k_max 40, k_stein 15, cyclic
+ * annealing C 5 p 2, eta 1, cost weights 1 (lambda 1), convergence 2e-4. */
+typedef struct {
+  int32_t k_max;        /* iterations, >= 1                                          */
+  int32_t k_stein;      /* iterations with the Stein update, 0 .. k_max; SGD after   */
+  float eta;            /* learning rate, > 0                                        */
+  float lambda;         /* weight of the TCP-CoM loss (eq. 13), >= 0                 */
+  int32_t precond;      /* ASICP_PRECOND_*                                           */
+  int32_t schedule;     /* ASICP_SCHED_*                                             */
+  float T0, T1;         /* geometric schedule, > 0                                   */
+  float cyc_C, cyc_p;   /* cyclic schedule, > 0                                      */
+  int32_t kernel_mode;  /* ASICP_KERNEL_*                                            */
+  int32_t bw_mode;      /* ASICP_BW_*                                                */
+  float h_fixed;        /* bandwidth for ASICP_BW_FIXED, > 0                         */
+  float h_min;          /* floor of the median bandwidth, > 0                        */
+  float conv_tol;       /* relative cost change counted as converged, >= 0           */
+  uint32_t flags;       /* ASICP_FLAG_*                                              */
+} asicp_config;
+
+/* Outputs.  Every pointer may be NULL.  Host arrays hold n_objects entries
+ * (best_theta 7 per object); device arrays use Ktot = n_objects*n_preshapes*K,
+ * G = n_objects*n_preshapes, Nmax = largest preshape, Mcmax = largest
+ * collision cloud.  Per-particle values are those of the last evaluation:
+ * after asicp_step, the evaluation that the last update used; after
+ * asicp_solve, the final evaluation at theta_{k_max}. */
+typedef struct {
+  /* host */
+  int32_t* best_particle;   /* [n_objects] particle index i of the returned grasp       */
+  int32_t* best_free;       /* [n_objects] 1 if it is collision free, 0 if none was     */
+  float* best_theta;        /* [7*n_objects]                                            */
+  float* best_cost;         /* [n_objects]                                              */
+  int32_t iterations_done;  /* out: the next iteration to run                           */
+  int32_t final_evaluated;  /* out: 1 once asicp_solve has run the final evaluation     */
+  /* device */
+  float* theta;             /* [7][Ktot] current poses                                  */
+  float* cost;              /* [Ktot] C = 1/2 (L_ct + lambda L_com), eqs. (13)-(15)     */
+  float* col_cost;          /* [Ktot] 1/2 L_col of eq. (18); 0 without collision        */
+  int32_t* ncol;            /* [Ktot] colliding points                                  */
+  int32_t* converged;       /* [Ktot]                                                   */
+  float* prev_cost;         /* [Ktot]                                                   */
+  float* grad;              /* [6][Ktot] gradient used: (g_t, g_w), collision if ncol>0 */
+  float* grad_ct;           /* [6][Ktot] gradient of C                                  */
+  float* grad_col;          /* [6][Ktot] gradient of 1/2 L_col                          */
+  float* phi;               /* [6][Ktot] last update direction (Stein phi, or -A g)     */
+  float* h;                 /* [G] last bandwidth (0 in the SGD phase)                  */
+  int32_t* nn_idx;          /* [Ktot][Nmax] forward NN index per contact point (DEBUG)  */
+  int32_t* rev_idx;         /* [Ktot][Mcmax] reverse NN index, -1 if the point does not */
+                            /*   collide (DEBUG)                                        */
+} asicp_result_t;
+
+typedef struct asicp_ctx_s* asicp_ctx;
+
+/* Workspace size for this problem and config (host only, no device work). */
+asicp_status asicp_workspace_bytes(const asicp_problem* pb, const asicp_config* cfg, size_t* bytes);
+
+/* Validate everything on the host (ASICP_E_INVALID before any device work),
+ * carve the workspace and enqueue the per-object / per-preshape set-up on
+ * `stream`: centre of mass of each object cloud, tool centre point (centroid
+ * of each contact cloud), preconditioner, MFMA-ready copies of the clouds,
+ * and the particle state from theta0 (and the resume arrays).  `*out` is
+ * library-owned host memory released by asicp_destroy.  The workspace is
+ * borrowed like the problem's device arrays. */
+asicp_status asicp_create(const asicp_problem* pb, const asicp_config* cfg, void* workspace,
+                          size_t workspace_bytes, void* stream, asicp_ctx* out);
+
+/* Enqueue n_iters iterations of Algorithm 1 (n_iters >= 0).  Running past
+ * k_max, or stepping after the final evaluation, is ASICP_E_STATE. */
+asicp_status asicp_step(asicp_ctx ctx, int32_t n_iters, void* stream);
+
+/* Enqueue the remaining iterations, the final evaluation at theta_{k_max} and
+ * the selection of the returned grasp per object. */
+asicp_status asicp_solve(asicp_ctx ctx, void* stream);
+
+/* Synchronise `stream`, then fill `out` (see asicp_result_t).  Device outputs
+ * are copied on `stream` before it is synchronised.  Returns ASICP_E_HIP for
+ * an asynchronous HIP error and ASICP_E_NUMERIC if the device flagged a
+ * non-finite pose, cost or gradient (the outputs are still written). */
+asicp_status asicp_result(asicp_ctx ctx, asicp_result_t* out, void* stream);
+
+/* With ASICP_FLAG_TIMING: total time and count of the forward-NN kernel
+ * launches enqueued so far, from HIP events recorded on the launch stream
+ * around each launch.  Synchronises on those events. */
+asicp_status asicp_kernel_time(asicp_ctx ctx, double* total_ms, int32_t* launches);
+
+/* Release the context (host memory and HIP events only). NULL is a no-op. */
+void asicp_destroy(asicp_ctx ctx);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* asicp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ASICP_H */

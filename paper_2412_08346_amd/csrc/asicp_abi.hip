@@ -1,0 +1,501 @@
+// asicp_abi.hip -- host side of the C ABI declared in include/asicp.h:
+// validation, workspace layout, the iteration schedule and the kernel
+// sequence of Algorithm 1.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "asicp_internal.h"
+
+using namespace asicp;
+
+namespace {
+
+thread_local std::string g_err;
+
+asicp_status fail(asicp_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+constexpr int kMaxPoints = 1 << 22;   // per object / collision cloud / preshape
+constexpr int kMaxGroups = 1 << 16;
+
+struct Layout {
+  size_t groups, objs, pres, obj_prep, pre_prep, obj_com, pre_const;
+  size_t theta, cost, col_cost, prev_cost, ncol, converged, grad, grad_ct, grad_col, phi, h;
+  size_t nn_part, col_part, best, best_theta, flags, dbg_nn, dbg_rev;
+  size_t total;
+};
+
+struct Shape {
+  int n_obj, n_pre, K, G, Ktot;
+  int obj_tg, pre_tg, max_waves_pp, max_gate_chunks, n_max, mc_max;
+  long long total_waves, total_gate_wgs;
+  bool debug;
+};
+
+size_t bump(size_t& cur, size_t bytes) {
+  const size_t off = cur;
+  cur += (bytes + 255) & ~(size_t)255;
+  return off;
+}
+
+Layout layout_of(const Shape& s) {
+  Layout L;
+  size_t c = 0;
+  const size_t K = (size_t)s.Ktot;
+  L.groups = bump(c, sizeof(GroupInfo) * s.G);
+  L.objs = bump(c, sizeof(ObjInfo) * s.n_obj);
+  L.pres = bump(c, sizeof(PreInfo) * s.n_pre);
+  L.obj_prep = bump(c, (size_t)s.obj_tg * 64 * 16);
+  L.pre_prep = bump(c, (size_t)s.pre_tg * 64 * 16);
+  L.obj_com = bump(c, 16 * (size_t)s.n_obj);
+  L.pre_const = bump(c, 32 * (size_t)s.n_pre);
+  L.theta = bump(c, 4 * 7 * K);
+  L.cost = bump(c, 4 * K);
+  L.col_cost = bump(c, 4 * K);
+  L.prev_cost = bump(c, 4 * K);
+  L.ncol = bump(c, 4 * K);
+  L.converged = bump(c, 4 * K);
+  L.grad = bump(c, 4 * 6 * K);
+  L.grad_ct = bump(c, 4 * 6 * K);
+  L.grad_col = bump(c, 4 * 6 * K);
+  L.phi = bump(c, 4 * 6 * K);
+  L.h = bump(c, 4 * (size_t)s.G);
+  L.nn_part = bump(c, 4 * kPartStride * K * (size_t)s.max_waves_pp);
+  L.col_part = bump(c, 4 * kPartStride * K * (size_t)(s.max_gate_chunks > 0 ? s.max_gate_chunks : 1));
+  L.best = bump(c, 8 * (size_t)s.n_obj);
+  L.best_theta = bump(c, 32 * (size_t)s.n_obj);
+  L.flags = bump(c, 16);
+  L.dbg_nn = s.debug ? bump(c, 4 * K * (size_t)s.n_max) : 0;
+  L.dbg_rev = s.debug ? bump(c, 4 * K * (size_t)(s.mc_max > 0 ? s.mc_max : 1)) : 0;
+  L.total = c;
+  return L;
+}
+
+bool finite_pos(float v) { return std::isfinite(v) && v > 0.f; }
+
+// Host-only validation of every argument; fills `s`.
+asicp_status validate(const asicp_problem* pb, const asicp_config* cfg, Shape& s) {
+  if (!pb || !cfg) return fail(ASICP_E_INVALID, "problem and config must not be NULL");
+  if (pb->n_objects < 1) return fail(ASICP_E_INVALID, "n_objects must be >= 1");
+  if (pb->n_preshapes < 1) return fail(ASICP_E_INVALID, "n_preshapes must be >= 1");
+  if (pb->particles_per_group < 1 || pb->particles_per_group > 1024)
+    return fail(ASICP_E_INVALID, "particles_per_group must be in 1..1024");
+  if ((long long)pb->n_objects * pb->n_preshapes > kMaxGroups)
+    return fail(ASICP_E_INVALID, "too many (object, preshape) groups");
+  const long long ktot = (long long)pb->n_objects * pb->n_preshapes * pb->particles_per_group;
+  if (ktot > (1ll << 24)) return fail(ASICP_E_INVALID, "too many particles");
+  if (!pb->rx || !pb->ry || !pb->rz || !pb->sx || !pb->sy || !pb->sz || !pb->theta0)
+    return fail(ASICP_E_INVALID, "object cloud, contact cloud and theta0 device pointers are required");
+  if (!pb->r_off || !pb->c_off || !pb->s_off || !pb->sdf)
+    return fail(ASICP_E_INVALID, "offset arrays and the SDF array are required");
+  if (pb->r_off[0] != 0 || pb->c_off[0] != 0 || pb->s_off[0] != 0)
+    return fail(ASICP_E_INVALID, "offset arrays must start at 0");
+  s.n_obj = pb->n_objects;
+  s.n_pre = pb->n_preshapes;
+  s.K = pb->particles_per_group;
+  s.G = s.n_obj * s.n_pre;
+  s.Ktot = (int)ktot;
+  s.obj_tg = s.pre_tg = 0;
+  s.n_max = s.mc_max = 0;
+  s.max_waves_pp = 0;
+  s.max_gate_chunks = 0;
+  bool any_c = false;
+  for (int o = 0; o < s.n_obj; ++o) {
+    const long long m = (long long)pb->r_off[o + 1] - pb->r_off[o];
+    const long long mc = (long long)pb->c_off[o + 1] - pb->c_off[o];
+    if (m < 1 || m > kMaxPoints) return fail(ASICP_E_INVALID, "object " + std::to_string(o) + " must have 1..4194304 points");
+    if (mc < 0 || mc > kMaxPoints) return fail(ASICP_E_INVALID, "collision cloud " + std::to_string(o) + " must have 0..4194304 points");
+    s.obj_tg += (int)((m + 63) / 64);
+    s.mc_max = std::max(s.mc_max, (int)mc);
+    s.max_gate_chunks = std::max(s.max_gate_chunks, (int)((mc + kGateChunk - 1) / kGateChunk));
+    any_c = any_c || mc > 0;
+  }
+  if (any_c && (!pb->cx || !pb->cy || !pb->cz))
+    return fail(ASICP_E_INVALID, "collision cloud device pointers are required");
+  if ((long long)pb->r_off[s.n_obj] > (1ll << 30) || (long long)pb->c_off[s.n_obj] > (1ll << 30))
+    return fail(ASICP_E_INVALID, "clouds too large");
+  for (int p = 0; p < s.n_pre; ++p) {
+    const long long n = (long long)pb->s_off[p + 1] - pb->s_off[p];
+    if (n < 1 || n > kMaxPoints) return fail(ASICP_E_INVALID, "preshape " + std::to_string(p) + " must have 1..4194304 points");
+    s.pre_tg += (int)((n + 63) / 64);
+    s.n_max = std::max(s.n_max, (int)n);
+    s.max_waves_pp = std::max(s.max_waves_pp, (int)((n + 63) / 64));
+    const asicp_sdf& g = pb->sdf[p];
+    if (!g.values) return fail(ASICP_E_INVALID, "SDF values of preshape " + std::to_string(p) + " are NULL");
+    if (g.nx < 2 || g.ny < 2 || g.nz < 2 || (long long)g.nx * g.ny * g.nz > (1ll << 30))
+      return fail(ASICP_E_INVALID, "SDF grid of preshape " + std::to_string(p) + " needs 2..1024^3 nodes per axis product");
+    if (!finite_pos(g.cell)) return fail(ASICP_E_INVALID, "SDF cell must be finite and > 0");
+    if (!std::isfinite(g.origin[0]) || !std::isfinite(g.origin[1]) || !std::isfinite(g.origin[2]))
+      return fail(ASICP_E_INVALID, "SDF origin must be finite");
+  }
+  if ((long long)pb->s_off[s.n_pre] > (1ll << 30)) return fail(ASICP_E_INVALID, "contact clouds too large");
+  s.total_waves = 0;
+  s.total_gate_wgs = 0;
+  for (int o = 0; o < s.n_obj; ++o)
+    for (int p = 0; p < s.n_pre; ++p) {
+      const long long n = (long long)pb->s_off[p + 1] - pb->s_off[p];
+      const long long mc = (long long)pb->c_off[o + 1] - pb->c_off[o];
+      s.total_waves += (long long)s.K * ((n + 63) / 64);
+      s.total_gate_wgs += (long long)s.K * ((mc + kGateChunk - 1) / kGateChunk);
+    }
+  if (s.total_waves > (1ll << 30) || s.total_gate_wgs > (1ll << 30))
+    return fail(ASICP_E_INVALID, "problem too large for one launch");
+  if (cfg->k_max < 1) return fail(ASICP_E_INVALID, "k_max must be >= 1");
+  if (cfg->k_stein < 0 || cfg->k_stein > cfg->k_max) return fail(ASICP_E_INVALID, "k_stein must be in 0..k_max");
+  if (pb->k_start < 0 || pb->k_start > cfg->k_max) return fail(ASICP_E_INVALID, "k_start must be in 0..k_max");
+  if (!finite_pos(cfg->eta)) return fail(ASICP_E_INVALID, "eta must be finite and > 0");
+  if (!std::isfinite(cfg->lambda) || cfg->lambda < 0.f) return fail(ASICP_E_INVALID, "lambda must be finite and >= 0");
+  if (cfg->precond != ASICP_PRECOND_GN_DIAG && cfg->precond != ASICP_PRECOND_IDENTITY)
+    return fail(ASICP_E_INVALID, "unknown preconditioner");
+  if (cfg->schedule == ASICP_SCHED_GEOMETRIC) {
+    if (!finite_pos(cfg->T0) || !finite_pos(cfg->T1)) return fail(ASICP_E_INVALID, "T0 and T1 must be finite and > 0");
+  } else if (cfg->schedule == ASICP_SCHED_PAPER_CYCLIC) {
+    if (!finite_pos(cfg->cyc_C) || !finite_pos(cfg->cyc_p)) return fail(ASICP_E_INVALID, "cyc_C and cyc_p must be finite and > 0");
+  } else {
+    return fail(ASICP_E_INVALID, "unknown schedule");
+  }
+  if (cfg->kernel_mode != ASICP_KERNEL_PRODUCT && cfg->kernel_mode != ASICP_KERNEL_BLOCK)
+    return fail(ASICP_E_INVALID, "unknown kernel mode");
+  if (cfg->bw_mode == ASICP_BW_FIXED) {
+    if (!finite_pos(cfg->h_fixed)) return fail(ASICP_E_INVALID, "h_fixed must be finite and > 0");
+  } else if (cfg->bw_mode != ASICP_BW_MEDIAN) {
+    return fail(ASICP_E_INVALID, "unknown bandwidth mode");
+  }
+  if (!finite_pos(cfg->h_min)) return fail(ASICP_E_INVALID, "h_min must be finite and > 0");
+  if (!std::isfinite(cfg->conv_tol) || cfg->conv_tol < 0.f) return fail(ASICP_E_INVALID, "conv_tol must be finite and >= 0");
+  if (cfg->flags & ~(ASICP_FLAG_DEBUG | ASICP_FLAG_TIMING)) return fail(ASICP_E_INVALID, "unknown flag bits");
+  s.debug = (cfg->flags & ASICP_FLAG_DEBUG) != 0;
+  return ASICP_OK;
+}
+
+asicp_status check_launch(const char* what) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(ASICP_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+  return ASICP_OK;
+}
+
+}  // namespace
+
+struct asicp_ctx_s {
+  Dev d;
+  asicp_config cfg;
+  int k;               // next iteration
+  bool final_done;
+  float inv_log_k;
+  std::vector<hipEvent_t> ev;  // start/stop pairs around forward-NN launches
+  int n_timed;
+};
+
+extern "C" {
+
+const char* asicp_last_error(void) { return g_err.c_str(); }
+
+asicp_status asicp_workspace_bytes(const asicp_problem* pb, const asicp_config* cfg, size_t* bytes) {
+  g_err.clear();
+  if (!bytes) return fail(ASICP_E_INVALID, "bytes must not be NULL");
+  Shape s;
+  const asicp_status st = validate(pb, cfg, s);
+  if (st != ASICP_OK) return st;
+  *bytes = layout_of(s).total;
+  return ASICP_OK;
+}
+
+asicp_status asicp_create(const asicp_problem* pb, const asicp_config* cfg, void* workspace,
+                          size_t workspace_bytes, void* stream, asicp_ctx* out) {
+  g_err.clear();
+  if (!out) return fail(ASICP_E_INVALID, "out must not be NULL");
+  *out = nullptr;
+  Shape s;
+  asicp_status st = validate(pb, cfg, s);
+  if (st != ASICP_OK) return st;
+  const Layout L = layout_of(s);
+  if (!workspace) return fail(ASICP_E_INVALID, "workspace must not be NULL");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return fail(ASICP_E_INVALID, "workspace must be 256-byte aligned");
+  if (workspace_bytes < L.total)
+    return fail(ASICP_E_INVALID, "workspace too small: need " + std::to_string(L.total) + " bytes");
+
+  // host tables
+  std::vector<GroupInfo> groups(s.G);
+  std::vector<ObjInfo> objs(s.n_obj);
+  std::vector<PreInfo> pres(s.n_pre);
+  int tg = 0;
+  for (int o = 0; o < s.n_obj; ++o) {
+    ObjInfo& oi = objs[o];
+    oi.r_begin = pb->r_off[o];
+    oi.m = pb->r_off[o + 1] - pb->r_off[o];
+    oi.c_begin = pb->c_off[o];
+    oi.mc = pb->c_off[o + 1] - pb->c_off[o];
+    oi.prep_tg_begin = tg;
+    oi.ntg = (oi.m + 63) / 64;
+    oi.gate_chunks = (oi.mc + kGateChunk - 1) / kGateChunk;
+    oi.pad = 0;
+    tg += oi.ntg;
+  }
+  tg = 0;
+  for (int p = 0; p < s.n_pre; ++p) {
+    PreInfo& pi = pres[p];
+    std::memset(&pi, 0, sizeof pi);
+    pi.s_begin = pb->s_off[p];
+    pi.n = pb->s_off[p + 1] - pb->s_off[p];
+    pi.prep_tg_begin = tg;
+    pi.ntg = (pi.n + 63) / 64;
+    pi.waves = pi.ntg;
+    tg += pi.ntg;
+    const asicp_sdf& g = pb->sdf[p];
+    pi.nx = g.nx; pi.ny = g.ny; pi.nz = g.nz;
+    pi.sdf = g.values;
+    pi.ox = g.origin[0]; pi.oy = g.origin[1]; pi.oz = g.origin[2];
+    pi.cell = g.cell;
+    pi.inv_cell = (float)(1.0 / (double)g.cell);
+  }
+  int wave_off = 0, gate_off = 0;
+  for (int o = 0; o < s.n_obj; ++o)
+    for (int p = 0; p < s.n_pre; ++p) {
+      GroupInfo& gi = groups[o * s.n_pre + p];
+      gi.obj = o;
+      gi.pre = p;
+      gi.wave_off = wave_off;
+      gi.gate_off = gate_off;
+      wave_off += s.K * pres[p].waves;
+      gate_off += s.K * objs[o].gate_chunks;
+    }
+
+  char* ws = static_cast<char*>(workspace);
+  Dev d;
+  std::memset(&d, 0, sizeof d);
+  d.rx = pb->rx; d.ry = pb->ry; d.rz = pb->rz;
+  d.cx = pb->cx; d.cy = pb->cy; d.cz = pb->cz;
+  d.sx = pb->sx; d.sy = pb->sy; d.sz = pb->sz;
+  d.groups = reinterpret_cast<const GroupInfo*>(ws + L.groups);
+  d.objs = reinterpret_cast<const ObjInfo*>(ws + L.objs);
+  d.pres = reinterpret_cast<const PreInfo*>(ws + L.pres);
+  d.n_obj = s.n_obj; d.n_pre = s.n_pre; d.K = s.K; d.G = s.G; d.Ktot = s.Ktot;
+  d.total_waves = (int)s.total_waves;
+  d.total_gate_wgs = (int)s.total_gate_wgs;
+  d.max_waves_pp = s.max_waves_pp;
+  d.max_gate_chunks = s.max_gate_chunks > 0 ? s.max_gate_chunks : 1;
+  d.n_max = s.n_max;
+  d.mc_max = s.mc_max > 0 ? s.mc_max : 1;
+  d.obj_prep = reinterpret_cast<float4*>(ws + L.obj_prep);
+  d.pre_prep = reinterpret_cast<float4*>(ws + L.pre_prep);
+  d.obj_com = reinterpret_cast<float*>(ws + L.obj_com);
+  d.pre_const = reinterpret_cast<float*>(ws + L.pre_const);
+  d.theta = reinterpret_cast<float*>(ws + L.theta);
+  d.cost = reinterpret_cast<float*>(ws + L.cost);
+  d.col_cost = reinterpret_cast<float*>(ws + L.col_cost);
+  d.prev_cost = reinterpret_cast<float*>(ws + L.prev_cost);
+  d.ncol = reinterpret_cast<int32_t*>(ws + L.ncol);
+  d.converged = reinterpret_cast<int32_t*>(ws + L.converged);
+  d.grad = reinterpret_cast<float*>(ws + L.grad);
+  d.grad_ct = reinterpret_cast<float*>(ws + L.grad_ct);
+  d.grad_col = reinterpret_cast<float*>(ws + L.grad_col);
+  d.phi = reinterpret_cast<float*>(ws + L.phi);
+  d.h = reinterpret_cast<float*>(ws + L.h);
+  d.nn_part = reinterpret_cast<float*>(ws + L.nn_part);
+  d.col_part = reinterpret_cast<float*>(ws + L.col_part);
+  d.best = reinterpret_cast<int32_t*>(ws + L.best);
+  d.best_theta = reinterpret_cast<float*>(ws + L.best_theta);
+  d.flags = reinterpret_cast<int32_t*>(ws + L.flags);
+  d.dbg_nn = s.debug ? reinterpret_cast<int32_t*>(ws + L.dbg_nn) : nullptr;
+  d.dbg_rev = s.debug ? reinterpret_cast<int32_t*>(ws + L.dbg_rev) : nullptr;
+  d.eta = cfg->eta;
+  d.lambda = cfg->lambda;
+  d.k_stein = cfg->k_stein;
+  d.kernel_mode = cfg->kernel_mode;
+  d.bw_mode = cfg->bw_mode;
+  d.precond = cfg->precond;
+  d.h_fixed = cfg->h_fixed;
+  d.h_min = cfg->h_min;
+  d.conv_tol = cfg->conv_tol;
+
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  (void)hipGetLastError();  // start from a clean error state
+  upload_words(ws + L.groups, groups.data(), sizeof(GroupInfo) * groups.size(), hs);
+  upload_words(ws + L.objs, objs.data(), sizeof(ObjInfo) * objs.size(), hs);
+  upload_words(ws + L.pres, pres.data(), sizeof(PreInfo) * pres.size(), hs);
+  if ((st = check_launch("table upload")) != ASICP_OK) return st;
+  launch_setup(d, pb->theta0, pb->prev_cost, pb->converged, hs);
+  if ((st = check_launch("setup")) != ASICP_OK) return st;
+  if (s.debug) {
+    if (hipMemsetAsync(d.dbg_nn, 0xff, 4 * (size_t)s.Ktot * s.n_max, hs) != hipSuccess ||
+        hipMemsetAsync(d.dbg_rev, 0xff, 4 * (size_t)s.Ktot * d.mc_max, hs) != hipSuccess)
+      return fail(ASICP_E_HIP, "debug buffer clear failed");
+  }
+
+  asicp_ctx_s* c = new asicp_ctx_s();
+  c->d = d;
+  c->cfg = *cfg;
+  c->k = pb->k_start;
+  c->final_done = false;
+  c->inv_log_k = s.K >= 2 ? (float)(1.0 / std::log((double)s.K)) : 1.0f;
+  c->n_timed = 0;
+  *out = c;
+  return ASICP_OK;
+}
+
+static void schedule_of(const asicp_config& cfg, int k, float* gamma, float* tau) {
+  if (cfg.schedule == ASICP_SCHED_PAPER_CYCLIC) {
+    const double period = (double)cfg.k_max / (double)cfg.cyc_C;
+    *gamma = (float)std::pow(std::fmod((double)k, period) / period, (double)cfg.cyc_p);
+    *tau = 1.0f;
+  } else {
+    *gamma = 1.0f;
+    const double frac = cfg.k_max > 1 ? (double)k / (double)(cfg.k_max - 1) : 0.0;
+    *tau = (float)((double)cfg.T0 * std::pow((double)cfg.T1 / (double)cfg.T0, frac));
+  }
+}
+
+static asicp_status nn_forward_timed(asicp_ctx c, hipStream_t hs) {
+  const bool timing = (c->cfg.flags & ASICP_FLAG_TIMING) != 0;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (timing) {
+    if ((size_t)(2 * c->n_timed + 2) > c->ev.size()) {
+      hipEvent_t a, b;
+      if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+        return fail(ASICP_E_HIP, "hipEventCreate failed");
+      c->ev.push_back(a);
+      c->ev.push_back(b);
+    }
+    e0 = c->ev[2 * c->n_timed];
+    e1 = c->ev[2 * c->n_timed + 1];
+    if (hipEventRecord(e0, hs) != hipSuccess) return fail(ASICP_E_HIP, "hipEventRecord failed");
+  }
+  launch_nn_forward(c->d, hs);
+  asicp_status st = check_launch("nn_forward");
+  if (st != ASICP_OK) return st;
+  if (timing) {
+    if (hipEventRecord(e1, hs) != hipSuccess) return fail(ASICP_E_HIP, "hipEventRecord failed");
+    ++c->n_timed;
+  }
+  return ASICP_OK;
+}
+
+static asicp_status evaluate(asicp_ctx c, int k, int final_eval, hipStream_t hs) {
+  asicp_status st = nn_forward_timed(c, hs);
+  if (st != ASICP_OK) return st;
+  launch_gate_reverse(c->d, hs);
+  if ((st = check_launch("gate_reverse")) != ASICP_OK) return st;
+  launch_finalize(c->d, k, final_eval, hs);
+  return check_launch("finalize");
+}
+
+asicp_status asicp_step(asicp_ctx c, int32_t n_iters, void* stream) {
+  g_err.clear();
+  if (!c) return fail(ASICP_E_INVALID, "ctx is NULL");
+  if (n_iters < 0) return fail(ASICP_E_INVALID, "n_iters must be >= 0");
+  if (c->final_done) return fail(ASICP_E_STATE, "the solve has already run its final evaluation");
+  if (c->k + n_iters > c->cfg.k_max)
+    return fail(ASICP_E_STATE, "stepping past k_max (" + std::to_string(c->cfg.k_max) + ")");
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  for (int it = 0; it < n_iters; ++it) {
+    const int k = c->k;
+    asicp_status st = evaluate(c, k, 0, hs);
+    if (st != ASICP_OK) return st;
+    if (k < c->cfg.k_stein) {
+      float gamma, tau;
+      schedule_of(c->cfg, k, &gamma, &tau);
+      launch_svgd(c->d, gamma, tau, c->inv_log_k, hs);
+      if ((st = check_launch("svgd")) != ASICP_OK) return st;
+    }
+    ++c->k;
+  }
+  return ASICP_OK;
+}
+
+asicp_status asicp_solve(asicp_ctx c, void* stream) {
+  g_err.clear();
+  if (!c) return fail(ASICP_E_INVALID, "ctx is NULL");
+  if (c->final_done) return fail(ASICP_E_STATE, "the solve has already run its final evaluation");
+  asicp_status st = asicp_step(c, c->cfg.k_max - c->k, stream);
+  if (st != ASICP_OK) return st;
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  if ((st = evaluate(c, c->k, 1, hs)) != ASICP_OK) return st;
+  launch_select(c->d, hs);
+  if ((st = check_launch("select")) != ASICP_OK) return st;
+  c->final_done = true;
+  return ASICP_OK;
+}
+
+asicp_status asicp_result(asicp_ctx c, asicp_result_t* out, void* stream) {
+  g_err.clear();
+  if (!c || !out) return fail(ASICP_E_INVALID, "ctx and out must not be NULL");
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  const Dev& d = c->d;
+  const size_t K = (size_t)d.Ktot;
+  struct Cp { void* dst; const void* src; size_t bytes; };
+  const Cp dev[] = {
+      {out->theta, d.theta, 4 * 7 * K},        {out->cost, d.cost, 4 * K},
+      {out->col_cost, d.col_cost, 4 * K},      {out->ncol, d.ncol, 4 * K},
+      {out->converged, d.converged, 4 * K},    {out->prev_cost, d.prev_cost, 4 * K},
+      {out->grad, d.grad, 4 * 6 * K},          {out->grad_ct, d.grad_ct, 4 * 6 * K},
+      {out->grad_col, d.grad_col, 4 * 6 * K},  {out->phi, d.phi, 4 * 6 * K},
+      {out->h, d.h, 4 * (size_t)d.G},
+  };
+  for (const Cp& x : dev)
+    if (x.dst && hipMemcpyAsync(x.dst, x.src, x.bytes, hipMemcpyDeviceToDevice, hs) != hipSuccess)
+      return fail(ASICP_E_HIP, "device-to-device copy of a result failed");
+  if (out->nn_idx) {
+    if (!d.dbg_nn) return fail(ASICP_E_STATE, "nn_idx needs ASICP_FLAG_DEBUG");
+    if (hipMemcpyAsync(out->nn_idx, d.dbg_nn, 4 * K * d.n_max, hipMemcpyDeviceToDevice, hs) != hipSuccess)
+      return fail(ASICP_E_HIP, "copy of nn_idx failed");
+  }
+  if (out->rev_idx) {
+    if (!d.dbg_rev) return fail(ASICP_E_STATE, "rev_idx needs ASICP_FLAG_DEBUG");
+    if (hipMemcpyAsync(out->rev_idx, d.dbg_rev, 4 * K * d.mc_max, hipMemcpyDeviceToDevice, hs) != hipSuccess)
+      return fail(ASICP_E_HIP, "copy of rev_idx failed");
+  }
+  std::vector<int32_t> best(2 * (size_t)d.n_obj);
+  std::vector<float> bt(8 * (size_t)d.n_obj);
+  int32_t flags[4] = {0, 0, 0, 0};
+  if (hipMemcpyAsync(flags, d.flags, sizeof flags, hipMemcpyDeviceToHost, hs) != hipSuccess)
+    return fail(ASICP_E_HIP, "copy of the device flags failed");
+  if (c->final_done) {
+    if (hipMemcpyAsync(best.data(), d.best, 4 * best.size(), hipMemcpyDeviceToHost, hs) != hipSuccess ||
+        hipMemcpyAsync(bt.data(), d.best_theta, 4 * bt.size(), hipMemcpyDeviceToHost, hs) != hipSuccess)
+      return fail(ASICP_E_HIP, "copy of the selected grasps failed");
+  }
+  const hipError_t e = hipStreamSynchronize(hs);
+  if (e != hipSuccess) return fail(ASICP_E_HIP, std::string("stream synchronisation: ") + hipGetErrorString(e));
+  out->iterations_done = c->k;
+  out->final_evaluated = c->final_done ? 1 : 0;
+  for (int o = 0; o < d.n_obj; ++o) {
+    if (out->best_particle) out->best_particle[o] = c->final_done ? best[2 * o] : -1;
+    if (out->best_free) out->best_free[o] = c->final_done ? best[2 * o + 1] : 0;
+    if (out->best_cost) out->best_cost[o] = c->final_done ? bt[8 * o + 7] : NAN;
+    if (out->best_theta)
+      for (int a = 0; a < 7; ++a) out->best_theta[7 * o + a] = c->final_done ? bt[8 * o + a] : NAN;
+  }
+  if (flags[1] != 0) return fail(ASICP_E_NUMERIC, "nearest-neighbour re-scan missed (non-finite distances)");
+  if (flags[0] != 0) return fail(ASICP_E_NUMERIC, "a pose, cost or gradient became non-finite");
+  return ASICP_OK;
+}
+
+asicp_status asicp_kernel_time(asicp_ctx c, double* total_ms, int32_t* launches) {
+  g_err.clear();
+  if (!c || !total_ms || !launches) return fail(ASICP_E_INVALID, "NULL argument");
+  if (!(c->cfg.flags & ASICP_FLAG_TIMING)) return fail(ASICP_E_STATE, "context was created without ASICP_FLAG_TIMING");
+  double tot = 0.0;
+  for (int j = 0; j < c->n_timed; ++j) {
+    if (hipEventSynchronize(c->ev[2 * j + 1]) != hipSuccess) return fail(ASICP_E_HIP, "hipEventSynchronize failed");
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->ev[2 * j], c->ev[2 * j + 1]) != hipSuccess)
+      return fail(ASICP_E_HIP, "hipEventElapsedTime failed");
+    tot += ms;
+  }
+  *total_ms = tot;
+  *launches = c->n_timed;
+  return ASICP_OK;
+}
+
+void asicp_destroy(asicp_ctx c) {
+  if (!c) return;
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,135 @@
+"""The C ABI on the host: the library loads, exports every declared entry
+point, and rejects bad arguments before touching the device.  No compute
+call runs here (no GPU needed)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2412_08346_amd as A
+from paper_2412_08346_amd import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "asicp.h")).read()
+    return sorted(set(re.findall(r"\b(asicp_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = A.load()
+    names = declared_symbols()
+    assert set(names) == set(A.EXPORTS)
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def host_problem(pb, sdf_ok=True):
+    """A problem whose device pointers are placeholders: only host-side
+    validation and sizing may look at it."""
+    sd = (A.asicp_sdf * pb.n_pre)()
+    for p, g in enumerate(pb.grids):
+        nz, ny, nx = g.values.shape
+        sd[p] = A.asicp_sdf(1 if sdf_ok else None, nx, ny, nz, (C.c_float * 3)(*g.origin), g.cell)
+    keep = [sd, pb.r_off, pb.c_off, pb.s_off]
+    p = A.asicp_problem(pb.n_obj, pb.n_pre, pb.K, 8, 8, 8, pb.r_off.ctypes.data, 8, 8, 8,
+                        pb.c_off.ctypes.data, 8, 8, 8, pb.s_off.ctypes.data,
+                        C.cast(sd, C.c_void_p).value, 8, None, None, 0)
+    return p, keep
+
+
+def test_workspace_bytes_grows_with_problem_and_debug():
+    pb, st = synth.workload_small()
+    p, keep = host_problem(pb)
+    n0 = A.asicp_workspace_bytes(p, A.make_config(st))
+    n1 = A.asicp_workspace_bytes(p, A.make_config(st, A.ASICP_FLAG_DEBUG))
+    assert 0 < n0 < n1
+    assert n1 - n0 >= 4 * pb.k_tot * (512 + 1024)  # per-point NN records
+
+
+@pytest.mark.parametrize("mutate, needle", [
+    (lambda p, c: setattr(c, "k_stein", c.k_max + 1), "k_stein"),
+    (lambda p, c: setattr(c, "k_max", 0), "k_max"),
+    (lambda p, c: setattr(c, "eta", float("nan")), "eta"),
+    (lambda p, c: setattr(c, "lambda_", -1.0), "lambda"),
+    (lambda p, c: setattr(c, "schedule", 7), "schedule"),
+    (lambda p, c: setattr(c, "T1", 0.0), "T0 and T1"),
+    (lambda p, c: setattr(c, "kernel_mode", 3), "kernel mode"),
+    (lambda p, c: setattr(c, "bw_mode", 2), "bandwidth"),
+    (lambda p, c: setattr(c, "h_min", 0.0), "h_min"),
+    (lambda p, c: setattr(c, "flags", 64), "flag"),
+    (lambda p, c: setattr(p, "particles_per_group", 0), "particles_per_group"),
+    (lambda p, c: setattr(p, "particles_per_group", 2048), "particles_per_group"),
+    (lambda p, c: setattr(p, "n_objects", 0), "n_objects"),
+    (lambda p, c: setattr(p, "k_start", 99), "k_start"),
+    (lambda p, c: setattr(p, "theta0", None), "theta0"),
+])
+def test_invalid_arguments_rejected_on_host(mutate, needle):
+    pb, st = synth.workload_small()
+    p, keep = host_problem(pb)
+    cfg = A.make_config(st)
+    mutate(p, cfg)
+    with pytest.raises(A.AsicpError) as e:
+        A.asicp_workspace_bytes(p, cfg)
+    assert e.value.status == A.ASICP_E_INVALID
+    assert needle in str(e.value)
+    # create validates the same way before any device work
+    ctx = C.c_void_p()
+    st_code = A.load().asicp_create(C.byref(p), C.byref(cfg), C.c_void_p(256), 1 << 30, None, C.byref(ctx))
+    assert st_code == A.ASICP_E_INVALID and not ctx.value
+
+
+def test_bad_clouds_and_grids_rejected():
+    pb, st = synth.workload_small()
+    cfg = A.make_config(st)
+    # empty object
+    pb2, _ = synth.workload_small()
+    pb2.r_off = np.array([0, 0], np.int32)
+    p, keep = host_problem(pb2)
+    with pytest.raises(A.AsicpError, match="object 0"):
+        A.asicp_workspace_bytes(p, cfg)
+    # SDF grid with a single node along x
+    pb3, _ = synth.workload_small()
+    pb3.grids[0].values = pb3.grids[0].values[:, :, :1]
+    p, keep = host_problem(pb3)
+    with pytest.raises(A.AsicpError, match="SDF grid"):
+        A.asicp_workspace_bytes(p, cfg)
+    p, keep = host_problem(pb, sdf_ok=False)
+    with pytest.raises(A.AsicpError, match="NULL"):
+        A.asicp_workspace_bytes(p, cfg)
+
+
+def test_workspace_checks_before_device_work():
+    pb, st = synth.workload_small()
+    p, keep = host_problem(pb)
+    cfg = A.make_config(st)
+    need = A.asicp_workspace_bytes(p, cfg)
+    L = A.load()
+    ctx = C.c_void_p()
+    assert L.asicp_create(C.byref(p), C.byref(cfg), C.c_void_p(256), need - 1, None, C.byref(ctx)) == A.ASICP_E_INVALID
+    assert "too small" in A.asicp_last_error()
+    assert L.asicp_create(C.byref(p), C.byref(cfg), C.c_void_p(260), need, None, C.byref(ctx)) == A.ASICP_E_INVALID
+    assert "aligned" in A.asicp_last_error()
+
+
+def test_null_context_calls():
+    L = A.load()
+    assert L.asicp_step(None, 1, None) == A.ASICP_E_INVALID
+    assert L.asicp_solve(None, None) == A.ASICP_E_INVALID
+    assert L.asicp_result(None, None, None) == A.ASICP_E_INVALID
+    L.asicp_destroy(None)
+    assert "NULL" in A.asicp_last_error()
+
+
+def test_product_path_has_no_oracle_dependency():
+    """The package must not import, link or call the oracle."""
+    pkg = os.path.join(ROOT, "paper_2412_08346_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "asicp_oracle" not in text, f
+                assert "from oracle" not in text, f

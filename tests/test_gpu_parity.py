@@ -1,0 +1,339 @@
+"""GPU (HIP, gfx950) vs FP64 oracle parity, through the C ABI.
+
+Teacher forcing: the oracle runs its own trajectory; its pose at iteration k,
+rounded to float32, is the input of one step on both sides.  No input and no
+expected value comes from the HIP path.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2412_08346_amd import synth
+import parity_util as pu
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2412_08346_amd as A
+    return A, torch
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def col_scales(pb, theta_soa, or_rev):
+    S = pb.S.astype(np.float64)
+    Cc = pb.C.astype(np.float64)
+    th = np.asarray(theta_soa, np.float64)
+    st = np.zeros(th.shape[1])
+    sw = np.zeros(th.shape[1])
+    for i in range(th.shape[1]):
+        g = i // pb.K
+        o, p = g // pb.n_pre, g % pb.n_pre
+        c0, c1 = pb.c_off[o], pb.c_off[o + 1]
+        r = np.asarray(or_rev[i][: c1 - c0])
+        sel = np.nonzero(r >= 0)[0]
+        if len(sel) == 0:
+            continue
+        Rm = oracle.quat_to_rot(th[3:, i])
+        u = S[pb.s_off[p] + r[sel]] @ Rm.T
+        e = u + th[:3, i] - Cc[c0 + sel]
+        ne = np.linalg.norm(e, axis=1)
+        st[i] = ne.mean()
+        sw[i] = (np.linalg.norm(u, axis=1) * ne).mean()
+    return st, sw
+
+
+def compare_step(pb, st, theta, k, prev_cost=None, converged=None, label=""):
+    """One teacher-forced step from float32 `theta` (7, Ktot); returns stats."""
+    A, torch = _gpu()
+    theta = np.ascontiguousarray(theta, np.float32)
+    say(f"[parity] {label} k={k} Ktot={pb.k_tot} n_obj={pb.n_obj} n_pre={pb.n_pre}")
+    pc32 = None if prev_cost is None else np.asarray(prev_cost, np.float32)
+    sol = A.Solver(pb, st, debug=True, theta0=theta, k_start=k, prev_cost=pc32, converged=converged)
+    sol.step(1)
+    g = sol.result()
+    sol.close()
+    o = oracle.Oracle(pb, st)
+    r = o.step(k, theta, prev_cost=None if pc32 is None else pc32.astype(np.float64),
+               converged=converged, full=True)
+    setup = o.setup()
+    ties = pu.check_nn(pb, theta, g["nn_idx"], r["nn_idx"])
+    excused = pu.check_gate(pb, g["rev_idx"], r["gate"], r["phi_c"])
+    rties = pu.check_rev(pb, theta, g["rev_idx"], r["rev_idx"])
+    gate_gpu = (g["rev_idx"] >= 0).sum(1)
+    gate_or = r["gate"].astype(np.int64).sum(1)
+    if excused == 0:
+        assert np.array_equal(g["ncol"], r["ncol"]), "collision counts differ"
+    assert np.array_equal(g["ncol"], gate_gpu), "ncol disagrees with the GPU's own gate record"
+    assert np.abs(gate_gpu - gate_or).sum() == excused
+    s_t, s_w = pu.scales(pb, theta, r["nn_idx"], st.lam, setup)
+    pu.close(g["cost"], r["cost"], r["cost"], what="cost")
+    pu.close(g["grad_ct"][:3].T, r["g_ct"][:, :3], s_t[:, None], what="g_t")
+    pu.close(g["grad_ct"][3:].T, r["g_ct"][:, 3:], s_w[:, None], what="g_w")
+    both = (g["ncol"] > 0) & (r["ncol"] > 0) & (g["ncol"] == r["ncol"])
+    if both.any():
+        c_t, c_w = col_scales(pb, theta, r["rev_idx"])
+        pu.close(g["col_cost"][both], r["col_cost"][both], r["col_cost"][both], what="col_cost")
+        pu.close(g["grad_col"][:3].T[both], r["g_col"][both, :3], c_t[both, None], what="gcol_t")
+        pu.close(g["grad_col"][3:].T[both], r["g_col"][both, 3:], c_w[both, None], what="gcol_w")
+    same = g["ncol"] == r["ncol"]
+    # the update
+    svgd = k < st.k_stein
+    th64 = theta.astype(np.float64)
+    if svgd:
+        pu.close(g["h"], r["h"], r["h"], what="h")
+        # scale of phi: kernel-weighted magnitudes of driving and repulsion terms
+        ph_t = np.zeros(pb.k_tot)
+        ph_w = np.zeros(pb.k_tot)
+        gam, tau = oracle.schedule(st, k)
+        for gi in range(pb.n_obj * pb.n_pre):
+            p = gi % pb.n_pre
+            sl = slice(gi * pb.K, (gi + 1) * pb.K)
+            aos = th64[:, sl].T
+            _, kmat = oracle.svgd_direction(aos, r["g_fin"][sl], r["h"][gi], gam, tau,
+                                            setup["a_t"][p], setup["a_w"][p], st.kernel_mode)
+            gt = np.abs(r["g_fin"][sl, :3]).max(1)
+            gw = np.abs(r["g_fin"][sl, 3:]).max(1)
+            dt = np.abs(aos[:, None, :3] - aos[None, :, :3]).max(-1)
+            ph_t[sl] = (kmat * (gam * setup["a_t"][p] * gt[None, :] + tau * dt)).mean(1)
+            ph_w[sl] = (kmat * (gam * setup["a_w"][p] * gw[None, :]) + tau).mean(1)
+        if same.all() and excused == 0:
+            pu.close(g["phi"][:3].T, r["phi"][:, :3], ph_t[:, None], what="phi_t")
+            pu.close(g["phi"][3:].T, r["phi"][:, 3:], ph_w[:, None], what="phi_w")
+            step_t, step_w = st.eta * ph_t, st.eta * ph_w
+        else:
+            step_t = step_w = None
+    else:
+        p_of = (np.arange(pb.k_tot) // pb.K) % pb.n_pre
+        step_t = st.eta * setup["a_t"][p_of] * np.maximum(np.abs(r["g_fin"][:, :3]).max(1), s_t)
+        step_w = st.eta * setup["a_w"][p_of] * np.maximum(np.abs(r["g_fin"][:, 3:]).max(1), s_w)
+        conv_or = r["converged"].astype(bool)
+        conv_gpu = g["converged"].astype(bool)
+        pcv = np.asarray(prev_cost if prev_cost is not None else np.full(pb.k_tot, -1.0), np.float64)
+        near = np.abs(np.abs(r["cost"] - pcv) - st.conv_tol * pcv) <= 1e-3 * st.conv_tol * np.abs(pcv)
+        bad = (conv_or != conv_gpu) & ~near
+        assert not bad.any(), f"converged flags differ for particles {np.nonzero(bad)[0][:8]}"
+        same &= conv_or == conv_gpu
+    if step_t is not None:
+        sel = same
+        dt_err = np.abs(g["theta"][:3].astype(np.float64) - r["theta"][:3]).max(0)
+        tol_t = 1e-4 * step_t + 2e-7 * np.maximum(np.abs(th64[:3]).max(0), 1e-2)
+        assert (dt_err[sel] <= tol_t[sel]).all(), f"translation update: worst {(dt_err / tol_t)[sel].max():.3g}x tol"
+        ang = pu.angle_between(g["theta"][3:], r["theta"][3:])
+        tol_w = 1e-4 * step_w + 2e-6
+        assert (ang[sel] <= tol_w[sel]).all(), f"rotation update: worst {(ang / tol_w)[sel].max():.3g}x tol"
+    assert g["status"] == 0
+    return dict(ties=ties, gate_excused=excused, rev_ties=rties, ncol=int(g["ncol"].sum()))
+
+
+def oracle_trajectory(pb, st, ks):
+    o = oracle.Oracle(pb, st)
+    th = pb.theta0.astype(np.float64)
+    pc, cv = None, None
+    snaps = {}
+    for k in range(max(ks) + 1):
+        if k in ks:
+            snaps[k] = (th.astype(np.float32), None if pc is None else pc.copy(),
+                        None if cv is None else cv.copy())
+        r = o.step(k, th, pc, cv)
+        th, pc, cv = r["theta"], r["prev_cost"], r["converged"]
+    return snaps
+
+
+# ---------------------------------------------------------------------------
+
+def test_small_first_step():
+    pb, st = synth.workload_small()
+    out = compare_step(pb, st, pb.theta0, 0, label="small first step")
+    say("[parity] small first step", out)
+
+
+def test_small_teacher_forced_steps():
+    pb, st = synth.workload_small()
+    ks = [1, 5, 9, 14, 20, 29]
+    snaps = oracle_trajectory(pb, st, ks)
+    for k in ks:
+        th, pc, cv = snaps[k]
+        out = compare_step(pb, st, th, k, pc, cv, label="small teacher-forced")
+        say("[parity] k", k, out)
+
+
+def test_paper_preset_sgd_phase_with_collisions():
+    pb, _ = synth.workload_small()
+    st = synth.paper_settings(k_max=40, k_stein=15)
+    ks = [0, 14, 15, 16, 20, 33]
+    snaps = oracle_trajectory(pb, st, ks)
+    total_col = 0
+    for k in ks:
+        th, pc, cv = snaps[k]
+        out = compare_step(pb, st, th, k, pc, cv, label="paper preset")
+        total_col += out["ncol"]
+        say("[parity] paper preset k", k, out)
+    assert total_col > 1000  # the collision branch was exercised
+
+
+def test_block_kernel_identity_preconditioner_fixed_bandwidth():
+    pb, st = synth.workload_small()
+    st.kernel_mode = synth.KERNEL_BLOCK
+    st.precond = synth.PRECOND_IDENTITY
+    st.eta = 0.5
+    th = oracle_trajectory(pb, st, [4])[4]
+    compare_step(pb, st, th[0], 4, th[1], th[2], label="block kernel")
+    st.bw_mode, st.h_fixed = synth.BW_FIXED, 0.003
+    compare_step(pb, st, th[0], 4, th[1], th[2], label="fixed bandwidth")
+
+
+def pulled_in(pb, frac):
+    """Poses moved a fraction of the way towards the object (collisions)."""
+    th = pb.theta0.astype(np.float64).copy()
+    com = pb.R.astype(np.float64).mean(0)
+    th[:3] = th[:3] + frac * (com[:, None] - th[:3])
+    return th.astype(np.float32)
+
+
+def test_paper_scale_step_full_size():
+    pb, st = synth.workload_paper_scale()
+    out = compare_step(pb, st, pb.theta0, 0, label="paper scale theta0")
+    say("[parity] paper scale theta0", out)
+    out = compare_step(pb, st, pulled_in(pb, 0.75), 50, label="paper scale pulled in")
+    say("[parity] paper scale pulled in", out)
+    assert out["ncol"] > 0
+
+
+def ragged_problem(seed, n_obj, ms, ns, K, mcs=None):
+    rng = np.random.default_rng(seed)
+    objs = [synth.superquadric(m, rng) if m > 8 else rng.uniform(-0.03, 0.03, (m, 3)).astype(np.float32)
+            for m in ms]
+    pre = [synth.gripper_contact_cloud(0.04 + 0.02 * j, n, rng) for j, n in enumerate(ns)]
+    grids = [synth.gripper_sdf_grid(0.04 + 0.02 * j, 48, 0.003) for j in range(len(ns))]
+    pb = synth._assemble(objs, pre, grids, K, [0.07] * n_obj)
+    if mcs is not None:
+        cs = [o[:mc] for o, mc in zip(objs, mcs)]
+        pb.C = np.concatenate(cs) if sum(mcs) else np.zeros((0, 3), np.float32)
+        pb.c_off = np.cumsum([0] + list(mcs)).astype(np.int32)
+    return pb
+
+
+def test_ragged_sizes_and_edges():
+    st = synth.Settings(k_max=6, k_stein=3)
+    # ragged M (77, 1, 130), ragged N (100, 65), K = 3; object 1 has one point
+    pb = ragged_problem(5, 3, [77, 1, 130], [100, 65], 3)
+    for k, frac in [(0, 0.0), (2, 0.6), (4, 0.8)]:
+        compare_step(pb, st, pulled_in(pb, frac), k, label=f"ragged k={k}")
+    # a single particle, an empty collision cloud for one object
+    pb = ragged_problem(6, 2, [200, 64], [64], 1, mcs=[0, 64])
+    compare_step(pb, st, pulled_in(pb, 0.7), 0, label="K=1 empty collision cloud")
+    compare_step(pb, st, pulled_in(pb, 0.7), 4, label="K=1 SGD")
+
+
+def test_batched_objects_first_steps():
+    pb, st = synth.workload_batched(n_obj=4, K=16, k_max=10, m_lo=512, m_hi=4096, n=640, grid_n=64)
+    compare_step(pb, st, pb.theta0, 0, label="batched")
+    compare_step(pb, st, pulled_in(pb, 0.7), 3, label="batched pulled in")
+
+
+def test_determinism_and_resume():
+    A, torch = _gpu()
+    pb, st = synth.workload_small()
+    runs = []
+    for _ in range(2):
+        s = A.Solver(pb, st)
+        s.solve()
+        runs.append(s.result())
+        s.close()
+    assert np.array_equal(runs[0]["theta"], runs[1]["theta"])
+    assert np.array_equal(runs[0]["cost"], runs[1]["cost"])
+    # 12 + 18 iterations through a new context equal 30 straight
+    s = A.Solver(pb, st)
+    s.step(12)
+    mid = s.result()
+    s.close()
+    s = A.Solver(pb, st, theta0=mid["theta"], k_start=12, prev_cost=mid["prev_cost"],
+                 converged=mid["converged"])
+    s.solve()
+    res = s.result()
+    s.close()
+    assert np.array_equal(res["theta"], runs[0]["theta"])
+    assert np.array_equal(res["best_particle"], runs[0]["best_particle"])
+
+
+def test_free_running_solve_small():
+    """Free-running trajectories: while every correspondence agrees the poses
+    agree to 1e-3 rad / 0.5 mm; the selected grasp is valid either way."""
+    A, torch = _gpu()
+    pb, st = synth.workload_small()
+    o = oracle.Oracle(pb, st)
+    s = A.Solver(pb, st, debug=True)
+    th = pb.theta0.astype(np.float64)
+    pc = cv = None
+    agreed = 0
+    for k in range(st.k_max):
+        s.step(1)
+        g = s.result()
+        r = o.step(k, th, pc, cv, full=True)
+        try:  # correspondences and gate decisions equal up to ties
+            pu.check_nn(pb, th, g["nn_idx"], r["nn_idx"])
+            pu.check_gate(pb, g["rev_idx"], r["gate"], r["phi_c"])
+        except AssertionError:
+            break
+        th, pc, cv = r["theta"], r["prev_cost"], r["converged"]
+        dt = np.abs(g["theta"][:3] - th[:3]).max()
+        ang = pu.angle_between(g["theta"][3:], th[3:]).max()
+        assert dt < 5e-4 and ang < 1e-3, (k, dt, ang)
+        agreed = k + 1
+    say("[parity] iterations with correspondences equal up to ties:", agreed)
+    s.close()
+    s = A.Solver(pb, st)
+    s.solve()
+    res = s.result()
+    s.close()
+    assert agreed >= 5
+    b = res["best_particle"][0]
+    assert 0 <= b < pb.k_tot
+    if res["best_free"][0]:
+        assert res["ncol"][b] == 0
+        assert res["cost"][b] == res["cost"][res["ncol"] == 0].min()
+    assert np.allclose(res["best_theta"][0], res["theta"][:, b])
+
+
+def test_abi_state_and_numeric_errors():
+    A, torch = _gpu()
+    pb, st = synth.workload_small(k_max=3)
+    s = A.Solver(pb, st)
+    s.step(3)
+    with pytest.raises(A.AsicpError) as e:
+        s.step(1)
+    assert e.value.status == A.ASICP_E_STATE
+    s.solve()
+    with pytest.raises(A.AsicpError) as e:
+        s.solve()
+    assert e.value.status == A.ASICP_E_STATE
+    s.close()
+    bad = pb.theta0.copy()
+    bad[0, 5] = np.nan
+    s = A.Solver(pb, st, theta0=bad)
+    s.solve()
+    r = s.result(check=False)
+    assert r["status"] == A.ASICP_E_NUMERIC
+    s.close()
+
+
+def test_timing_hook_counts_launches():
+    A, torch = _gpu()
+    pb, st = synth.workload_small(k_max=4)
+    s = A.Solver(pb, st, timing=True)
+    s.solve()
+    s.result(per_particle=False)
+    ms, n = s.kernel_time()
+    assert n == 5 and ms > 0
+    s.close()
