@@ -45,6 +45,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--k-max", type=int, default=100)
+    ap.add_argument("--brute", action="store_true",
+                    help="forward NN visits every object chunk (no exact pruning)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="also run a plain device copy of MIB MiB (3 times): the reference "
+                         "kernel that scales rocprofv3 FETCH_SIZE / WRITE_SIZE to bytes")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (objects and groups are "
@@ -57,9 +62,18 @@ def main():
     import paper_2412_08346_amd as A
     from paper_2412_08346_amd import synth
 
-    pb, st = synth.workload_paper_scale(k_max=args.k_max)
     torch.cuda.set_device(0)
-    solver = A.Solver(pb, st, timing=True)
+    if args.calibrate_copy:
+        n = args.calibrate_copy * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] calibration copy: 3 x {args.calibrate_copy} MiB", file=sys.stderr, flush=True)
+        del src, dst
+    pb, st = synth.workload_paper_scale(k_max=args.k_max)
+    solver = A.Solver(pb, st, timing=True, prune=not args.brute)
     stream = torch.cuda.current_stream()
     print(f"[bench] workload ready: Ktot={pb.k_tot} M={pb.R.shape[0]} N={pb.S.shape[0] // pb.n_pre} "
           f"k_max={st.k_max}", file=sys.stderr, flush=True)
@@ -81,10 +95,10 @@ def main():
         ctxs.append(ctx)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    nn_ms, nn_n = 0.0, 0
+    nn_ms, nn_n, nn_pairs = 0.0, 0, 0.0
     for ctx in ctxs:
-        ms, n = A.asicp_kernel_time(ctx)
-        nn_ms, nn_n = nn_ms + ms, nn_n + n
+        ms, n, pr = A.asicp_kernel_time(ctx)
+        nn_ms, nn_n, nn_pairs = nn_ms + ms, nn_n + n, nn_pairs + pr
     solver.ctx = ctxs[-1]
     res = solver.result(per_particle=False)
     for ctx in ctxs:
@@ -93,8 +107,9 @@ def main():
     wall = t1 - t0
     ms_per_step = 1e3 * wall / args.steps
     p_iters = pb.k_tot * st.k_max * args.steps
-    pairs = sum(pb.K * int(np.diff(pb.s_off)[p]) * int(np.diff(pb.r_off)[o])
-                for o in range(pb.n_obj) for p in range(pb.n_pre))
+    all_pairs = sum(pb.K * int(np.diff(pb.s_off)[p]) * int(np.diff(pb.r_off)[o])
+                    for o in range(pb.n_obj) for p in range(pb.n_pre))
+    pairs = nn_pairs / max(nn_n, 1)  # distances actually evaluated per launch
     avg_nn = nn_ms / max(nn_n, 1) / 1e3
     achieved = FLOP_PER_PAIR * pairs / avg_nn
     line = {
@@ -114,7 +129,8 @@ def main():
         "roofline": {"bound": "mfma", "kernel": "k_nn_forward", "achieved": achieved / 1e12,
                      "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA,
                      "traffic": None, "avg_launch_ms": avg_nn * 1e3, "launches": nn_n,
-                     "pairs_per_launch": pairs, "flop_per_pair": FLOP_PER_PAIR},
+                     "pairs_per_launch": pairs, "brute_force_pairs_per_launch": all_pairs,
+                     "pruned": not args.brute, "flop_per_pair": FLOP_PER_PAIR},
         "best_cost": float(res["best_cost"][0]), "best_free": int(res["best_free"][0]),
     }
     if not args.no_cpu_baseline:

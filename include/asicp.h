@@ -60,6 +60,9 @@ typedef int32_t asicp_status;
 /* Flags. */
 #define ASICP_FLAG_DEBUG 1u  /* record per-point forward and reverse NN indices (needs more workspace) */
 #define ASICP_FLAG_TIMING 2u /* record HIP events around every forward-NN launch                     */
+#define ASICP_FLAG_NO_PRUNE 4u /* visit every object chunk in the forward NN (plain brute force); by    */
+                               /* default chunks whose bounding box is provably farther than every     */
+                               /* query's current best are skipped (same nearest-neighbour values)     */
 
 /* Signed distance grid of one preshape (Sec. IV-C): value at node (i, j, k)
  * is the signed distance of origin + cell * (i, j, k) to the complete
@@ -179,8 +182,10 @@ asicp_status asicp_result(asicp_ctx ctx, asicp_result_t* out, void* stream);
 
 /* With ASICP_FLAG_TIMING: total time and count of the forward-NN kernel
  * launches enqueued so far, from HIP events recorded on the launch stream
- * around each launch.  Synchronises on those events. */
-asicp_status asicp_kernel_time(asicp_ctx ctx, double* total_ms, int32_t* launches);
+ * around each launch, and (nn_pairs, may be NULL) the number of (contact
+ * point, object point) distances those launches evaluated.  Synchronises on
+ * the events. */
+asicp_status asicp_kernel_time(asicp_ctx ctx, double* total_ms, int32_t* launches, double* nn_pairs);
 
 /* Release the context (host memory and HIP events only). NULL is a no-op. */
 void asicp_destroy(asicp_ctx ctx);

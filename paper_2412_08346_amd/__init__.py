@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libasicp.so")
 
 ASICP_OK, ASICP_E_INVALID, ASICP_E_STATE, ASICP_E_HIP, ASICP_E_NUMERIC = 0, -1, -2, -3, -4
-ASICP_FLAG_DEBUG, ASICP_FLAG_TIMING = 1, 2
+ASICP_FLAG_DEBUG, ASICP_FLAG_TIMING, ASICP_FLAG_NO_PRUNE = 1, 2, 4
 
 EXPORTS = ("asicp_workspace_bytes", "asicp_create", "asicp_step", "asicp_solve", "asicp_result",
            "asicp_kernel_time", "asicp_destroy", "asicp_last_error")
@@ -86,7 +86,7 @@ def load():
         L.asicp_solve.restype = i32
         L.asicp_result.argtypes = [vp, vp, vp]
         L.asicp_result.restype = i32
-        L.asicp_kernel_time.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(i32)]
+        L.asicp_kernel_time.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(i32), C.POINTER(C.c_double)]
         L.asicp_kernel_time.restype = i32
         L.asicp_destroy.argtypes = [vp]
         L.asicp_destroy.restype = None
@@ -133,10 +133,12 @@ def asicp_result(ctx, out: asicp_result_t, stream: int, check: bool = True):
 
 
 def asicp_kernel_time(ctx):
+    """(total ms, launches, distance evaluations) of the forward-NN launches."""
     ms = C.c_double(0.0)
     n = C.c_int32(0)
-    _check(load().asicp_kernel_time(ctx, C.byref(ms), C.byref(n)))
-    return float(ms.value), int(n.value)
+    pairs = C.c_double(0.0)
+    _check(load().asicp_kernel_time(ctx, C.byref(ms), C.byref(n), C.byref(pairs)))
+    return float(ms.value), int(n.value), float(pairs.value)
 
 
 def asicp_destroy(ctx):
@@ -157,7 +159,7 @@ class Solver:
 
     def __init__(self, pb: "synth.Problem", st: "synth.Settings", debug: bool = False,
                  timing: bool = False, theta0=None, k_start: int = 0, prev_cost=None,
-                 converged=None, device: str = "cuda", stream=None):
+                 converged=None, device: str = "cuda", stream=None, prune: bool = True):
         import torch
 
         load()
@@ -201,7 +203,8 @@ class Solver:
             self._offs["s"].ctypes.data, C.cast(sdfs, C.c_void_p).value, k["theta0"].data_ptr(),
             k["prev_cost"].data_ptr() if "prev_cost" in k else None,
             k["converged"].data_ptr() if "converged" in k else None, int(k_start))
-        flags = (ASICP_FLAG_DEBUG if debug else 0) | (ASICP_FLAG_TIMING if timing else 0)
+        flags = ((ASICP_FLAG_DEBUG if debug else 0) | (ASICP_FLAG_TIMING if timing else 0) |
+                 (0 if prune else ASICP_FLAG_NO_PRUNE))
         self.config = make_config(st, flags)
         self.ws_bytes = asicp_workspace_bytes(self.problem, self.config)
         self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=dv)

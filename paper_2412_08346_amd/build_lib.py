@@ -24,26 +24,36 @@ FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-Wall",
          "-I", os.path.join(HERE, "..", "include")]
 
 
+# Per-file extra flags.  The forward-NN kernel assumes finite inputs in its
+# min-reduction (no NaN canonicalisation before v_min3); non-finite poses are
+# caught by the finaliser's check and a re-scan miss only ever yields index 0.
+EXTRA = {"k_nn_forward.hip": ["-fno-honor-nans"]}
+
+
 def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, defines=(), out: str = LIB) -> str:
+    """Compile every source and link `out`.  `defines` are extra -D tuning
+    macros (e.g. ASICP_NN_Q=2) for building variants side by side."""
     objs = []
-    obj_dir = os.path.join(HERE, "_build")
+    tag = "_".join(d.replace("=", "") for d in defines)
+    obj_dir = os.path.join(HERE, "_build" + ("_" + tag if tag else ""))
     os.makedirs(obj_dir, exist_ok=True)
     procs = []
     for src in sources():
         obj = os.path.join(obj_dir, os.path.basename(src) + ".o")
         objs.append(obj)
-        cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+        cmd = [HIPCC, *FLAGS, *[f"-D{d}" for d in defines], *EXTRA.get(os.path.basename(src), []),
+               "-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
     failed = False
     for cmd, p in procs:
-        out, _ = p.communicate()
-        text = "\n".join(l for l in out.decode(errors="replace").splitlines()
+        text_out, _ = p.communicate()
+        text = "\n".join(l for l in text_out.decode(errors="replace").splitlines()
                          if "packed-fp32-ops" not in l)
         if p.returncode != 0:
             failed = True
@@ -52,11 +62,11 @@ def build(verbose: bool = False) -> str:
             print(text)
     if failed:
         raise RuntimeError("hipcc failed")
-    tmp = LIB + ".tmp"
+    tmp = out + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

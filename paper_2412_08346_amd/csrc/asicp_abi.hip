@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "asicp_internal.h"
+#include "nn_core.h"
 
 using namespace asicp;
 
@@ -24,8 +25,9 @@ constexpr int kMaxPoints = 1 << 22;   // per object / collision cloud / preshape
 constexpr int kMaxGroups = 1 << 16;
 
 struct Layout {
-  size_t groups, objs, pres, obj_prep, pre_prep, obj_com, pre_const;
-  size_t theta, cost, col_cost, prev_cost, ncol, converged, grad, grad_ct, grad_col, phi, h;
+  size_t groups, objs, pres, obj_prep, pre_prep, obj_pts, pre_pts, obj_perm, pre_perm, obj_box, pre_box;
+  size_t sort_keys, counters, obj_com, pre_const, col_pts, col_perm;
+  size_t theta, cost, col_cost, prev_cost, ncol, converged, grad, grad_ct, grad_col, phi, h, bw_hist, bw_state;
   size_t nn_part, col_part, best, best_theta, flags, dbg_nn, dbg_rev;
   size_t total;
 };
@@ -33,6 +35,8 @@ struct Layout {
 struct Shape {
   int n_obj, n_pre, K, G, Ktot;
   int obj_tg, pre_tg, max_waves_pp, max_gate_chunks, n_max, mc_max;
+  long long sort_keys;  // total power-of-two padded cloud sizes
+  long long c_total;    // collision points over all objects
   long long total_waves, total_gate_wgs;
   bool debug;
 };
@@ -52,6 +56,16 @@ Layout layout_of(const Shape& s) {
   L.pres = bump(c, sizeof(PreInfo) * s.n_pre);
   L.obj_prep = bump(c, (size_t)s.obj_tg * 64 * 16);
   L.pre_prep = bump(c, (size_t)s.pre_tg * 64 * 16);
+  L.obj_pts = bump(c, (size_t)s.obj_tg * 64 * 16);
+  L.pre_pts = bump(c, (size_t)s.pre_tg * 64 * 16);
+  L.obj_perm = bump(c, (size_t)s.obj_tg * 64 * 4);
+  L.pre_perm = bump(c, (size_t)s.pre_tg * 64 * 4);
+  L.obj_box = bump(c, (size_t)s.obj_tg / kChunkTG * 32);
+  L.pre_box = bump(c, (size_t)s.pre_tg / kChunkTG * 32);
+  L.sort_keys = bump(c, (size_t)s.sort_keys * 8);
+  L.col_pts = bump(c, (size_t)(s.c_total > 0 ? s.c_total : 1) * 16);
+  L.col_perm = bump(c, (size_t)(s.c_total > 0 ? s.c_total : 1) * 4);
+  L.counters = bump(c, 16);
   L.obj_com = bump(c, 16 * (size_t)s.n_obj);
   L.pre_const = bump(c, 32 * (size_t)s.n_pre);
   L.theta = bump(c, 4 * 7 * K);
@@ -65,6 +79,8 @@ Layout layout_of(const Shape& s) {
   L.grad_col = bump(c, 4 * 6 * K);
   L.phi = bump(c, 4 * 6 * K);
   L.h = bump(c, 4 * (size_t)s.G);
+  L.bw_hist = bump(c, 4 * 256 * (size_t)s.G);
+  L.bw_state = bump(c, 16 * (size_t)s.G);
   L.nn_part = bump(c, 4 * kPartStride * K * (size_t)s.max_waves_pp);
   L.col_part = bump(c, 4 * kPartStride * K * (size_t)(s.max_gate_chunks > 0 ? s.max_gate_chunks : 1));
   L.best = bump(c, 8 * (size_t)s.n_obj);
@@ -77,6 +93,12 @@ Layout layout_of(const Shape& s) {
 }
 
 bool finite_pos(float v) { return std::isfinite(v) && v > 0.f; }
+
+long long pow2_at_least(long long n) {
+  long long p = 2;
+  while (p < n) p <<= 1;
+  return p;
+}
 
 // Host-only validation of every argument; fills `s`.
 asicp_status validate(const asicp_problem* pb, const asicp_config* cfg, Shape& s) {
@@ -101,6 +123,7 @@ asicp_status validate(const asicp_problem* pb, const asicp_config* cfg, Shape& s
   s.G = s.n_obj * s.n_pre;
   s.Ktot = (int)ktot;
   s.obj_tg = s.pre_tg = 0;
+  s.sort_keys = 0;
   s.n_max = s.mc_max = 0;
   s.max_waves_pp = 0;
   s.max_gate_chunks = 0;
@@ -110,21 +133,25 @@ asicp_status validate(const asicp_problem* pb, const asicp_config* cfg, Shape& s
     const long long mc = (long long)pb->c_off[o + 1] - pb->c_off[o];
     if (m < 1 || m > kMaxPoints) return fail(ASICP_E_INVALID, "object " + std::to_string(o) + " must have 1..4194304 points");
     if (mc < 0 || mc > kMaxPoints) return fail(ASICP_E_INVALID, "collision cloud " + std::to_string(o) + " must have 0..4194304 points");
-    s.obj_tg += (int)((m + 63) / 64);
+    s.obj_tg += (int)((m + kPadPoints - 1) / kPadPoints) * (kPadPoints / 64);
+    s.sort_keys += pow2_at_least((long long)m);
+    if (mc > 0) s.sort_keys += pow2_at_least((long long)mc);
     s.mc_max = std::max(s.mc_max, (int)mc);
     s.max_gate_chunks = std::max(s.max_gate_chunks, (int)((mc + kGateChunk - 1) / kGateChunk));
     any_c = any_c || mc > 0;
   }
   if (any_c && (!pb->cx || !pb->cy || !pb->cz))
     return fail(ASICP_E_INVALID, "collision cloud device pointers are required");
+  s.c_total = pb->c_off[s.n_obj];
   if ((long long)pb->r_off[s.n_obj] > (1ll << 30) || (long long)pb->c_off[s.n_obj] > (1ll << 30))
     return fail(ASICP_E_INVALID, "clouds too large");
   for (int p = 0; p < s.n_pre; ++p) {
     const long long n = (long long)pb->s_off[p + 1] - pb->s_off[p];
     if (n < 1 || n > kMaxPoints) return fail(ASICP_E_INVALID, "preshape " + std::to_string(p) + " must have 1..4194304 points");
-    s.pre_tg += (int)((n + 63) / 64);
+    s.pre_tg += (int)((n + kPadPoints - 1) / kPadPoints) * (kPadPoints / 64);
+    s.sort_keys += pow2_at_least((long long)n);
     s.n_max = std::max(s.n_max, (int)n);
-    s.max_waves_pp = std::max(s.max_waves_pp, (int)((n + 63) / 64));
+    s.max_waves_pp = std::max(s.max_waves_pp, (int)((n + kQueriesPerWave - 1) / kQueriesPerWave));
     const asicp_sdf& g = pb->sdf[p];
     if (!g.values) return fail(ASICP_E_INVALID, "SDF values of preshape " + std::to_string(p) + " are NULL");
     if (g.nx < 2 || g.ny < 2 || g.nz < 2 || (long long)g.nx * g.ny * g.nz > (1ll << 30))
@@ -140,7 +167,7 @@ asicp_status validate(const asicp_problem* pb, const asicp_config* cfg, Shape& s
     for (int p = 0; p < s.n_pre; ++p) {
       const long long n = (long long)pb->s_off[p + 1] - pb->s_off[p];
       const long long mc = (long long)pb->c_off[o + 1] - pb->c_off[o];
-      s.total_waves += (long long)s.K * ((n + 63) / 64);
+      s.total_waves += (long long)s.K * ((n + kQueriesPerWave - 1) / kQueriesPerWave);
       s.total_gate_wgs += (long long)s.K * ((mc + kGateChunk - 1) / kGateChunk);
     }
   if (s.total_waves > (1ll << 30) || s.total_gate_wgs > (1ll << 30))
@@ -168,7 +195,9 @@ asicp_status validate(const asicp_problem* pb, const asicp_config* cfg, Shape& s
   }
   if (!finite_pos(cfg->h_min)) return fail(ASICP_E_INVALID, "h_min must be finite and > 0");
   if (!std::isfinite(cfg->conv_tol) || cfg->conv_tol < 0.f) return fail(ASICP_E_INVALID, "conv_tol must be finite and >= 0");
-  if (cfg->flags & ~(ASICP_FLAG_DEBUG | ASICP_FLAG_TIMING)) return fail(ASICP_E_INVALID, "unknown flag bits");
+  if (cfg->flags & ~(ASICP_FLAG_DEBUG | ASICP_FLAG_TIMING | ASICP_FLAG_NO_PRUNE))
+    return fail(ASICP_E_INVALID, "unknown flag bits");
+  if (s.sort_keys > (1ll << 30)) return fail(ASICP_E_INVALID, "clouds too large to sort");
   s.debug = (cfg->flags & ASICP_FLAG_DEBUG) != 0;
   return ASICP_OK;
 }
@@ -224,16 +253,21 @@ asicp_status asicp_create(const asicp_problem* pb, const asicp_config* cfg, void
   std::vector<ObjInfo> objs(s.n_obj);
   std::vector<PreInfo> pres(s.n_pre);
   int tg = 0;
+  long long key_off = 0;
   for (int o = 0; o < s.n_obj; ++o) {
     ObjInfo& oi = objs[o];
+    std::memset(&oi, 0, sizeof oi);  // the cloud's bounding box is filled in on the device
     oi.r_begin = pb->r_off[o];
     oi.m = pb->r_off[o + 1] - pb->r_off[o];
     oi.c_begin = pb->c_off[o];
     oi.mc = pb->c_off[o + 1] - pb->c_off[o];
     oi.prep_tg_begin = tg;
-    oi.ntg = (oi.m + 63) / 64;
+    oi.ntg = ((oi.m + kPadPoints - 1) / kPadPoints) * (kPadPoints / 64);
     oi.gate_chunks = (oi.mc + kGateChunk - 1) / kGateChunk;
-    oi.pad = 0;
+    oi.key_off = (int32_t)key_off;
+    key_off += pow2_at_least(oi.m);
+    oi.c_key_off = (int32_t)key_off;
+    if (oi.mc > 0) key_off += pow2_at_least(oi.mc);
     tg += oi.ntg;
   }
   tg = 0;
@@ -243,8 +277,10 @@ asicp_status asicp_create(const asicp_problem* pb, const asicp_config* cfg, void
     pi.s_begin = pb->s_off[p];
     pi.n = pb->s_off[p + 1] - pb->s_off[p];
     pi.prep_tg_begin = tg;
-    pi.ntg = (pi.n + 63) / 64;
-    pi.waves = pi.ntg;
+    pi.ntg = ((pi.n + kPadPoints - 1) / kPadPoints) * (kPadPoints / 64);
+    pi.waves = (pi.n + kQueriesPerWave - 1) / kQueriesPerWave;
+    pi.key_off = (int32_t)key_off;
+    key_off += pow2_at_least(pi.n);
     tg += pi.ntg;
     const asicp_sdf& g = pb->sdf[p];
     pi.nx = g.nx; pi.ny = g.ny; pi.nz = g.nz;
@@ -252,6 +288,10 @@ asicp_status asicp_create(const asicp_problem* pb, const asicp_config* cfg, void
     pi.ox = g.origin[0]; pi.oy = g.origin[1]; pi.oz = g.origin[2];
     pi.cell = g.cell;
     pi.inv_cell = (float)(1.0 / (double)g.cell);
+    for (int ax = 0; ax < 3; ++ax) {
+      pi.neg_lo[ax] = 0x7fffffff;  // reduced on the device by the set-up
+      pi.neg_hi[ax] = -1;
+    }
   }
   int wave_off = 0, gate_off = 0;
   for (int o = 0; o < s.n_obj; ++o)
@@ -283,6 +323,17 @@ asicp_status asicp_create(const asicp_problem* pb, const asicp_config* cfg, void
   d.mc_max = s.mc_max > 0 ? s.mc_max : 1;
   d.obj_prep = reinterpret_cast<float4*>(ws + L.obj_prep);
   d.pre_prep = reinterpret_cast<float4*>(ws + L.pre_prep);
+  d.obj_pts = reinterpret_cast<float4*>(ws + L.obj_pts);
+  d.pre_pts = reinterpret_cast<float4*>(ws + L.pre_pts);
+  d.obj_perm = reinterpret_cast<int32_t*>(ws + L.obj_perm);
+  d.pre_perm = reinterpret_cast<int32_t*>(ws + L.pre_perm);
+  d.obj_box = reinterpret_cast<float*>(ws + L.obj_box);
+  d.pre_box = reinterpret_cast<float*>(ws + L.pre_box);
+  d.sort_keys = reinterpret_cast<unsigned long long*>(ws + L.sort_keys);
+  d.col_pts = reinterpret_cast<float4*>(ws + L.col_pts);
+  d.col_perm = reinterpret_cast<int32_t*>(ws + L.col_perm);
+  d.counters = reinterpret_cast<unsigned long long*>(ws + L.counters);
+  d.prune = (cfg->flags & ASICP_FLAG_NO_PRUNE) ? 0 : 1;
   d.obj_com = reinterpret_cast<float*>(ws + L.obj_com);
   d.pre_const = reinterpret_cast<float*>(ws + L.pre_const);
   d.theta = reinterpret_cast<float*>(ws + L.theta);
@@ -296,6 +347,8 @@ asicp_status asicp_create(const asicp_problem* pb, const asicp_config* cfg, void
   d.grad_col = reinterpret_cast<float*>(ws + L.grad_col);
   d.phi = reinterpret_cast<float*>(ws + L.phi);
   d.h = reinterpret_cast<float*>(ws + L.h);
+  d.bw_hist = reinterpret_cast<unsigned int*>(ws + L.bw_hist);
+  d.bw_state = reinterpret_cast<unsigned int*>(ws + L.bw_state);
   d.nn_part = reinterpret_cast<float*>(ws + L.nn_part);
   d.col_part = reinterpret_cast<float*>(ws + L.col_part);
   d.best = reinterpret_cast<int32_t*>(ws + L.best);
@@ -475,7 +528,7 @@ asicp_status asicp_result(asicp_ctx c, asicp_result_t* out, void* stream) {
   return ASICP_OK;
 }
 
-asicp_status asicp_kernel_time(asicp_ctx c, double* total_ms, int32_t* launches) {
+asicp_status asicp_kernel_time(asicp_ctx c, double* total_ms, int32_t* launches, double* nn_pairs) {
   g_err.clear();
   if (!c || !total_ms || !launches) return fail(ASICP_E_INVALID, "NULL argument");
   if (!(c->cfg.flags & ASICP_FLAG_TIMING)) return fail(ASICP_E_STATE, "context was created without ASICP_FLAG_TIMING");
@@ -486,6 +539,12 @@ asicp_status asicp_kernel_time(asicp_ctx c, double* total_ms, int32_t* launches)
     if (hipEventElapsedTime(&ms, c->ev[2 * j], c->ev[2 * j + 1]) != hipSuccess)
       return fail(ASICP_E_HIP, "hipEventElapsedTime failed");
     tot += ms;
+  }
+  if (nn_pairs) {
+    unsigned long long cnt = 0;
+    if (c->n_timed > 0 && hipMemcpy(&cnt, c->d.counters, sizeof cnt, hipMemcpyDeviceToHost) != hipSuccess)
+      return fail(ASICP_E_HIP, "reading the pair counter failed");
+    *nn_pairs = (double)cnt;
   }
   *total_ms = tot;
   *launches = c->n_timed;

@@ -10,9 +10,22 @@ namespace asicp {
 
 constexpr int kWave = 64;          // CDNA wavefront
 constexpr int kTileGroup = 64;     // points per MFMA-ready tile group (4 tiles of 16)
-constexpr int kQueriesPerWave = 64;
-constexpr int kGateChunk = 256;    // collision points per gate workgroup
+// Query blocks of 16 per forward-NN wavefront (tuning knob, 1..4) and an
+// optional waves-per-SIMD occupancy request for that kernel (0: compiler's).
+#ifndef ASICP_NN_Q
+#define ASICP_NN_Q 4
+#endif
+#ifndef ASICP_NN_WPE
+#define ASICP_NN_WPE 4
+#endif
+#ifndef ASICP_NN_SPLIT
+#define ASICP_NN_SPLIT 0
+#endif
+constexpr int kNnQ = ASICP_NN_Q;
+constexpr int kQueriesPerWave = 16 * kNnQ;
+constexpr int kGateChunk = 2048;   // collision points per gate workgroup (8 per thread)
 constexpr int kPartStride = 8;     // floats per partial-sum record
+constexpr int kBwSlices = 32;      // workgroups per group in each bandwidth pass
 constexpr float kDummyNorm = 1.0e30f;  // |r|^2 of padding points: never a nearest neighbour
 
 // Per-group descriptor (group = (object, preshape)).
@@ -28,8 +41,11 @@ struct ObjInfo {
   int32_t c_begin, mc;     // offset into C inputs, point count
   int32_t prep_tg_begin;   // first tile group in the prepared object clouds
   int32_t ntg;             // tile groups (ceil(m / 64))
-  int32_t gate_chunks;     // ceil(mc / 256)
-  int32_t pad;
+  int32_t gate_chunks;     // ceil(mc / kGateChunk)
+  int32_t key_off;         // offset of this cloud's sort keys (uint64) in the scratch
+  float cmin[3], cmax[3];  // bounding box of the collision cloud (set on the device)
+  int32_t c_key_off;       // sort keys of the collision cloud
+  int32_t pad2;
 };
 
 // Per-preshape descriptor.
@@ -40,7 +56,9 @@ struct PreInfo {
   int32_t nx, ny, nz;
   const float* sdf;
   float ox, oy, oz, cell, inv_cell;
-  float pad[3];
+  int32_t neg_lo[3];       // per axis: lowest / highest node index with a
+  int32_t neg_hi[3];       //   negative value (set on the device at set-up)
+  int32_t key_off;         // offset of this cloud's sort keys (uint64) in the scratch
 };
 
 // Everything a kernel needs, passed by value.
@@ -55,9 +73,22 @@ struct Dev {
   int32_t total_waves, total_gate_wgs;
   int32_t max_waves_pp, max_gate_chunks;  // partial-record strides
   int32_t n_max, mc_max;
-  // prepared clouds: float4 per point in MFMA A-operand order
+  // clouds in Morton order (index = prep_tg_begin*64 + k): MFMA-ready float4
+  // (A-operand order), plain float4 (x, y, z, 0), original index (-1 for
+  // padding), and one bounding box per 128-point chunk (lo xyz, -, hi xyz, -)
   float4* obj_prep;
   float4* pre_prep;
+  float4* obj_pts;
+  float4* pre_pts;
+  int32_t* obj_perm;
+  int32_t* pre_perm;
+  float* obj_box;
+  float* pre_box;
+  float4* col_pts;    // collision clouds in Morton order (offsets as the input's)
+  int32_t* col_perm;
+  unsigned long long* sort_keys;
+  unsigned long long* counters;  // [0]: forward-NN distance evaluations
+  int32_t prune;                 // skip object chunks that cannot hold a nearest neighbour
   float* obj_com;   // [n_obj][4]
   float* pre_const; // [n_pre][8]: tcp xyz, rho2, a_t, a_w, -, -
   // state
@@ -72,6 +103,8 @@ struct Dev {
   float* grad_col;
   float* phi;       // [6][Ktot]
   float* h;         // [G]
+  unsigned int* bw_hist;   // [G][256] radix histogram (zero between passes)
+  unsigned int* bw_state;  // [G][4] prefix, mask, rank, finished workgroups
   float* nn_part;   // [Ktot][max_waves_pp][8]
   float* col_part;  // [Ktot][max_gate_chunks][8]
   int32_t* best;    // [n_obj][2]: particle, free flag
@@ -109,11 +142,86 @@ __device__ __forceinline__ void load_pose(const float* theta, int Ktot, int i, f
   q[3] = theta[6 * Ktot + i];
 }
 
-// Sum over the 64 lanes of a wave in a fixed butterfly order; every lane gets the total.
+// Cross-lane helpers built from VALU lane permutes only (no LDS crossbar):
+// DPP within a row of 16 lanes, and gfx950's permlane16/32 swaps across rows.
+template <int CTRL>
+__device__ __forceinline__ float dppf(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL>
+__device__ __forceinline__ int dppi(int v) {
+  return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, true);
+}
+constexpr int kDppXor1 = 0xB1;         // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;         // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141;  // lane l <-> 7-l within each 8
+constexpr int kDppMirror = 0x140;      // lane l <-> 15-l within each row
+
+// Value of the same position j in row 2k and row 2k+1 (k = lane's row pair),
+// and of rows (0,2) / (1,3) after the 32-lane swap.
+struct RowPair {
+  float even, odd;
+};
+__device__ __forceinline__ RowPair swap16(float v) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return {__uint_as_float(r[0]), __uint_as_float(r[1])};
+}
+__device__ __forceinline__ RowPair swap32(float v) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return {__uint_as_float(r[0]), __uint_as_float(r[1])};
+}
+__device__ __forceinline__ int2 swap16i(int v) {
+  const auto r = __builtin_amdgcn_permlane16_swap((unsigned)v, (unsigned)v, false, false);
+  return make_int2((int)r[0], (int)r[1]);
+}
+__device__ __forceinline__ int2 swap32i(int v) {
+  const auto r = __builtin_amdgcn_permlane32_swap((unsigned)v, (unsigned)v, false, false);
+  return make_int2((int)r[0], (int)r[1]);
+}
+
+// Reductions over the four rows (lanes j, j+16, j+32, j+48); every lane gets the result.
+__device__ __forceinline__ float rows_min(float v) {
+  const RowPair a = swap16(v);
+  v = fminf(a.even, a.odd);
+  const RowPair b = swap32(v);
+  return fminf(b.even, b.odd);
+}
+__device__ __forceinline__ int rows_min_i(int v) {
+  const int2 a = swap16i(v);
+  v = min(a.x, a.y);
+  const int2 b = swap32i(v);
+  return min(b.x, b.y);
+}
+__device__ __forceinline__ int rows_sum_i(int v) {
+  const int2 a = swap16i(v);
+  v = a.x + a.y;
+  const int2 b = swap32i(v);
+  return b.x + b.y;
+}
+// Reductions within each row of 16 lanes.
+__device__ __forceinline__ float row_max(float v) {
+  v = fmaxf(v, dppf<kDppXor1>(v));
+  v = fmaxf(v, dppf<kDppXor2>(v));
+  v = fmaxf(v, dppf<kDppHalfMirror>(v));
+  return fmaxf(v, dppf<kDppMirror>(v));
+}
+__device__ __forceinline__ float row_min(float v) {
+  v = fminf(v, dppf<kDppXor1>(v));
+  v = fminf(v, dppf<kDppXor2>(v));
+  v = fminf(v, dppf<kDppHalfMirror>(v));
+  return fminf(v, dppf<kDppMirror>(v));
+}
+
+// Sum over the 64 lanes of a wave in a fixed order; every lane gets the total.
 __device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+  v += dppf<kDppXor1>(v);
+  v += dppf<kDppXor2>(v);
+  v += dppf<kDppHalfMirror>(v);
+  v += dppf<kDppMirror>(v);
+  const RowPair a = swap16(v);
+  v = a.even + a.odd;
+  const RowPair b = swap32(v);
+  return b.even + b.odd;
 }
 
 // Launchers (host side), one per kernel family.

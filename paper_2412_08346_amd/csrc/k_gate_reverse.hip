@@ -1,17 +1,24 @@
 // k_gate_reverse.hip -- SDF collision gate and reverse nearest neighbour
 // (Sec. IV-C and eq. (18); Algorithm 1's collision branch).
 //
-// One workgroup = one particle x 256 points of its collision cloud.  Each
+// One workgroup = one particle x 2048 points of its collision cloud.  Each
 // point is moved into the gripper frame, c' = R^T (c - t), and looked up in
 // the preshape's SDF by trilinear interpolation; it collides when it lies in
 // the node box and the value is strictly negative.  Colliding points are
-// compacted in index order and paired with their nearest contact point, in
+// compacted in a fixed order and paired with their nearest contact point in
 // the gripper frame (a rigid motion preserves distances, so this is the
 // nearest transformed contact point of eq. (18)).  Partial sums, gripper
 // frame: [sum |s - c'|^2, sum (s - c') (3), sum s x (s - c') (3), count].
+//
+// Trilinear weights are non-negative, so a point can only collide inside a
+// cell with a negative corner: the box of such cells (from the negative SDF
+// nodes) culls whole workgroups (transformed bounding box of the cloud) and
+// single points without reading the grid.  Both tests are exact.
 #include "nn_core.h"
 
 namespace asicp {
+
+constexpr int kPerThread = kGateChunk / 256;
 
 __device__ __forceinline__ int xcd_logical_g(int b, int nwg) {
   const int per = (nwg + 7) >> 3;
@@ -28,6 +35,9 @@ __device__ __forceinline__ bool sdf_collides(const PreInfo& pi, float px, float 
   const int ix = min((int)floorf(ux), pi.nx - 2);
   const int iy = min((int)floorf(uy), pi.ny - 2);
   const int iz = min((int)floorf(uz), pi.nz - 2);
+  if (ix < pi.neg_lo[0] - 1 || ix > pi.neg_hi[0] || iy < pi.neg_lo[1] - 1 || iy > pi.neg_hi[1] ||
+      iz < pi.neg_lo[2] - 1 || iz > pi.neg_hi[2])
+    return false;
   const float fx = ux - (float)ix, fy = uy - (float)iy, fz = uz - (float)iz;
   const size_t sx = 1, sy = (size_t)pi.nx, sz = (size_t)pi.nx * pi.ny;
   const float* v = pi.sdf + (size_t)iz * sz + (size_t)iy * sy + ix;
@@ -40,15 +50,61 @@ __device__ __forceinline__ bool sdf_collides(const PreInfo& pi, float px, float 
   return (1.f - fz) * c0 + fz * c1 < 0.f;
 }
 
+// Can any point of the cloud's bounding box reach a cell with a negative
+// corner?  Box corners are moved into the gripper frame; a 10 um margin covers
+// the rounding of the per-point transform.
+__device__ __forceinline__ bool box_may_collide(const PreInfo& pi, const ObjInfo& oi, const float R[9],
+                                                const float t[3]) {
+  if (pi.neg_hi[0] < 0) return false;  // no negative node at all
+  float lo[3] = {__builtin_inff(), __builtin_inff(), __builtin_inff()};
+  float hi[3] = {-__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
+  for (int c = 0; c < 8; ++c) {
+    const float dx = ((c & 1) ? oi.cmax[0] : oi.cmin[0]) - t[0];
+    const float dy = ((c & 2) ? oi.cmax[1] : oi.cmin[1]) - t[1];
+    const float dz = ((c & 4) ? oi.cmax[2] : oi.cmin[2]) - t[2];
+    const float p[3] = {R[0] * dx + R[3] * dy + R[6] * dz, R[1] * dx + R[4] * dy + R[7] * dz,
+                        R[2] * dx + R[5] * dy + R[8] * dz};
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = fminf(lo[a], p[a]);
+      hi[a] = fmaxf(hi[a], p[a]);
+    }
+  }
+  const float o[3] = {pi.ox, pi.oy, pi.oz};
+  const float margin = 1e-5f;
+  for (int a = 0; a < 3; ++a) {
+    const float b0 = o[a] + (float)(pi.neg_lo[a] - 1) * pi.cell - margin;
+    const float b1 = o[a] + (float)(pi.neg_hi[a] + 1) * pi.cell + margin;
+    if (!(hi[a] >= b0 && lo[a] <= b1)) return false;
+  }
+  return true;
+}
+
+// Reverse NN of Q blocks of colliding points (gripper frame) against the
+// Morton-sorted contact cloud, skipping contact chunks that cannot hold a
+// nearest point (same exact result as scanning them all).
 template <int Q>
 __device__ __forceinline__ void rev_scan(const Dev& d, const PreInfo& pi, const float* bq, int* idx) {
-  nn_scan<Q>(d.pre_prep + (size_t)pi.prep_tg_begin * 64, pi.ntg, bq, idx, d.flags + 1);
+  const int lane = threadIdx.x & 63;
+  float snorm[Q];
+  int vq[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    // the lane's query: components from the four rows at its position
+    const float x = __shfl(bq[q], (lane & 15), 64);
+    const float y = __shfl(bq[q], (lane & 15) + 16, 64);
+    const float z = __shfl(bq[q], (lane & 15) + 32, 64);
+    snorm[q] = x * x + y * y + z * z;
+    vq[q] = 16;
+  }
+  nn_scan_pruned<Q>(d.pre_prep + (size_t)pi.prep_tg_begin * 64, pi.ntg, pi.n,
+                    d.pre_box + (size_t)pi.prep_tg_begin / kChunkTG * 8, bq, snorm, vq, idx,
+                    d.flags + 1);
 }
 
 __global__ __launch_bounds__(256) void k_gate_reverse(Dev d) {
   __shared__ float lx[kGateChunk], ly[kGateChunk], lz[kGateChunk];
   __shared__ int lm[kGateChunk];
-  __shared__ int wcount[4];
+  __shared__ int wtot[4];
   __shared__ float wpart[4][kPartStride];
 
   const int nwg = d.total_gate_wgs;
@@ -67,61 +123,91 @@ __global__ __launch_bounds__(256) void k_gate_reverse(Dev d) {
   const int local = logical - gi.gate_off;
   const int pj = local / oi.gate_chunks, cc = local - pj * oi.gate_chunks;
   const int i = lo * d.K + pj;
+  float* out = d.col_part + ((size_t)i * d.max_gate_chunks + cc) * kPartStride;
 
   float t[3], qv[4], R[9];
   load_pose(d.theta, d.Ktot, i, t, qv);
   quat_to_rot(qv[0], qv[1], qv[2], qv[3], R);
 
-  const int m = cc * kGateChunk + tid;
-  bool col = false;
-  float px = 0.f, py = 0.f, pz = 0.f;
-  if (m < oi.mc) {
-    const float dx = d.cx[oi.c_begin + m] - t[0];
-    const float dy = d.cy[oi.c_begin + m] - t[1];
-    const float dz = d.cz[oi.c_begin + m] - t[2];
-    px = R[0] * dx + R[3] * dy + R[6] * dz;
-    py = R[1] * dx + R[4] * dy + R[7] * dz;
-    pz = R[2] * dx + R[5] * dy + R[8] * dz;
-    col = sdf_collides(pi, px, py, pz);
-    if (d.dbg_rev && !col) d.dbg_rev[(size_t)i * d.mc_max + m] = -1;
+  if (!box_may_collide(pi, oi, R, t)) {
+    if (tid < kPartStride) out[tid] = 0.f;
+    if (d.dbg_rev)
+      for (int r = 0; r < kPerThread; ++r) {
+        const int m = cc * kGateChunk + r * 256 + tid;
+        if (m < oi.mc) d.dbg_rev[(size_t)i * d.mc_max + d.col_perm[oi.c_begin + m]] = -1;
+      }
+    return;
   }
-  const unsigned long long mask = __ballot(col);
-  const int before = __popcll(mask & ((1ull << lane) - 1ull));
-  if (lane == 0) wcount[w] = __popcll(mask);
+
+  // gate: thread tid owns points cc*2048 + r*256 + tid, r = 0..7, of the
+  // Morton-sorted collision cloud (so colliding points come out clustered)
+  unsigned int bits = 0u;
+  float px[kPerThread], py[kPerThread], pz[kPerThread];
+#pragma unroll
+  for (int r = 0; r < kPerThread; ++r) {
+    const int m = cc * kGateChunk + r * 256 + tid;
+    px[r] = py[r] = pz[r] = 0.f;
+    if (m < oi.mc) {
+      const float4 c = d.col_pts[oi.c_begin + m];
+      const float dx = c.x - t[0];
+      const float dy = c.y - t[1];
+      const float dz = c.z - t[2];
+      px[r] = R[0] * dx + R[3] * dy + R[6] * dz;
+      py[r] = R[1] * dx + R[4] * dy + R[7] * dz;
+      pz[r] = R[2] * dx + R[5] * dy + R[8] * dz;
+      const bool col = sdf_collides(pi, px[r], py[r], pz[r]);
+      if (col) bits |= 1u << r;
+      else if (d.dbg_rev) d.dbg_rev[(size_t)i * d.mc_max + d.col_perm[oi.c_begin + m]] = -1;
+    }
+  }
+  // workgroup exclusive scan of the per-thread counts (thread order)
+  const int cnt = __popc(bits);
+  int incl = cnt;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int o = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += o;
+  }
+  if (lane == 63) wtot[w] = incl;
   __syncthreads();
   int base = 0, total = 0;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    base += (k < w) ? wcount[k] : 0;
-    total += wcount[k];
+    base += (k < w) ? wtot[k] : 0;
+    total += wtot[k];
   }
-  if (col) {
-    const int pos = base + before;
-    lx[pos] = px; ly[pos] = py; lz[pos] = pz; lm[pos] = m;
+  int pos = base + incl - cnt;
+#pragma unroll
+  for (int r = 0; r < kPerThread; ++r) {
+    if (bits & (1u << r)) {
+      lx[pos] = px[r]; ly[pos] = py[r]; lz[pos] = pz[r];
+      lm[pos] = cc * kGateChunk + r * 256 + tid;
+      ++pos;
+    }
   }
   __syncthreads();
-
-  float* out = d.col_part + ((size_t)i * d.max_gate_chunks + cc) * kPartStride;
   if (total == 0) {
     if (tid < kPartStride) out[tid] = 0.f;
     return;
   }
-  // reverse NN: blocks of 16 colliding points, block b handled by wave b % 4
+  // reverse NN: blocks of 16 colliding points; wave w takes blocks w, w+4, ...
+  // in batches of up to 4 blocks per scan of the contact cloud
   const int nb = (total + 15) >> 4;
   const int nbw = (nb > w) ? (nb - w + 3) >> 2 : 0;
+  const int comp = lane >> 4;
   float e2 = 0.f, ex = 0.f, ey = 0.f, ez = 0.f, mx = 0.f, my = 0.f, mz = 0.f;
-  if (nbw > 0) {
-    const int comp = lane >> 4;
+  for (int k0 = 0; k0 < nbw; k0 += 4) {
+    const int qn = min(4, nbw - k0);
     float bq[4];
+    const int pfirst = (w + 4 * k0) * 16;  // a colliding point of this batch
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int pos = (w + 4 * q) * 16 + (lane & 15);
-      float v = 0.f;
-      if (q < nbw && pos < total) v = comp == 0 ? lx[pos] : comp == 1 ? ly[pos] : lz[pos];
+      int p = (w + 4 * (k0 + q)) * 16 + (lane & 15);
+      if (!(q < qn && p < total)) p = pfirst;  // padding queries repeat it
+      const float v = comp == 0 ? lx[p] : comp == 1 ? ly[p] : lz[p];
       bq[q] = comp == 3 ? 1.0f : v;
     }
     int idx[4] = {0, 0, 0, 0};
-    switch (nbw) {
+    switch (qn) {
       case 1: rev_scan<1>(d, pi, bq, idx); break;
       case 2: rev_scan<2>(d, pi, bq, idx); break;
       case 3: rev_scan<3>(d, pi, bq, idx); break;
@@ -131,23 +217,23 @@ __global__ __launch_bounds__(256) void k_gate_reverse(Dev d) {
     if (comp == 1) my_idx = idx[1];
     if (comp == 2) my_idx = idx[2];
     if (comp == 3) my_idx = idx[3];
-    const int pos = (w + 4 * comp) * 16 + (lane & 15);
-    if (comp < nbw && pos < total) {
+    const int p = (w + 4 * (k0 + comp)) * 16 + (lane & 15);
+    if (comp < qn && p < total) {
       if (my_idx >= pi.n) {
         atomicOr(d.flags + 1, 4);
         my_idx = pi.n - 1;
       }
-      const float sx = d.sx[pi.s_begin + my_idx];
-      const float sy = d.sy[pi.s_begin + my_idx];
-      const float sz = d.sz[pi.s_begin + my_idx];
-      ex = sx - lx[pos];
-      ey = sy - ly[pos];
-      ez = sz - lz[pos];
-      e2 = ex * ex + ey * ey + ez * ez;
-      mx = sy * ez - sz * ey;
-      my = sz * ex - sx * ez;
-      mz = sx * ey - sy * ex;
-      if (d.dbg_rev) d.dbg_rev[(size_t)i * d.mc_max + lm[pos]] = my_idx;
+      const float4 sp = d.pre_pts[(size_t)pi.prep_tg_begin * 64 + my_idx];  // Morton-sorted copy
+      const float sx = sp.x, sy = sp.y, sz = sp.z;
+      const float dx = sx - lx[p], dy = sy - ly[p], dz = sz - lz[p];
+      e2 += dx * dx + dy * dy + dz * dz;
+      ex += dx; ey += dy; ez += dz;
+      mx += sy * dz - sz * dy;
+      my += sz * dx - sx * dz;
+      mz += sx * dy - sy * dx;
+      if (d.dbg_rev)
+        d.dbg_rev[(size_t)i * d.mc_max + d.col_perm[oi.c_begin + lm[p]]] =
+            d.pre_perm[(size_t)pi.prep_tg_begin * 64 + my_idx];
     }
   }
   e2 = wave_sum(e2);

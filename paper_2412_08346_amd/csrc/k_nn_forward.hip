@@ -2,9 +2,12 @@
 // partial sums (Algorithm 1: transform the source cloud, pair it with the
 // object cloud by eq. (1), accumulate the terms of eqs. (14), (16), (17)).
 //
-// One wavefront = one particle x 64 contact points, matched against the whole
-// object cloud of its group with the MFMA core.  Partial sums per wavefront:
-// [sum |e|^2, sum e (3), sum (R s) x e (3), points], e = s' - r_nn.
+// One wavefront = one particle x 16*Q contact points (consecutive in the
+// Morton-sorted contact cloud, so spatially close), matched against the object
+// cloud of its group with the MFMA core.  By default object chunks that
+// provably cannot hold any of the wave's nearest neighbours are skipped.
+// Partial sums per wavefront: [sum |e|^2, sum e (3), sum (R s) x e (3),
+// points], e = s' - r_nn.
 #include "nn_core.h"
 
 namespace asicp {
@@ -16,7 +19,13 @@ __device__ __forceinline__ int xcd_logical(int b, int nwg) {
   return (b & 7) * per + (b >> 3);
 }
 
-__global__ __launch_bounds__(256) void k_nn_forward(Dev d) {
+#if ASICP_NN_WPE > 0
+#define NN_OCCUPANCY __attribute__((amdgpu_waves_per_eu(ASICP_NN_WPE)))
+#else
+#define NN_OCCUPANCY
+#endif
+
+__global__ __launch_bounds__(256) NN_OCCUPANCY void k_nn_forward(Dev d) {
   const int nwg = (d.total_waves + 3) >> 2;
   const int logical = xcd_logical(blockIdx.x, nwg);
   if (logical >= nwg) return;
@@ -40,50 +49,64 @@ __global__ __launch_bounds__(256) void k_nn_forward(Dev d) {
   load_pose(d.theta, d.Ktot, i, t, qv);
   quat_to_rot(qv[0], qv[1], qv[2], qv[3], R);
 
-  const int comp = lane >> 4;
-  float bq[4];
+  constexpr int Q = kNnQ, QPW = kQueriesPerWave;
+  const float4* spts = d.pre_pts + (size_t)pi.prep_tg_begin * 64;  // Morton-sorted contact cloud
+  const int comp = lane >> 4, j = lane & 15;
+  float bq[Q], snorm[Q];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int n = chunk * 64 + q * 16 + (lane & 15);
-    float sx = 0.f, sy = 0.f, sz = 0.f;
-    if (n < pi.n) {
-      sx = d.sx[pi.s_begin + n];
-      sy = d.sy[pi.s_begin + n];
-      sz = d.sz[pi.s_begin + n];
-    }
-    const float px = R[0] * sx + R[1] * sy + R[2] * sz + t[0];
-    const float py = R[3] * sx + R[4] * sy + R[5] * sz + t[1];
-    const float pz = R[6] * sx + R[7] * sy + R[8] * sz + t[2];
+  for (int q = 0; q < Q; ++q) {
+    int n = chunk * QPW + q * 16 + j;
+    if (n >= pi.n) n = chunk * QPW;  // padding queries repeat the wave's first point
+    const float4 s = spts[n];
+    const float px = R[0] * s.x + R[1] * s.y + R[2] * s.z + t[0];
+    const float py = R[3] * s.x + R[4] * s.y + R[5] * s.z + t[1];
+    const float pz = R[6] * s.x + R[7] * s.y + R[8] * s.z + t[2];
     bq[q] = comp == 0 ? px : comp == 1 ? py : comp == 2 ? pz : 1.0f;
+    snorm[q] = px * px + py * py + pz * pz;
   }
-  int idx[4];
-  nn_scan<4>(d.obj_prep + (size_t)oi.prep_tg_begin * 64, oi.ntg, bq, idx, d.flags + 1);
+  int idx[Q];
+  const float4* prep = d.obj_prep + (size_t)oi.prep_tg_begin * 64;
+  long long pairs;
+  if (d.prune) {
+    int vq[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) vq[q] = max(0, min(16, pi.n - (chunk * QPW + q * 16)));
+    pairs = nn_scan_pruned<Q>(prep, oi.ntg, oi.m, d.obj_box + (size_t)oi.prep_tg_begin / kChunkTG * 8,
+                              bq, snorm, vq, idx, d.flags + 1);
+  } else {
+    nn_scan<Q>(prep, oi.ntg, bq, idx, d.flags + 1);
+    pairs = (long long)oi.m * min(QPW, pi.n - chunk * QPW);
+  }
 
-  // lane l now owns contact point chunk*64 + l (block l/16, query l%16)
+  // lane l < 16*Q now owns sorted contact point chunk*16Q + l (block l/16, query l%16)
   int my = idx[0];
-  if (comp == 1) my = idx[1];
-  if (comp == 2) my = idx[2];
-  if (comp == 3) my = idx[3];
-  const int n = chunk * 64 + lane;
+#pragma unroll
+  for (int q = 1; q < Q; ++q)
+    if (comp == q) my = idx[q];
+  const int n = chunk * QPW + lane;
   float e2 = 0.f, ex = 0.f, ey = 0.f, ez = 0.f, mx = 0.f, my_ = 0.f, mz = 0.f, cnt = 0.f;
-  if (n < pi.n) {
+  if (lane < QPW && n < pi.n) {
     if (my >= oi.m) {
       atomicOr(d.flags + 1, 2);
       my = oi.m - 1;
     }
-    const float sx = d.sx[pi.s_begin + n], sy = d.sy[pi.s_begin + n], sz = d.sz[pi.s_begin + n];
-    const float ux = R[0] * sx + R[1] * sy + R[2] * sz;
-    const float uy = R[3] * sx + R[4] * sy + R[5] * sz;
-    const float uz = R[6] * sx + R[7] * sy + R[8] * sz;
-    ex = ux + t[0] - d.rx[oi.r_begin + my];
-    ey = uy + t[1] - d.ry[oi.r_begin + my];
-    ez = uz + t[2] - d.rz[oi.r_begin + my];
+    const float4 s = spts[n];
+    const float ux = R[0] * s.x + R[1] * s.y + R[2] * s.z;
+    const float uy = R[3] * s.x + R[4] * s.y + R[5] * s.z;
+    const float uz = R[6] * s.x + R[7] * s.y + R[8] * s.z;
+    const float4 r = d.obj_pts[(size_t)oi.prep_tg_begin * 64 + my];
+    ex = ux + t[0] - r.x;
+    ey = uy + t[1] - r.y;
+    ez = uz + t[2] - r.z;
     e2 = ex * ex + ey * ey + ez * ez;
     mx = uy * ez - uz * ey;
     my_ = uz * ex - ux * ez;
     mz = ux * ey - uy * ex;
     cnt = 1.f;
-    if (d.dbg_nn) d.dbg_nn[(size_t)i * d.n_max + n] = my;
+    if (d.dbg_nn) {
+      const int n_orig = d.pre_perm[(size_t)pi.prep_tg_begin * 64 + n];
+      d.dbg_nn[(size_t)i * d.n_max + n_orig] = d.obj_perm[(size_t)oi.prep_tg_begin * 64 + my];
+    }
   }
   e2 = wave_sum(e2);
   ex = wave_sum(ex);
@@ -97,6 +120,7 @@ __global__ __launch_bounds__(256) void k_nn_forward(Dev d) {
     float* out = d.nn_part + ((size_t)i * d.max_waves_pp + chunk) * kPartStride;
     out[0] = e2; out[1] = ex; out[2] = ey; out[3] = ez;
     out[4] = mx; out[5] = my_; out[6] = mz; out[7] = cnt;
+    atomicAdd(d.counters, (unsigned long long)pairs);
   }
 }
 

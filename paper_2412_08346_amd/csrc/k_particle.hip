@@ -39,22 +39,36 @@ __device__ __forceinline__ bool finite3(float a, float b, float c) {
   return isfinite(a) && isfinite(b) && isfinite(c);
 }
 
+// One wavefront per particle: lanes read the partial records in parallel and
+// add them with a fixed butterfly; lane 0 finishes the particle.
 __global__ __launch_bounds__(256) void k_finalize(Dev d, int k, int final_eval) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (i >= d.Ktot) return;
+  const int lane = threadIdx.x & 63;
   const int g = i / d.K;
   const GroupInfo gi = d.groups[g];
   const PreInfo& pi = d.pres[gi.pre];
   const ObjInfo& oi = d.objs[gi.obj];
-  float t[3], q[4], R[9];
-  load_pose(d.theta, d.Ktot, i, t, q);
-  quat_to_rot(q[0], q[1], q[2], q[3], R);
 
   float s[7] = {0, 0, 0, 0, 0, 0, 0};
   const float* np = d.nn_part + (size_t)i * d.max_waves_pp * kPartStride;
-  for (int c = 0; c < pi.waves; ++c)
+  for (int c = lane; c < pi.waves; c += 64)
 #pragma unroll
     for (int a = 0; a < 7; ++a) s[a] += np[c * kPartStride + a];
+  float cs[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const float* cp = d.col_part + (size_t)i * d.max_gate_chunks * kPartStride;
+  for (int c = lane; c < oi.gate_chunks; c += 64)
+#pragma unroll
+    for (int a = 0; a < 8; ++a) cs[a] += cp[c * kPartStride + a];
+#pragma unroll
+  for (int a = 0; a < 7; ++a) s[a] = wave_sum(s[a]);
+#pragma unroll
+  for (int a = 0; a < 8; ++a) cs[a] = wave_sum(cs[a]);
+  if (lane != 0) return;
+
+  float t[3], q[4], R[9];
+  load_pose(d.theta, d.Ktot, i, t, q);
+  quat_to_rot(q[0], q[1], q[2], q[3], R);
   const float* pc = d.pre_const + gi.pre * 8;
   const float* com = d.obj_com + gi.obj * 4;
   const float invN = 1.0f / (float)pi.n;
@@ -72,11 +86,6 @@ __global__ __launch_bounds__(256) void k_finalize(Dev d, int k, int final_eval) 
   gct[4] = s[5] * invN + lam * (uTz * eTx - uTx * eTz);
   gct[5] = s[6] * invN + lam * (uTx * eTy - uTy * eTx);
 
-  float cs[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  const float* cp = d.col_part + (size_t)i * d.max_gate_chunks * kPartStride;
-  for (int c = 0; c < oi.gate_chunks; ++c)
-#pragma unroll
-    for (int a = 0; a < 8; ++a) cs[a] += cp[c * kPartStride + a];
   const int ncol = (int)cs[7];
   float gcol[6] = {0, 0, 0, 0, 0, 0}, ccost = 0.f;
   if (ncol > 0) {
@@ -180,7 +189,7 @@ __global__ __launch_bounds__(256) void k_select(Dev d) {
 }
 
 void launch_finalize(const Dev& d, int k, int final_eval, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize, dim3((d.Ktot + 255) / 256), dim3(256), 0, s, d, k, final_eval);
+  hipLaunchKernelGGL(k_finalize, dim3((d.Ktot + 3) / 4), dim3(256), 0, s, d, k, final_eval);
 }
 
 void launch_select(const Dev& d, hipStream_t s) {

@@ -1,9 +1,10 @@
 // k_setup.hip -- per-object and per-preshape set-up (Algorithm 1
 // preprocessing): centre of mass of each object cloud (its centroid), tool
 // centre point of each contact cloud (its centroid, Sec. IV-B), the
-// Gauss-Newton diagonal preconditioner of eq. (3), MFMA-ready augmented copies
-// of the clouds, and the initial particle state.  Sums run in FP64 over a
-// fixed order (strided per thread, then a fixed tree).
+// Gauss-Newton diagonal preconditioner of eq. (3), spatially sorted MFMA-ready
+// copies of the clouds with per-chunk bounding boxes, the box of negative SDF
+// nodes, and the initial particle state.  Sums run in FP64 over a fixed order
+// (strided per thread, then a fixed tree).
 #include "nn_core.h"
 
 namespace asicp {
@@ -24,6 +25,7 @@ __device__ void block_sum4(double v[4], double (*sh)[4]) {
 // one workgroup per object
 __global__ __launch_bounds__(256) void k_setup_obj(Dev d) {
   __shared__ double sh[256][4];
+  __shared__ float sb[256][6];
   const int o = blockIdx.x, tid = threadIdx.x;
   const ObjInfo oi = d.objs[o];
   double v[4] = {0, 0, 0, 0};
@@ -37,13 +39,28 @@ __global__ __launch_bounds__(256) void k_setup_obj(Dev d) {
     for (int a = 0; a < 3; ++a) d.obj_com[4 * o + a] = (float)(v[a] / (double)oi.m);
     d.obj_com[4 * o + 3] = 0.f;
   }
-  float* prep = reinterpret_cast<float*>(d.obj_prep + (size_t)oi.prep_tg_begin * 64);
-  for (int m = tid; m < oi.ntg * 64; m += 256) {
-    if (m < oi.m) {
-      const float x = d.rx[oi.r_begin + m], y = d.ry[oi.r_begin + m], z = d.rz[oi.r_begin + m];
-      prep_store(prep, m, -2.f * x, -2.f * y, -2.f * z, __builtin_fmaf(z, z, __builtin_fmaf(y, y, x * x)));
-    } else {
-      prep_store(prep, m, 0.f, 0.f, 0.f, kDummyNorm);
+  // bounding box of the collision cloud
+  float b[6] = {__builtin_inff(), __builtin_inff(), __builtin_inff(),
+                -__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
+  for (int m = tid; m < oi.mc; m += 256) {
+    const float x = d.cx[oi.c_begin + m], y = d.cy[oi.c_begin + m], z = d.cz[oi.c_begin + m];
+    b[0] = fminf(b[0], x); b[1] = fminf(b[1], y); b[2] = fminf(b[2], z);
+    b[3] = fmaxf(b[3], x); b[4] = fmaxf(b[4], y); b[5] = fmaxf(b[5], z);
+  }
+  for (int a = 0; a < 6; ++a) sb[tid][a] = b[a];
+  __syncthreads();
+  for (int off = 128; off >= 1; off >>= 1) {
+    if (tid < off) {
+      for (int a = 0; a < 3; ++a) sb[tid][a] = fminf(sb[tid][a], sb[tid + off][a]);
+      for (int a = 3; a < 6; ++a) sb[tid][a] = fmaxf(sb[tid][a], sb[tid + off][a]);
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    ObjInfo* w = const_cast<ObjInfo*>(d.objs) + o;
+    for (int a = 0; a < 3; ++a) {
+      w->cmin[a] = sb[0][a];
+      w->cmax[a] = sb[0][3 + a];
     }
   }
 }
@@ -73,13 +90,180 @@ __global__ __launch_bounds__(256) void k_setup_pre(Dev d) {
     pc[0] = (float)tx; pc[1] = (float)ty; pc[2] = (float)tz; pc[3] = (float)rho2;
     pc[4] = (float)at; pc[5] = (float)aw; pc[6] = 0.f; pc[7] = 0.f;
   }
-  float* prep = reinterpret_cast<float*>(d.pre_prep + (size_t)pi.prep_tg_begin * 64);
-  for (int n = tid; n < pi.ntg * 64; n += 256) {
-    if (n < pi.n) {
-      const float x = d.sx[pi.s_begin + n], y = d.sy[pi.s_begin + n], z = d.sz[pi.s_begin + n];
-      prep_store(prep, n, -2.f * x, -2.f * y, -2.f * z, __builtin_fmaf(z, z, __builtin_fmaf(y, y, x * x)));
+}
+
+// 10-bit Morton interleave of one axis
+__device__ __forceinline__ unsigned int spread10(unsigned int v) {
+  v &= 1023u;
+  v = (v | (v << 16)) & 0x030000FFu;
+  v = (v | (v << 8)) & 0x0300F00Fu;
+  v = (v | (v << 4)) & 0x030C30C3u;
+  v = (v | (v << 2)) & 0x09249249u;
+  return v;
+}
+
+// One workgroup (1024 threads) per cloud: blocks [0, n_obj) sort object
+// clouds, blocks [n_obj, n_obj + n_pre) contact clouds, the last n_obj blocks
+// collision clouds (only a sorted copy and the original index for those).  Points are ordered by
+// the Morton code of their position in the cloud's bounding box (ties by
+// original index: the keys are unique, so the order is deterministic), then
+// written as MFMA-ready float4, plain float4, the original index, and one
+// bounding box per 128-point chunk.  Padding points carry |r|^2 = 1e30.
+__global__ __launch_bounds__(1024) void k_sort_cloud(Dev d) {
+  __shared__ float sb[1024][6];
+  __shared__ float s_box[6];
+  const int tid = threadIdx.x;
+  // kind 0: object cloud, 1: contact cloud, 2: collision cloud (no MFMA copy)
+  const int kind = blockIdx.x < d.n_obj ? 0 : (blockIdx.x < d.n_obj + d.n_pre ? 1 : 2);
+  const float *sx, *sy, *sz;
+  int n, tg0 = 0, ntg = 0, key_off;
+  float4 *prep = nullptr, *pts;
+  int32_t* perm;
+  float* box = nullptr;
+  size_t base;  // first output index
+  if (kind == 0) {
+    const ObjInfo& oi = d.objs[blockIdx.x];
+    sx = d.rx + oi.r_begin; sy = d.ry + oi.r_begin; sz = d.rz + oi.r_begin;
+    n = oi.m; tg0 = oi.prep_tg_begin; ntg = oi.ntg; key_off = oi.key_off;
+    prep = d.obj_prep; pts = d.obj_pts; perm = d.obj_perm; box = d.obj_box;
+    base = (size_t)tg0 * 64;
+  } else if (kind == 1) {
+    const PreInfo& pi = d.pres[blockIdx.x - d.n_obj];
+    sx = d.sx + pi.s_begin; sy = d.sy + pi.s_begin; sz = d.sz + pi.s_begin;
+    n = pi.n; tg0 = pi.prep_tg_begin; ntg = pi.ntg; key_off = pi.key_off;
+    prep = d.pre_prep; pts = d.pre_pts; perm = d.pre_perm; box = d.pre_box;
+    base = (size_t)tg0 * 64;
+  } else {
+    const ObjInfo& oi = d.objs[blockIdx.x - d.n_obj - d.n_pre];
+    sx = d.cx + oi.c_begin; sy = d.cy + oi.c_begin; sz = d.cz + oi.c_begin;
+    n = oi.mc; key_off = oi.c_key_off;
+    pts = d.col_pts; perm = d.col_perm;
+    base = (size_t)oi.c_begin;
+  }
+  if (n == 0) return;  // uniform: an empty collision cloud
+  // bounding box
+  float b[6] = {__builtin_inff(), __builtin_inff(), __builtin_inff(),
+                -__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
+  for (int k = tid; k < n; k += 1024) {
+    const float x = sx[k], y = sy[k], z = sz[k];
+    b[0] = fminf(b[0], x); b[1] = fminf(b[1], y); b[2] = fminf(b[2], z);
+    b[3] = fmaxf(b[3], x); b[4] = fmaxf(b[4], y); b[5] = fmaxf(b[5], z);
+  }
+  for (int a = 0; a < 6; ++a) sb[tid][a] = b[a];
+  __syncthreads();
+  for (int off = 512; off >= 1; off >>= 1) {
+    if (tid < off) {
+      for (int a = 0; a < 3; ++a) sb[tid][a] = fminf(sb[tid][a], sb[tid + off][a]);
+      for (int a = 3; a < 6; ++a) sb[tid][a] = fmaxf(sb[tid][a], sb[tid + off][a]);
+    }
+    __syncthreads();
+  }
+  if (tid < 6) s_box[tid] = sb[0][tid];
+  __syncthreads();
+  float scale[3];
+  for (int a = 0; a < 3; ++a) {
+    const float ext = s_box[3 + a] - s_box[a];
+    scale[a] = ext > 0.f ? 1023.0f / ext : 0.f;
+  }
+  // keys, padded to a power of two with the largest key
+  int npow2 = 2;
+  while (npow2 < n) npow2 <<= 1;
+  unsigned long long* keys = d.sort_keys + key_off;
+  for (int k = tid; k < npow2; k += 1024) {
+    unsigned long long key = ~0ull;
+    if (k < n) {
+      const unsigned int qx = (unsigned int)fminf(fmaxf((sx[k] - s_box[0]) * scale[0], 0.f), 1023.f);
+      const unsigned int qy = (unsigned int)fminf(fmaxf((sy[k] - s_box[1]) * scale[1], 0.f), 1023.f);
+      const unsigned int qz = (unsigned int)fminf(fmaxf((sz[k] - s_box[2]) * scale[2], 0.f), 1023.f);
+      const unsigned int code = spread10(qx) | (spread10(qy) << 1) | (spread10(qz) << 2);
+      key = ((unsigned long long)code << 32) | (unsigned int)k;
+    }
+    keys[k] = key;
+  }
+  __syncthreads();
+  // bitonic sort, ascending
+  for (int size = 2; size <= npow2; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int t = tid; t < (npow2 >> 1); t += 1024) {
+        const int i = 2 * stride * (t / stride) + (t % stride);
+        const int j = i + stride;
+        const bool asc = (i & size) == 0;
+        const unsigned long long a = keys[i], c = keys[j];
+        if ((a > c) == asc) {
+          keys[i] = c;
+          keys[j] = a;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // emit the sorted copies
+  if (kind == 2) {
+    for (int k = tid; k < n; k += 1024) {
+      const int orig = (int)(keys[k] & 0xffffffffull);
+      pts[base + k] = make_float4(sx[orig], sy[orig], sz[orig], 0.f);
+      perm[base + k] = orig;
+    }
+    return;
+  }
+  float* pf = reinterpret_cast<float*>(prep + (size_t)tg0 * 64);
+  for (int k = tid; k < ntg * 64; k += 1024) {
+    const size_t g = base + k;
+    if (k < n) {
+      const int orig = (int)(keys[k] & 0xffffffffull);
+      const float x = sx[orig], y = sy[orig], z = sz[orig];
+      prep_store(pf, k, -2.f * x, -2.f * y, -2.f * z, __builtin_fmaf(z, z, __builtin_fmaf(y, y, x * x)));
+      pts[g] = make_float4(x, y, z, 0.f);
+      perm[g] = orig;
     } else {
-      prep_store(prep, n, 0.f, 0.f, 0.f, kDummyNorm);
+      prep_store(pf, k, 0.f, 0.f, 0.f, kDummyNorm);
+      pts[g] = make_float4(0.f, 0.f, 0.f, 0.f);
+      perm[g] = -1;
+    }
+  }
+  __syncthreads();
+  // chunk boxes (128 points per chunk; an all-padding chunk gets an empty box)
+  const int nch = ntg / kChunkTG;
+  for (int c = tid; c < nch; c += 1024) {
+    float bb[6] = {__builtin_inff(), __builtin_inff(), __builtin_inff(),
+                   -__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
+    const int k1 = min(n, (c + 1) * 128);
+    for (int k = c * 128; k < k1; ++k) {
+      const float4 p = pts[base + k];
+      bb[0] = fminf(bb[0], p.x); bb[1] = fminf(bb[1], p.y); bb[2] = fminf(bb[2], p.z);
+      bb[3] = fmaxf(bb[3], p.x); bb[4] = fmaxf(bb[4], p.y); bb[5] = fmaxf(bb[5], p.z);
+    }
+    float* o = box + ((size_t)tg0 / kChunkTG + c) * 8;
+    o[0] = bb[0]; o[1] = bb[1]; o[2] = bb[2]; o[3] = 0.f;
+    o[4] = bb[3]; o[5] = bb[4]; o[6] = bb[5]; o[7] = 0.f;
+  }
+}
+
+// Box of negative SDF nodes per preshape (grid: n_pre x 64 workgroups).
+__global__ __launch_bounds__(256) void k_sdf_bounds(Dev d) {
+  const int p = blockIdx.y;
+  PreInfo* pi = const_cast<PreInfo*>(d.pres) + p;
+  const int nx = pi->nx, ny = pi->ny, nz = pi->nz;
+  const float* v = pi->sdf;
+  const long long total = (long long)nx * ny * nz;
+  int lo[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, hi[3] = {-1, -1, -1};
+  for (long long idx = (long long)blockIdx.x * 256 + threadIdx.x; idx < total; idx += (long long)gridDim.x * 256) {
+    if (v[idx] < 0.f) {
+      const int x = (int)(idx % nx), y = (int)((idx / nx) % ny), z = (int)(idx / ((long long)nx * ny));
+      lo[0] = min(lo[0], x); lo[1] = min(lo[1], y); lo[2] = min(lo[2], z);
+      hi[0] = max(hi[0], x); hi[1] = max(hi[1], y); hi[2] = max(hi[2], z);
+    }
+  }
+  for (int a = 0; a < 3; ++a) {
+    for (int off = 32; off >= 1; off >>= 1) {
+      lo[a] = min(lo[a], __shfl_xor(lo[a], off, 64));
+      hi[a] = max(hi[a], __shfl_xor(hi[a], off, 64));
+    }
+  }
+  if ((threadIdx.x & 63) == 0) {
+    for (int a = 0; a < 3; ++a) {
+      if (lo[a] != 0x7fffffff) atomicMin(&pi->neg_lo[a], lo[a]);
+      if (hi[a] != -1) atomicMax(&pi->neg_hi[a], hi[a]);
     }
   }
 }
@@ -87,8 +271,13 @@ __global__ __launch_bounds__(256) void k_setup_pre(Dev d) {
 __global__ __launch_bounds__(256) void k_setup_state(Dev d, const float* theta0, const float* prev0,
                                                      const int32_t* conv0) {
   const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i < d.G) d.h[i] = 0.f;
+  if (i < d.G) {
+    d.h[i] = 0.f;
+    for (int a = 0; a < 4; ++a) d.bw_state[4 * i + a] = 0u;
+  }
+  for (int w = i; w < d.G * 256; w += gridDim.x * 256) d.bw_hist[w] = 0u;
   if (i < 4) d.flags[i] = 0;
+  if (i < 2) d.counters[i] = 0ull;
   if (i >= d.Ktot) return;
   const int K = d.Ktot;
   for (int a = 0; a < 7; ++a) d.theta[a * K + i] = theta0[a * K + i];
@@ -132,6 +321,8 @@ void launch_setup(const Dev& d, const float* theta0, const float* prev_cost0,
                   const int32_t* converged0, hipStream_t s) {
   hipLaunchKernelGGL(k_setup_obj, dim3(d.n_obj), dim3(256), 0, s, d);
   hipLaunchKernelGGL(k_setup_pre, dim3(d.n_pre), dim3(256), 0, s, d);
+  hipLaunchKernelGGL(k_sdf_bounds, dim3(64, d.n_pre), dim3(256), 0, s, d);
+  hipLaunchKernelGGL(k_sort_cloud, dim3(2 * d.n_obj + d.n_pre), dim3(1024), 0, s, d);
   const int n = d.Ktot > d.G ? d.Ktot : d.G;
   hipLaunchKernelGGL(k_setup_state, dim3((n + 255) / 256), dim3(256), 0, s, d,
                      theta0, prev_cost0, converged0);

@@ -1,36 +1,127 @@
-// k_svgd.hip -- annealed Stein ICP update of one group (eqs. (6)-(11)).
-//
-// One workgroup per (object, preshape) group of K <= 1024 particles, all in
-// LDS.  (1) bandwidth h of the RBF kernel (eq. 9): lower median of the
-// squared translation distances over pairs, by a 4-pass radix select on the
-// FP32 bit patterns (monotone for non-negative floats), divided by ln K and
-// floored; (2) Stein direction in the 6-D tangent: kernel-weighted mean of
-// the preconditioned driving terms -gamma A g_j plus tau times the kernel
-// gradient with respect to particle j (translation part scaled by h/2);
-// (3) pose update t += eta phi_t, q <- canon(normalize(Exp(eta phi_w) (x) q)).
-// All phi are computed from the poses of the same iteration before any pose
-// is written back.
+// k_svgd.hip -- annealed Stein ICP update of each (object, preshape) group
+// (eqs. (6)-(11)), in six launches:
+//   k_bw_pass     x4: h of the RBF kernel (eq. 9), the lower median of
+//                 |t_i - t_j|^2 over pairs i < j divided by ln K and floored,
+//                 found exactly by a radix select over the FP32 bit patterns
+//                 (monotone for non-negative floats), 8 bits per pass;
+//   k_svgd_phi    Stein direction in the 6-D tangent: kernel-weighted mean of
+//                 the preconditioned driving terms -gamma A g_j plus tau times
+//                 the kernel gradient with respect to particle j (translation
+//                 part scaled by h/2); 64 particles per workgroup, 4 lanes per
+//                 particle;
+//   k_svgd_apply  t += eta phi_t, q <- canon(normalize(Exp(eta phi_w) (x) q)).
+// Every phi is computed from the poses of the same iteration: poses are only
+// written by the last launch.
 #include "asicp_internal.h"
 
 namespace asicp {
 
 constexpr int kMaxK = 1024;
 
-__device__ __forceinline__ float d2_pair(const float* st, int i, int j) {
+__device__ __forceinline__ float d2_of(const float* st, int i, int j) {
   const float dx = st[3 * i + 0] - st[3 * j + 0];
   const float dy = st[3 * i + 1] - st[3 * j + 1];
   const float dz = st[3 * i + 2] - st[3 * j + 2];
   return __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
 }
 
-__global__ __launch_bounds__(256) void k_svgd(Dev d, float gamma, float tau, float inv_log_k) {
+// One radix pass over the K x K ordered pairs (i != j: every unordered pair
+// twice) of group blockIdx.y, sliced over gridDim.x workgroups.  Each
+// workgroup builds a digit histogram of the pairs matching the current prefix
+// in LDS (one atomic per distinct digit of a wave), adds it into the group's
+// global histogram, and the last workgroup to finish picks the digit holding
+// the target rank, clears the histogram and, after the last pass, writes h.
+__global__ __launch_bounds__(256) void k_bw_pass(Dev d, int pass, float inv_log_k) {
+  __shared__ float st[kMaxK * 3];
+  __shared__ unsigned int hist[256];
+  __shared__ int s_last;
+  const int g = blockIdx.y, tid = threadIdx.x, lane = tid & 63, K = d.K, Kt = d.Ktot;
+  unsigned int* ghist = d.bw_hist + (size_t)g * 256;
+  unsigned int* state = d.bw_state + (size_t)g * 4;  // prefix, mask, rank, done
+  for (int j = tid; j < K; j += 256)
+    for (int a = 0; a < 3; ++a) st[3 * j + a] = d.theta[a * Kt + g * K + j];
+  hist[tid] = 0u;
+  const unsigned int P = (unsigned int)K * (unsigned int)(K - 1) / 2u;
+  const unsigned int prefix = pass == 0 ? 0u : state[0];
+  const unsigned int mask = pass == 0 ? 0u : state[1];
+  __syncthreads();
+  const int shift = 24 - 8 * pass;
+  const int slots = K * K;
+  const int per = (slots + gridDim.x - 1) / gridDim.x;
+  const int s0 = blockIdx.x * per, s1 = min(slots, s0 + per);
+  for (int sb = s0; sb < s1; sb += 256) {
+    const int sidx = sb + tid;
+    bool act = false;
+    unsigned int dig = 0u;
+    if (sidx < s1) {
+      const int i = sidx / K, j = sidx - (sidx / K) * K;
+      if (i != j) {
+        const float dx = st[3 * i] - st[3 * j], dy = st[3 * i + 1] - st[3 * j + 1], dz = st[3 * i + 2] - st[3 * j + 2];
+        const unsigned int bits = __float_as_uint(__builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx)));
+        act = (bits & mask) == prefix;
+        dig = (bits >> shift) & 255u;
+      }
+    }
+    unsigned long long pending = __ballot(act);
+    while (pending) {
+      const int leader = __ffsll((long long)pending) - 1;
+      const unsigned int b = __shfl(dig, leader, 64);
+      const unsigned long long same = __ballot(act && dig == b);
+      if (lane == leader) atomicAdd(&hist[b], (unsigned int)__popcll(same));
+      if (act && dig == b) act = false;
+      pending &= ~same;
+    }
+  }
+  __syncthreads();
+  if (hist[tid]) atomicAdd(&ghist[tid], hist[tid]);
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) s_last = (atomicAdd(&state[3], 1u) == gridDim.x - 1) ? 1 : 0;
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  if (tid < 64) {  // wave 0 locates the digit holding the rank
+    unsigned int c[4], run = 0u;
+    for (int r = 0; r < 4; ++r) {
+      c[r] = atomicAdd(&ghist[4 * tid + r], 0u);
+      run += c[r];
+    }
+    unsigned int incl = run;
+    for (int off = 1; off < 64; off <<= 1) {
+      const unsigned int o = __shfl_up(incl, off, 64);
+      if (tid >= off) incl += o;
+    }
+    const unsigned int excl = incl - run;
+    const unsigned int rank = pass == 0 ? 2u * ((P - 1u) / 2u) : state[2];
+    if (rank >= excl && rank < incl) {
+      unsigned int cum = excl;
+      for (int r = 0; r < 4; ++r) {
+        if (rank < cum + c[r]) {
+          const unsigned int np = prefix | ((unsigned int)(4 * tid + r) << shift);
+          state[0] = np;
+          state[1] = mask | (255u << shift);
+          state[2] = rank - cum;
+          if (pass == 3) d.h[g] = fmaxf(__uint_as_float(np) * inv_log_k, d.h_min);
+          break;
+        }
+        cum += c[r];
+      }
+    }
+    for (int r = 0; r < 4; ++r) ghist[4 * tid + r] = 0u;
+    if (tid == 0) state[3] = 0u;
+  }
+}
+
+// bandwidth without a median: fixed h, or h = 1 for a single particle
+__global__ void k_bw_const(Dev d) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < d.G) d.h[g] = d.bw_mode == ASICP_BW_FIXED ? d.h_fixed : 1.0f;
+}
+
+__global__ __launch_bounds__(256) void k_svgd_phi(Dev d, float gamma, float tau) {
   __shared__ float st[kMaxK * 3];
   __shared__ float sq[kMaxK * 4];
   __shared__ float sg[kMaxK * 6];
-  __shared__ unsigned int hist[256];
-  __shared__ unsigned int s_prefix, s_mask, s_rank;
-  __shared__ float s_h;
-
   const int g = blockIdx.x, tid = threadIdx.x, K = d.K, Kt = d.Ktot;
   const int base = g * K;
   for (int j = tid; j < K; j += 256) {
@@ -39,69 +130,19 @@ __global__ __launch_bounds__(256) void k_svgd(Dev d, float gamma, float tau, flo
     for (int a = 0; a < 4; ++a) sq[4 * j + a] = d.theta[(3 + a) * Kt + i];
     for (int a = 0; a < 6; ++a) sg[6 * j + a] = d.grad[a * Kt + i];
   }
-  if (tid == 0) {
-    s_prefix = 0u;
-    s_mask = 0u;
-    const unsigned int P = (unsigned int)K * (unsigned int)(K - 1) / 2u;
-    s_rank = (K >= 2) ? 2u * ((P - 1u) / 2u) : 0u;  // rank in the doubled (i != j) multiset
-  }
   __syncthreads();
-
-  float h;
-  if (d.bw_mode == ASICP_BW_FIXED) {
-    h = d.h_fixed;
-  } else if (K < 2) {
-    h = 1.0f;
-  } else {
-    for (int pass = 0; pass < 4; ++pass) {
-      const int shift = 24 - 8 * pass;
-      hist[tid] = 0u;
-      __syncthreads();
-      const unsigned int prefix = s_prefix, mask = s_mask;
-      for (int i = tid; i < K; i += 256)
-        for (int j = 0; j < K; ++j) {
-          if (j == i) continue;
-          const unsigned int bits = __float_as_uint(d2_pair(st, i, j));
-          if ((bits & mask) == prefix) atomicAdd(&hist[(bits >> shift) & 255u], 1u);
-        }
-      __syncthreads();
-      if (tid == 0) {
-        unsigned int cum = 0u, r = s_rank;
-        for (int b = 0; b < 256; ++b) {
-          if (cum + hist[b] > r) {
-            s_prefix = prefix | ((unsigned int)b << shift);
-            s_mask = mask | (255u << shift);
-            s_rank = r - cum;
-            break;
-          }
-          cum += hist[b];
-        }
-      }
-      __syncthreads();
-    }
-    const float med = __uint_as_float(s_prefix);
-    h = fmaxf(med * inv_log_k, d.h_min);
-  }
-  if (tid == 0) {
-    s_h = h;
-    d.h[g] = h;
-  }
-  __syncthreads();
-  h = s_h;
+  const int ii = blockIdx.y * 64 + (tid >> 2), part = tid & 3;
+  const float h = d.h[g];
   const float inv_h = 1.0f / h;
-
   const GroupInfo gi = d.groups[g];
   const float at = d.pre_const[gi.pre * 8 + 4], aw = d.pre_const[gi.pre * 8 + 5];
   const float ga_t = gamma * at, ga_w = gamma * aw;
   const bool block = d.kernel_mode == ASICP_KERNEL_BLOCK;
-  const float invK = 1.0f / (float)K;
-  float newv[4][7];
-  int cnt = 0;
-  for (int ii = tid; ii < K; ii += 256, ++cnt) {
+  float acc[6] = {0, 0, 0, 0, 0, 0};
+  if (ii < K) {
     const float tix = st[3 * ii], tiy = st[3 * ii + 1], tiz = st[3 * ii + 2];
     const float qw = sq[4 * ii], qx = sq[4 * ii + 1], qy = sq[4 * ii + 2], qz = sq[4 * ii + 3];
-    float acc[6] = {0, 0, 0, 0, 0, 0};
-    for (int j = 0; j < K; ++j) {
+    for (int j = part; j < K; j += 4) {
       const float dx = tix - st[3 * j], dy = tiy - st[3 * j + 1], dz = tiz - st[3 * j + 2];
       const float kt = expf(-__builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx)) * inv_h);
       const float pw = sq[4 * j], px = sq[4 * j + 1], py = sq[4 * j + 2], pz = sq[4 * j + 3];
@@ -126,46 +167,59 @@ __global__ __launch_bounds__(256) void k_svgd(Dev d, float gamma, float tau, flo
       acc[4] += wdw * (-ga_w * gj[4]) + tau * wrw * 0.5f * vy;
       acc[5] += wdw * (-ga_w * gj[5]) + tau * wrw * 0.5f * vz;
     }
-    const int i = base + ii;
-    float phi[6];
-    for (int a = 0; a < 6; ++a) {
-      phi[a] = acc[a] * invK;
-      d.phi[a * Kt + i] = phi[a];
-    }
-    // t += eta phi_t ; q <- canon(normalize(Exp(eta phi_w) (x) q))
-    const float e = d.eta;
-    const float wx = e * phi[3], wy = e * phi[4], wz = e * phi[5];
-    const float th = sqrtf(wx * wx + wy * wy + wz * wz);
-    float ew = 1.f, ex = 0.f, ey = 0.f, ez = 0.f;
-    if (th > 0.f) {
-      float sh, ch;
-      sincosf(0.5f * th, &sh, &ch);
-      const float s = sh / th;
-      ew = ch; ex = s * wx; ey = s * wy; ez = s * wz;
-    }
-    const float nw = ew * qw - ex * qx - ey * qy - ez * qz;
-    const float nx = ew * qx + qw * ex + (ey * qz - ez * qy);
-    const float ny = ew * qy + qw * ey + (ez * qx - ex * qz);
-    const float nz = ew * qz + qw * ez + (ex * qy - ey * qx);
-    const float nrm = sqrtf(nw * nw + nx * nx + ny * ny + nz * nz);
-    const float inv = ((nw < 0.f) ? -1.f : 1.f) / nrm;
-    newv[cnt][0] = tix + e * phi[0];
-    newv[cnt][1] = tiy + e * phi[1];
-    newv[cnt][2] = tiz + e * phi[2];
-    newv[cnt][3] = nw * inv;
-    newv[cnt][4] = nx * inv;
-    newv[cnt][5] = ny * inv;
-    newv[cnt][6] = nz * inv;
   }
-  // poses are read from LDS only, so writing them back to global memory now
-  // cannot disturb the other particles' directions
-  cnt = 0;
-  for (int ii = tid; ii < K; ii += 256, ++cnt)
-    for (int a = 0; a < 7; ++a) d.theta[a * Kt + base + ii] = newv[cnt][a];
+#pragma unroll
+  for (int a = 0; a < 6; ++a) {
+    acc[a] += __shfl_xor(acc[a], 1, 64);
+    acc[a] += __shfl_xor(acc[a], 2, 64);
+  }
+  if (ii < K && part == 0) {
+    const float invK = 1.0f / (float)K;
+    for (int a = 0; a < 6; ++a) d.phi[a * Kt + base + ii] = acc[a] * invK;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_svgd_apply(Dev d) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= d.Ktot) return;
+  const int Kt = d.Ktot;
+  const float e = d.eta;
+  float t[3], q[4];
+  load_pose(d.theta, Kt, i, t, q);
+  const float wx = e * d.phi[3 * Kt + i], wy = e * d.phi[4 * Kt + i], wz = e * d.phi[5 * Kt + i];
+  const float th = sqrtf(wx * wx + wy * wy + wz * wz);
+  float ew = 1.f, ex = 0.f, ey = 0.f, ez = 0.f;
+  if (th > 0.f) {
+    float sh, ch;
+    sincosf(0.5f * th, &sh, &ch);
+    const float s = sh / th;
+    ew = ch; ex = s * wx; ey = s * wy; ez = s * wz;
+  }
+  const float nw = ew * q[0] - ex * q[1] - ey * q[2] - ez * q[3];
+  const float nx = ew * q[1] + q[0] * ex + (ey * q[3] - ez * q[2]);
+  const float ny = ew * q[2] + q[0] * ey + (ez * q[1] - ex * q[3]);
+  const float nz = ew * q[3] + q[0] * ez + (ex * q[2] - ey * q[1]);
+  const float nrm = sqrtf(nw * nw + nx * nx + ny * ny + nz * nz);
+  const float inv = ((nw < 0.f) ? -1.f : 1.f) / nrm;
+  d.theta[0 * Kt + i] = t[0] + e * d.phi[0 * Kt + i];
+  d.theta[1 * Kt + i] = t[1] + e * d.phi[1 * Kt + i];
+  d.theta[2 * Kt + i] = t[2] + e * d.phi[2 * Kt + i];
+  d.theta[3 * Kt + i] = nw * inv;
+  d.theta[4 * Kt + i] = nx * inv;
+  d.theta[5 * Kt + i] = ny * inv;
+  d.theta[6 * Kt + i] = nz * inv;
 }
 
 void launch_svgd(const Dev& d, float gamma, float tau, float inv_log_k, hipStream_t s) {
-  hipLaunchKernelGGL(k_svgd, dim3(d.G), dim3(256), 0, s, d, gamma, tau, inv_log_k);
+  if (d.K >= 2 && d.bw_mode == ASICP_BW_MEDIAN) {
+    const int slices = kBwSlices;
+    for (int pass = 0; pass < 4; ++pass)
+      hipLaunchKernelGGL(k_bw_pass, dim3(slices, d.G), dim3(256), 0, s, d, pass, inv_log_k);
+  } else {
+    hipLaunchKernelGGL(k_bw_const, dim3((d.G + 255) / 256), dim3(256), 0, s, d);
+  }
+  hipLaunchKernelGGL(k_svgd_phi, dim3(d.G, (d.K + 63) / 64), dim3(256), 0, s, d, gamma, tau);
+  hipLaunchKernelGGL(k_svgd_apply, dim3((d.Ktot + 255) / 256), dim3(256), 0, s, d);
 }
 
 }  // namespace asicp

@@ -28,101 +28,265 @@ __device__ __forceinline__ void prep_store(float* prep_f, int m, float ax, float
   base[(3 * 16 + i) * 4] = an;
 }
 
-__device__ __forceinline__ float min16(const f4v& a, const f4v& b, const f4v& c, const f4v& d) {
-  float m = fminf(fminf(a[0], a[1]), a[2]);
-  m = fminf(fminf(m, a[3]), b[0]);
-  m = fminf(fminf(m, b[1]), b[2]);
-  m = fminf(fminf(m, b[3]), c[0]);
-  m = fminf(fminf(m, c[1]), c[2]);
-  m = fminf(fminf(m, c[3]), d[0]);
-  m = fminf(fminf(m, d[1]), d[2]);
-  return fminf(m, d[3]);
-}
+// Chunk = 2 tile groups = 128 points; prepared clouds are padded to a whole
+// number of chunk pairs (256 points) so the main loop runs without a tail.
+constexpr int kChunkTG = 2;
+constexpr int kPadPoints = 256;
 
-// Q blocks of 16 queries.  Lane l supplies bq[q] = component (l / 16) of the
-// augmented query (s_x, s_y, s_z, 1) number (l % 16) of block q.  On return,
-// every lane holds in idx[q] the index (0 .. 64*ntg-1) of the nearest point
-// for query (l % 16) of block q: the lowest index among the candidates with
-// the smallest FP32 value.  A query whose minimum cannot be re-found (only
-// possible with non-finite inputs) gets index 0 and sets *miss.
+// Fold the 16 distances a lane holds for one query and one tile group into
+// its running minimum: one v_min3 per two distances (the floor for a
+// min-reduction; on gfx950 VALU work does not overlap the matrix core).
 template <int Q>
-__device__ __forceinline__ void nn_scan(const float4* __restrict__ prep, int ntg, const float* bq,
-                                        int* idx, int32_t* miss) {
-  const int lane = threadIdx.x & 63;
-  const int grp = lane >> 4;
+__device__ __forceinline__ void tile_group(const float4& a, const float* b, float* m,
+                                           const bool* need = nullptr) {
   const f4v zero = {0.0f, 0.0f, 0.0f, 0.0f};
-  float b[Q], best[Q];
-  int bchunk[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    b[q] = bq[q];
-    best[q] = __builtin_inff();
-    bchunk[q] = 0;
+    if (need && !need[q]) continue;  // wave-uniform
+    const f4v d0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b[q], zero, 0, 0, 0);
+    const f4v d1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b[q], zero, 0, 0, 0);
+    const f4v d2 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b[q], zero, 0, 0, 0);
+    const f4v d3 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b[q], zero, 0, 0, 0);
+    float r = m[q];
+    r = fminf(fminf(r, d0[0]), d0[1]);
+    r = fminf(fminf(r, d0[2]), d0[3]);
+    r = fminf(fminf(r, d1[0]), d1[1]);
+    r = fminf(fminf(r, d1[2]), d1[3]);
+    r = fminf(fminf(r, d2[0]), d2[1]);
+    r = fminf(fminf(r, d2[2]), d2[3]);
+    r = fminf(fminf(r, d3[0]), d3[1]);
+    r = fminf(fminf(r, d3[2]), d3[3]);
+    m[q] = r;
   }
-  float4 a0 = prep[lane];
-  float4 a1 = (ntg > 1) ? prep[64 + lane] : a0;
-  for (int tg = 0; tg < ntg; ++tg) {
-    float4 a2 = a1;
-    if (tg + 2 < ntg) a2 = prep[(size_t)(tg + 2) * 64 + lane];
-    f4v acc[Q][4];
+}
+
+template <int Q>
+__device__ __forceinline__ void chunk_step(const float4& a0, const float4& a1, const float* b,
+                                           float* best, int* bch, int c, const bool* need = nullptr) {
+  float m[Q];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      acc[q][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0.x, b[q], zero, 0, 0, 0);
-      acc[q][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0.y, b[q], zero, 0, 0, 0);
-      acc[q][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0.z, b[q], zero, 0, 0, 0);
-      acc[q][3] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0.w, b[q], zero, 0, 0, 0);
-    }
+  for (int q = 0; q < Q; ++q) m[q] = best[q];
+  tile_group<Q>(a0, b, m, need);
+#if ASICP_NN_SPLIT
+  __builtin_amdgcn_sched_barrier(0);  // keep one tile group's MFMA results live at a time
+#endif
+  tile_group<Q>(a1, b, m, need);
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const float m = min16(acc[q][0], acc[q][1], acc[q][2], acc[q][3]);
-      if (m < best[q]) {
-        best[q] = m;
-        bchunk[q] = tg;
-      }
-    }
-    a0 = a1;
-    a1 = a2;
+  for (int q = 0; q < Q; ++q) {
+    bch[q] = (m[q] != best[q]) ? c : bch[q];
+    best[q] = m[q];
   }
-  // Re-find the index: each lane group owns rows 4*grp .. 4*grp+3 of every
-  // tile; the earliest tile group holding its minimum is bchunk.
+}
+
+// Re-find the index of each query's minimum.  Each lane group owns rows
+// 4*grp .. 4*grp+3 of every 16-point tile and knows its minimum and the chunk
+// where its running minimum last decreased.  Among the lane groups reaching
+// the query's minimum, the one with the lowest such chunk is chosen; the four
+// lanes of the query split that chunk's 8 tiles and recompute candidate
+// values with the exact fused multiply-add chain the MFMA performs, returning
+// the lowest index in the chunk holding the minimal value.
+template <int Q>
+__device__ __forceinline__ void nn_rescan(const float4* __restrict__ prep, const float* b,
+                                          const float* best, const int* bch, int* idx, int32_t* miss) {
+  const int lane = threadIdx.x & 63;
+  const int grp = lane >> 4;
   const float* pf = reinterpret_cast<const float*>(prep);
+  const int j = lane & 15;
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const float v = best[q];
-    float vmin = fminf(v, __shfl_xor(v, 16, 64));
-    vmin = fminf(vmin, __shfl_xor(vmin, 32, 64));
-    const int j = lane & 15;
+    const float vmin = rows_min(v);
+    const int cmin = rows_min_i((v == vmin) ? bch[q] : 0x7fffffff);
+    const bool mine = (v == vmin) && (bch[q] == cmin);
+    const int gw = rows_min_i(mine ? grp : 4);
+    const int ng = rows_sum_i(mine ? 1 : 0);
     const float s0 = __shfl(b[q], j, 64);
     const float s1 = __shfl(b[q], j + 16, 64);
     const float s2 = __shfl(b[q], j + 32, 64);
     const float s3 = __shfl(b[q], j + 48, 64);
+    // rows to test: the winning group's 4 rows, or all 16 if groups tie
+    const int r0 = (ng > 1) ? 0 : 4 * gw, r1 = (ng > 1) ? 16 : 4 * gw + 4;
     int cand = 0x7fffffff;
-    if (v == vmin) {
-      const float* base = pf + (size_t)bchunk[q] * 256;
-      for (int u = 0; u < 4 && cand == 0x7fffffff; ++u) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int i = 4 * grp + r;
-          const float c0 = base[(0 * 16 + i) * 4 + u];
-          const float c1 = base[(1 * 16 + i) * 4 + u];
-          const float c2 = base[(2 * 16 + i) * 4 + u];
-          const float c3 = base[(3 * 16 + i) * 4 + u];
-          float acc = __builtin_fmaf(c0, s0, 0.0f);
-          acc = __builtin_fmaf(c1, s1, acc);
-          acc = __builtin_fmaf(c2, s2, acc);
-          acc = __builtin_fmaf(c3, s3, acc);
-          if (acc == v && cand == 0x7fffffff) cand = (bchunk[q] * 4 + u) * 16 + i;
+    if (cmin != 0x7fffffff) {
+      for (int tt = 0; tt < 2 && cand == 0x7fffffff; ++tt) {
+        const int t = grp + 4 * tt;  // tile within the chunk: tile group t/4, sub-tile t%4
+        const float* base = pf + (size_t)(cmin * kChunkTG + (t >> 2)) * 256 + (t & 3);
+        for (int i = r0; i < r1; ++i) {
+          float acc = __builtin_fmaf(base[(0 * 16 + i) * 4], s0, 0.0f);
+          acc = __builtin_fmaf(base[(1 * 16 + i) * 4], s1, acc);
+          acc = __builtin_fmaf(base[(2 * 16 + i) * 4], s2, acc);
+          acc = __builtin_fmaf(base[(3 * 16 + i) * 4], s3, acc);
+          if (acc == vmin) {
+            cand = ((cmin * kChunkTG + (t >> 2)) * 4 + (t & 3)) * 16 + i;
+            break;
+          }
         }
       }
     }
-    cand = min(cand, __shfl_xor(cand, 16, 64));
-    cand = min(cand, __shfl_xor(cand, 32, 64));
+    cand = rows_min_i(cand);
     if (cand == 0x7fffffff) {
-      if (j == 0 && grp == 0) atomicOr(miss, 1);
+      if (lane == 0) atomicOr(miss, 1);
       cand = 0;
     }
     idx[q] = cand;
   }
+}
+
+// Q blocks of 16 queries.  Lane l supplies bq[q] = component (l / 16) of the
+// augmented query (s_x, s_y, s_z, 1) number (l % 16) of block q.  `ntg` (a
+// multiple of 4) tile groups of the prepared cloud are scanned in order.  On
+// return every lane holds in idx[q] the index (0 .. 64*ntg-1) of the nearest
+// point for query (l % 16) of block q: the lowest index among the candidates
+// with the smallest FP32 value.  A query whose minimum cannot be re-found
+// (only possible with non-finite inputs) gets index 0 and sets *miss.
+template <int Q>
+__device__ __forceinline__ void nn_scan(const float4* __restrict__ prep, int ntg, const float* bq,
+                                        int* idx, int32_t* miss) {
+  const int lane = threadIdx.x & 63;
+  float b[Q], best[Q];
+  int bch[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    b[q] = bq[q];
+    best[q] = __builtin_inff();
+    bch[q] = 0;
+  }
+  const int nch = ntg / kChunkTG;  // even
+  const float4* p = prep + lane;
+  float4 x0 = p[0], x1 = p[64];
+  for (int c = 0; c < nch; c += 2) {
+    const float4 y0 = p[(size_t)(2 * c + 2) * 64];
+    const float4 y1 = p[(size_t)(2 * c + 3) * 64];
+    chunk_step<Q>(x0, x1, b, best, bch, c);
+    if (c + 2 < nch) {
+      x0 = p[(size_t)(2 * c + 4) * 64];
+      x1 = p[(size_t)(2 * c + 5) * 64];
+    }
+    chunk_step<Q>(y0, y1, b, best, bch, c + 1);
+  }
+  nn_rescan<Q>(prep, b, best, bch, idx, miss);
+}
+
+// Squared distance from the box [lo, hi] to the box [qlo, qhi] (0 if they
+// overlap): a lower bound of |s - r|^2 for any query s in the query box and
+// any point r in the chunk box.
+__device__ __forceinline__ float box_gap2(const float* bx, const float qlo[3], const float qhi[3]) {
+  float s = 0.f;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float g = fmaxf(fmaxf(bx[a] - qhi[a], qlo[a] - bx[4 + a]), 0.f);
+    s = __builtin_fmaf(g, g, s);
+  }
+  return s;
+}
+
+// As nn_scan, but a chunk is only compared with a block of 16 queries if the
+// chunk's box can hold a point nearer than the block's current worst bound:
+// exact (the same nearest distances as scanning everything).  Queries must be
+// spatially coherent for this to pay (contact clouds are Morton sorted).  The
+// chunk nearest to the wave's query box is scanned first; the other candidate
+// chunks follow in index order, the bounds refreshed every second chunk.
+// snorm[q] = |s|^2 of the lane's query in block q (turns the reduced value
+// |r|^2 - 2 r.s into a squared distance); box = the cloud's chunk boxes;
+// m = real points of the cloud; vq[q] = real queries of block q.  Returns the
+// number of (query, point) distances evaluated (wave-uniform).
+template <int Q>
+__device__ __forceinline__ long long nn_scan_pruned(const float4* __restrict__ prep, int ntg, int m,
+                                                    const float* __restrict__ box, const float* bq,
+                                                    const float* snorm, const int* vq, int* idx,
+                                                    int32_t* miss) {
+  const int lane = threadIdx.x & 63;
+  float b[Q], best[Q];
+  int bch[Q];
+  float qlo[Q][3], qhi[Q][3];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    b[q] = bq[q];
+    best[q] = __builtin_inff();
+    bch[q] = 0;
+    // block q's query box: row a of the lanes holds component a
+    const float lo = row_min(bq[q]), hi = row_max(bq[q]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      qlo[q][a] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lo), 16 * a));
+      qhi[q][a] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(hi), 16 * a));
+    }
+  }
+  const int nch = ntg / kChunkTG;
+  const float4* p = prep + lane;
+  // per-block bound: largest squared distance a query of the block may still
+  // need, with rounding slack
+  float ub[Q];
+  auto refresh = [&]() {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) ub[q] = row_max(rows_min(best[q]) + snorm[q]) * 1.0001f + 1e-7f;
+  };
+  // nearest chunk to the union of the blocks' boxes
+  float ulo[3], uhi[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    ulo[a] = qlo[0][a];
+    uhi[a] = qhi[0][a];
+#pragma unroll
+    for (int q = 1; q < Q; ++q) {
+      ulo[a] = fminf(ulo[a], qlo[q][a]);
+      uhi[a] = fmaxf(uhi[a], qhi[q][a]);
+    }
+  }
+  unsigned long long near = ~0ull;
+  for (int c = lane; c < nch; c += 64) {
+    const unsigned long long key =
+        ((unsigned long long)__float_as_uint(box_gap2(box + (size_t)c * 8, ulo, uhi)) << 32) | (unsigned)c;
+    near = key < near ? key : near;
+  }
+  for (int off = 1; off < 64; off <<= 1) {
+    const unsigned long long o = __shfl_xor(near, off, 64);
+    near = o < near ? o : near;
+  }
+  const int c0 = (int)(near & 0xffffffffull);
+  long long pairs = 0;
+  {
+    const int pts = max(0, min(128, m - 128 * c0));
+    chunk_step<Q>(p[(size_t)(2 * c0) * 64], p[(size_t)(2 * c0 + 1) * 64], b, best, bch, c0);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) pairs += (long long)pts * vq[q];
+  }
+  refresh();
+  int since = 0;
+  for (int blk = 0; blk < nch; blk += 64) {
+    const int c = blk + lane;
+    float lb[Q];
+    unsigned long long cand = 0ull;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      lb[q] = c < nch ? box_gap2(box + (size_t)c * 8, qlo[q], qhi[q]) : __builtin_inff();
+      cand |= __ballot(c != c0 && lb[q] <= ub[q]);
+    }
+    while (cand) {
+      const int cl = __ffsll((long long)cand) - 1;
+      const int cc = blk + cl;
+      cand &= cand - 1;
+      bool need[Q];
+      const int pts = max(0, min(128, m - 128 * cc));
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        need[q] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lb[q]), cl)) <= ub[q];
+        pairs += need[q] ? (long long)pts * vq[q] : 0ll;
+      }
+      const float4 x0 = p[(size_t)(2 * cc) * 64], x1 = p[(size_t)(2 * cc + 1) * 64];
+      chunk_step<Q>(x0, x1, b, best, bch, cc, need);
+      if (++since == 2) {
+        since = 0;
+        refresh();
+        unsigned long long keep = 0ull;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) keep |= __ballot(lb[q] <= ub[q]);
+        cand &= keep;
+      }
+    }
+  }
+  nn_rescan<Q>(prep, b, best, bch, idx, miss);
+  return pairs;
 }
 
 }  // namespace asicp

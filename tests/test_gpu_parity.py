@@ -78,14 +78,22 @@ def compare_step(pb, st, theta, k, prev_cost=None, converged=None, label=""):
     assert np.abs(gate_gpu - gate_or).sum() == excused
     s_t, s_w = pu.scales(pb, theta, r["nn_idx"], st.lam, setup)
     pu.close(g["cost"], r["cost"], r["cost"], what="cost")
-    pu.close(g["grad_ct"][:3].T, r["g_ct"][:, :3], s_t[:, None], what="g_t")
-    pu.close(g["grad_ct"][3:].T, r["g_ct"][:, 3:], s_w[:, None], what="g_w")
+    b_t, b_w = pu.tie_bounds(pb, theta, g["nn_idx"], r["nn_idx"])
+    pu.close(g["grad_ct"][:3].T, r["g_ct"][:, :3], s_t[:, None], what="g_t", extra=b_t[:, None])
+    pu.close(g["grad_ct"][3:].T, r["g_ct"][:, 3:], s_w[:, None], what="g_w", extra=b_w[:, None])
     both = (g["ncol"] > 0) & (r["ncol"] > 0) & (g["ncol"] == r["ncol"])
+    rb_t, rb_w = pu.rev_tie_bounds(pb, theta, g["rev_idx"], r["rev_idx"])
     if both.any():
         c_t, c_w = col_scales(pb, theta, r["rev_idx"])
-        pu.close(g["col_cost"][both], r["col_cost"][both], r["col_cost"][both], what="col_cost")
-        pu.close(g["grad_col"][:3].T[both], r["g_col"][both, :3], c_t[both, None], what="gcol_t")
-        pu.close(g["grad_col"][3:].T[both], r["g_col"][both, 3:], c_w[both, None], what="gcol_w")
+        pu.close(g["col_cost"][both], r["col_cost"][both], r["col_cost"][both], what="col_cost",
+                 extra=rb_t[both] * 0.05)
+        pu.close(g["grad_col"][:3].T[both], r["g_col"][both, :3], c_t[both, None], what="gcol_t",
+                 extra=rb_t[both, None])
+        pu.close(g["grad_col"][3:].T[both], r["g_col"][both, 3:], c_w[both, None], what="gcol_w",
+                 extra=rb_w[both, None])
+    # bound on what excused ties may change in the gradient the update uses
+    xb_t = np.where(r["ncol"] > 0, rb_t, b_t)
+    xb_w = np.where(r["ncol"] > 0, rb_w, b_w)
     same = g["ncol"] == r["ncol"]
     # the update
     svgd = k < st.k_stein
@@ -95,6 +103,8 @@ def compare_step(pb, st, theta, k, prev_cost=None, converged=None, label=""):
         # scale of phi: kernel-weighted magnitudes of driving and repulsion terms
         ph_t = np.zeros(pb.k_tot)
         ph_w = np.zeros(pb.k_tot)
+        ex_t = np.zeros(pb.k_tot)
+        ex_w = np.zeros(pb.k_tot)
         gam, tau = oracle.schedule(st, k)
         for gi in range(pb.n_obj * pb.n_pre):
             p = gi % pb.n_pre
@@ -107,16 +117,21 @@ def compare_step(pb, st, theta, k, prev_cost=None, converged=None, label=""):
             dt = np.abs(aos[:, None, :3] - aos[None, :, :3]).max(-1)
             ph_t[sl] = (kmat * (gam * setup["a_t"][p] * gt[None, :] + tau * dt)).mean(1)
             ph_w[sl] = (kmat * (gam * setup["a_w"][p] * gw[None, :]) + tau).mean(1)
+            ex_t[sl] = (kmat * (gam * setup["a_t"][p] * xb_t[sl][None, :])).mean(1)
+            ex_w[sl] = (kmat * (gam * setup["a_w"][p] * xb_w[sl][None, :])).mean(1)
         if same.all() and excused == 0:
-            pu.close(g["phi"][:3].T, r["phi"][:, :3], ph_t[:, None], what="phi_t")
-            pu.close(g["phi"][3:].T, r["phi"][:, 3:], ph_w[:, None], what="phi_w")
+            pu.close(g["phi"][:3].T, r["phi"][:, :3], ph_t[:, None], what="phi_t", extra=ex_t[:, None])
+            pu.close(g["phi"][3:].T, r["phi"][:, 3:], ph_w[:, None], what="phi_w", extra=ex_w[:, None])
             step_t, step_w = st.eta * ph_t, st.eta * ph_w
+            ext_t, ext_w = st.eta * ex_t, st.eta * ex_w
         else:
             step_t = step_w = None
     else:
         p_of = (np.arange(pb.k_tot) // pb.K) % pb.n_pre
         step_t = st.eta * setup["a_t"][p_of] * np.maximum(np.abs(r["g_fin"][:, :3]).max(1), s_t)
         step_w = st.eta * setup["a_w"][p_of] * np.maximum(np.abs(r["g_fin"][:, 3:]).max(1), s_w)
+        ext_t = st.eta * setup["a_t"][p_of] * xb_t
+        ext_w = st.eta * setup["a_w"][p_of] * xb_w
         conv_or = r["converged"].astype(bool)
         conv_gpu = g["converged"].astype(bool)
         pcv = np.asarray(prev_cost if prev_cost is not None else np.full(pb.k_tot, -1.0), np.float64)
@@ -127,10 +142,10 @@ def compare_step(pb, st, theta, k, prev_cost=None, converged=None, label=""):
     if step_t is not None:
         sel = same
         dt_err = np.abs(g["theta"][:3].astype(np.float64) - r["theta"][:3]).max(0)
-        tol_t = 1e-4 * step_t + 2e-7 * np.maximum(np.abs(th64[:3]).max(0), 1e-2)
+        tol_t = 1e-4 * step_t + 2e-7 * np.maximum(np.abs(th64[:3]).max(0), 1e-2) + ext_t
         assert (dt_err[sel] <= tol_t[sel]).all(), f"translation update: worst {(dt_err / tol_t)[sel].max():.3g}x tol"
         ang = pu.angle_between(g["theta"][3:], r["theta"][3:])
-        tol_w = 1e-4 * step_w + 2e-6
+        tol_w = 1e-4 * step_w + 2e-6 + ext_w
         assert (ang[sel] <= tol_w[sel]).all(), f"rotation update: worst {(ang / tol_w)[sel].max():.3g}x tol"
     assert g["status"] == 0
     return dict(ties=ties, gate_excused=excused, rev_ties=rties, ncol=int(g["ncol"].sum()))
@@ -208,6 +223,36 @@ def test_paper_scale_step_full_size():
     out = compare_step(pb, st, pulled_in(pb, 0.75), 50, label="paper scale pulled in")
     say("[parity] paper scale pulled in", out)
     assert out["ncol"] > 0
+
+
+def test_pruned_and_brute_force_nn_agree():
+    """Skipping chunks never changes a nearest distance: the pruned and the
+    plain scan return the same index, or (FP32 ties across chunks visited in
+    a different order) a point whose distance rounds to the same value."""
+    A, torch = _gpu()
+    pb, st = synth.workload_paper_scale()
+    for theta in (pb.theta0, pulled_in(pb, 0.75), pulled_in(pb, 0.95)):
+        res = []
+        for prune in (True, False):
+            s = A.Solver(pb, st, debug=True, theta0=theta, prune=prune)
+            s.step(1)
+            res.append(s.result())
+            s.close()
+        a, b = res[0]["nn_idx"], res[1]["nn_idx"]
+        diff = np.argwhere(a != b)
+        say("[parity] pruned vs plain index differences:", len(diff))
+        assert len(diff) <= 1e-4 * a.size
+        S = pb.S.astype(np.float64)
+        R = pb.R.astype(np.float64)
+        th = np.asarray(theta, np.float64)
+        for i, n in diff[:200]:
+            p = (i // pb.K) % pb.n_pre
+            sp = oracle.quat_to_rot(th[3:, i]) @ S[pb.s_off[p] + n] + th[:3, i]
+            da = ((sp - R[a[i, n]]) ** 2).sum()
+            db = ((sp - R[b[i, n]]) ** 2).sum()
+            # both round to the same FP32 value of |r|^2 - 2 r.s (a few ulp of ~0.01 m^2)
+            assert abs(da - db) <= 1e-8
+        assert np.array_equal(res[0]["ncol"], res[1]["ncol"])
 
 
 def ragged_problem(seed, n_obj, ms, ns, K, mcs=None):
@@ -334,6 +379,14 @@ def test_timing_hook_counts_launches():
     s = A.Solver(pb, st, timing=True)
     s.solve()
     s.result(per_particle=False)
-    ms, n = s.kernel_time()
+    ms, n, pairs = s.kernel_time()
     assert n == 5 and ms > 0
+    # every launch compares each contact point with at most every object point
+    assert 0 < pairs <= 5 * pb.k_tot * (pb.s_off[1] - pb.s_off[0]) * (pb.r_off[1] - pb.r_off[0])
+    s.close()
+    s = A.Solver(pb, st, timing=True, prune=False)
+    s.solve()
+    s.result(per_particle=False)
+    ms, n, pairs = s.kernel_time()
+    assert pairs == 5 * pb.k_tot * (pb.s_off[1] - pb.s_off[0]) * (pb.r_off[1] - pb.r_off[0])
     s.close()
