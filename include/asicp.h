@@ -99,6 +99,15 @@ typedef struct {
   const float* prev_cost;      /* device [Ktot] or NULL: resume state (cost of the   */
   const int32_t* converged;    /*   previous iteration, converged flags)             */
   int32_t k_start;             /* first iteration to run (0 .. k_max)                */
+  const float* prior;          /* HOST, optional (NULL: none), [n_objects*n_preshapes][9]
+                                  per group, Sec. III-B / eq. (8): mean translation
+                                  mu_t[3], translation precision w_t = 1/sigma^2
+                                  (>= 0), mean rotation mu_q[4] (w, x, y, z; unit
+                                  within 1e-3, normalised on use), von Mises
+                                  concentration kappa (>= 0).  Log prior
+                                  -w_t/2 |t - mu_t|^2 + kappa tr(R(mu_q)^T R(q)); its
+                                  gradient joins the Stein driving term only (the SGD
+                                  phase of eq. (3) has none).  Copied during create. */
 } asicp_problem;
 
 /* Iteration settings.  Table I of the paper: k_max 40, k_stein 15, cyclic
@@ -117,6 +126,14 @@ typedef struct {
   float h_fixed;        /* bandwidth for ASICP_BW_FIXED, > 0                         */
   float h_min;          /* floor of the median bandwidth, > 0                        */
   float conv_tol;       /* relative cost change counted as converged, >= 0           */
+  float w_pen;          /* weight of an optional SDF penetration term added to C:    */
+                        /*   w_pen / M_c * sum over colliding points of phi^2; 0     */
+                        /*   gives the paper's cost (not in the paper; for the       */
+                        /*   adjoint of asicp_cost_grad)                             */
+  int32_t minibatch;    /* 0: the whole object cloud; 1: a mini-batch per iteration  */
+                        /*   of size M min(k, 2 k_max/3) / (2 k_max/3) (>= 1),       */
+                        /*   Table I, drawn by a keyed permutation from `seed`       */
+  uint64_t seed;        /* mini-batch seed                                           */
   uint32_t flags;       /* ASICP_FLAG_*                                              */
 } asicp_config;
 
@@ -174,6 +191,28 @@ asicp_status asicp_step(asicp_ctx ctx, int32_t n_iters, void* stream);
  * the selection of the returned grasp per object. */
 asicp_status asicp_solve(asicp_ctx ctx, void* stream);
 
+/* Per-particle cost and its gradient at arbitrary poses: the adjoint of the
+ * iteration's cost with respect to each 6-DoF pose.  `theta` (device
+ * [7][Ktot]) replaces the context's poses; the cost C = 1/2 (L_ct + lambda
+ * L_com) of eqs. (13)-(15), plus the penetration term when w_pen > 0, and its
+ * gradient with respect to (translation, world rotation vector about the
+ * gripper origin), with nearest-neighbour pairs and gate decisions held at
+ * `theta`, go to cost_out (device [Ktot]) and grad_out (device [6][Ktot]);
+ * either may be NULL.  Enqueued on `stream`. */
+asicp_status asicp_cost_grad(asicp_ctx ctx, const float* theta, float* cost_out, float* grad_out,
+                             void* stream);
+
+/* Run the whole solve again as one HIP graph on `stream`: set-up from the
+ * borrowed inputs (which the caller may have rewritten in place: a new object
+ * of the same size, new initial particles), iterations k_start .. k_max-1,
+ * the final evaluation and the selection.  The graph is captured on the first
+ * call (on a private stream; `stream` may be the null stream) and replayed
+ * after, so repeated solves
+ * pay no per-kernel launch cost.  Afterwards the context is in the state
+ * asicp_solve leaves it in.  Not available with ASICP_FLAG_DEBUG
+ * (ASICP_E_STATE); ASICP_FLAG_TIMING events are not recorded inside the graph. */
+asicp_status asicp_replay(asicp_ctx ctx, void* stream);
+
 /* Synchronise `stream`, then fill `out` (see asicp_result_t).  Device outputs
  * are copied on `stream` before it is synchronised.  Returns ASICP_E_HIP for
  * an asynchronous HIP error and ASICP_E_NUMERIC if the device flagged a
@@ -181,7 +220,8 @@ asicp_status asicp_solve(asicp_ctx ctx, void* stream);
 asicp_status asicp_result(asicp_ctx ctx, asicp_result_t* out, void* stream);
 
 /* With ASICP_FLAG_TIMING: total time and count of the forward-NN kernel
- * launches enqueued so far, from HIP events recorded on the launch stream
+ * launches enqueued so far by asicp_step / asicp_solve / asicp_cost_grad,
+ * from HIP events recorded on the launch stream
  * around each launch, and (nn_pairs, may be NULL) the number of (contact
  * point, object point) distances those launches evaluated.  Synchronises on
  * the events. */

@@ -34,7 +34,7 @@ class _Problem(C.Structure):
                 ("R", C.c_void_p), ("r_off", C.c_void_p), ("C", C.c_void_p), ("c_off", C.c_void_p),
                 ("S", C.c_void_p), ("s_off", C.c_void_p), ("sdf", C.c_void_p),
                 ("sdf_off", C.c_void_p), ("sdf_n", C.c_void_p), ("sdf_origin", C.c_void_p),
-                ("sdf_cell", C.c_void_p)]
+                ("sdf_cell", C.c_void_p), ("prior", C.c_void_p)]
 
 
 class _Config(C.Structure):
@@ -42,12 +42,13 @@ class _Config(C.Structure):
                 ("lam", C.c_double), ("precond", C.c_int32), ("schedule", C.c_int32),
                 ("T0", C.c_double), ("T1", C.c_double), ("cyc_C", C.c_double), ("cyc_p", C.c_double),
                 ("kernel_mode", C.c_int32), ("bw_mode", C.c_int32), ("h_fixed", C.c_double),
-                ("h_min", C.c_double), ("conv_tol", C.c_double)]
+                ("h_min", C.c_double), ("conv_tol", C.c_double), ("w_pen", C.c_double),
+                ("minibatch", C.c_int32), ("seed", C.c_uint64)]
 
 
 class _EvalOut(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in ("cost", "g_ct", "g_q", "ncol", "col_cost", "g_col",
-                                          "g_fin", "nn_idx", "gate", "phi_c", "rev_idx")]
+                                          "g_fin", "nn_idx", "gate", "phi_c", "rev_idx", "pen")]
 
 
 _lib = None
@@ -66,9 +67,19 @@ def lib():
         L.or_nn_brute.restype = i32
         L.or_sdf_trilinear.argtypes = [vp, vp, vp, f64, vp, vp]
         L.or_sdf_trilinear.restype = f64
+        L.or_sdf_trilinear_grad.argtypes = [vp, vp, vp, f64, vp, vp, vp]
+        L.or_sdf_trilinear_grad.restype = f64
         L.or_setup.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.or_schedule.argtypes = [vp, i32, vp, vp]
-        L.or_eval.argtypes = [vp, vp, vp, vp]
+        L.or_eval.argtypes = [vp, vp, i32, vp, vp]
+        L.or_splitmix64.argtypes = [C.c_uint64]
+        L.or_splitmix64.restype = C.c_uint64
+        L.or_batch_size.argtypes = [vp, i32, C.c_int64]
+        L.or_batch_size.restype = C.c_int64
+        L.or_batch_perm.argtypes = [C.c_int64, C.c_int64, C.c_uint64]
+        L.or_batch_perm.restype = C.c_int64
+        L.or_batch_key.argtypes = [vp, i32, i32]
+        L.or_batch_key.restype = C.c_uint64
         L.or_bandwidth.argtypes = [vp, i32, vp]
         L.or_bandwidth.restype = f64
         L.or_svgd_direction.argtypes = [vp, vp, i32, f64, f64, f64, f64, f64, i32, vp, vp]
@@ -78,6 +89,8 @@ def lib():
         L.or_solve.argtypes = [vp, vp, i32, i32, vp, vp, vp, vp, vp, vp]
         L.or_solve.restype = i32
         L.or_select.argtypes = [vp, vp, vp, vp, vp]
+        L.or_log_prior.argtypes = [vp, vp, vp]
+        L.or_log_prior.restype = f64
         L.or_threads.restype = i32
         _lib = L
     return _lib
@@ -135,6 +148,44 @@ def sdf_trilinear(grid, origin, cell, p):
     return float(v), bool(inside[0])
 
 
+def sdf_trilinear_grad(grid, origin, cell, p):
+    g = np.ascontiguousarray(grid, np.float64)
+    n = np.array([g.shape[2], g.shape[1], g.shape[0]], np.int32)
+    o = np.ascontiguousarray(origin, np.float64)
+    p = np.ascontiguousarray(p, np.float64)
+    inside = np.zeros(1, np.int32)
+    grad = np.zeros(3)
+    v = lib().or_sdf_trilinear_grad(_p(g), _p(n), _p(o), float(cell), _p(p), _p(inside), _p(grad))
+    return float(v), bool(inside[0]), grad
+
+
+def splitmix64(x: int) -> int:
+    return int(lib().or_splitmix64(x & 0xFFFFFFFFFFFFFFFF))
+
+
+def batch_size(settings, k, M) -> int:
+    cfg = _config(settings)
+    return int(lib().or_batch_size(C.byref(cfg), int(k), int(M)))
+
+
+def batch_key(settings, k, o) -> int:
+    cfg = _config(settings)
+    return int(lib().or_batch_key(C.byref(cfg), int(k), int(o)))
+
+
+def batch_perm(j, M, key) -> int:
+    return int(lib().or_batch_perm(int(j), int(M), int(key)))
+
+
+def log_prior(prior9, theta7):
+    """Log prior of one pose (up to a constant) and its (t, w) gradient."""
+    pr = np.ascontiguousarray(prior9, np.float64)
+    th = np.ascontiguousarray(theta7, np.float64)
+    g = np.zeros(6)
+    v = lib().or_log_prior(_p(pr), _p(th), _p(g))
+    return float(v), g
+
+
 def bandwidth(theta_aos, settings) -> float:
     th = np.ascontiguousarray(theta_aos, np.float64)
     cfg = _config(settings)
@@ -163,7 +214,8 @@ def _config(st) -> _Config:
     return _Config(int(st.k_max), int(st.k_stein), float(st.eta), float(st.lam), int(st.precond),
                    int(st.schedule), float(st.T0), float(st.T1), float(st.cyc_C), float(st.cyc_p),
                    int(st.kernel_mode), int(st.bw_mode), float(st.h_fixed), float(st.h_min),
-                   float(st.conv_tol))
+                   float(st.conv_tol), float(getattr(st, "w_pen", 0.0)),
+                   int(getattr(st, "minibatch", 0)), int(getattr(st, "seed", 0)))
 
 
 def schedule(settings, k):
@@ -209,7 +261,8 @@ class Oracle:
         self._pb = _Problem(pb.n_obj, pb.n_pre, pb.K, arr(pb.R, np.float64), arr(pb.r_off, np.int32),
                             arr(pb.C, np.float64), arr(pb.c_off, np.int32), arr(pb.S, np.float64),
                             arr(pb.s_off, np.int32), arr(sdf, np.float64), arr(sdf_off, np.int64),
-                            arr(sdf_n, np.int32), arr(sdf_origin, np.float64), arr(sdf_cell, np.float64))
+                            arr(sdf_n, np.int32), arr(sdf_origin, np.float64), arr(sdf_cell, np.float64),
+                            None if getattr(pb, "prior", None) is None else arr(pb.prior, np.float64))
         self._cfg = _config(settings)
 
     def setup(self):
@@ -225,7 +278,7 @@ class Oracle:
         K = self.k_tot
         d = dict(cost=np.zeros(K), g_ct=np.zeros((K, 6)), g_q=np.zeros((K, 4)),
                  ncol=np.zeros(K, np.int32), col_cost=np.zeros(K), g_col=np.zeros((K, 6)),
-                 g_fin=np.zeros((K, 6)))
+                 g_fin=np.zeros((K, 6)), pen=np.zeros(K))
         if full:
             d.update(nn_idx=np.full((K, self.n_max), -1, np.int32),
                      gate=np.zeros((K, self.mc_max), np.uint8),
@@ -236,13 +289,17 @@ class Oracle:
 
     @staticmethod
     def aos(theta_soa) -> np.ndarray:
-        """(7, Ktot) SoA pose array (any float type) -> (Ktot, 7) float64."""
-        return np.ascontiguousarray(np.asarray(theta_soa, np.float64).T)
+        """(7, Ktot) SoA pose array (any float type) -> (Ktot, 7) float64, always
+        a fresh copy (the C calls update poses in place)."""
+        return np.array(np.asarray(theta_soa, np.float64).T, order="C", copy=True)
 
-    def evaluate(self, theta_soa, full: bool = True) -> dict:
+    def evaluate(self, theta_soa, full: bool = True, k=None) -> dict:
+        """Evaluation at poses theta; k selects the iteration's mini-batch
+        (default k_max: the whole cloud)."""
         th = self.aos(theta_soa)
         d, out = self._alloc_eval(full)
-        lib().or_eval(C.byref(self._pb), C.byref(self._cfg), _p(th), C.byref(out))
+        k = self.settings.k_max if k is None else k
+        lib().or_eval(C.byref(self._pb), C.byref(self._cfg), int(k), _p(th), C.byref(out))
         return d
 
     def step(self, k, theta_soa, prev_cost=None, converged=None, full: bool = False) -> dict:

@@ -85,6 +85,56 @@ static void cross(const double a[3], const double b[3], double out[3]) {
   out[2] = a[0] * b[1] - a[1] * b[0];
 }
 
+/* SplitMix64 (Steele, Lea and Flood, OOPSLA 2014): the published mixing
+ * function, used as a counter-based generator. */
+uint64_t or_splitmix64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+/* Mini-batch size of Table I at iteration k: the whole cloud scaled by
+ * min(k, 2 k_max / 3) / (2 k_max / 3), at least one point (the table's "N" is
+ * read as the object cloud size). */
+int64_t or_batch_size(const or_config* cfg, int32_t k, int64_t M) {
+  if (!cfg->minibatch) return M;
+  const double full = 2.0 * (double)cfg->k_max / 3.0;
+  const double frac = ((double)k < full ? (double)k : full) / full;
+  int64_t m = (int64_t)ceil((double)M * frac);
+  if (m < 1) m = 1;
+  if (m > M) m = M;
+  return m;
+}
+
+/* Key of the mini-batch of object o at iteration k. */
+uint64_t or_batch_key(const or_config* cfg, int32_t k, int32_t o) {
+  return or_splitmix64(or_splitmix64(cfg->seed) ^ ((uint64_t)(uint32_t)k << 20) ^ (uint64_t)(uint32_t)o);
+}
+
+/* A permutation of [0, M) keyed by `key`: a 4-round balanced Feistel network
+ * on 2h bits (2^(2h) >= M) with SplitMix64 round functions, cycle-walked back
+ * into [0, M).  The mini-batch of an iteration is {perm(j) : j < m_k}. */
+int64_t or_batch_perm(int64_t j, int64_t M, uint64_t key) {
+  int bits = 2;
+  while (((int64_t)1 << bits) < M) ++bits;
+  if (bits & 1) ++bits;
+  const int hb = bits / 2;
+  const uint64_t mask = ((uint64_t)1 << hb) - 1;
+  uint64_t x = (uint64_t)j;
+  do {
+    uint64_t L = x >> hb, R = x & mask;
+    for (uint64_t r = 0; r < 4; ++r) {
+      const uint64_t F = or_splitmix64(key ^ (r << 56) ^ R) & mask;
+      const uint64_t nL = R, nR = L ^ F;
+      L = nL;
+      R = nR;
+    }
+    x = (L << hb) | R;
+  } while (x >= (uint64_t)M);
+  return (int64_t)x;
+}
+
 /* Nearest neighbour of x among n points (eq. 1, point-to-point metric):
  * argmin of the squared distance; the lowest index wins an exact tie. */
 int32_t or_nn_brute(const double* pts, int32_t n, const double x[3], double* d2) {
@@ -98,6 +148,21 @@ int32_t or_nn_brute(const double* pts, int32_t n, const double x[3], double* d2)
     if (d < bd) { bd = d; best = m; }
   }
   if (d2) *d2 = bd;
+  return best;
+}
+
+/* As or_nn_brute over the points with mask[m] != 0. */
+static int32_t or_nn_masked(const double* pts, int32_t n, const uint8_t* mask, const double x[3]) {
+  int32_t best = -1;
+  double bd = INFINITY;
+  for (int32_t m = 0; m < n; ++m) {
+    if (!mask[m]) continue;
+    const double dx = x[0] - pts[3 * m + 0];
+    const double dy = x[1] - pts[3 * m + 1];
+    const double dz = x[2] - pts[3 * m + 2];
+    const double d = dx * dx + dy * dy + dz * dz;
+    if (d < bd) { bd = d; best = m; }
+  }
   return best;
 }
 
@@ -133,6 +198,46 @@ double or_sdf_trilinear(const double* grid, const int32_t n[3], const double ori
   const double c0 = (1.0 - f[1]) * c00 + f[1] * c10;
   const double c1 = (1.0 - f[1]) * c01 + f[1] * c11;
   return (1.0 - f[2]) * c0 + f[2] * c1;
+}
+
+/* Gradient of the trilinear interpolant with respect to the point (the
+ * derivative of each lerp along its own axis, the other two weights held),
+ * inside the node box; value as or_sdf_trilinear. */
+double or_sdf_trilinear_grad(const double* grid, const int32_t n[3], const double origin[3],
+                             double cell, const double p[3], int32_t* inside, double grad[3]) {
+  const double phi = or_sdf_trilinear(grid, n, origin, cell, p, inside);
+  grad[0] = grad[1] = grad[2] = 0.0;
+  if (!*inside) return phi;
+  int32_t i0[3];
+  double f[3];
+  for (int d = 0; d < 3; ++d) {
+    const double u = (p[d] - origin[d]) / cell;
+    int32_t fl = (int32_t)floor(u);
+    if (fl > n[d] - 2) fl = n[d] - 2;
+    i0[d] = fl;
+    f[d] = u - (double)fl;
+  }
+  const int64_t nx = n[0], ny = n[1];
+#define V(a, b, c) grid[((int64_t)(i0[2] + (c)) * ny + (i0[1] + (b))) * nx + (i0[0] + (a))]
+  double g[3] = {0, 0, 0};
+  for (int b = 0; b < 2; ++b)
+    for (int c2 = 0; c2 < 2; ++c2) {
+      const double wy = b ? f[1] : 1.0 - f[1], wz = c2 ? f[2] : 1.0 - f[2];
+      g[0] += wy * wz * (V(1, b, c2) - V(0, b, c2));
+    }
+  for (int a = 0; a < 2; ++a)
+    for (int c2 = 0; c2 < 2; ++c2) {
+      const double wx = a ? f[0] : 1.0 - f[0], wz = c2 ? f[2] : 1.0 - f[2];
+      g[1] += wx * wz * (V(a, 1, c2) - V(a, 0, c2));
+    }
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) {
+      const double wx = a ? f[0] : 1.0 - f[0], wy = b ? f[1] : 1.0 - f[1];
+      g[2] += wx * wy * (V(a, b, 1) - V(a, b, 0));
+    }
+#undef V
+  for (int d = 0; d < 3; ++d) grad[d] = g[d] / cell;
+  return phi;
 }
 
 /* Per-object centre of mass (Algorithm 1 preprocessing; the centroid of the
@@ -231,7 +336,8 @@ static int32_t max_col_points(const or_problem* pb) {
  *      transformed contact point (eq. 18, the reverse direction of eq. 1) and
  *      replace the gradient by the gradient of 1/2 L_col taken as in eqs.
  *      (4)-(5); the TCP-CoM term is left out there. */
-void or_eval(const or_problem* pb, const or_config* cfg, const double* theta, or_eval_out* out) {
+void or_eval(const or_problem* pb, const or_config* cfg, int32_t k, const double* theta,
+             or_eval_out* out) {
   const int32_t Ktot = pb->n_obj * pb->n_pre * pb->K;
   const int32_t Nmax = max_pre_points(pb);
   const int32_t Mcmax = max_col_points(pb);
@@ -242,6 +348,20 @@ void or_eval(const or_problem* pb, const or_config* cfg, const double* theta, or
   double* a_w = (double*)malloc(sizeof(double) * (size_t)pb->n_pre);
   or_setup(pb, cfg, com, tcp, rho2, a_t, a_w);
   const double lam = cfg->lambda;
+  /* mini-batch of each object cloud (Algorithm 1 "select a mini-batch from R",
+   * Table I size schedule; one batch per object and iteration, shared by its
+   * particles): in_batch[m] over the concatenated clouds */
+  const int32_t Mtot = pb->r_off[pb->n_obj];
+  uint8_t* in_batch = (uint8_t*)malloc((size_t)Mtot + 1);
+  for (int32_t o = 0; o < pb->n_obj; ++o) {
+    const int32_t m0 = pb->r_off[o], M = pb->r_off[o + 1] - m0;
+    const int64_t mb = or_batch_size(cfg, k, M);
+    memset(in_batch + m0, mb == M ? 1 : 0, (size_t)M);
+    if (mb < M) {
+      const uint64_t key = or_batch_key(cfg, k, o);
+      for (int64_t j = 0; j < mb; ++j) in_batch[m0 + or_batch_perm(j, M, key)] = 1;
+    }
+  }
 
 #pragma omp parallel for schedule(dynamic, 1)
   for (int32_t i = 0; i < Ktot; ++i) {
@@ -274,7 +394,7 @@ void or_eval(const or_problem* pb, const or_config* cfg, const double* theta, or
       mat_vec(Rm, S + 3 * n, u);
       for (int d = 0; d < 3; ++d) sp[d] = u[d] + tv[d];
       memcpy(sw + 3 * n, sp, sizeof sp);
-      const int32_t j = or_nn_brute(Rc, M, sp, NULL);
+      const int32_t j = or_nn_masked(Rc, M, in_batch + m0, sp);
       if (out->nn_idx) out->nn_idx[(size_t)i * Nmax + n] = j;
       double e[3], mxe[3];
       for (int d = 0; d < 3; ++d) e[d] = sp[d] - Rc[3 * j + d];
@@ -303,6 +423,8 @@ void or_eval(const or_problem* pb, const or_config* cfg, const double* theta, or
     }
     if (out->cost) out->cost[i] = cost;
     if (out->g_ct) memcpy(out->g_ct + 6 * (size_t)i, gct, sizeof gct);
+    double* costp = out->cost ? out->cost + i : NULL;
+    double* gctp = out->g_ct ? out->g_ct + 6 * (size_t)i : NULL;
     if (out->g_q) {
       for (int a = 0; a < 4; ++a) {
         double v[3];
@@ -318,14 +440,28 @@ void or_eval(const or_problem* pb, const or_config* cfg, const double* theta, or
     const double gcell = pb->sdf_cell[p];
     int32_t ncol = 0;
     double col_e2 = 0.0, col_e[3] = {0, 0, 0}, col_m[3] = {0, 0, 0};
+    double pen = 0.0, pen_t[3] = {0, 0, 0}, pen_w[3] = {0, 0, 0};
     for (int32_t m = 0; m < Mc; ++m) {
       const double* c = Cc + 3 * m;
       double dc[3], cp[3];
       for (int d = 0; d < 3; ++d) dc[d] = c[d] - tv[d];
       mat_t_vec(Rm, dc, cp);
       int32_t inside = 0;
-      const double phi = or_sdf_trilinear(grid, gn, gorg, gcell, cp, &inside);
+      double gphi[3];
+      const double phi = or_sdf_trilinear_grad(grid, gn, gorg, gcell, cp, &inside, gphi);
       const int collides = inside && (phi < 0.0);
+      if (collides && cfg->w_pen > 0.0) {
+        /* penetration phi^2 and its gradient: c' = R^T (c - t), so
+         * d/dt = -R grad(phi) and d/dw = (R grad(phi)) x (c - t) */
+        double rg[3], xg[3];
+        mat_vec(Rm, gphi, rg);
+        cross(rg, dc, xg);
+        pen += phi * phi;
+        for (int d = 0; d < 3; ++d) {
+          pen_t[d] += 2.0 * phi * (-rg[d]);
+          pen_w[d] += 2.0 * phi * xg[d];
+        }
+      }
       if (out->gate) out->gate[(size_t)i * Mcmax + m] = (uint8_t)collides;
       if (out->phi_c) out->phi_c[(size_t)i * Mcmax + m] = inside ? phi : NAN;
       int32_t jn = -1;
@@ -341,6 +477,18 @@ void or_eval(const or_problem* pb, const or_config* cfg, const double* theta, or
       }
       if (out->rev_idx) out->rev_idx[(size_t)i * Mcmax + m] = jn;
     }
+    /* optional penetration term (w_pen (1/M_c) sum of phi^2 over colliding
+     * points), added to the cost and to its gradient */
+    double gpen[6] = {0, 0, 0, 0, 0, 0}, pcost = 0.0;
+    if (cfg->w_pen > 0.0 && Mc > 0) {
+      const double s = cfg->w_pen / (double)Mc;
+      pcost = s * pen;
+      for (int d = 0; d < 3; ++d) { gpen[d] = s * pen_t[d]; gpen[3 + d] = s * pen_w[d]; }
+    }
+    for (int d = 0; d < 6; ++d) gct[d] += gpen[d];
+    if (costp) *costp = cost + pcost;
+    if (gctp) memcpy(gctp, gct, sizeof gct);
+    if (out->pen) out->pen[i] = pcost;
     double gcol[6] = {0, 0, 0, 0, 0, 0}, ccost = 0.0;
     if (ncol > 0) {
       const double inv = 1.0 / (double)ncol;
@@ -354,6 +502,7 @@ void or_eval(const or_problem* pb, const or_config* cfg, const double* theta, or
     free(sw);
   }
   free(com); free(tcp); free(rho2); free(a_t); free(a_w);
+  free(in_batch);
 }
 
 static int cmp_double(const void* a, const void* b) {
@@ -463,7 +612,7 @@ int32_t or_step(const or_problem* pb, const or_config* cfg, int32_t k, double* t
   int32_t* ncol = local.ncol ? local.ncol : (int32_t*)malloc(sizeof(int32_t) * Ktot);
   double* g = local.g_fin ? local.g_fin : (double*)malloc(sizeof(double) * 6 * (size_t)Ktot);
   local.cost = cost; local.ncol = ncol; local.g_fin = g;
-  or_eval(pb, cfg, theta, &local);
+  or_eval(pb, cfg, k, theta, &local);
 
   double* com = (double*)malloc(sizeof(double) * 3 * (size_t)pb->n_obj);
   double* tcp = (double*)malloc(sizeof(double) * 3 * (size_t)pb->n_pre);
@@ -479,14 +628,26 @@ int32_t or_step(const or_problem* pb, const or_config* cfg, int32_t k, double* t
 
   if (k < cfg->k_stein) {
     double* phi = (double*)malloc(sizeof(double) * 6 * (size_t)Ktot);
+    /* eq. (8): the driving term is the gradient of the log posterior, i.e.
+     * minus the cost gradient plus the gradient of the log prior */
+    double* gd = g;
+    if (pb->prior) {
+      gd = (double*)malloc(sizeof(double) * 6 * (size_t)Ktot);
+      for (int32_t i = 0; i < Ktot; ++i) {
+        double gp[6];
+        or_log_prior(pb->prior + 9 * (size_t)(i / K), theta + 7 * (size_t)i, gp);
+        for (int a = 0; a < 6; ++a) gd[6 * (size_t)i + a] = g[6 * (size_t)i + a] - gp[a];
+      }
+    }
     for (int32_t gi = 0; gi < G; ++gi) {
       const int32_t p = gi % pb->n_pre;
       const double* thg = theta + 7 * (size_t)gi * K;
       const double h = or_bandwidth(thg, K, cfg);
       if (h_out) h_out[gi] = h;
-      or_svgd_direction(thg, g + 6 * (size_t)gi * K, K, h, gamma, tau, a_t[p], a_w[p],
+      or_svgd_direction(thg, gd + 6 * (size_t)gi * K, K, h, gamma, tau, a_t[p], a_w[p],
                         cfg->kernel_mode, NULL, phi + 6 * (size_t)gi * K);
     }
+    if (gd != g) free(gd);
     for (int32_t i = 0; i < Ktot; ++i) {
       const double* ph = phi + 6 * (size_t)i;
       const double dt[3] = {cfg->eta * ph[0], cfg->eta * ph[1], cfg->eta * ph[2]};
@@ -523,6 +684,38 @@ int32_t or_step(const or_problem* pb, const or_config* cfg, int32_t k, double* t
   if (!ev || !ev->g_fin) free(g);
   free(com); free(tcp); free(rho2); free(a_t); free(a_w);
   return 0;
+}
+
+/* Log prior of a pose (Sec. III-B: Gaussian in translation, von Mises in
+ * rotation), up to a constant, and its gradient in the 6-D tangent (t, world
+ * rotation vector).  Translation: -w_t/2 |t - mu_t|^2.  Rotation: the matrix
+ * von Mises-Fisher density on SO(3), kappa tr(R(mu_q)^T R(q)); its rotation
+ * gradient is kappa times the axial vector of A - A^T with A = R(q) R(mu_q)^T,
+ * the derivative of tr(M^T Exp(w) R) at w = 0. */
+double or_log_prior(const double pr[9], const double theta[7], double grad[6]) {
+  const double* mu = pr;
+  const double w = pr[3], kappa = pr[8];
+  double Rq[9], Rm[9], A[9];
+  or_quat_to_rot(theta + 3, Rq);
+  or_quat_to_rot(pr + 4, Rm);
+  double lp = 0.0, tr = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    const double e = theta[a] - mu[a];
+    lp -= 0.5 * w * e * e;
+    grad[a] = -w * e;
+  }
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) {
+      double v = 0.0;
+      for (int m = 0; m < 3; ++m) v += Rq[3 * r + m] * Rm[3 * c + m];
+      A[3 * r + c] = v;
+    }
+  tr = A[0] + A[4] + A[8];
+  lp += kappa * tr;
+  grad[3] = kappa * (A[5] - A[7]);
+  grad[4] = kappa * (A[6] - A[2]);
+  grad[5] = kappa * (A[1] - A[3]);
+  return lp;
 }
 
 /* Returned grasp (Algorithm 1 return; Sec. V-A): per object, the particle
@@ -562,7 +755,7 @@ int32_t or_solve(const or_problem* pb, const or_config* cfg, int32_t k_start, in
     double* cost = local.cost ? local.cost : (double*)malloc(sizeof(double) * Ktot);
     int32_t* ncol = local.ncol ? local.ncol : (int32_t*)malloc(sizeof(int32_t) * Ktot);
     local.cost = cost; local.ncol = ncol;
-    or_eval(pb, cfg, theta, &local);
+    or_eval(pb, cfg, cfg->k_max, theta, &local);
     if (best_idx && best_free) or_select(pb, cost, ncol, best_idx, best_free);
     if (!final_ev || !final_ev->cost) free(cost);
     if (!final_ev || !final_ev->ncol) free(ncol);

@@ -40,6 +40,10 @@ typedef struct {
   const int32_t* sdf_n;        /* [3*n_pre] (nx, ny, nz)                         */
   const double* sdf_origin;    /* [3*n_pre] position of node (0,0,0)             */
   const double* sdf_cell;      /* [n_pre] node spacing                           */
+  const double* prior;         /* optional [n_obj*n_pre*9] per group: mean
+                                  translation mu_t[3], its precision w_t
+                                  (1/sigma^2), mean rotation mu_q[4] (unit),
+                                  concentration kappa; NULL: no prior          */
 } or_problem;
 
 enum { OR_PRECOND_GN_DIAG = 0, OR_PRECOND_IDENTITY = 1 };
@@ -61,6 +65,9 @@ typedef struct {
   double h_fixed;       /* bandwidth for OR_BW_FIXED                           */
   double h_min;         /* floor of the median-heuristic bandwidth             */
   double conv_tol;      /* relative cost change that counts as converged       */
+  double w_pen;         /* weight of the SDF penetration term (0: paper's cost) */
+  int32_t minibatch;    /* 0: whole object cloud; 1: Table I mini-batch schedule */
+  uint64_t seed;        /* mini-batch sampling seed                             */
 } or_config;
 
 /* Per-particle results of one evaluation (steps 1-4 of an iteration).  Every
@@ -78,6 +85,7 @@ typedef struct {
   uint8_t* gate;      /* [Ktot*Mcmax] 1 if the collision point collides        */
   double* phi_c;      /* [Ktot*Mcmax] SDF value at the point (NaN outside)     */
   int32_t* rev_idx;   /* [Ktot*Mcmax] reverse NN index (-1 if not colliding)   */
+  double* pen;        /* [Ktot] penetration term included in cost              */
 } or_eval_out;
 
 /* --- geometry helpers ---------------------------------------------------- */
@@ -87,12 +95,20 @@ void or_quat_exp(const double v[3], double out[4]);
 int32_t or_nn_brute(const double* pts, int32_t n, const double x[3], double* d2);
 double or_sdf_trilinear(const double* grid, const int32_t n[3], const double origin[3],
                         double cell, const double p[3], int32_t* inside);
+double or_sdf_trilinear_grad(const double* grid, const int32_t n[3], const double origin[3],
+                             double cell, const double p[3], int32_t* inside, double grad[3]);
 
 /* --- the method ---------------------------------------------------------- */
+double or_log_prior(const double pr[9], const double theta[7], double grad[6]);
 void or_setup(const or_problem* pb, const or_config* cfg, double* com, double* tcp,
               double* rho2, double* a_t, double* a_w);
 void or_schedule(const or_config* cfg, int32_t k, double* gamma, double* tau);
-void or_eval(const or_problem* pb, const or_config* cfg, const double* theta, or_eval_out* out);
+void or_eval(const or_problem* pb, const or_config* cfg, int32_t k, const double* theta,
+             or_eval_out* out);
+uint64_t or_splitmix64(uint64_t x);
+int64_t or_batch_size(const or_config* cfg, int32_t k, int64_t M);
+int64_t or_batch_perm(int64_t j, int64_t M, uint64_t key);
+uint64_t or_batch_key(const or_config* cfg, int32_t k, int32_t o);
 double or_bandwidth(const double* theta, int32_t K, const or_config* cfg);
 void or_svgd_direction(const double* theta, const double* g, int32_t K, double h, double gamma,
                        double tau, double a_t, double a_w, int32_t kernel_mode,

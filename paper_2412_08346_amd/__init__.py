@@ -22,8 +22,8 @@ LIB_PATH = os.path.join(_HERE, "libasicp.so")
 ASICP_OK, ASICP_E_INVALID, ASICP_E_STATE, ASICP_E_HIP, ASICP_E_NUMERIC = 0, -1, -2, -3, -4
 ASICP_FLAG_DEBUG, ASICP_FLAG_TIMING, ASICP_FLAG_NO_PRUNE = 1, 2, 4
 
-EXPORTS = ("asicp_workspace_bytes", "asicp_create", "asicp_step", "asicp_solve", "asicp_result",
-           "asicp_kernel_time", "asicp_destroy", "asicp_last_error")
+EXPORTS = ("asicp_workspace_bytes", "asicp_create", "asicp_step", "asicp_solve", "asicp_replay",
+           "asicp_cost_grad", "asicp_result", "asicp_kernel_time", "asicp_destroy", "asicp_last_error")
 
 
 class AsicpError(RuntimeError):
@@ -44,7 +44,7 @@ class asicp_problem(C.Structure):
                 ("cx", C.c_void_p), ("cy", C.c_void_p), ("cz", C.c_void_p), ("c_off", C.c_void_p),
                 ("sx", C.c_void_p), ("sy", C.c_void_p), ("sz", C.c_void_p), ("s_off", C.c_void_p),
                 ("sdf", C.c_void_p), ("theta0", C.c_void_p), ("prev_cost", C.c_void_p),
-                ("converged", C.c_void_p), ("k_start", C.c_int32)]
+                ("converged", C.c_void_p), ("k_start", C.c_int32), ("prior", C.c_void_p)]
 
 
 class asicp_config(C.Structure):
@@ -52,7 +52,8 @@ class asicp_config(C.Structure):
                 ("lambda_", C.c_float), ("precond", C.c_int32), ("schedule", C.c_int32),
                 ("T0", C.c_float), ("T1", C.c_float), ("cyc_C", C.c_float), ("cyc_p", C.c_float),
                 ("kernel_mode", C.c_int32), ("bw_mode", C.c_int32), ("h_fixed", C.c_float),
-                ("h_min", C.c_float), ("conv_tol", C.c_float), ("flags", C.c_uint32)]
+                ("h_min", C.c_float), ("conv_tol", C.c_float), ("w_pen", C.c_float),
+                ("minibatch", C.c_int32), ("seed", C.c_uint64), ("flags", C.c_uint32)]
 
 
 class asicp_result_t(C.Structure):
@@ -84,6 +85,10 @@ def load():
         L.asicp_step.restype = i32
         L.asicp_solve.argtypes = [vp, vp]
         L.asicp_solve.restype = i32
+        L.asicp_cost_grad.argtypes = [vp, vp, vp, vp, vp]
+        L.asicp_cost_grad.restype = i32
+        L.asicp_replay.argtypes = [vp, vp]
+        L.asicp_replay.restype = i32
         L.asicp_result.argtypes = [vp, vp, vp]
         L.asicp_result.restype = i32
         L.asicp_kernel_time.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(i32), C.POINTER(C.c_double)]
@@ -127,6 +132,15 @@ def asicp_solve(ctx, stream: int):
     return _check(load().asicp_solve(ctx, C.c_void_p(stream)))
 
 
+def asicp_cost_grad(ctx, theta_ptr: int, cost_ptr, grad_ptr, stream: int):
+    return _check(load().asicp_cost_grad(ctx, C.c_void_p(theta_ptr), C.c_void_p(cost_ptr),
+                                         C.c_void_p(grad_ptr), C.c_void_p(stream)))
+
+
+def asicp_replay(ctx, stream: int):
+    return _check(load().asicp_replay(ctx, C.c_void_p(stream)))
+
+
 def asicp_result(ctx, out: asicp_result_t, stream: int, check: bool = True):
     st = load().asicp_result(ctx, C.byref(out), C.c_void_p(stream))
     return _check(st) if check else st
@@ -149,7 +163,8 @@ def make_config(st: "synth.Settings", flags: int = 0) -> asicp_config:
     return asicp_config(int(st.k_max), int(st.k_stein), float(st.eta), float(st.lam), int(st.precond),
                         int(st.schedule), float(st.T0), float(st.T1), float(st.cyc_C), float(st.cyc_p),
                         int(st.kernel_mode), int(st.bw_mode), float(st.h_fixed), float(st.h_min),
-                        float(st.conv_tol), int(flags))
+                        float(st.conv_tol), float(getattr(st, "w_pen", 0.0)),
+                        int(getattr(st, "minibatch", 0)), int(getattr(st, "seed", 0)), int(flags))
 
 
 class Solver:
@@ -189,6 +204,8 @@ class Solver:
             self._keep["converged"] = torch.as_tensor(np.asarray(converged, np.int32)).to(dv)
         self._offs = dict(r=np.ascontiguousarray(pb.r_off, np.int32), c=np.ascontiguousarray(pb.c_off, np.int32),
                           s=np.ascontiguousarray(pb.s_off, np.int32))
+        pr = getattr(pb, "prior", None)
+        self._prior = None if pr is None else np.ascontiguousarray(pr, np.float32).reshape(-1, 9)
         sdfs = (asicp_sdf * pb.n_pre)()
         for p, g in enumerate(pb.grids):
             nz, ny, nx = g.values.shape
@@ -202,7 +219,8 @@ class Solver:
             self._offs["c"].ctypes.data, k["sx"].data_ptr(), k["sy"].data_ptr(), k["sz"].data_ptr(),
             self._offs["s"].ctypes.data, C.cast(sdfs, C.c_void_p).value, k["theta0"].data_ptr(),
             k["prev_cost"].data_ptr() if "prev_cost" in k else None,
-            k["converged"].data_ptr() if "converged" in k else None, int(k_start))
+            k["converged"].data_ptr() if "converged" in k else None, int(k_start),
+            self._prior.ctypes.data if self._prior is not None else None)
         flags = ((ASICP_FLAG_DEBUG if debug else 0) | (ASICP_FLAG_TIMING if timing else 0) |
                  (0 if prune else ASICP_FLAG_NO_PRUNE))
         self.config = make_config(st, flags)
@@ -232,6 +250,19 @@ class Solver:
 
     def solve(self, stream=None):
         asicp_solve(self.ctx, self._stream(stream))
+
+    def cost_grad(self, theta, stream=None):
+        """Cost and 6-D gradient per particle at poses `theta` (7, Ktot) on the
+        device (the adjoint of the cost; pairs and gates held at theta)."""
+        torch = self.torch
+        th = torch.as_tensor(theta, dtype=torch.float32, device=self.dev).contiguous()
+        cost = torch.empty(self.k_tot, device=self.dev)
+        grad = torch.empty((6, self.k_tot), device=self.dev)
+        asicp_cost_grad(self.ctx, th.data_ptr(), cost.data_ptr(), grad.data_ptr(), self._stream(stream))
+        return cost, grad
+
+    def replay(self, stream=None):
+        asicp_replay(self.ctx, self._stream(stream))
 
     def result(self, per_particle: bool = True, stream=None, check: bool = True) -> dict:
         torch = self.torch
@@ -277,3 +308,45 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+def _pose_autograd():
+    import torch
+
+    class PoseCost(torch.autograd.Function):
+        """cost_i(theta_i) of the grasp iteration with a hand-written backward.
+
+        Input: poses (7, Ktot) on the device (translation, unit quaternion).
+        Forward runs the library's kernels (asicp_cost_grad); backward maps
+        the 6-D gradient (translation, world rotation vector) to the pose
+        parameters: d/dt = g_t, d/dq = 2 M(q) g_w with
+        M(q) = [-q_v^T ; q_w I - [q_v]x] (the tangent of unit quaternions)."""
+
+        @staticmethod
+        def forward(ctx, theta, solver):
+            cost, grad = solver.cost_grad(theta.detach())
+            ctx.save_for_backward(theta.detach(), grad)
+            return cost
+
+        @staticmethod
+        def backward(ctx, gout):
+            theta, grad = ctx.saved_tensors
+            q = theta[3:]
+            gw = grad[3:]
+            w, x, y, z = q[0], q[1], q[2], q[3]
+            # 2 M(q) g_w, M = [-q_v^T ; w I - [q_v]x]
+            dq = torch.stack([
+                -(x * gw[0] + y * gw[1] + z * gw[2]),
+                w * gw[0] + z * gw[1] - y * gw[2],
+                -z * gw[0] + w * gw[1] + x * gw[2],
+                y * gw[0] - x * gw[1] + w * gw[2],
+            ]) * 2.0
+            dtheta = torch.cat([grad[:3], dq], 0) * gout[None, :]
+            return dtheta, None
+
+    return PoseCost
+
+
+def pose_cost(theta, solver):
+    """Differentiable per-particle cost at poses `theta` (see PoseCost)."""
+    return _pose_autograd().apply(theta, solver)

@@ -26,9 +26,9 @@ constexpr int kMaxGroups = 1 << 16;
 
 struct Layout {
   size_t groups, objs, pres, obj_prep, pre_prep, obj_pts, pre_pts, obj_perm, pre_perm, obj_box, pre_box;
-  size_t sort_keys, counters, obj_com, pre_const, col_pts, col_perm;
+  size_t sort_keys, counters, obj_com, pre_const, col_pts, col_perm, obj_prep_mb, batch_mark, prior;
   size_t theta, cost, col_cost, prev_cost, ncol, converged, grad, grad_ct, grad_col, phi, h, bw_hist, bw_state;
-  size_t nn_part, col_part, best, best_theta, flags, dbg_nn, dbg_rev;
+  size_t nn_part, col_part, pen_part, best, best_theta, flags, dbg_nn, dbg_rev;
   size_t total;
 };
 
@@ -37,6 +37,10 @@ struct Shape {
   int obj_tg, pre_tg, max_waves_pp, max_gate_chunks, n_max, mc_max;
   long long sort_keys;  // total power-of-two padded cloud sizes
   long long c_total;    // collision points over all objects
+  long long r_total;    // object points over all objects
+  int max_m, max_m_pad;
+  bool minibatch;
+  bool prior;
   long long total_waves, total_gate_wgs;
   bool debug;
 };
@@ -64,6 +68,9 @@ Layout layout_of(const Shape& s) {
   L.pre_box = bump(c, (size_t)s.pre_tg / kChunkTG * 32);
   L.sort_keys = bump(c, (size_t)s.sort_keys * 8);
   L.col_pts = bump(c, (size_t)(s.c_total > 0 ? s.c_total : 1) * 16);
+  L.obj_prep_mb = s.minibatch ? bump(c, (size_t)s.obj_tg * 64 * 16) : 0;
+  L.batch_mark = s.minibatch ? bump(c, (size_t)s.r_total) : 0;
+  L.prior = s.prior ? bump(c, 48 * (size_t)s.G) : 0;
   L.col_perm = bump(c, (size_t)(s.c_total > 0 ? s.c_total : 1) * 4);
   L.counters = bump(c, 16);
   L.obj_com = bump(c, 16 * (size_t)s.n_obj);
@@ -83,6 +90,7 @@ Layout layout_of(const Shape& s) {
   L.bw_state = bump(c, 16 * (size_t)s.G);
   L.nn_part = bump(c, 4 * kPartStride * K * (size_t)s.max_waves_pp);
   L.col_part = bump(c, 4 * kPartStride * K * (size_t)(s.max_gate_chunks > 0 ? s.max_gate_chunks : 1));
+  L.pen_part = bump(c, 4 * kPartStride * K * (size_t)(s.max_gate_chunks > 0 ? s.max_gate_chunks : 1));
   L.best = bump(c, 8 * (size_t)s.n_obj);
   L.best_theta = bump(c, 32 * (size_t)s.n_obj);
   L.flags = bump(c, 16);
@@ -143,6 +151,14 @@ asicp_status validate(const asicp_problem* pb, const asicp_config* cfg, Shape& s
   if (any_c && (!pb->cx || !pb->cy || !pb->cz))
     return fail(ASICP_E_INVALID, "collision cloud device pointers are required");
   s.c_total = pb->c_off[s.n_obj];
+  s.r_total = pb->r_off[s.n_obj];
+  s.max_m = 0;
+  s.max_m_pad = 0;
+  for (int o = 0; o < s.n_obj; ++o) {
+    const int m = pb->r_off[o + 1] - pb->r_off[o];
+    s.max_m = std::max(s.max_m, m);
+    s.max_m_pad = std::max(s.max_m_pad, ((m + kPadPoints - 1) / kPadPoints) * kPadPoints);
+  }
   if ((long long)pb->r_off[s.n_obj] > (1ll << 30) || (long long)pb->c_off[s.n_obj] > (1ll << 30))
     return fail(ASICP_E_INVALID, "clouds too large");
   for (int p = 0; p < s.n_pre; ++p) {
@@ -195,9 +211,24 @@ asicp_status validate(const asicp_problem* pb, const asicp_config* cfg, Shape& s
   }
   if (!finite_pos(cfg->h_min)) return fail(ASICP_E_INVALID, "h_min must be finite and > 0");
   if (!std::isfinite(cfg->conv_tol) || cfg->conv_tol < 0.f) return fail(ASICP_E_INVALID, "conv_tol must be finite and >= 0");
+  if (!std::isfinite(cfg->w_pen) || cfg->w_pen < 0.f) return fail(ASICP_E_INVALID, "w_pen must be finite and >= 0");
   if (cfg->flags & ~(ASICP_FLAG_DEBUG | ASICP_FLAG_TIMING | ASICP_FLAG_NO_PRUNE))
     return fail(ASICP_E_INVALID, "unknown flag bits");
   if (s.sort_keys > (1ll << 30)) return fail(ASICP_E_INVALID, "clouds too large to sort");
+  if (cfg->minibatch != 0 && cfg->minibatch != 1) return fail(ASICP_E_INVALID, "minibatch must be 0 or 1");
+  s.minibatch = cfg->minibatch == 1;
+  s.prior = pb->prior != nullptr;
+  if (s.prior) {
+    for (int g = 0; g < s.G; ++g) {
+      const float* pr = pb->prior + 9 * (size_t)g;
+      bool finite = true;
+      for (int a = 0; a < 9; ++a) finite = finite && std::isfinite(pr[a]);
+      const double n2 = (double)pr[4] * pr[4] + (double)pr[5] * pr[5] + (double)pr[6] * pr[6] + (double)pr[7] * pr[7];
+      if (!finite || pr[3] < 0.f || pr[8] < 0.f || std::fabs(std::sqrt(n2) - 1.0) > 1e-3)
+        return fail(ASICP_E_INVALID, "prior of group " + std::to_string(g) +
+                                         ": values must be finite, w_t and kappa >= 0, mu_q a unit quaternion");
+    }
+  }
   s.debug = (cfg->flags & ASICP_FLAG_DEBUG) != 0;
   return ASICP_OK;
 }
@@ -210,14 +241,34 @@ asicp_status check_launch(const char* what) {
 
 }  // namespace
 
+__global__ void k_set_theta(float* dst, const float* src, int n) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+__global__ void k_get_cost_grad(const float* cost, const float* grad_ct, float* cost_out, float* grad_out, int K) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= K) return;
+  if (cost_out) cost_out[i] = cost[i];
+  if (grad_out)
+    for (int a = 0; a < 6; ++a) grad_out[a * K + i] = grad_ct[a * K + i];
+}
+
 struct asicp_ctx_s {
   Dev d;
   asicp_config cfg;
   int k;               // next iteration
+  int k_start;
   bool final_done;
   float inv_log_k;
   std::vector<hipEvent_t> ev;  // start/stop pairs around forward-NN launches
   int n_timed;
+  const float* theta0;          // borrowed set-up inputs, for asicp_replay
+  const float* prev_cost0;
+  const int32_t* converged0;
+  hipGraphExec_t graph;         // whole-solve graph of asicp_replay
+  hipStream_t cap_stream;       // private stream the graph is captured on
+  bool capturing;               // no timing events inside a captured graph
 };
 
 extern "C" {
@@ -351,6 +402,7 @@ asicp_status asicp_create(const asicp_problem* pb, const asicp_config* cfg, void
   d.bw_state = reinterpret_cast<unsigned int*>(ws + L.bw_state);
   d.nn_part = reinterpret_cast<float*>(ws + L.nn_part);
   d.col_part = reinterpret_cast<float*>(ws + L.col_part);
+  d.pen_part = reinterpret_cast<float*>(ws + L.pen_part);
   d.best = reinterpret_cast<int32_t*>(ws + L.best);
   d.best_theta = reinterpret_cast<float*>(ws + L.best_theta);
   d.flags = reinterpret_cast<int32_t*>(ws + L.flags);
@@ -365,12 +417,34 @@ asicp_status asicp_create(const asicp_problem* pb, const asicp_config* cfg, void
   d.h_fixed = cfg->h_fixed;
   d.h_min = cfg->h_min;
   d.conv_tol = cfg->conv_tol;
+  d.w_pen = cfg->w_pen;
+  d.minibatch = s.minibatch ? 1 : 0;
+  d.seed = cfg->seed;
+  d.obj_prep_mb = s.minibatch ? reinterpret_cast<float4*>(ws + L.obj_prep_mb) : nullptr;
+  d.batch_mark = s.minibatch ? reinterpret_cast<unsigned char*>(ws + L.batch_mark) : nullptr;
+  d.max_m = s.max_m;
+  d.max_m_pad = s.max_m_pad;
+  d.prior = s.prior ? reinterpret_cast<const float*>(ws + L.prior) : nullptr;
+  std::vector<float> prior_words;
+  if (s.prior) {
+    prior_words.assign(12 * (size_t)s.G, 0.f);
+    for (int g = 0; g < s.G; ++g) {
+      const float* pr = pb->prior + 9 * (size_t)g;
+      float* w = prior_words.data() + 12 * (size_t)g;
+      const double n = std::sqrt((double)pr[4] * pr[4] + (double)pr[5] * pr[5] + (double)pr[6] * pr[6] +
+                                 (double)pr[7] * pr[7]);
+      for (int a = 0; a < 4; ++a) w[a] = pr[a];
+      for (int a = 0; a < 4; ++a) w[4 + a] = (float)(pr[4 + a] / n);
+      w[8] = pr[8];
+    }
+  }
 
   hipStream_t hs = static_cast<hipStream_t>(stream);
   (void)hipGetLastError();  // start from a clean error state
   upload_words(ws + L.groups, groups.data(), sizeof(GroupInfo) * groups.size(), hs);
   upload_words(ws + L.objs, objs.data(), sizeof(ObjInfo) * objs.size(), hs);
   upload_words(ws + L.pres, pres.data(), sizeof(PreInfo) * pres.size(), hs);
+  if (s.prior) upload_words(ws + L.prior, prior_words.data(), 4 * prior_words.size(), hs);
   if ((st = check_launch("table upload")) != ASICP_OK) return st;
   launch_setup(d, pb->theta0, pb->prev_cost, pb->converged, hs);
   if ((st = check_launch("setup")) != ASICP_OK) return st;
@@ -384,6 +458,13 @@ asicp_status asicp_create(const asicp_problem* pb, const asicp_config* cfg, void
   c->d = d;
   c->cfg = *cfg;
   c->k = pb->k_start;
+  c->k_start = pb->k_start;
+  c->theta0 = pb->theta0;
+  c->prev_cost0 = pb->prev_cost;
+  c->converged0 = pb->converged;
+  c->graph = nullptr;
+  c->cap_stream = nullptr;
+  c->capturing = false;
   c->final_done = false;
   c->inv_log_k = s.K >= 2 ? (float)(1.0 / std::log((double)s.K)) : 1.0f;
   c->n_timed = 0;
@@ -404,7 +485,7 @@ static void schedule_of(const asicp_config& cfg, int k, float* gamma, float* tau
 }
 
 static asicp_status nn_forward_timed(asicp_ctx c, hipStream_t hs) {
-  const bool timing = (c->cfg.flags & ASICP_FLAG_TIMING) != 0;
+  const bool timing = (c->cfg.flags & ASICP_FLAG_TIMING) != 0 && !c->capturing;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (timing) {
     if ((size_t)(2 * c->n_timed + 2) > c->ev.size()) {
@@ -429,7 +510,14 @@ static asicp_status nn_forward_timed(asicp_ctx c, hipStream_t hs) {
 }
 
 static asicp_status evaluate(asicp_ctx c, int k, int final_eval, hipStream_t hs) {
-  asicp_status st = nn_forward_timed(c, hs);
+  asicp_status st;
+  if (c->d.minibatch) {  // Table I: batch size grows linearly to the whole cloud at 2 k_max / 3
+    const double full = 2.0 * (double)c->cfg.k_max / 3.0;
+    const double frac = ((double)k < full ? (double)k : full) / full;
+    launch_minibatch(c->d, k, frac, hs);
+    if ((st = check_launch("minibatch")) != ASICP_OK) return st;
+  }
+  st = nn_forward_timed(c, hs);
   if (st != ASICP_OK) return st;
   launch_gate_reverse(c->d, hs);
   if ((st = check_launch("gate_reverse")) != ASICP_OK) return st;
@@ -470,6 +558,80 @@ asicp_status asicp_solve(asicp_ctx c, void* stream) {
   if ((st = evaluate(c, c->k, 1, hs)) != ASICP_OK) return st;
   launch_select(c->d, hs);
   if ((st = check_launch("select")) != ASICP_OK) return st;
+  c->final_done = true;
+  return ASICP_OK;
+}
+
+// Enqueue iterations k0 .. k_max-1, the final evaluation and the selection.
+static asicp_status enqueue_rest(asicp_ctx c, int k0, hipStream_t hs) {
+  asicp_status st;
+  for (int k = k0; k < c->cfg.k_max; ++k) {
+    if ((st = evaluate(c, k, 0, hs)) != ASICP_OK) return st;
+    if (k < c->cfg.k_stein) {
+      float gamma, tau;
+      schedule_of(c->cfg, k, &gamma, &tau);
+      launch_svgd(c->d, gamma, tau, c->inv_log_k, hs);
+      if ((st = check_launch("svgd")) != ASICP_OK) return st;
+    }
+  }
+  if ((st = evaluate(c, c->cfg.k_max, 1, hs)) != ASICP_OK) return st;
+  launch_select(c->d, hs);
+  return check_launch("select");
+}
+
+asicp_status asicp_cost_grad(asicp_ctx c, const float* theta, float* cost_out, float* grad_out, void* stream) {
+  g_err.clear();
+  if (!c || !theta) return fail(ASICP_E_INVALID, "ctx and theta must not be NULL");
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  const int K = c->d.Ktot;
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(k_set_theta, dim3((7 * K + 255) / 256), dim3(256), 0, hs, c->d.theta, theta, 7 * K);
+  asicp_status st = check_launch("set theta");
+  if (st != ASICP_OK) return st;
+  if ((st = evaluate(c, c->cfg.k_max, 1, hs)) != ASICP_OK) return st;
+  hipLaunchKernelGGL(k_get_cost_grad, dim3((K + 255) / 256), dim3(256), 0, hs, c->d.cost, c->d.grad_ct,
+                     cost_out, grad_out, K);
+  return check_launch("cost/grad copy");
+}
+
+asicp_status asicp_replay(asicp_ctx c, void* stream) {
+  g_err.clear();
+  if (!c) return fail(ASICP_E_INVALID, "ctx is NULL");
+  if (c->d.dbg_nn) return fail(ASICP_E_STATE, "asicp_replay is not available with ASICP_FLAG_DEBUG");
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  if (!c->graph) {
+    // Capture on a private stream (the caller's may be the null stream,
+    // which cannot be captured); capturing enqueues nothing.  Default
+    // priority.
+    if (!c->cap_stream && hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+      c->cap_stream = nullptr;
+      return fail(ASICP_E_HIP, "hipStreamCreateWithFlags failed");
+    }
+    hipStream_t cs = c->cap_stream;
+    (void)hipGetLastError();
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess)
+      return fail(ASICP_E_HIP, "hipStreamBeginCapture failed");
+    c->capturing = true;
+    launch_setup(c->d, c->theta0, c->prev_cost0, c->converged0, cs);
+    asicp_status st = check_launch("setup");
+    if (st == ASICP_OK) st = enqueue_rest(c, c->k_start, cs);
+    c->capturing = false;
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(cs, &g);
+    if (st != ASICP_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess || !g) return fail(ASICP_E_HIP, "hipStreamEndCapture failed");
+    const hipError_t ei = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) {
+      c->graph = nullptr;
+      return fail(ASICP_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+    }
+  }
+  if (hipGraphLaunch(c->graph, hs) != hipSuccess) return fail(ASICP_E_HIP, "hipGraphLaunch failed");
+  c->k = c->cfg.k_max;
   c->final_done = true;
   return ASICP_OK;
 }
@@ -553,6 +715,8 @@ asicp_status asicp_kernel_time(asicp_ctx c, double* total_ms, int32_t* launches,
 
 void asicp_destroy(asicp_ctx c) {
   if (!c) return;
+  if (c->graph) (void)hipGraphExecDestroy(c->graph);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   delete c;
 }

@@ -73,6 +73,7 @@ struct Dev {
   int32_t total_waves, total_gate_wgs;
   int32_t max_waves_pp, max_gate_chunks;  // partial-record strides
   int32_t n_max, mc_max;
+  int32_t max_m, max_m_pad;  // largest object cloud, and padded to whole tile groups
   // clouds in Morton order (index = prep_tg_begin*64 + k): MFMA-ready float4
   // (A-operand order), plain float4 (x, y, z, 0), original index (-1 for
   // padding), and one bounding box per 128-point chunk (lo xyz, -, hi xyz, -)
@@ -107,6 +108,7 @@ struct Dev {
   unsigned int* bw_state;  // [G][4] prefix, mask, rank, finished workgroups
   float* nn_part;   // [Ktot][max_waves_pp][8]
   float* col_part;  // [Ktot][max_gate_chunks][8]
+  float* pen_part;  // [Ktot][max_gate_chunks][8] penetration sums (w_pen > 0)
   int32_t* best;    // [n_obj][2]: particle, free flag
   float* best_theta;  // [n_obj][8]: theta(7), cost
   int32_t* flags;   // [0] non-finite, [1] NN re-scan miss
@@ -116,6 +118,13 @@ struct Dev {
   float eta, lambda;
   int32_t k_stein, kernel_mode, bw_mode, precond;
   float h_fixed, h_min, conv_tol;
+  float w_pen;      // weight of the optional SDF penetration term
+  int32_t minibatch;        // Table I mini-batch schedule of the object clouds
+  unsigned long long seed;  // its sampling seed
+  float4* obj_prep_mb;      // MFMA-ready object clouds with points outside the
+                            //   iteration's mini-batch at |r|^2 = 1e30
+  unsigned char* batch_mark;  // [sum M] 1 if the point is in the mini-batch
+  const float* prior;       // [G][12] mu_t[3], w_t, mu_q[4] (unit), kappa, pad; NULL: none
 };
 
 typedef float f4v __attribute__((ext_vector_type(4)));
@@ -232,6 +241,7 @@ void launch_gate_reverse(const Dev& d, hipStream_t s);
 void launch_finalize(const Dev& d, int k, int final_eval, hipStream_t s);
 void launch_svgd(const Dev& d, float gamma, float tau, float inv_log_k, hipStream_t s);
 void launch_select(const Dev& d, hipStream_t s);
+void launch_minibatch(const Dev& d, int k, double frac, hipStream_t s);
 void upload_words(void* dst, const void* src, size_t bytes, hipStream_t s);
 
 }  // namespace asicp

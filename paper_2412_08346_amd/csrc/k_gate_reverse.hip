@@ -25,7 +25,11 @@ __device__ __forceinline__ int xcd_logical_g(int b, int nwg) {
   return (b & 7) * per + (b >> 3);
 }
 
-__device__ __forceinline__ bool sdf_collides(const PreInfo& pi, float px, float py, float pz) {
+// Trilinear SDF at a gripper-frame point.  Returns true if the point
+// collides (inside the node box, value strictly negative); then *phi holds
+// the value and, if grad is given, grad the interpolant's gradient.
+__device__ __forceinline__ bool sdf_collides(const PreInfo& pi, float px, float py, float pz,
+                                             float* phi = nullptr, float* grad = nullptr) {
   const float ux = (px - pi.ox) * pi.inv_cell;
   const float uy = (py - pi.oy) * pi.inv_cell;
   const float uz = (pz - pi.oz) * pi.inv_cell;
@@ -41,13 +45,27 @@ __device__ __forceinline__ bool sdf_collides(const PreInfo& pi, float px, float 
   const float fx = ux - (float)ix, fy = uy - (float)iy, fz = uz - (float)iz;
   const size_t sx = 1, sy = (size_t)pi.nx, sz = (size_t)pi.nx * pi.ny;
   const float* v = pi.sdf + (size_t)iz * sz + (size_t)iy * sy + ix;
-  const float c00 = (1.f - fx) * v[0] + fx * v[sx];
-  const float c10 = (1.f - fx) * v[sy] + fx * v[sy + sx];
-  const float c01 = (1.f - fx) * v[sz] + fx * v[sz + sx];
-  const float c11 = (1.f - fx) * v[sz + sy] + fx * v[sz + sy + sx];
+  const float v000 = v[0], v100 = v[sx], v010 = v[sy], v110 = v[sy + sx];
+  const float v001 = v[sz], v101 = v[sz + sx], v011 = v[sz + sy], v111 = v[sz + sy + sx];
+  const float c00 = (1.f - fx) * v000 + fx * v100;
+  const float c10 = (1.f - fx) * v010 + fx * v110;
+  const float c01 = (1.f - fx) * v001 + fx * v101;
+  const float c11 = (1.f - fx) * v011 + fx * v111;
   const float c0 = (1.f - fy) * c00 + fy * c10;
   const float c1 = (1.f - fy) * c01 + fy * c11;
-  return (1.f - fz) * c0 + fz * c1 < 0.f;
+  const float val = (1.f - fz) * c0 + fz * c1;
+  if (!(val < 0.f)) return false;
+  if (phi) *phi = val;
+  if (grad) {
+    const float gx = (1.f - fy) * (1.f - fz) * (v100 - v000) + fy * (1.f - fz) * (v110 - v010) +
+                     (1.f - fy) * fz * (v101 - v001) + fy * fz * (v111 - v011);
+    const float gy = (1.f - fx) * (1.f - fz) * (v010 - v000) + fx * (1.f - fz) * (v110 - v100) +
+                     (1.f - fx) * fz * (v011 - v001) + fx * fz * (v111 - v101);
+    grad[0] = gx * pi.inv_cell;
+    grad[1] = gy * pi.inv_cell;
+    grad[2] = (c1 - c0) * pi.inv_cell;
+  }
+  return true;
 }
 
 // Can any point of the cloud's bounding box reach a cell with a negative
@@ -129,8 +147,12 @@ __global__ __launch_bounds__(256) void k_gate_reverse(Dev d) {
   load_pose(d.theta, d.Ktot, i, t, qv);
   quat_to_rot(qv[0], qv[1], qv[2], qv[3], R);
 
+  float* pout = d.pen_part + ((size_t)i * d.max_gate_chunks + cc) * kPartStride;
   if (!box_may_collide(pi, oi, R, t)) {
-    if (tid < kPartStride) out[tid] = 0.f;
+    if (tid < kPartStride) {
+      out[tid] = 0.f;
+      pout[tid] = 0.f;
+    }
     if (d.dbg_rev)
       for (int r = 0; r < kPerThread; ++r) {
         const int m = cc * kGateChunk + r * 256 + tid;
@@ -143,6 +165,9 @@ __global__ __launch_bounds__(256) void k_gate_reverse(Dev d) {
   // Morton-sorted collision cloud (so colliding points come out clustered)
   unsigned int bits = 0u;
   float px[kPerThread], py[kPerThread], pz[kPerThread];
+  // penetration sums (gripper frame): phi^2, -2 phi grad, 2 phi grad x c'
+  float pn[7] = {0, 0, 0, 0, 0, 0, 0};
+  const bool want_pen = d.w_pen > 0.f;
 #pragma unroll
   for (int r = 0; r < kPerThread; ++r) {
     const int m = cc * kGateChunk + r * 256 + tid;
@@ -155,7 +180,17 @@ __global__ __launch_bounds__(256) void k_gate_reverse(Dev d) {
       px[r] = R[0] * dx + R[3] * dy + R[6] * dz;
       py[r] = R[1] * dx + R[4] * dy + R[7] * dz;
       pz[r] = R[2] * dx + R[5] * dy + R[8] * dz;
-      const bool col = sdf_collides(pi, px[r], py[r], pz[r]);
+      float phi, gr[3];
+      const bool col = sdf_collides(pi, px[r], py[r], pz[r], &phi, want_pen ? gr : nullptr);
+      if (col && want_pen) {
+        pn[0] += phi * phi;
+        pn[1] -= 2.f * phi * gr[0];
+        pn[2] -= 2.f * phi * gr[1];
+        pn[3] -= 2.f * phi * gr[2];
+        pn[4] += 2.f * phi * (gr[1] * pz[r] - gr[2] * py[r]);
+        pn[5] += 2.f * phi * (gr[2] * px[r] - gr[0] * pz[r]);
+        pn[6] += 2.f * phi * (gr[0] * py[r] - gr[1] * px[r]);
+      }
       if (col) bits |= 1u << r;
       else if (d.dbg_rev) d.dbg_rev[(size_t)i * d.mc_max + d.col_perm[oi.c_begin + m]] = -1;
     }
@@ -176,6 +211,17 @@ __global__ __launch_bounds__(256) void k_gate_reverse(Dev d) {
     total += wtot[k];
   }
   int pos = base + incl - cnt;
+  if (want_pen) {  // fixed-order workgroup sums of the penetration terms
+#pragma unroll
+    for (int a = 0; a < 7; ++a) pn[a] = wave_sum(pn[a]);
+    if (lane == 0)
+      for (int a = 0; a < 7; ++a) wpart[w][a] = pn[a];
+    __syncthreads();
+    if (tid < 7) pout[tid] = ((wpart[0][tid] + wpart[1][tid]) + wpart[2][tid]) + wpart[3][tid];
+    __syncthreads();
+  } else if (tid < kPartStride) {
+    pout[tid] = 0.f;
+  }
 #pragma unroll
   for (int r = 0; r < kPerThread; ++r) {
     if (bits & (1u << r)) {

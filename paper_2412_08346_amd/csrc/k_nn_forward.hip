@@ -25,7 +25,8 @@ __device__ __forceinline__ int xcd_logical(int b, int nwg) {
 #define NN_OCCUPANCY
 #endif
 
-__global__ __launch_bounds__(256) NN_OCCUPANCY void k_nn_forward(Dev d) {
+template <bool PRUNE>
+__device__ __forceinline__ void nn_forward_body(const Dev& d) {
   const int nwg = (d.total_waves + 3) >> 2;
   const int logical = xcd_logical(blockIdx.x, nwg);
   if (logical >= nwg) return;
@@ -65,9 +66,9 @@ __global__ __launch_bounds__(256) NN_OCCUPANCY void k_nn_forward(Dev d) {
     snorm[q] = px * px + py * py + pz * pz;
   }
   int idx[Q];
-  const float4* prep = d.obj_prep + (size_t)oi.prep_tg_begin * 64;
+  const float4* prep = (d.minibatch ? d.obj_prep_mb : d.obj_prep) + (size_t)oi.prep_tg_begin * 64;
   long long pairs;
-  if (d.prune) {
+  if (PRUNE) {
     int vq[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) vq[q] = max(0, min(16, pi.n - (chunk * QPW + q * 16)));
@@ -124,10 +125,19 @@ __global__ __launch_bounds__(256) NN_OCCUPANCY void k_nn_forward(Dev d) {
   }
 }
 
+// The pruned scan keeps fewer registers live per wavefront and gains from
+// more wavefronts per SIMD to hide its per-chunk loads; the full scan does
+// not (a lower register budget makes it spill).
+__global__ __launch_bounds__(256) NN_OCCUPANCY void k_nn_forward(Dev d) { nn_forward_body<true>(d); }
+__global__ __launch_bounds__(256) void k_nn_forward_full(Dev d) { nn_forward_body<false>(d); }
+
 void launch_nn_forward(const Dev& d, hipStream_t s) {
   const int nwg = (d.total_waves + 3) / 4;
   const int grid = ((nwg + 7) / 8) * 8;
-  hipLaunchKernelGGL(k_nn_forward, dim3(grid), dim3(256), 0, s, d);
+  if (d.prune)
+    hipLaunchKernelGGL(k_nn_forward, dim3(grid), dim3(256), 0, s, d);
+  else
+    hipLaunchKernelGGL(k_nn_forward_full, dim3(grid), dim3(256), 0, s, d);
 }
 
 }  // namespace asicp

@@ -77,7 +77,8 @@ __global__ __launch_bounds__(256) void k_finalize(Dev d, int k, int final_eval) 
   const float uTz = R[6] * pc[0] + R[7] * pc[1] + R[8] * pc[2];
   const float eTx = uTx + t[0] - com[0], eTy = uTy + t[1] - com[1], eTz = uTz + t[2] - com[2];
   const float lam = d.lambda;
-  const float cost = 0.5f * (s[0] * invN + lam * (eTx * eTx + eTy * eTy + eTz * eTz));
+  const float cost_ct = 0.5f * (s[0] * invN + lam * (eTx * eTx + eTy * eTy + eTz * eTz));
+  float cost_pen = 0.f;
   float gct[6];
   gct[0] = s[1] * invN + lam * eTx;
   gct[1] = s[2] * invN + lam * eTy;
@@ -100,6 +101,21 @@ __global__ __launch_bounds__(256) void k_finalize(Dev d, int k, int final_eval) 
     gcol[5] = R[6] * mx + R[7] * my + R[8] * mz;
     ccost = 0.5f * cs[0] * inv;
   }
+  if (d.w_pen > 0.f && oi.mc > 0) {  // optional penetration term, added to C and its gradient
+    float pn[7] = {0, 0, 0, 0, 0, 0, 0};
+    const float* pp = d.pen_part + (size_t)i * d.max_gate_chunks * kPartStride;
+    for (int c = 0; c < oi.gate_chunks; ++c)
+      for (int a = 0; a < 7; ++a) pn[a] += pp[c * kPartStride + a];
+    const float sw = d.w_pen / (float)oi.mc;
+    cost_pen = sw * pn[0];
+    gct[0] += sw * (R[0] * pn[1] + R[1] * pn[2] + R[2] * pn[3]);
+    gct[1] += sw * (R[3] * pn[1] + R[4] * pn[2] + R[5] * pn[3]);
+    gct[2] += sw * (R[6] * pn[1] + R[7] * pn[2] + R[8] * pn[3]);
+    gct[3] += sw * (R[0] * pn[4] + R[1] * pn[5] + R[2] * pn[6]);
+    gct[4] += sw * (R[3] * pn[4] + R[4] * pn[5] + R[5] * pn[6]);
+    gct[5] += sw * (R[6] * pn[4] + R[7] * pn[5] + R[8] * pn[6]);
+  }
+  const float cost = cost_ct + cost_pen;
   const float* gf = ncol > 0 ? gcol : gct;
   const int K = d.Ktot;
   d.cost[i] = cost;

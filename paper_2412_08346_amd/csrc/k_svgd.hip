@@ -5,7 +5,8 @@
 //                 found exactly by a radix select over the FP32 bit patterns
 //                 (monotone for non-negative floats), 8 bits per pass;
 //   k_svgd_phi    Stein direction in the 6-D tangent: kernel-weighted mean of
-//                 the preconditioned driving terms -gamma A g_j plus tau times
+//                 the preconditioned driving terms -gamma A g_j (g_j minus the
+//                 log-prior gradient when a prior is given, eq. 8) plus tau times
 //                 the kernel gradient with respect to particle j (translation
 //                 part scaled by h/2); 64 particles per workgroup, 4 lanes per
 //                 particle;
@@ -118,6 +119,22 @@ __global__ void k_bw_const(Dev d) {
   if (g < d.G) d.h[g] = d.bw_mode == ASICP_BW_FIXED ? d.h_fixed : 1.0f;
 }
 
+// Gradient of the log prior of one pose in (t, world rotation vector):
+// -w (t - mu_t), and for kappa tr(R(mu)^T R(q)) = kappa (4 (mu.q)^2 - 1) the
+// rotation part 4 kappa (mu.q) vec(mu (x) conj q), since the derivative of
+// mu.q under q <- Exp(w) q is 1/2 vec(mu (x) conj q).
+__device__ __forceinline__ void log_prior_grad(const float* pr, const float* t, const float* q, float* gp) {
+  gp[0] = -pr[3] * (t[0] - pr[0]);
+  gp[1] = -pr[3] * (t[1] - pr[1]);
+  gp[2] = -pr[3] * (t[2] - pr[2]);
+  const float mw = pr[4], mx = pr[5], my = pr[6], mz = pr[7];
+  const float dot = mw * q[0] + mx * q[1] + my * q[2] + mz * q[3];
+  const float c = 4.f * pr[8] * dot;
+  gp[3] = c * (q[0] * mx - mw * q[1] - (my * q[3] - mz * q[2]));
+  gp[4] = c * (q[0] * my - mw * q[2] - (mz * q[1] - mx * q[3]));
+  gp[5] = c * (q[0] * mz - mw * q[3] - (mx * q[2] - my * q[1]));
+}
+
 __global__ __launch_bounds__(256) void k_svgd_phi(Dev d, float gamma, float tau) {
   __shared__ float st[kMaxK * 3];
   __shared__ float sq[kMaxK * 4];
@@ -129,6 +146,11 @@ __global__ __launch_bounds__(256) void k_svgd_phi(Dev d, float gamma, float tau)
     for (int a = 0; a < 3; ++a) st[3 * j + a] = d.theta[a * Kt + i];
     for (int a = 0; a < 4; ++a) sq[4 * j + a] = d.theta[(3 + a) * Kt + i];
     for (int a = 0; a < 6; ++a) sg[6 * j + a] = d.grad[a * Kt + i];
+    if (d.prior) {
+      float gp[6];
+      log_prior_grad(d.prior + 12 * g, st + 3 * j, sq + 4 * j, gp);
+      for (int a = 0; a < 6; ++a) sg[6 * j + a] -= gp[a];
+    }
   }
   __syncthreads();
   const int ii = blockIdx.y * 64 + (tid >> 2), part = tid & 3;

@@ -260,12 +260,17 @@ __device__ __forceinline__ long long nn_scan_pruned(const float4* __restrict__ p
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       lb[q] = c < nch ? box_gap2(box + (size_t)c * 8, qlo[q], qhi[q]) : __builtin_inff();
-      cand |= __ballot(c != c0 && lb[q] <= ub[q]);
+      cand |= __ballot(c < nch && c != c0 && lb[q] <= ub[q]);
     }
+    // candidates in index order; the next candidate's data is loaded while
+    // the current one is compared
+    int cl = cand ? __ffsll((long long)cand) - 1 : 0;
+    float4 x0 = p[(size_t)(2 * (blk + cl)) * 64], x1 = p[(size_t)(2 * (blk + cl) + 1) * 64];
     while (cand) {
-      const int cl = __ffsll((long long)cand) - 1;
       const int cc = blk + cl;
       cand &= cand - 1;
+      const int nl = cand ? __ffsll((long long)cand) - 1 : cl;
+      const float4 y0 = p[(size_t)(2 * (blk + nl)) * 64], y1 = p[(size_t)(2 * (blk + nl) + 1) * 64];
       bool need[Q];
       const int pts = max(0, min(128, m - 128 * cc));
 #pragma unroll
@@ -273,7 +278,6 @@ __device__ __forceinline__ long long nn_scan_pruned(const float4* __restrict__ p
         need[q] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lb[q]), cl)) <= ub[q];
         pairs += need[q] ? (long long)pts * vq[q] : 0ll;
       }
-      const float4 x0 = p[(size_t)(2 * cc) * 64], x1 = p[(size_t)(2 * cc + 1) * 64];
       chunk_step<Q>(x0, x1, b, best, bch, cc, need);
       if (++since == 2) {
         since = 0;
@@ -282,6 +286,13 @@ __device__ __forceinline__ long long nn_scan_pruned(const float4* __restrict__ p
 #pragma unroll
         for (int q = 0; q < Q; ++q) keep |= __ballot(lb[q] <= ub[q]);
         cand &= keep;
+      }
+      x0 = y0;
+      x1 = y1;
+      cl = cand ? __ffsll((long long)cand) - 1 : cl;
+      if (cl != nl) {  // the prefetched chunk was dropped by the refresh
+        x0 = p[(size_t)(2 * (blk + cl)) * 64];
+        x1 = p[(size_t)(2 * (blk + cl) + 1) * 64];
       }
     }
   }

@@ -48,13 +48,17 @@ class Settings:
     h_fixed: float = 1.0
     h_min: float = 1e-8
     conv_tol: float = 2e-4
+    w_pen: float = 0.0  # optional SDF penetration term (0: the paper's cost)
+    minibatch: int = 0  # 1: Table I mini-batch schedule of the object cloud
+    seed: int = 0       # mini-batch sampling seed
 
 
-def paper_settings(k_max: int = 40, k_stein: int = 15) -> Settings:
+def paper_settings(k_max: int = 40, k_stein: int = 15, minibatch: int = 1, seed: int = 7) -> Settings:
     """Table I: 15 SVGD + 25 SGD iterations, cyclic annealing C=5, p=2,
-    learning rate and cost weights 1, convergence 0.02 %."""
+    learning rate and cost weights 1, convergence 0.02 %, mini-batch size
+    growing linearly to the whole cloud at 2 k_max / 3."""
     return Settings(k_max=k_max, k_stein=k_stein, schedule=SCHED_PAPER_CYCLIC, cyc_C=5.0,
-                    cyc_p=2.0, eta=1.0, lam=1.0, conv_tol=2e-4)
+                    cyc_p=2.0, eta=1.0, lam=1.0, conv_tol=2e-4, minibatch=minibatch, seed=seed)
 
 
 @dataclasses.dataclass
@@ -77,6 +81,8 @@ class Problem:
     grids: list          # [Grid] per preshape
     theta0: np.ndarray   # (7, Ktot) float32 SoA: tx ty tz qw qx qy qz
     K: int               # particles per (object, preshape) group
+    prior: np.ndarray | None = None  # optional (n_obj*n_pre, 9) float32 per group:
+    #   mu_t (3), translation precision 1/sigma^2, mu_q (4, unit), kappa
 
     @property
     def n_obj(self) -> int:
@@ -270,29 +276,108 @@ def _rot_to_quat(Rm: np.ndarray) -> np.ndarray:
     return q if q[0] >= 0 else -q
 
 
-def fibonacci_poses(k: int, anchor: np.ndarray, tip: np.ndarray, dist: float) -> np.ndarray:
-    """k poses on a Fibonacci sphere around `anchor` (the paper initialises
-    with the Fibonacci sequence): direction u_j with z_j = 1 - (2j+1)/k and
-    azimuth j*pi*(3 - sqrt 5); the gripper's +z axis points back at the
-    anchor, roll fixed by a look-at frame, and the gripper-frame point `tip`
-    placed at distance `dist` from the anchor.  Returns (7, k) float32."""
-    out = np.zeros((7, k))
+def _look_at(u: np.ndarray, anchor: np.ndarray, tip: np.ndarray, dist: float,
+             roll: float = 0.0):
+    """Pose whose gripper +z axis points along -u (back at `anchor`), with the
+    gripper-frame point `tip` at `anchor + dist u`; the roll about +z is fixed
+    by a look-at frame (up = world z, or world y when the approach is nearly
+    vertical) and then turned by `roll`.  Returns (t, q) in float64."""
+    ez = -u
+    w = np.array([0.0, 0.0, 1.0]) if abs(ez[2]) <= 0.9 else np.array([0.0, 1.0, 0.0])
+    ex = np.cross(w, ez)
+    ex /= np.linalg.norm(ex)
+    ey = np.cross(ez, ex)
+    if roll != 0.0:
+        ex, ey = math.cos(roll) * ex + math.sin(roll) * ey, -math.sin(roll) * ex + math.cos(roll) * ey
+    Rm = np.stack([ex, ey, ez], axis=1)
+    return anchor + dist * u - Rm @ tip, _rot_to_quat(Rm)
+
+
+def _fibonacci_dirs(k: int) -> np.ndarray:
+    """Fibonacci sphere: z_j = 1 - (2j+1)/k, azimuth j*pi*(3 - sqrt 5)."""
     golden = math.pi * (3.0 - math.sqrt(5.0))
+    out = np.zeros((k, 3))
     for j in range(k):
         z = 1.0 - (2.0 * j + 1.0) / k
         r = math.sqrt(max(0.0, 1.0 - z * z))
-        u = np.array([r * math.cos(j * golden), r * math.sin(j * golden), z])
-        ez = -u
-        w = np.array([0.0, 0.0, 1.0]) if abs(ez[2]) <= 0.9 else np.array([0.0, 1.0, 0.0])
-        ex = np.cross(w, ez)
-        ex /= np.linalg.norm(ex)
-        ey = np.cross(ez, ex)
-        Rm = np.stack([ex, ey, ez], axis=1)
-        q = _rot_to_quat(Rm)
-        t = anchor + dist * u - Rm @ tip
+        out[j] = (r * math.cos(j * golden), r * math.sin(j * golden), z)
+    return out
+
+
+def _poses(dirs, anchor, tip, dist, rolls=None) -> np.ndarray:
+    out = np.zeros((7, len(dirs)))
+    for j, u in enumerate(dirs):
+        t, q = _look_at(np.asarray(u, np.float64), anchor, tip, dist, 0.0 if rolls is None else rolls[j])
         out[:3, j] = t
         out[3:, j] = q
     return out.astype(np.float32)
+
+
+def fibonacci_poses(k: int, anchor: np.ndarray, tip: np.ndarray, dist: float) -> np.ndarray:
+    """k poses on a Fibonacci sphere around `anchor` (the paper initialises
+    with the Fibonacci sequence, Sec. III-C): direction u_j, the gripper's +z
+    axis pointing back at the anchor and the gripper-frame point `tip` at
+    distance `dist` from the anchor.  Returns (7, k) float32."""
+    return _poses(_fibonacci_dirs(k), anchor, tip, dist)
+
+
+def quarter_sphere_dirs(k: int, arm=(-1.0, 0.0, 0.0)) -> np.ndarray:
+    """Exactly k Fibonacci directions on the quarter sphere that faces the
+    robot arm (Sec. V-A, Fig. 4(b)): above the table (u_z >= 0) and on the
+    arm's side (u . arm >= 0).  The Fibonacci count is the smallest whose
+    quarter holds k points."""
+    a = np.asarray(arm, np.float64)
+    a = a / np.linalg.norm(a)
+    for n in range(k, 16 * k + 64):
+        d = _fibonacci_dirs(n)
+        keep = d[(d[:, 2] >= 0.0) & (d @ a >= 0.0)]
+        if len(keep) == k:
+            return keep
+    raise ValueError(f"no Fibonacci count gives {k} quarter-sphere points")
+
+
+def top_poses(k: int, anchor: np.ndarray, tip: np.ndarray, dist: float) -> np.ndarray:
+    """k poses straight above the object (Sec. V-A adds six of them): gripper
+    +z pointing down, rolls j*pi/k, j < k (a parallel gripper repeats itself
+    after half a turn)."""
+    dirs = np.tile([0.0, 0.0, 1.0], (k, 1))
+    return _poses(dirs, anchor, tip, dist, [j * math.pi / k for j in range(k)])
+
+
+def tabletop_poses(k: int, anchor: np.ndarray, tip: np.ndarray, dist: float, n_top: int = 6,
+                   arm=(-1.0, 0.0, 0.0)) -> np.ndarray:
+    """The paper's simulation initialisation (Sec. V-A): k - n_top
+    quarter-sphere Fibonacci poses plus n_top poses from above."""
+    quarter = _poses(quarter_sphere_dirs(k - n_top, arm), anchor, tip, dist)
+    return np.concatenate([quarter, top_poses(n_top, anchor, tip, dist)], axis=1)
+
+
+def gmm_poses(k: int, anchor: np.ndarray, tip: np.ndarray, dist: float, means, sigma: float,
+              rng: np.random.Generator) -> np.ndarray:
+    """Initialisation from a mixture of Gaussians (Fig. 4(a), Sec. III-C):
+    approach directions drawn from equal-weight isotropic Gaussians of
+    standard deviation `sigma` around the unit directions `means`, projected
+    to the unit sphere; the gripper looks at the anchor from `dist`."""
+    mu = np.asarray(means, np.float64)
+    mu = mu / np.linalg.norm(mu, axis=1, keepdims=True)
+    comp = rng.integers(0, len(mu), k)
+    d = mu[comp] + sigma * rng.standard_normal((k, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    return _poses(d, anchor, tip, dist)
+
+
+def table_plane(obj: np.ndarray, spacing: float = 0.005, margin: float = 0.05) -> np.ndarray:
+    """Points of the supporting table (the collision cloud C holds the object
+    and the table, Sec. IV-A): a square grid at `spacing` (Table I's 5 mm
+    voxels) in the plane just below the object's lowest point, extending
+    `margin` beyond the object's footprint."""
+    o = obj.astype(np.float64)
+    lo, hi = o.min(0) - margin, o.max(0) + margin
+    xs = np.arange(lo[0], hi[0] + 1e-12, spacing)
+    ys = np.arange(lo[1], hi[1] + 1e-12, spacing)
+    X, Y = np.meshgrid(xs, ys, indexing="xy")
+    Z = np.full(X.shape, o[:, 2].min() - 0.002)
+    return np.stack([X.ravel(), Y.ravel(), Z.ravel()], 1).astype(np.float32)
 
 
 # ----------------------------------------------------------------------------
@@ -367,3 +452,89 @@ def workload_batched(n_obj: int = 64, K: int = 128, k_max: int = 100, m_lo: int 
     grids = [gripper_sdf_grid(g, grid_n, 0.0015) for g in gaps]
     pb = _assemble(objs, pre, grids, K, [standoff(o) for o in objs])
     return pb, Settings(k_max=k_max, k_stein=k_max)
+
+
+def random_poses(k: int, anchor: np.ndarray, radius: float, rng: np.random.Generator) -> np.ndarray:
+    """k poses with uniformly random rotations and the gripper origin
+    uniformly in a ball of `radius` around `anchor`.  Returns (7, k) float32."""
+    q = rng.standard_normal((k, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    q[q[:, 0] < 0] *= -1
+    u = _unit_vectors(rng, k) * (radius * rng.uniform(0, 1, (k, 1)) ** (1 / 3))
+    return np.concatenate([(anchor + u).T, q.T]).astype(np.float32)
+
+
+def workload_adjoint(n_obj: int = 16, K: int = 512, m: int = 4096, n: int = 4096, grid_n: int = 128,
+                     seed: int = 5, w_pen: float = 1.0):
+    """Cost-and-gradient workload: n_obj superquadrics of m points, one
+    preshape (finger gap 6 cm, n contact points, grid_n^3 SDF at 1.5 mm), K
+    particles per object at random poses near the object (some colliding,
+    some free)."""
+    rng = np.random.default_rng(seed)
+    objs = [superquadric(m, rng) for _ in range(n_obj)]
+    S = gripper_contact_cloud(0.06, n, np.random.default_rng((seed, 1)))
+    grid = gripper_sdf_grid(0.06, grid_n, 0.0015)
+    pb = _assemble(objs, [S], [grid], K, [0.1] * n_obj)
+    th = []
+    for o in objs:
+        c = o.astype(np.float64).mean(0)
+        rb = float(np.linalg.norm(o.astype(np.float64) - c, axis=1).max())
+        th.append(random_poses(K, c, rb + 0.03, rng))
+    pb.theta0 = np.ascontiguousarray(np.concatenate(th, 1))
+    return pb, Settings(k_max=1, k_stein=1, w_pen=w_pen)
+
+
+def grasp_prior(pb: Problem, sigma: float = 0.05, kappa: float = 2.0) -> np.ndarray:
+    """A prior per group (Sec. III-B names Gaussian translation and von Mises
+    rotation priors without parameters): the translation mean places the
+    contact cloud's centroid on the object's mean point from straight above,
+    the rotation mean points the gripper down; sigma in metres, kappa the
+    von Mises concentration."""
+    out = np.zeros((pb.n_obj * pb.n_pre, 9), np.float32)
+    for o in range(pb.n_obj):
+        anchor = pb.R[pb.r_off[o]:pb.r_off[o + 1]].astype(np.float64).mean(0)
+        for p in range(pb.n_pre):
+            tip = pb.S[pb.s_off[p]:pb.s_off[p + 1]].astype(np.float64).mean(0)
+            t, q = _look_at(np.array([0.0, 0.0, 1.0]), anchor, tip, 0.0)
+            out[o * pb.n_pre + p] = np.concatenate([t, [1.0 / sigma ** 2], q, [kappa]])
+    return out
+
+
+def workload_tabletop(n_pre: int = 10, K: int = 30, m: int = 800, n: int = 96, grid_n: int = 64,
+                      seed: int = 8, init: str = "quarter"):
+    """The paper's simulation set-up (Sec. V-A, Table I) at its own scale: a
+    superquadric of m points resting on a table; the collision cloud C is the
+    object plus a 5 mm table grid 2 cm beyond its footprint (about 1100-1900
+    points in all); n_pre preshapes of a parallel gripper with finger gaps
+    3-8 cm and n contact points each (5 mm spacing); per preshape K poses:
+    K - 6 quarter-sphere Fibonacci poses facing the arm plus 6 from above
+    (init="quarter"), or a mixture of four Gaussians around the up, arm-side
+    and two lateral directions (init="gmm"); Table I settings (15 Stein + 25
+    SGD iterations, cyclic annealing, mini-batch schedule)."""
+    rng = np.random.default_rng(seed)
+    obj = superquadric(m, rng, noise=0.001).astype(np.float64)
+    obj[:, 2] -= obj[:, 2].min()  # resting on the table plane z = -2 mm
+    obj = obj.astype(np.float32)
+    table = table_plane(obj, 0.005, 0.02)
+    gaps = np.linspace(0.03, 0.08, n_pre)
+    pre = [gripper_contact_cloud(float(g), n, np.random.default_rng((seed, i))) for i, g in enumerate(gaps)]
+    grids = [gripper_sdf_grid(float(g), grid_n, 0.002) for g in gaps]
+    anchor = obj.astype(np.float64).mean(0)
+    dist = standoff(obj)
+    th = []
+    for i, s in enumerate(pre):
+        tip = s.astype(np.float64).mean(0)
+        if init == "quarter":
+            th.append(tabletop_poses(K, anchor, tip, dist))
+        elif init == "gmm":
+            means = [(0.0, 0.0, 1.0), (-1.0, 0.0, 0.3), (0.0, 1.0, 0.3), (0.0, -1.0, 0.3)]
+            th.append(gmm_poses(K, anchor, tip, dist, means, 0.25, np.random.default_rng((seed, 100 + i))))
+        else:
+            raise ValueError(init)
+    C = np.ascontiguousarray(np.concatenate([obj, table]).astype(np.float32))
+    pb = Problem(R=np.ascontiguousarray(obj), r_off=np.array([0, len(obj)], np.int32),
+                 C=C, c_off=np.array([0, len(C)], np.int32),
+                 S=np.ascontiguousarray(np.concatenate(pre).astype(np.float32)),
+                 s_off=np.cumsum([0] + [len(s) for s in pre]).astype(np.int32),
+                 grids=grids, theta0=np.ascontiguousarray(np.concatenate(th, 1)), K=K)
+    return pb, paper_settings()

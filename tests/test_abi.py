@@ -48,6 +48,9 @@ def test_workspace_bytes_grows_with_problem_and_debug():
     n1 = A.asicp_workspace_bytes(p, A.make_config(st, A.ASICP_FLAG_DEBUG))
     assert 0 < n0 < n1
     assert n1 - n0 >= 4 * pb.k_tot * (512 + 1024)  # per-point NN records
+    st.minibatch = 1
+    n2 = A.asicp_workspace_bytes(p, A.make_config(st))
+    assert n2 - n0 >= 16 * 1024 + 1024  # masked operand copy and batch marks
 
 
 @pytest.mark.parametrize("mutate, needle", [
@@ -61,6 +64,7 @@ def test_workspace_bytes_grows_with_problem_and_debug():
     (lambda p, c: setattr(c, "bw_mode", 2), "bandwidth"),
     (lambda p, c: setattr(c, "h_min", 0.0), "h_min"),
     (lambda p, c: setattr(c, "flags", 64), "flag"),
+    (lambda p, c: setattr(c, "minibatch", 2), "minibatch"),
     (lambda p, c: setattr(p, "particles_per_group", 0), "particles_per_group"),
     (lambda p, c: setattr(p, "particles_per_group", 2048), "particles_per_group"),
     (lambda p, c: setattr(p, "n_objects", 0), "n_objects"),
@@ -133,3 +137,21 @@ def test_product_path_has_no_oracle_dependency():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "asicp_oracle" not in text, f
                 assert "from oracle" not in text, f
+
+
+@pytest.mark.parametrize("col, value", [(3, -1.0), (8, -0.5), (4, 2.0), (0, float("nan"))])
+def test_bad_prior_rejected_on_host(col, value):
+    pb, st = synth.workload_small()
+    p, keep = host_problem(pb)
+    pr = synth.grasp_prior(pb)
+    cfg = A.make_config(st)
+    p.prior = pr.ctypes.data
+    n_ok = A.asicp_workspace_bytes(p, cfg)
+    p.prior = None
+    assert n_ok > A.asicp_workspace_bytes(p, cfg)  # room for the per-group prior
+    bad = pr.copy()
+    bad[0, col] = value
+    p.prior = bad.ctypes.data
+    with pytest.raises(A.AsicpError) as e:
+        A.asicp_workspace_bytes(p, cfg)
+    assert e.value.status == A.ASICP_E_INVALID and "prior" in str(e.value)

@@ -106,14 +106,19 @@ def compare_step(pb, st, theta, k, prev_cost=None, converged=None, label=""):
         ex_t = np.zeros(pb.k_tot)
         ex_w = np.zeros(pb.k_tot)
         gam, tau = oracle.schedule(st, k)
+        # driving gradient: the cost gradient minus the log-prior gradient
+        gdrive = r["g_fin"].copy()
+        if getattr(pb, "prior", None) is not None:
+            for i in range(pb.k_tot):
+                gdrive[i] -= oracle.log_prior(pb.prior[i // pb.K].astype(np.float64), th64[:, i])[1]
         for gi in range(pb.n_obj * pb.n_pre):
             p = gi % pb.n_pre
             sl = slice(gi * pb.K, (gi + 1) * pb.K)
             aos = th64[:, sl].T
-            _, kmat = oracle.svgd_direction(aos, r["g_fin"][sl], r["h"][gi], gam, tau,
+            _, kmat = oracle.svgd_direction(aos, gdrive[sl], r["h"][gi], gam, tau,
                                             setup["a_t"][p], setup["a_w"][p], st.kernel_mode)
-            gt = np.abs(r["g_fin"][sl, :3]).max(1)
-            gw = np.abs(r["g_fin"][sl, 3:]).max(1)
+            gt = np.abs(gdrive[sl, :3]).max(1)
+            gw = np.abs(gdrive[sl, 3:]).max(1)
             dt = np.abs(aos[:, None, :3] - aos[None, :, :3]).max(-1)
             ph_t[sl] = (kmat * (gam * setup["a_t"][p] * gt[None, :] + tau * dt)).mean(1)
             ph_w[sl] = (kmat * (gam * setup["a_w"][p] * gw[None, :]) + tau).mean(1)
@@ -197,6 +202,42 @@ def test_paper_preset_sgd_phase_with_collisions():
     assert total_col > 1000  # the collision branch was exercised
 
 
+@pytest.mark.parametrize("init", ["quarter", "gmm"])
+def test_tabletop_paper_setup(init):
+    """Sec. V-A set-up: collision cloud = object + table (C differs from R),
+    10 preshapes of 96 points, 30 poses each, Table I schedule with the
+    mini-batch."""
+    pb, st = synth.workload_tabletop(init=init)
+    ks = [0, 9, 15, 27, 39]
+    snaps = oracle_trajectory(pb, st, ks)
+    total_col = 0
+    for k in ks:
+        th, pc, cv = snaps[k]
+        out = compare_step(pb, st, th, k, pc, cv, label=f"tabletop {init}")
+        total_col += out["ncol"]
+        say("[parity] tabletop", init, "k", k, out)
+    assert total_col > 0
+
+
+def test_priors_in_the_stein_update():
+    """Gaussian translation and von Mises rotation priors (eq. 8) on the
+    small workload and the tabletop set-up (Stein phase and SGD phase)."""
+    pb, st = synth.workload_small()
+    pb.prior = synth.grasp_prior(pb, sigma=0.05, kappa=2.0)
+    ks = [0, 5, 17]
+    snaps = oracle_trajectory(pb, st, ks)
+    for k in ks:
+        th, pc, cv = snaps[k]
+        say("[parity] prior small k", k, compare_step(pb, st, th, k, pc, cv, label="prior small"))
+    pb, st = synth.workload_tabletop()
+    pb.prior = synth.grasp_prior(pb, sigma=0.03, kappa=5.0)
+    ks = [1, 14, 20]
+    snaps = oracle_trajectory(pb, st, ks)
+    for k in ks:
+        th, pc, cv = snaps[k]
+        say("[parity] prior tabletop k", k, compare_step(pb, st, th, k, pc, cv, label="prior tabletop"))
+
+
 def test_block_kernel_identity_preconditioner_fixed_bandwidth():
     pb, st = synth.workload_small()
     st.kernel_mode = synth.KERNEL_BLOCK
@@ -223,6 +264,18 @@ def test_paper_scale_step_full_size():
     out = compare_step(pb, st, pulled_in(pb, 0.75), 50, label="paper scale pulled in")
     say("[parity] paper scale pulled in", out)
     assert out["ncol"] > 0
+
+
+def test_paper_scale_minibatch_steps():
+    """Table I mini-batch at full size: both sides draw the same batch of the
+    8192-point cloud (keyed permutation), so the nearest neighbours agree."""
+    pb, _ = synth.workload_paper_scale()
+    st = synth.paper_settings(k_max=100, k_stein=100, seed=21)
+    for k in (1, 30):
+        out = compare_step(pb, st, pb.theta0, k, label="paper scale mini-batch")
+        say("[parity] paper scale mini-batch k", k, out)
+    out = compare_step(pb, st, pulled_in(pb, 0.75), 45, label="paper scale mini-batch pulled in")
+    say("[parity] paper scale mini-batch pulled in", out)
 
 
 def test_pruned_and_brute_force_nn_agree():
@@ -310,6 +363,38 @@ def test_determinism_and_resume():
     s.close()
     assert np.array_equal(res["theta"], runs[0]["theta"])
     assert np.array_equal(res["best_particle"], runs[0]["best_particle"])
+
+
+def test_graph_replay_matches_solve():
+    """asicp_replay (whole solve as one captured HIP graph) gives bitwise the
+    result of asicp_solve, on every replay, also after the initial particles
+    are rewritten in place."""
+    A, torch = _gpu()
+    pb, st = synth.workload_small(k_max=8)
+    ref = A.Solver(pb, st)
+    ref.solve()
+    r0 = ref.result()
+    ref.close()
+    g = A.Solver(pb, st)
+    for _ in range(3):
+        g.replay()
+        torch.cuda.synchronize()  # eager work between replays
+        r = g.result()
+        assert np.array_equal(r["theta"], r0["theta"]) and np.array_equal(r["cost"], r0["cost"])
+        assert np.array_equal(r["best_particle"], r0["best_particle"])
+    # new initial particles written into the borrowed buffer
+    th2 = pb.theta0.copy()
+    th2[:3] += np.float32(0.003)
+    g._keep["theta0"].copy_(torch.as_tensor(th2))
+    g.replay()
+    r2 = g.result()
+    g.close()
+    ref2 = A.Solver(pb, st, theta0=th2)
+    ref2.solve()
+    e2 = ref2.result()
+    ref2.close()
+    assert np.array_equal(r2["theta"], e2["theta"])
+    assert not np.array_equal(r2["theta"], r0["theta"])
 
 
 def test_free_running_solve_small():

@@ -555,3 +555,248 @@ def test_contact_cloud_on_inner_faces():
     assert np.allclose(synth.box_union_sdf(S, boxes), 0.0, atol=1e-7)
     on_finger = np.isclose(np.abs(S[:, 0]), 0.03)
     assert 180 < on_finger.sum() < 290  # two fingers, about 116 points each
+
+
+# ---------------------------------------------------------------------------
+# optional SDF penetration term (adjoint extension)
+# ---------------------------------------------------------------------------
+
+def test_trilinear_gradient_matches_finite_differences():
+    g = synth.gripper_sdf_grid(0.06, 40, 0.003)
+    vals = g.values.astype(np.float64)
+    rng = np.random.default_rng(31)
+    h = 1e-7
+    for _ in range(100):
+        p = rng.uniform(-0.04, 0.04, 3) + [0, 0, 0.025]
+        v, ins, grad = oracle.sdf_trilinear_grad(vals, g.origin, g.cell, p)
+        assert ins
+        for a in range(3):
+            e = np.zeros(3)
+            e[a] = h
+            fd = (oracle.sdf_trilinear(vals, g.origin, g.cell, p + e)[0] -
+                  oracle.sdf_trilinear(vals, g.origin, g.cell, p - e)[0]) / (2 * h)
+            assert abs(fd - grad[a]) < 1e-6 * max(1.0, abs(grad[a]))
+    # an affine field has the constant gradient
+    n = (5, 6, 7)
+    origin = np.array([-0.1, 0.2, 0.05])
+    a_vec = np.array([0.3, -1.2, 2.5])
+    zz, yy, xx = np.meshgrid(np.arange(n[2]), np.arange(n[1]), np.arange(n[0]), indexing="ij")
+    grid = (np.stack([xx, yy, zz], -1) * 0.01 + origin) @ a_vec
+    _, ins, grad = oracle.sdf_trilinear_grad(grid, origin, 0.01, origin + [0.013, 0.021, 0.034])
+    assert ins and np.allclose(grad, a_vec, atol=1e-12)
+
+
+@pytest.mark.parametrize("lam", [1.0, 0.0])
+def test_penetration_gradient_is_finite_difference_of_cost(lam):
+    # particles whose gripper cuts into the object cloud; with w_pen > 0 the
+    # cost includes w_pen/Mc sum phi^2 over colliding points and g_ct its gradient
+    rng = np.random.default_rng(41)
+    obj = rng.uniform(-0.02, 0.02, (400, 3))
+    pb, st = tiny_problem(seed=9, R=obj, K=3, lam=lam)
+    pb.theta0[:, :] = 0
+    pb.theta0[3, :] = 1
+    pb.theta0[:3, 0] = [0.0, 0.0, -0.012]
+    pb.theta0[:3, 1] = [0.008, 0.004, -0.02]
+    pb.theta0[:3, 2] = [-0.004, 0.002, -0.016]
+    st.w_pen = 3.0
+    o = oracle.Oracle(pb, st)
+    base = o.evaluate(pb.theta0)
+    assert (base["pen"] > 0).all()
+    h = 1e-7  # a collision point this close to a cell face is rare; see below
+    checked = 0
+    for i in range(pb.k_tot):
+        for ax in range(6):
+            ep = o.evaluate(perturb(pb.theta0, i, ax, h))
+            em = o.evaluate(perturb(pb.theta0, i, ax, -h))
+            if not all(np.array_equal(e[k][i], base[k][i]) for e in (ep, em) for k in ("nn_idx", "gate")):
+                continue
+            # the interpolant is continuous but its slope jumps at cell faces: a
+            # collision point within h of a face makes the central difference
+            # the mean of two slopes, so the one-sided difference on the
+            # point's own side must then match
+            c0 = base["cost"][i]
+            fds = ((ep["cost"][i] - em["cost"][i]) / (2 * h), (ep["cost"][i] - c0) / h, (c0 - em["cost"][i]) / h)
+            g = base["g_ct"][i, ax]
+            tol = 2e-6 * max(1e-3, abs(g))
+            assert min(abs(fd - g) for fd in fds) <= tol, (i, ax, fds, g)
+            checked += 1
+    assert checked >= 12
+    # w_pen = 0 gives back the plain cost
+    st.w_pen = 0.0
+    plain = oracle.Oracle(pb, st).evaluate(pb.theta0)
+    assert np.allclose(base["cost"] - base["pen"], plain["cost"], rtol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# mini-batch of the object cloud (Algorithm 1; size schedule of Table I)
+# ---------------------------------------------------------------------------
+
+def test_splitmix64_published_sequence():
+    # first three outputs of SplitMix64 (Steele, Lea and Flood, 2014) from
+    # state 0: the generator adds the golden-gamma increment, then mixes
+    gamma = 0x9E3779B97F4A7C15
+    expect = [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+    for i, e in enumerate(expect):
+        assert oracle.splitmix64((i * gamma) & 0xFFFFFFFFFFFFFFFF) == e
+
+
+@pytest.mark.parametrize("M", [1, 2, 3, 5, 16, 17, 100, 1000, 4097])
+def test_batch_permutation_is_bijection(M):
+    for key in (0, 1, 0xDEADBEEF12345678):
+        img = [oracle.batch_perm(j, M, key) for j in range(M)]
+        assert sorted(img) == list(range(M))
+
+
+def test_batch_permutation_depends_on_key():
+    M = 1000
+    a = [oracle.batch_perm(j, M, 1) for j in range(M)]
+    b = [oracle.batch_perm(j, M, 2) for j in range(M)]
+    assert a != list(range(M)) and a != b
+    # a prefix of a random permutation: each point lands in the first half
+    # about half the time over many keys (binomial, 400 draws, 5 sigma)
+    hits = np.zeros(M)
+    for key in range(400):
+        for j in range(M // 2):
+            hits[oracle.batch_perm(j, M, key * 7919 + 3)] += 1
+    assert np.all(np.abs(hits - 200) < 5 * 10)
+
+
+def test_batch_size_follows_table1():
+    # Table I: the batch grows linearly with k to the whole cloud at 2 k_max / 3
+    st = synth.paper_settings(k_max=30)
+    M = 1000
+    sizes = [oracle.batch_size(st, k, M) for k in range(31)]
+    assert sizes[0] == 1                       # never empty
+    assert sizes[10] == 500                    # half-way to 2 k_max / 3 = 20
+    assert sizes[5] == 250 and sizes[15] == 750
+    assert all(s == M for s in sizes[20:])
+    assert all(b >= a for a, b in zip(sizes, sizes[1:]))
+    st0 = synth.paper_settings(k_max=30, minibatch=0)
+    assert all(oracle.batch_size(st0, k, M) == M for k in range(31))
+
+
+def test_minibatch_nn_is_brute_force_over_the_batch(small_workload):
+    pb, _ = small_workload
+    st = synth.paper_settings(k_max=30, seed=11)
+    o = oracle.Oracle(pb, st)
+    M = pb.r_off[1] - pb.r_off[0]
+    R = pb.R.astype(np.float64)
+    S = pb.S.astype(np.float64)
+    for k in (0, 3, 10):
+        mb = oracle.batch_size(st, k, M)
+        key = oracle.batch_key(st, k, 0)
+        batch = np.array(sorted(oracle.batch_perm(j, M, key) for j in range(mb)))
+        r = o.evaluate(pb.theta0, full=True, k=k)
+        for i in range(0, pb.k_tot, 7):
+            q = pb.theta0[3:, i].astype(np.float64)
+            Sp = S @ oracle.quat_to_rot(q).T + pb.theta0[:3, i]
+            D = ((Sp[:, None, :] - R[None, batch, :]) ** 2).sum(-1)
+            want = batch[np.argmin(D, axis=1)]
+            got = r["nn_idx"][i, :len(S)]
+            ok = got == want
+            # an FP64 near-tie may resolve either way: accept equal distances
+            dg = ((Sp - R[got]) ** 2).sum(-1)
+            dw = ((Sp - R[want]) ** 2).sum(-1)
+            assert np.all(ok | (np.abs(dg - dw) <= 1e-15))
+            assert np.all(np.isin(got, batch))
+
+
+def test_minibatch_full_size_equals_whole_cloud(small_workload):
+    pb, _ = small_workload
+    st = synth.paper_settings(k_max=30, seed=3)
+    st0 = synth.paper_settings(k_max=30, minibatch=0)
+    a = oracle.Oracle(pb, st).evaluate(pb.theta0, full=True, k=20)
+    b = oracle.Oracle(pb, st0).evaluate(pb.theta0, full=True, k=20)
+    assert np.array_equal(a["nn_idx"], b["nn_idx"])
+    assert np.array_equal(a["cost"], b["cost"])
+    # different iterations draw different batches
+    c1 = oracle.Oracle(pb, st).evaluate(pb.theta0, full=True, k=4)
+    c2 = oracle.Oracle(pb, st).evaluate(pb.theta0, full=True, k=5)
+    assert not np.array_equal(c1["nn_idx"], c2["nn_idx"])
+
+
+# ---------------------------------------------------------------------------
+# priors (Sec. III-B: Gaussian in translation, von Mises in rotation)
+# ---------------------------------------------------------------------------
+
+def axis_angle_quat(v):
+    th = np.linalg.norm(v)
+    if th == 0:
+        return np.array([1.0, 0, 0, 0])
+    return np.concatenate([[math.cos(th / 2)], math.sin(th / 2) * v / th])
+
+
+def prior_case(rng):
+    vm, vq = rng.uniform(-2, 2, 3), rng.uniform(-2, 2, 3)
+    mu_t, t = rng.uniform(-0.05, 0.05, 3), rng.uniform(-0.05, 0.05, 3)
+    w, kappa = float(rng.uniform(10, 500)), float(rng.uniform(0.5, 5))
+    prior = np.concatenate([mu_t, [w], axis_angle_quat(vm), [kappa]])
+    return prior, vm, vq, mu_t, t, w, kappa
+
+
+def test_log_prior_gradient_is_finite_difference():
+    # test-side log density from Rodrigues matrices: -w/2 |t - mu|^2 + kappa tr(M^T R)
+    rng = np.random.default_rng(71)
+    for _ in range(10):
+        prior, vm, vq, mu_t, t, w, kappa = prior_case(rng)
+        M = rodrigues(vm)
+
+        def lp(tt, Rr):
+            return -0.5 * w * np.sum((tt - mu_t) ** 2) + kappa * np.trace(M.T @ Rr)
+
+        Rq = rodrigues(vq)
+        val, g = oracle.log_prior(prior, np.concatenate([t, axis_angle_quat(vq)]))
+        h = 1e-6
+        for a in range(3):
+            e = np.zeros(3)
+            e[a] = h
+            fd_t = (lp(t + e, Rq) - lp(t - e, Rq)) / (2 * h)
+            fd_w = (lp(t, rodrigues(e) @ Rq) - lp(t, rodrigues(-e) @ Rq)) / (2 * h)
+            assert g[a] == pytest.approx(fd_t, rel=1e-7, abs=1e-7)
+            assert g[3 + a] == pytest.approx(fd_w, rel=1e-6, abs=1e-7)
+        # values agree up to the constant: compare two poses
+        val2, _ = oracle.log_prior(prior, np.concatenate([mu_t, axis_angle_quat(vm)]))
+        assert val2 - val == pytest.approx(lp(mu_t, M) - lp(t, Rq), rel=1e-12, abs=1e-12)
+
+
+def test_log_prior_mode_and_double_cover():
+    rng = np.random.default_rng(72)
+    prior, vm, vq, mu_t, t, w, kappa = prior_case(rng)
+    val, g = oracle.log_prior(prior, np.concatenate([mu_t, axis_angle_quat(vm)]))
+    assert np.allclose(g, 0, atol=1e-12) and val == pytest.approx(3 * kappa, rel=1e-12)
+    th = np.concatenate([t, axis_angle_quat(vq)])
+    th_neg = np.concatenate([t, -axis_angle_quat(vq)])
+    a, b = oracle.log_prior(prior, th), oracle.log_prior(prior, th_neg)
+    assert a[0] == pytest.approx(b[0], rel=1e-14) and np.allclose(a[1], b[1], atol=1e-13)
+    # a half turn away from the mean is a minimum of the rotation part
+    ax = rng.standard_normal(3)
+    ax *= math.pi / np.linalg.norm(ax)
+    q_far = qmul_np(axis_angle_quat(ax), axis_angle_quat(vm))
+    v, g = oracle.log_prior(prior, np.concatenate([mu_t, q_far]))
+    assert np.allclose(g[3:], 0, atol=1e-12) and v == pytest.approx(-kappa, rel=1e-12)
+
+
+def test_prior_enters_the_stein_driving_term():
+    # K = 1, tau = 0: phi = -gamma A (g - grad log p); with the prior the
+    # direction moves by exactly gamma A grad log p (eq. 8)
+    pb, st = tiny_problem(seed=13, K=1)
+    th = pb.theta0.astype(np.float64)
+    th[3:] /= np.linalg.norm(th[3:], axis=0)
+    st.T0 = st.T1 = 1e-300
+    rng = np.random.default_rng(5)
+    prior, *_ = prior_case(rng)
+    base = oracle.Oracle(pb, st).step(0, th)
+    pb.prior = prior[None, :].astype(np.float32)
+    o = oracle.Oracle(pb, st)
+    withp = o.step(0, th)
+    setup = o.setup()
+    _, gp = oracle.log_prior(pb.prior[0].astype(np.float64), th[:, 0])
+    A = np.array([setup["a_t"][0]] * 3 + [setup["a_w"][0]] * 3)
+    assert np.allclose(withp["phi"][0] - base["phi"][0], A * gp, rtol=1e-12, atol=1e-15)
+    # the SGD phase (eq. 3) has no prior
+    st2 = synth.Settings(**{**st.__dict__, "k_stein": 0})
+    pb.prior = None
+    a = oracle.Oracle(pb, st2).step(0, th)
+    pb.prior = prior[None, :].astype(np.float32)
+    b = oracle.Oracle(pb, st2).step(0, th)
+    assert np.array_equal(a["theta"], b["theta"])
