@@ -105,9 +105,12 @@ typedef struct {
                                   (>= 0), mean rotation mu_q[4] (w, x, y, z; unit
                                   within 1e-3, normalised on use), von Mises
                                   concentration kappa (>= 0).  Log prior
-                                  -w_t/2 |t - mu_t|^2 + kappa tr(R(mu_q)^T R(q)); its
-                                  gradient joins the Stein driving term only (the SGD
-                                  phase of eq. (3) has none).  Copied during create. */
+                                  -w_t/2 |t - mu_t|^2 + kappa tr(R(mu_q)^T R(q)), in the
+                                  cost's units (m^2): the cost stands for a likelihood
+                                  variance times a negative log likelihood, so w_t and
+                                  kappa carry that variance.  The prior's gradient joins
+                                  the Stein driving term only (the SGD phase of eq. (3)
+                                  has none).  Copied during create. */
 } asicp_problem;
 
 /* Iteration settings.  Table I of the paper: k_max 40, k_stein 15, cyclic

@@ -21,6 +21,16 @@ constexpr int kTileGroup = 64;     // points per MFMA-ready tile group (4 tiles 
 #ifndef ASICP_NN_SPLIT
 #define ASICP_NN_SPLIT 0
 #endif
+// How the pruned scan skips a query block for a candidate chunk it cannot
+// improve: 0 never skips, 1 tests the chunk's bound per block (vector
+// compare), 2 tests a bit of the block's wave-uniform candidate mask.
+#ifndef ASICP_NN_NEED
+#define ASICP_NN_NEED 2
+#endif
+// Candidate chunks compared between refreshes of the pruning bound.
+#ifndef ASICP_NN_REFRESH
+#define ASICP_NN_REFRESH 4
+#endif
 constexpr int kNnQ = ASICP_NN_Q;
 constexpr int kQueriesPerWave = 16 * kNnQ;
 constexpr int kGateChunk = 2048;   // collision points per gate workgroup (8 per thread)

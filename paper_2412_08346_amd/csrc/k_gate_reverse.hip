@@ -114,8 +114,8 @@ __device__ __forceinline__ void rev_scan(const Dev& d, const PreInfo& pi, const 
     snorm[q] = x * x + y * y + z * z;
     vq[q] = 16;
   }
-  nn_scan_pruned<Q>(d.pre_prep + (size_t)pi.prep_tg_begin * 64, pi.ntg, pi.n,
-                    d.pre_box + (size_t)pi.prep_tg_begin / kChunkTG * 8, bq, snorm, vq, idx,
+  nn_scan_pruned<Q, false>(d.pre_prep + (size_t)pi.prep_tg_begin * 64, pi.ntg, pi.n,
+                    d.pre_box + (size_t)pi.prep_tg_begin / kChunkTG * 8, bq, snorm, nullptr, vq, idx,
                     d.flags + 1);
 }
 

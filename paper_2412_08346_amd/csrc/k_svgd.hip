@@ -29,7 +29,8 @@ __device__ __forceinline__ float d2_of(const float* st, int i, int j) {
 // One radix pass over the K x K ordered pairs (i != j: every unordered pair
 // twice) of group blockIdx.y, sliced over gridDim.x workgroups.  Each
 // workgroup builds a digit histogram of the pairs matching the current prefix
-// in LDS (one atomic per distinct digit of a wave), adds it into the group's
+// in LDS (in the first pass one atomic per distinct digit of a wave, later one
+// per pair), adds it into the group's
 // global histogram, and the last workgroup to finish picks the digit holding
 // the target rank, clears the histogram and, after the last pass, writes h.
 __global__ __launch_bounds__(256) void k_bw_pass(Dev d, int pass, float inv_log_k) {
@@ -63,14 +64,20 @@ __global__ __launch_bounds__(256) void k_bw_pass(Dev d, int pass, float inv_log_
         dig = (bits >> shift) & 255u;
       }
     }
-    unsigned long long pending = __ballot(act);
-    while (pending) {
-      const int leader = __ffsll((long long)pending) - 1;
-      const unsigned int b = __shfl(dig, leader, 64);
-      const unsigned long long same = __ballot(act && dig == b);
-      if (lane == leader) atomicAdd(&hist[b], (unsigned int)__popcll(same));
-      if (act && dig == b) act = false;
-      pending &= ~same;
+    if (pass == 0) {
+      // sign and exponent bits: few distinct digits per wave, one atomic each
+      unsigned long long pending = __ballot(act);
+      while (pending) {
+        const int leader = __ffsll((long long)pending) - 1;
+        const unsigned int b = __shfl(dig, leader, 64);
+        const unsigned long long same = __ballot(act && dig == b);
+        if (lane == leader) atomicAdd(&hist[b], (unsigned int)__popcll(same));
+        if (act && dig == b) act = false;
+        pending &= ~same;
+      }
+    } else if (act) {
+      // mantissa digits are spread out: plain LDS atomics rarely collide
+      atomicAdd(&hist[dig], 1u);
     }
   }
   __syncthreads();

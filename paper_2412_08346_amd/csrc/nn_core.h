@@ -28,6 +28,36 @@ __device__ __forceinline__ void prep_store(float* prep_f, int m, float ax, float
   base[(3 * 16 + i) * 4] = an;
 }
 
+// The prepared cloud as a raw buffer (gfx9 resource word 3 = 0x00020000):
+// a tile group is read with a wave-uniform byte offset (scalar register) and
+// the lane's 16-byte offset (vector register), the hardware's own address
+// form, so no per-lane address arithmetic is spent in the scan loops.  The
+// buffer's size bounds every read (out-of-range lanes would read zeros).
+// The cloud is the same for the whole wavefront; reading the pointer and size
+// from the first lane puts the resource in scalar registers.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t cloud_rsrc(const float4* __restrict__ prep, int ntg) {
+  const unsigned long long a = reinterpret_cast<unsigned long long>(prep);
+  const unsigned long long lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)a);
+  const unsigned long long hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(a >> 32));
+  void* base = reinterpret_cast<void*>((hi << 32) | lo);
+  return __builtin_amdgcn_make_buffer_rsrc(base, (short)0, __builtin_amdgcn_readfirstlane(ntg) * 1024,
+                                           0x00020000);
+}
+
+__device__ __forceinline__ float2 load_f2(__amdgpu_buffer_rsrc_t r, unsigned byte_off) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, byte_off, 0, 0);
+  float2 f;
+  __builtin_memcpy(&f, &v, 8);
+  return f;
+}
+
+__device__ __forceinline__ float4 load_tg(__amdgpu_buffer_rsrc_t r, int tg, unsigned lane_off) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, lane_off, tg * 1024, 0);
+  float4 f;
+  __builtin_memcpy(&f, &v, 16);
+  return f;
+}
+
 // Chunk = 2 tile groups = 128 points; prepared clouds are padded to a whole
 // number of chunk pairs (256 points) so the main loop runs without a tail.
 constexpr int kChunkTG = 2;
@@ -81,13 +111,23 @@ __device__ __forceinline__ void chunk_step(const float4& a0, const float4& a1, c
 // Re-find the index of each query's minimum.  Each lane group owns rows
 // 4*grp .. 4*grp+3 of every 16-point tile and knows its minimum and the chunk
 // where its running minimum last decreased.  Among the lane groups reaching
-// the query's minimum, the one with the lowest such chunk is chosen; the four
-// lanes of the query split that chunk's 8 tiles and recompute candidate
-// values with the exact fused multiply-add chain the MFMA performs, returning
-// the lowest index in the chunk holding the minimal value.
-template <int Q>
-__device__ __forceinline__ void nn_rescan(const float4* __restrict__ prep, const float* b,
-                                          const float* best, const int* bch, int* idx, int32_t* miss) {
+// the query's minimum, the one with the lowest such chunk is chosen, and the
+// lowest index in that chunk holding the minimal value is returned; candidate
+// values are recomputed with the exact fused multiply-add chain the MFMA
+// performs.
+//
+// With BATCH, when one lane group wins (the usual case), the query's four
+// lanes test that group's 4 rows in all 8 tiles of the chunk: lane group g
+// takes tile group g/2 and its sub-tiles 2(g%2) and 2(g%2)+1, whose values
+// are adjacent in the prepared cloud, so 16 eight-byte buffer loads with
+// immediate offsets fetch all 32 operands at once; qc holds the lane's query
+// (x, y, z per block) from the caller.  Otherwise (or on ties between lane
+// groups, which test all 16 rows) the lanes split the 8 tiles and test row
+// by row, reading the query from the B operand.
+template <int Q, bool BATCH>
+__device__ __forceinline__ void nn_rescan(const float4* __restrict__ prep, __amdgpu_buffer_rsrc_t rs,
+                                          const float* b, const float* qc, const float* best,
+                                          const int* bch, int* idx, int32_t* miss) {
   const int lane = threadIdx.x & 63;
   const int grp = lane >> 4;
   const float* pf = reinterpret_cast<const float*>(prep);
@@ -100,25 +140,52 @@ __device__ __forceinline__ void nn_rescan(const float4* __restrict__ prep, const
     const bool mine = (v == vmin) && (bch[q] == cmin);
     const int gw = rows_min_i(mine ? grp : 4);
     const int ng = rows_sum_i(mine ? 1 : 0);
-    const float s0 = __shfl(b[q], j, 64);
-    const float s1 = __shfl(b[q], j + 16, 64);
-    const float s2 = __shfl(b[q], j + 32, 64);
-    const float s3 = __shfl(b[q], j + 48, 64);
-    // rows to test: the winning group's 4 rows, or all 16 if groups tie
-    const int r0 = (ng > 1) ? 0 : 4 * gw, r1 = (ng > 1) ? 16 : 4 * gw + 4;
     int cand = 0x7fffffff;
     if (cmin != 0x7fffffff) {
-      for (int tt = 0; tt < 2 && cand == 0x7fffffff; ++tt) {
-        const int t = grp + 4 * tt;  // tile within the chunk: tile group t/4, sub-tile t%4
-        const float* base = pf + (size_t)(cmin * kChunkTG + (t >> 2)) * 256 + (t & 3);
-        for (int i = r0; i < r1; ++i) {
-          float acc = __builtin_fmaf(base[(0 * 16 + i) * 4], s0, 0.0f);
-          acc = __builtin_fmaf(base[(1 * 16 + i) * 4], s1, acc);
-          acc = __builtin_fmaf(base[(2 * 16 + i) * 4], s2, acc);
-          acc = __builtin_fmaf(base[(3 * 16 + i) * 4], s3, acc);
-          if (acc == vmin) {
-            cand = ((cmin * kChunkTG + (t >> 2)) * 4 + (t & 3)) * 16 + i;
-            break;
+      if (BATCH && ng == 1) {
+        const float s0 = qc[3 * q], s1 = qc[3 * q + 1], s2 = qc[3 * q + 2];
+        const int tgi = grp >> 1, u0 = (grp & 1) * 2, r0 = 4 * gw;
+        const unsigned voff = 4u * (unsigned)((cmin * kChunkTG + tgi) * 256 + r0 * 4 + u0);
+        float2 a[4][4];  // [component][row]: sub-tiles u0 and u0 + 1
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+          for (int ii = 0; ii < 4; ++ii) a[k][ii] = load_f2(rs, voff + 16u * (unsigned)(k * 16 + ii));
+        const int tbase = ((cmin * kChunkTG + tgi) * 4 + u0) * 16 + r0;
+#pragma unroll
+        for (int ii = 3; ii >= 0; --ii) {  // the lowest index is tested last, so it wins
+          float acc = __builtin_fmaf(a[0][ii].y, s0, 0.0f);
+          acc = __builtin_fmaf(a[1][ii].y, s1, acc);
+          acc = __builtin_fmaf(a[2][ii].y, s2, acc);
+          acc = __builtin_fmaf(a[3][ii].y, 1.0f, acc);
+          if (acc == vmin) cand = tbase + 16 + ii;
+        }
+#pragma unroll
+        for (int ii = 3; ii >= 0; --ii) {
+          float acc = __builtin_fmaf(a[0][ii].x, s0, 0.0f);
+          acc = __builtin_fmaf(a[1][ii].x, s1, acc);
+          acc = __builtin_fmaf(a[2][ii].x, s2, acc);
+          acc = __builtin_fmaf(a[3][ii].x, 1.0f, acc);
+          if (acc == vmin) cand = tbase + ii;
+        }
+      } else {
+        const float s0 = __shfl(b[q], j, 64);
+        const float s1 = __shfl(b[q], j + 16, 64);
+        const float s2 = __shfl(b[q], j + 32, 64);
+        const float s3 = __shfl(b[q], j + 48, 64);
+        const int r0 = (ng > 1) ? 0 : 4 * gw, r1 = (ng > 1) ? 16 : 4 * gw + 4;
+        for (int tt = 0; tt < 2 && cand == 0x7fffffff; ++tt) {
+          const int t = grp + 4 * tt;  // tile within the chunk: tile group t/4, sub-tile t%4
+          const float* base = pf + (size_t)(cmin * kChunkTG + (t >> 2)) * 256 + (t & 3);
+          for (int i = r0; i < r1; ++i) {
+            float acc = __builtin_fmaf(base[(0 * 16 + i) * 4], s0, 0.0f);
+            acc = __builtin_fmaf(base[(1 * 16 + i) * 4], s1, acc);
+            acc = __builtin_fmaf(base[(2 * 16 + i) * 4], s2, acc);
+            acc = __builtin_fmaf(base[(3 * 16 + i) * 4], s3, acc);
+            if (acc == vmin) {
+              cand = ((cmin * kChunkTG + (t >> 2)) * 4 + (t & 3)) * 16 + i;
+              break;
+            }
           }
         }
       }
@@ -139,9 +206,10 @@ __device__ __forceinline__ void nn_rescan(const float4* __restrict__ prep, const
 // point for query (l % 16) of block q: the lowest index among the candidates
 // with the smallest FP32 value.  A query whose minimum cannot be re-found
 // (only possible with non-finite inputs) gets index 0 and sets *miss.
+// qc[3q + a] = component a of the lane's query (l % 16) of block q.
 template <int Q>
 __device__ __forceinline__ void nn_scan(const float4* __restrict__ prep, int ntg, const float* bq,
-                                        int* idx, int32_t* miss) {
+                                        const float* qc, int* idx, int32_t* miss) {
   const int lane = threadIdx.x & 63;
   float b[Q], best[Q];
   int bch[Q];
@@ -152,19 +220,20 @@ __device__ __forceinline__ void nn_scan(const float4* __restrict__ prep, int ntg
     bch[q] = 0;
   }
   const int nch = ntg / kChunkTG;  // even
-  const float4* p = prep + lane;
-  float4 x0 = p[0], x1 = p[64];
+  const unsigned lo = 16u * (unsigned)lane;
+  const __amdgpu_buffer_rsrc_t rs = cloud_rsrc(prep, ntg);
+  float4 x0 = load_tg(rs, 0, lo), x1 = load_tg(rs, 1, lo);
   for (int c = 0; c < nch; c += 2) {
-    const float4 y0 = p[(size_t)(2 * c + 2) * 64];
-    const float4 y1 = p[(size_t)(2 * c + 3) * 64];
+    const float4 y0 = load_tg(rs, 2 * c + 2, lo);
+    const float4 y1 = load_tg(rs, 2 * c + 3, lo);
     chunk_step<Q>(x0, x1, b, best, bch, c);
     if (c + 2 < nch) {
-      x0 = p[(size_t)(2 * c + 4) * 64];
-      x1 = p[(size_t)(2 * c + 5) * 64];
+      x0 = load_tg(rs, 2 * c + 4, lo);
+      x1 = load_tg(rs, 2 * c + 5, lo);
     }
     chunk_step<Q>(y0, y1, b, best, bch, c + 1);
   }
-  nn_rescan<Q>(prep, b, best, bch, idx, miss);
+  nn_rescan<Q, true>(prep, rs, b, qc, best, bch, idx, miss);
 }
 
 // Squared distance from the box [lo, hi] to the box [qlo, qhi] (0 if they
@@ -185,16 +254,17 @@ __device__ __forceinline__ float box_gap2(const float* bx, const float qlo[3], c
 // exact (the same nearest distances as scanning everything).  Queries must be
 // spatially coherent for this to pay (contact clouds are Morton sorted).  The
 // chunk nearest to the wave's query box is scanned first; the other candidate
-// chunks follow in index order, the bounds refreshed every second chunk.
+// chunks follow in index order, the bounds refreshed every ASICP_NN_REFRESH
+// chunks.
 // snorm[q] = |s|^2 of the lane's query in block q (turns the reduced value
 // |r|^2 - 2 r.s into a squared distance); box = the cloud's chunk boxes;
 // m = real points of the cloud; vq[q] = real queries of block q.  Returns the
 // number of (query, point) distances evaluated (wave-uniform).
-template <int Q>
+template <int Q, bool BATCH_RESCAN>
 __device__ __forceinline__ long long nn_scan_pruned(const float4* __restrict__ prep, int ntg, int m,
                                                     const float* __restrict__ box, const float* bq,
-                                                    const float* snorm, const int* vq, int* idx,
-                                                    int32_t* miss) {
+                                                    const float* snorm, const float* qc, const int* vq,
+                                                    int* idx, int32_t* miss) {
   const int lane = threadIdx.x & 63;
   float b[Q], best[Q];
   int bch[Q];
@@ -213,7 +283,8 @@ __device__ __forceinline__ long long nn_scan_pruned(const float4* __restrict__ p
     }
   }
   const int nch = ntg / kChunkTG;
-  const float4* p = prep + lane;
+  const unsigned lo = 16u * (unsigned)lane;
+  const __amdgpu_buffer_rsrc_t rs = cloud_rsrc(prep, ntg);
   // per-block bound: largest squared distance a query of the block may still
   // need, with rounding slack
   float ub[Q];
@@ -243,11 +314,11 @@ __device__ __forceinline__ long long nn_scan_pruned(const float4* __restrict__ p
     const unsigned long long o = __shfl_xor(near, off, 64);
     near = o < near ? o : near;
   }
-  const int c0 = (int)(near & 0xffffffffull);
+  const int c0 = __builtin_amdgcn_readfirstlane((int)(near & 0xffffffffull));  // same in every lane
   long long pairs = 0;
   {
     const int pts = max(0, min(128, m - 128 * c0));
-    chunk_step<Q>(p[(size_t)(2 * c0) * 64], p[(size_t)(2 * c0 + 1) * 64], b, best, bch, c0);
+    chunk_step<Q>(load_tg(rs, 2 * c0, lo), load_tg(rs, 2 * c0 + 1, lo), b, best, bch, c0);
 #pragma unroll
     for (int q = 0; q < Q; ++q) pairs += (long long)pts * vq[q];
   }
@@ -256,47 +327,70 @@ __device__ __forceinline__ long long nn_scan_pruned(const float4* __restrict__ p
   for (int blk = 0; blk < nch; blk += 64) {
     const int c = blk + lane;
     float lb[Q];
-    unsigned long long cand = 0ull;
+    // mq[q]: candidate chunks of this 64-chunk block that block q of the
+    // queries may still need (wave-uniform masks)
+    unsigned long long mq[Q], cand = 0ull;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       lb[q] = c < nch ? box_gap2(box + (size_t)c * 8, qlo[q], qhi[q]) : __builtin_inff();
-      cand |= __ballot(c < nch && c != c0 && lb[q] <= ub[q]);
+      mq[q] = __ballot(c < nch && c != c0 && lb[q] <= ub[q]);
+      cand |= mq[q];
     }
     // candidates in index order; the next candidate's data is loaded while
     // the current one is compared
     int cl = cand ? __ffsll((long long)cand) - 1 : 0;
-    float4 x0 = p[(size_t)(2 * (blk + cl)) * 64], x1 = p[(size_t)(2 * (blk + cl) + 1) * 64];
+    float4 x0 = load_tg(rs, 2 * (blk + cl), lo), x1 = load_tg(rs, 2 * (blk + cl) + 1, lo);
     while (cand) {
       const int cc = blk + cl;
       cand &= cand - 1;
       const int nl = cand ? __ffsll((long long)cand) - 1 : cl;
-      const float4 y0 = p[(size_t)(2 * (blk + nl)) * 64], y1 = p[(size_t)(2 * (blk + nl) + 1) * 64];
-      bool need[Q];
+      const float4 y0 = load_tg(rs, 2 * (blk + nl), lo), y1 = load_tg(rs, 2 * (blk + nl) + 1, lo);
       const int pts = max(0, min(128, m - 128 * cc));
+#if ASICP_NN_NEED == 0
+      // every block is compared with every candidate chunk
+#pragma unroll
+      for (int q = 0; q < Q; ++q) pairs += (long long)pts * vq[q];
+      chunk_step<Q>(x0, x1, b, best, bch, cc);
+#elif ASICP_NN_NEED == 1
+      bool need[Q];
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
         need[q] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lb[q]), cl)) <= ub[q];
         pairs += need[q] ? (long long)pts * vq[q] : 0ll;
       }
       chunk_step<Q>(x0, x1, b, best, bch, cc, need);
-      if (++since == 2) {
+#else
+      // block q is compared only if chunk cc is still in its mask: a scalar
+      // bit test, so the skip is a uniform branch
+      bool need[Q];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        need[q] = (mq[q] >> cl) & 1ull;
+        pairs += need[q] ? (long long)pts * vq[q] : 0ll;
+      }
+      chunk_step<Q>(x0, x1, b, best, bch, cc, need);
+#endif
+      if (++since == ASICP_NN_REFRESH) {
         since = 0;
         refresh();
         unsigned long long keep = 0ull;
 #pragma unroll
-        for (int q = 0; q < Q; ++q) keep |= __ballot(lb[q] <= ub[q]);
+        for (int q = 0; q < Q; ++q) {
+          mq[q] &= __ballot(lb[q] <= ub[q]);
+          keep |= mq[q];
+        }
         cand &= keep;
       }
       x0 = y0;
       x1 = y1;
       cl = cand ? __ffsll((long long)cand) - 1 : cl;
       if (cl != nl) {  // the prefetched chunk was dropped by the refresh
-        x0 = p[(size_t)(2 * (blk + cl)) * 64];
-        x1 = p[(size_t)(2 * (blk + cl) + 1) * 64];
+        x0 = load_tg(rs, 2 * (blk + cl), lo);
+        x1 = load_tg(rs, 2 * (blk + cl) + 1, lo);
       }
     }
   }
-  nn_rescan<Q>(prep, b, best, bch, idx, miss);
+  nn_rescan<Q, BATCH_RESCAN>(prep, rs, b, qc, best, bch, idx, miss);
   return pairs;
 }
 

@@ -484,19 +484,23 @@ def workload_adjoint(n_obj: int = 16, K: int = 512, m: int = 4096, n: int = 4096
     return pb, Settings(k_max=1, k_stein=1, w_pen=w_pen)
 
 
-def grasp_prior(pb: Problem, sigma: float = 0.05, kappa: float = 2.0) -> np.ndarray:
+def grasp_prior(pb: Problem, sigma: float = 0.03, kappa: float = 5.0, sigma_n: float = 0.005) -> np.ndarray:
     """A prior per group (Sec. III-B names Gaussian translation and von Mises
     rotation priors without parameters): the translation mean places the
     contact cloud's centroid on the object's mean point from straight above,
-    the rotation mean points the gripper down; sigma in metres, kappa the
-    von Mises concentration."""
+    the rotation mean points the gripper down.  sigma (m) is the translation
+    spread and kappa the von Mises concentration; both are expressed in the
+    cost's units by the likelihood scale sigma_n (m): the cost C stands for
+    sigma_n^2 times a negative log likelihood, so the stored weights are
+    w_t = sigma_n^2 / sigma^2 and sigma_n^2 kappa."""
     out = np.zeros((pb.n_obj * pb.n_pre, 9), np.float32)
     for o in range(pb.n_obj):
         anchor = pb.R[pb.r_off[o]:pb.r_off[o + 1]].astype(np.float64).mean(0)
         for p in range(pb.n_pre):
             tip = pb.S[pb.s_off[p]:pb.s_off[p + 1]].astype(np.float64).mean(0)
             t, q = _look_at(np.array([0.0, 0.0, 1.0]), anchor, tip, 0.0)
-            out[o * pb.n_pre + p] = np.concatenate([t, [1.0 / sigma ** 2], q, [kappa]])
+            out[o * pb.n_pre + p] = np.concatenate([t, [sigma_n ** 2 / sigma ** 2], q,
+                                                    [sigma_n ** 2 * kappa]])
     return out
 
 

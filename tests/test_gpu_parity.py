@@ -31,12 +31,23 @@ def say(*a):
 
 
 def col_scales(pb, theta_soa, or_rev):
+    """Scales of the collision terms: mean |e| and mean |R s| |e| over the
+    colliding points (e = s' - c), and bounds of the FP32 rounding the
+    kernel's arithmetic allows in (col_cost, g_t, g_w).  The kernel forms
+    e = s - R^T (c - t) in the gripper frame; each component then carries an
+    error of a few units of 2^-24 times |c - t| + |s| (a subtraction, a
+    three-term dot product, a subtraction), taken here as
+    delta = 16 * 2^-24 * (|c - t| + |s|) per component.  Near convergence a
+    colliding point sits on its contact point (|e| of micrometres), where
+    this absolute error dominates any relative tolerance."""
     S = pb.S.astype(np.float64)
     Cc = pb.C.astype(np.float64)
     th = np.asarray(theta_soa, np.float64)
-    st = np.zeros(th.shape[1])
-    sw = np.zeros(th.shape[1])
-    for i in range(th.shape[1]):
+    n_p = th.shape[1]
+    st, sw = np.zeros(n_p), np.zeros(n_p)
+    xc, xt, xw = np.zeros(n_p), np.zeros(n_p), np.zeros(n_p)
+    eps = 16 * 2.0 ** -24
+    for i in range(n_p):
         g = i // pb.K
         o, p = g // pb.n_pre, g % pb.n_pre
         c0, c1 = pb.c_off[o], pb.c_off[o + 1]
@@ -45,12 +56,18 @@ def col_scales(pb, theta_soa, or_rev):
         if len(sel) == 0:
             continue
         Rm = oracle.quat_to_rot(th[3:, i])
-        u = S[pb.s_off[p] + r[sel]] @ Rm.T
+        s_loc = S[pb.s_off[p] + r[sel]]
+        u = s_loc @ Rm.T
         e = u + th[:3, i] - Cc[c0 + sel]
         ne = np.linalg.norm(e, axis=1)
+        ns = np.linalg.norm(s_loc, axis=1)
         st[i] = ne.mean()
-        sw[i] = (np.linalg.norm(u, axis=1) * ne).mean()
-    return st, sw
+        sw[i] = (ns * ne).mean()
+        dv = math.sqrt(3) * eps * (np.linalg.norm(Cc[c0 + sel] - th[:3, i], axis=1) + ns)
+        xc[i] = (2 * ne * dv + dv * dv).mean() / 2
+        xt[i] = dv.mean()
+        xw[i] = (ns * dv).mean()
+    return st, sw, xc, xt, xw
 
 
 def compare_step(pb, st, theta, k, prev_cost=None, converged=None, label=""):
@@ -83,17 +100,17 @@ def compare_step(pb, st, theta, k, prev_cost=None, converged=None, label=""):
     pu.close(g["grad_ct"][3:].T, r["g_ct"][:, 3:], s_w[:, None], what="g_w", extra=b_w[:, None])
     both = (g["ncol"] > 0) & (r["ncol"] > 0) & (g["ncol"] == r["ncol"])
     rb_t, rb_w = pu.rev_tie_bounds(pb, theta, g["rev_idx"], r["rev_idx"])
+    c_t, c_w, x_c, x_t, x_w = col_scales(pb, theta, r["rev_idx"])
     if both.any():
-        c_t, c_w = col_scales(pb, theta, r["rev_idx"])
         pu.close(g["col_cost"][both], r["col_cost"][both], r["col_cost"][both], what="col_cost",
-                 extra=rb_t[both] * 0.05)
+                 extra=rb_t[both] * 0.05 + x_c[both])
         pu.close(g["grad_col"][:3].T[both], r["g_col"][both, :3], c_t[both, None], what="gcol_t",
-                 extra=rb_t[both, None])
+                 extra=rb_t[both, None] + x_t[both, None])
         pu.close(g["grad_col"][3:].T[both], r["g_col"][both, 3:], c_w[both, None], what="gcol_w",
-                 extra=rb_w[both, None])
+                 extra=rb_w[both, None] + x_w[both, None])
     # bound on what excused ties may change in the gradient the update uses
-    xb_t = np.where(r["ncol"] > 0, rb_t, b_t)
-    xb_w = np.where(r["ncol"] > 0, rb_w, b_w)
+    xb_t = np.where(r["ncol"] > 0, rb_t + x_t, b_t)
+    xb_w = np.where(r["ncol"] > 0, rb_w + x_w, b_w)
     same = g["ncol"] == r["ncol"]
     # the update
     svgd = k < st.k_stein
@@ -223,14 +240,14 @@ def test_priors_in_the_stein_update():
     """Gaussian translation and von Mises rotation priors (eq. 8) on the
     small workload and the tabletop set-up (Stein phase and SGD phase)."""
     pb, st = synth.workload_small()
-    pb.prior = synth.grasp_prior(pb, sigma=0.05, kappa=2.0)
+    pb.prior = synth.grasp_prior(pb, sigma=0.05, kappa=2.0, sigma_n=0.01)
     ks = [0, 5, 17]
     snaps = oracle_trajectory(pb, st, ks)
     for k in ks:
         th, pc, cv = snaps[k]
         say("[parity] prior small k", k, compare_step(pb, st, th, k, pc, cv, label="prior small"))
     pb, st = synth.workload_tabletop()
-    pb.prior = synth.grasp_prior(pb, sigma=0.03, kappa=5.0)
+    pb.prior = synth.grasp_prior(pb, sigma=0.03, kappa=5.0, sigma_n=0.005)
     ks = [1, 14, 20]
     snaps = oracle_trajectory(pb, st, ks)
     for k in ks:
