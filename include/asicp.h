@@ -216,6 +216,35 @@ asicp_status asicp_cost_grad(asicp_ctx ctx, const float* theta, float* cost_out,
  * (ASICP_E_STATE); ASICP_FLAG_TIMING events are not recorded inside the graph. */
 asicp_status asicp_replay(asicp_ctx ctx, void* stream);
 
+/* Launch choices that change no result: how work is placed on the XCDs and
+ * how much provably useless work the pruned nearest-neighbour search skips.
+ * Every choice returns bit-identical outputs; only the speed differs. */
+typedef struct {
+  int32_t xcd_map;  /* 0: each XCD takes a contiguous range of the per-particle */
+                    /*    work (one object's data stays in one L2);              */
+                    /* 1: dispatch order (consecutive work on different XCDs,    */
+                    /*    which balances uneven work).  Default 1.               */
+  int32_t fine;     /* forward NN: test each candidate chunk against every      */
+                    /*    query's own bound (1) or only the query block's (0).   */
+                    /*    Default 1.                                             */
+} asicp_launch_t;
+
+/* Read or set the launch choices of a context (set: each field 0 or 1, else
+ * ASICP_E_INVALID).  Setting them discards a captured asicp_replay graph. */
+asicp_status asicp_get_launch(asicp_ctx ctx, asicp_launch_t* out);
+asicp_status asicp_set_launch(asicp_ctx ctx, const asicp_launch_t* in);
+
+/* Time every launch choice on the context's current poses (the forward NN
+ * and the collision kernel, `reps` launches each after one warm-up, HIP
+ * events on `stream`), keep the fastest and return it in `chosen` (may be
+ * NULL); ms_out (host, may be NULL) receives the average time per
+ * evaluation of each choice, index 2 * xcd_map + fine.  Synchronises
+ * `stream`.  The solve's state and its pair counter are left as they were;
+ * a captured asicp_replay graph is discarded.  Results never depend on the
+ * choice, so tuning cannot change what a solve returns. */
+asicp_status asicp_autotune(asicp_ctx ctx, int32_t reps, void* stream, asicp_launch_t* chosen,
+                            float* ms_out);
+
 /* Synchronise `stream`, then fill `out` (see asicp_result_t).  Device outputs
  * are copied on `stream` before it is synchronised.  Returns ASICP_E_HIP for
  * an asynchronous HIP error and ASICP_E_NUMERIC if the device flagged a

@@ -23,7 +23,8 @@ ASICP_OK, ASICP_E_INVALID, ASICP_E_STATE, ASICP_E_HIP, ASICP_E_NUMERIC = 0, -1, 
 ASICP_FLAG_DEBUG, ASICP_FLAG_TIMING, ASICP_FLAG_NO_PRUNE = 1, 2, 4
 
 EXPORTS = ("asicp_workspace_bytes", "asicp_create", "asicp_step", "asicp_solve", "asicp_replay",
-           "asicp_cost_grad", "asicp_result", "asicp_kernel_time", "asicp_destroy", "asicp_last_error")
+           "asicp_cost_grad", "asicp_result", "asicp_kernel_time", "asicp_get_launch",
+           "asicp_set_launch", "asicp_autotune", "asicp_destroy", "asicp_last_error")
 
 
 class AsicpError(RuntimeError):
@@ -54,6 +55,10 @@ class asicp_config(C.Structure):
                 ("kernel_mode", C.c_int32), ("bw_mode", C.c_int32), ("h_fixed", C.c_float),
                 ("h_min", C.c_float), ("conv_tol", C.c_float), ("w_pen", C.c_float),
                 ("minibatch", C.c_int32), ("seed", C.c_uint64), ("flags", C.c_uint32)]
+
+
+class asicp_launch_t(C.Structure):
+    _fields_ = [("xcd_map", C.c_int32), ("fine", C.c_int32)]
 
 
 class asicp_result_t(C.Structure):
@@ -93,6 +98,12 @@ def load():
         L.asicp_result.restype = i32
         L.asicp_kernel_time.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(i32), C.POINTER(C.c_double)]
         L.asicp_kernel_time.restype = i32
+        L.asicp_get_launch.argtypes = [vp, vp]
+        L.asicp_get_launch.restype = i32
+        L.asicp_set_launch.argtypes = [vp, vp]
+        L.asicp_set_launch.restype = i32
+        L.asicp_autotune.argtypes = [vp, i32, vp, vp, vp]
+        L.asicp_autotune.restype = i32
         L.asicp_destroy.argtypes = [vp]
         L.asicp_destroy.restype = None
         L.asicp_last_error.argtypes = []
@@ -153,6 +164,25 @@ def asicp_kernel_time(ctx):
     pairs = C.c_double(0.0)
     _check(load().asicp_kernel_time(ctx, C.byref(ms), C.byref(n), C.byref(pairs)))
     return float(ms.value), int(n.value), float(pairs.value)
+
+
+def asicp_get_launch(ctx) -> dict:
+    out = asicp_launch_t()
+    _check(load().asicp_get_launch(ctx, C.byref(out)))
+    return {"xcd_map": int(out.xcd_map), "fine": int(out.fine)}
+
+
+def asicp_set_launch(ctx, xcd_map: int, fine: int):
+    return _check(load().asicp_set_launch(ctx, C.byref(asicp_launch_t(int(xcd_map), int(fine)))))
+
+
+def asicp_autotune(ctx, reps: int, stream: int):
+    """Time every launch choice; returns (chosen dict, ms per evaluation of
+    each choice indexed 2 * xcd_map + fine)."""
+    out = asicp_launch_t()
+    ms = (C.c_float * 4)()
+    _check(load().asicp_autotune(ctx, int(reps), C.c_void_p(stream), C.byref(out), ms))
+    return {"xcd_map": int(out.xcd_map), "fine": int(out.fine)}, [float(v) for v in ms]
 
 
 def asicp_destroy(ctx):
@@ -244,6 +274,8 @@ class Solver:
         arrays and workspace (runs the set-up kernels again)."""
         self.close()
         self.ctx = asicp_create(self.problem, self.config, self._ws_ptr, self.ws_bytes, self._stream(stream))
+        if getattr(self, "_launch", None) is not None:  # keep a chosen or tuned launch
+            asicp_set_launch(self.ctx, **self._launch)
 
     def step(self, n: int = 1, stream=None):
         asicp_step(self.ctx, n, self._stream(stream))
@@ -297,6 +329,18 @@ class Solver:
 
     def kernel_time(self):
         return asicp_kernel_time(self.ctx)
+
+    def launch(self) -> dict:
+        return asicp_get_launch(self.ctx)
+
+    def set_launch(self, xcd_map: int, fine: int):
+        asicp_set_launch(self.ctx, xcd_map, fine)
+        self._launch = {"xcd_map": int(xcd_map), "fine": int(fine)}
+
+    def autotune(self, reps: int = 3, stream=None):
+        chosen, ms = asicp_autotune(self.ctx, reps, self._stream(stream))
+        self._launch = chosen
+        return chosen, ms
 
     def close(self):
         if getattr(self, "ctx", None) is not None:

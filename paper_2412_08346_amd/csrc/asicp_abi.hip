@@ -241,6 +241,8 @@ asicp_status check_launch(const char* what) {
 
 }  // namespace
 
+__global__ void k_set_u64(unsigned long long* dst, unsigned long long v) { *dst = v; }
+
 __global__ void k_set_theta(float* dst, const float* src, int n) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i < n) dst[i] = src[i];
@@ -425,6 +427,8 @@ asicp_status asicp_create(const asicp_problem* pb, const asicp_config* cfg, void
   d.max_m = s.max_m;
   d.max_m_pad = s.max_m_pad;
   d.prior = s.prior ? reinterpret_cast<const float*>(ws + L.prior) : nullptr;
+  d.xcd_map = 1;  // launch defaults (asicp_set_launch / asicp_autotune change them)
+  d.fine = 1;
   std::vector<float> prior_words;
   if (s.prior) {
     prior_words.assign(12 * (size_t)s.G, 0.f);
@@ -710,6 +714,88 @@ asicp_status asicp_kernel_time(asicp_ctx c, double* total_ms, int32_t* launches,
   }
   *total_ms = tot;
   *launches = c->n_timed;
+  return ASICP_OK;
+}
+
+asicp_status asicp_get_launch(asicp_ctx c, asicp_launch_t* out) {
+  g_err.clear();
+  if (!c || !out) return fail(ASICP_E_INVALID, "NULL argument");
+  out->xcd_map = c->d.xcd_map;
+  out->fine = c->d.fine;
+  return ASICP_OK;
+}
+
+static void drop_graph(asicp_ctx c) {  // a captured solve holds the old launch choices
+  if (c->graph) (void)hipGraphExecDestroy(c->graph);
+  c->graph = nullptr;
+}
+
+asicp_status asicp_set_launch(asicp_ctx c, const asicp_launch_t* in) {
+  g_err.clear();
+  if (!c || !in) return fail(ASICP_E_INVALID, "NULL argument");
+  if ((in->xcd_map != 0 && in->xcd_map != 1) || (in->fine != 0 && in->fine != 1))
+    return fail(ASICP_E_INVALID, "xcd_map and fine must be 0 or 1");
+  c->d.xcd_map = in->xcd_map;
+  c->d.fine = in->fine;
+  drop_graph(c);
+  return ASICP_OK;
+}
+
+asicp_status asicp_autotune(asicp_ctx c, int32_t reps, void* stream, asicp_launch_t* chosen, float* ms_out) {
+  g_err.clear();
+  if (!c) return fail(ASICP_E_INVALID, "ctx is NULL");
+  if (reps < 1 || reps > 1000) return fail(ASICP_E_INVALID, "reps must be in 1..1000");
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  (void)hipGetLastError();
+  if (c->d.minibatch) {  // the forward kernel reads the current mini-batch operand
+    const int k = std::min(c->k, c->cfg.k_max);
+    const double full = 2.0 * (double)c->cfg.k_max / 3.0;
+    launch_minibatch(c->d, k, ((double)k < full ? (double)k : full) / full, hs);
+  }
+  unsigned long long cnt0 = 0;
+  if (hipMemcpyAsync(&cnt0, c->d.counters, sizeof cnt0, hipMemcpyDeviceToHost, hs) != hipSuccess ||
+      hipStreamSynchronize(hs) != hipSuccess)
+    return fail(ASICP_E_HIP, "reading the pair counter failed");
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return fail(ASICP_E_HIP, "hipEventCreate failed");
+  }
+  auto timed = [&](auto&& launch, float* ms) -> bool {
+    launch();  // warm-up
+    if (hipEventRecord(e0, hs) != hipSuccess) return false;
+    for (int r = 0; r < reps; ++r) launch();
+    if (hipEventRecord(e1, hs) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return false;
+    return hipEventElapsedTime(ms, e0, e1) == hipSuccess;
+  };
+  float nn_ms[4] = {0, 0, 0, 0}, gate_ms[2] = {0, 0};
+  bool ok = true;
+  for (int v = 0; v < 4 && ok; ++v) {  // v = 2 * xcd_map + fine
+    Dev dv = c->d;
+    dv.xcd_map = v >> 1;
+    dv.fine = v & 1;
+    ok = timed([&] { launch_nn_forward(dv, hs); }, &nn_ms[v]);
+    if (ok && dv.fine == 0) ok = timed([&] { launch_gate_reverse(dv, hs); }, &gate_ms[dv.xcd_map]);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (!ok) return fail(ASICP_E_HIP, "timing a launch variant failed");
+  hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, hs, c->d.counters, cnt0);
+  asicp_status st = check_launch("autotune");
+  if (st != ASICP_OK) return st;
+  int bestv = 2 * c->d.xcd_map + c->d.fine;  // keep the current choice unless another is faster
+  for (int v = 0; v < 4; ++v) {
+    const float tv = nn_ms[v] + gate_ms[v >> 1], tb = nn_ms[bestv] + gate_ms[bestv >> 1];
+    if (tv < tb) bestv = v;
+    if (ms_out) ms_out[v] = tv / (float)reps;
+  }
+  c->d.xcd_map = bestv >> 1;
+  c->d.fine = bestv & 1;
+  drop_graph(c);
+  if (chosen) {
+    chosen->xcd_map = c->d.xcd_map;
+    chosen->fine = c->d.fine;
+  }
   return ASICP_OK;
 }
 

@@ -21,12 +21,6 @@ constexpr int kTileGroup = 64;     // points per MFMA-ready tile group (4 tiles 
 #ifndef ASICP_NN_SPLIT
 #define ASICP_NN_SPLIT 0
 #endif
-// How the pruned scan skips a query block for a candidate chunk it cannot
-// improve: 0 never skips, 1 tests the chunk's bound per block (vector
-// compare), 2 tests a bit of the block's wave-uniform candidate mask.
-#ifndef ASICP_NN_NEED
-#define ASICP_NN_NEED 2
-#endif
 // Candidate chunks compared between refreshes of the pruning bound.
 #ifndef ASICP_NN_REFRESH
 #define ASICP_NN_REFRESH 4
@@ -135,6 +129,9 @@ struct Dev {
                             //   iteration's mini-batch at |r|^2 = 1e30
   unsigned char* batch_mark;  // [sum M] 1 if the point is in the mini-batch
   const float* prior;       // [G][12] mu_t[3], w_t, mu_q[4] (unit), kappa, pad; NULL: none
+  // launch choices that change no result (ASICP launch options)
+  int32_t xcd_map;          // 0: contiguous work per XCD, 1: dispatch order
+  int32_t fine;             // forward NN: per-query chunk test
 };
 
 typedef float f4v __attribute__((ext_vector_type(4)));

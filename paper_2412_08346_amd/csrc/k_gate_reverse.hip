@@ -20,7 +20,11 @@ namespace asicp {
 
 constexpr int kPerThread = kGateChunk / 256;
 
+// Workgroup placement over the XCDs, as for the forward kernel (MAP 0:
+// contiguous work per XCD, MAP 1: dispatch order); changes no result.
+template <int MAP>
 __device__ __forceinline__ int xcd_logical_g(int b, int nwg) {
+  if (MAP == 1) return b;
   const int per = (nwg + 7) >> 3;
   return (b & 7) * per + (b >> 3);
 }
@@ -114,11 +118,12 @@ __device__ __forceinline__ void rev_scan(const Dev& d, const PreInfo& pi, const 
     snorm[q] = x * x + y * y + z * z;
     vq[q] = 16;
   }
-  nn_scan_pruned<Q, false>(d.pre_prep + (size_t)pi.prep_tg_begin * 64, pi.ntg, pi.n,
+  nn_scan_pruned<Q, false, false>(d.pre_prep + (size_t)pi.prep_tg_begin * 64, pi.ntg, pi.n,
                     d.pre_box + (size_t)pi.prep_tg_begin / kChunkTG * 8, bq, snorm, nullptr, vq, idx,
                     d.flags + 1);
 }
 
+template <int MAP>
 __global__ __launch_bounds__(256) void k_gate_reverse(Dev d) {
   __shared__ float lx[kGateChunk], ly[kGateChunk], lz[kGateChunk];
   __shared__ int lm[kGateChunk];
@@ -126,7 +131,7 @@ __global__ __launch_bounds__(256) void k_gate_reverse(Dev d) {
   __shared__ float wpart[4][kPartStride];
 
   const int nwg = d.total_gate_wgs;
-  const int logical = xcd_logical_g(blockIdx.x, nwg);
+  const int logical = xcd_logical_g<MAP>(blockIdx.x, nwg);
   if (logical >= nwg) return;  // uniform over the workgroup
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
 
@@ -304,7 +309,8 @@ __global__ __launch_bounds__(256) void k_gate_reverse(Dev d) {
 void launch_gate_reverse(const Dev& d, hipStream_t s) {
   if (d.total_gate_wgs == 0) return;
   const int grid = ((d.total_gate_wgs + 7) / 8) * 8;
-  hipLaunchKernelGGL(k_gate_reverse, dim3(grid), dim3(256), 0, s, d);
+  if (d.xcd_map) hipLaunchKernelGGL(k_gate_reverse<1>, dim3(grid), dim3(256), 0, s, d);
+  else hipLaunchKernelGGL(k_gate_reverse<0>, dim3(grid), dim3(256), 0, s, d);
 }
 
 }  // namespace asicp

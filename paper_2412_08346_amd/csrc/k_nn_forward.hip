@@ -12,9 +12,13 @@
 
 namespace asicp {
 
-// Hardware places workgroup b on XCD b % 8; give each XCD a contiguous range
-// of logical workgroups so that one XCD's L2 serves the same objects.
+// Hardware places workgroup b on XCD b % 8.  MAP 0 gives each XCD a
+// contiguous range of logical workgroups (one object's data stays in one L2);
+// MAP 1 keeps the dispatch order (consecutive work on different XCDs, which
+// balances uneven work).  Neither changes any result.
+template <int MAP>
 __device__ __forceinline__ int xcd_logical(int b, int nwg) {
+  if (MAP == 1) return b;
   const int per = (nwg + 7) >> 3;
   return (b & 7) * per + (b >> 3);
 }
@@ -25,10 +29,10 @@ __device__ __forceinline__ int xcd_logical(int b, int nwg) {
 #define NN_OCCUPANCY
 #endif
 
-template <bool PRUNE>
+template <bool PRUNE, int MAP, bool FINE>
 __device__ __forceinline__ void nn_forward_body(const Dev& d) {
   const int nwg = (d.total_waves + 3) >> 2;
-  const int logical = xcd_logical(blockIdx.x, nwg);
+  const int logical = xcd_logical<MAP>(blockIdx.x, nwg);
   if (logical >= nwg) return;
   const int wave = logical * 4 + (threadIdx.x >> 6);
   if (wave >= d.total_waves) return;
@@ -75,7 +79,7 @@ __device__ __forceinline__ void nn_forward_body(const Dev& d) {
     int vq[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) vq[q] = max(0, min(16, pi.n - (chunk * QPW + q * 16)));
-    pairs = nn_scan_pruned<Q, true>(prep, oi.ntg, oi.m, d.obj_box + (size_t)oi.prep_tg_begin / kChunkTG * 8,
+    pairs = nn_scan_pruned<Q, true, FINE>(prep, oi.ntg, oi.m, d.obj_box + (size_t)oi.prep_tg_begin / kChunkTG * 8,
                                     bq, snorm, qc, vq, idx, d.flags + 1);
   } else {
     nn_scan<Q>(prep, oi.ntg, bq, qc, idx, d.flags + 1);
@@ -131,16 +135,29 @@ __device__ __forceinline__ void nn_forward_body(const Dev& d) {
 // The pruned scan keeps fewer registers live per wavefront and gains from
 // more wavefronts per SIMD to hide its per-chunk loads; the full scan does
 // not (a lower register budget makes it spill).
-__global__ __launch_bounds__(256) NN_OCCUPANCY void k_nn_forward(Dev d) { nn_forward_body<true>(d); }
-__global__ __launch_bounds__(256) void k_nn_forward_full(Dev d) { nn_forward_body<false>(d); }
+template <int MAP, bool FINE>
+__global__ __launch_bounds__(256) NN_OCCUPANCY void k_nn_forward(Dev d) {
+  nn_forward_body<true, MAP, FINE>(d);
+}
+template <int MAP>
+__global__ __launch_bounds__(256) void k_nn_forward_full(Dev d) {
+  nn_forward_body<false, MAP, false>(d);
+}
 
 void launch_nn_forward(const Dev& d, hipStream_t s) {
   const int nwg = (d.total_waves + 3) / 4;
   const int grid = ((nwg + 7) / 8) * 8;
-  if (d.prune)
-    hipLaunchKernelGGL(k_nn_forward, dim3(grid), dim3(256), 0, s, d);
-  else
-    hipLaunchKernelGGL(k_nn_forward_full, dim3(grid), dim3(256), 0, s, d);
+  const dim3 g(grid), b(256);
+  if (!d.prune) {
+    if (d.xcd_map) hipLaunchKernelGGL(k_nn_forward_full<1>, g, b, 0, s, d);
+    else hipLaunchKernelGGL(k_nn_forward_full<0>, g, b, 0, s, d);
+  } else if (d.xcd_map) {
+    if (d.fine) hipLaunchKernelGGL((k_nn_forward<1, true>), g, b, 0, s, d);
+    else hipLaunchKernelGGL((k_nn_forward<1, false>), g, b, 0, s, d);
+  } else {
+    if (d.fine) hipLaunchKernelGGL((k_nn_forward<0, true>), g, b, 0, s, d);
+    else hipLaunchKernelGGL((k_nn_forward<0, false>), g, b, 0, s, d);
+  }
 }
 
 }  // namespace asicp

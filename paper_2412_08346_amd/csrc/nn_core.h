@@ -249,18 +249,36 @@ __device__ __forceinline__ float box_gap2(const float* bx, const float qlo[3], c
   return s;
 }
 
+// Squared distance from point p to the box [bx[0..2], bx[4..6]] (0 inside).
+__device__ __forceinline__ float point_box2(const float* p, const float* bx) {
+  float s = 0.f;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float g = fmaxf(fmaxf(bx[a] - p[a], p[a] - bx[4 + a]), 0.f);
+    s = __builtin_fmaf(g, g, s);
+  }
+  return s;
+}
+
 // As nn_scan, but a chunk is only compared with a block of 16 queries if the
 // chunk's box can hold a point nearer than the block's current worst bound:
 // exact (the same nearest distances as scanning everything).  Queries must be
-// spatially coherent for this to pay (contact clouds are Morton sorted).  The
-// chunk nearest to the wave's query box is scanned first; the other candidate
-// chunks follow in index order, the bounds refreshed every ASICP_NN_REFRESH
-// chunks.
+// spatially coherent for this to pay (contact clouds are Morton sorted).
+//
+// The chunk nearest to the wave's query box is scanned first; the other
+// candidates follow in index order.  A block of queries takes a candidate
+// chunk only while the box-to-box lower bound is within the block's bound
+// (refreshed every ASICP_NN_REFRESH chunks) and, with FINE, only if some
+// query's point-to-box distance is within that query's own best (qc holds the
+// lane's query).  Neither test can drop a chunk holding a value equal to a
+// final minimum, so the results do not depend on them.
 // snorm[q] = |s|^2 of the lane's query in block q (turns the reduced value
 // |r|^2 - 2 r.s into a squared distance); box = the cloud's chunk boxes;
 // m = real points of the cloud; vq[q] = real queries of block q.  Returns the
-// number of (query, point) distances evaluated (wave-uniform).
-template <int Q, bool BATCH_RESCAN>
+// number of (query, point) distances evaluated (wave-uniform).  Every bound
+// carries a slack of 1e-4 relative plus 1e-7 (squared length units) for the
+// FP32 rounding of the distances it is compared with.
+template <int Q, bool BATCH_RESCAN, bool FINE>
 __device__ __forceinline__ long long nn_scan_pruned(const float4* __restrict__ prep, int ntg, int m,
                                                     const float* __restrict__ box, const float* bq,
                                                     const float* snorm, const float* qc, const int* vq,
@@ -285,12 +303,16 @@ __device__ __forceinline__ long long nn_scan_pruned(const float4* __restrict__ p
   const int nch = ntg / kChunkTG;
   const unsigned lo = 16u * (unsigned)lane;
   const __amdgpu_buffer_rsrc_t rs = cloud_rsrc(prep, ntg);
-  // per-block bound: largest squared distance a query of the block may still
-  // need, with rounding slack
-  float ub[Q];
+  // qb[q]: the lane's query's current best squared distance (block q), with
+  // slack; ub[q]: the largest of them over the block
+  float ub[Q], qb[Q];
   auto refresh = [&]() {
 #pragma unroll
-    for (int q = 0; q < Q; ++q) ub[q] = row_max(rows_min(best[q]) + snorm[q]) * 1.0001f + 1e-7f;
+    for (int q = 0; q < Q; ++q) {
+      qb[q] = (rows_min(best[q]) + snorm[q]) * 1.0001f + 1e-7f;
+      // every row holds the same 16 queries, so the row maximum is uniform
+      ub[q] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(row_max(qb[q]))));
+    }
   };
   // nearest chunk to the union of the blocks' boxes
   float ulo[3], uhi[3];
@@ -346,30 +368,17 @@ __device__ __forceinline__ long long nn_scan_pruned(const float4* __restrict__ p
       const int nl = cand ? __ffsll((long long)cand) - 1 : cl;
       const float4 y0 = load_tg(rs, 2 * (blk + nl), lo), y1 = load_tg(rs, 2 * (blk + nl) + 1, lo);
       const int pts = max(0, min(128, m - 128 * cc));
-#if ASICP_NN_NEED == 0
-      // every block is compared with every candidate chunk
-#pragma unroll
-      for (int q = 0; q < Q; ++q) pairs += (long long)pts * vq[q];
-      chunk_step<Q>(x0, x1, b, best, bch, cc);
-#elif ASICP_NN_NEED == 1
+      // block q is compared only if chunk cc is still in its mask (a scalar
+      // bit test) and, with FINE, some query of the block may improve
       bool need[Q];
-#pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        need[q] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lb[q]), cl)) <= ub[q];
-        pairs += need[q] ? (long long)pts * vq[q] : 0ll;
-      }
-      chunk_step<Q>(x0, x1, b, best, bch, cc, need);
-#else
-      // block q is compared only if chunk cc is still in its mask: a scalar
-      // bit test, so the skip is a uniform branch
-      bool need[Q];
+      const float* bx = box + (size_t)cc * 8;
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
         need[q] = (mq[q] >> cl) & 1ull;
+        if (FINE && need[q]) need[q] = __ballot(point_box2(qc + 3 * q, bx) <= qb[q]) != 0ull;
         pairs += need[q] ? (long long)pts * vq[q] : 0ll;
       }
       chunk_step<Q>(x0, x1, b, best, bch, cc, need);
-#endif
       if (++since == ASICP_NN_REFRESH) {
         since = 0;
         refresh();

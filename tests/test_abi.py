@@ -155,3 +155,11 @@ def test_bad_prior_rejected_on_host(col, value):
     with pytest.raises(A.AsicpError) as e:
         A.asicp_workspace_bytes(p, cfg)
     assert e.value.status == A.ASICP_E_INVALID and "prior" in str(e.value)
+
+
+def test_launch_calls_reject_null_and_bad_values():
+    L = A.load()
+    out = A.asicp_launch_t()
+    assert L.asicp_get_launch(None, C.byref(out)) == A.ASICP_E_INVALID
+    assert L.asicp_set_launch(None, C.byref(out)) == A.ASICP_E_INVALID
+    assert L.asicp_autotune(None, 3, None, None, None) == A.ASICP_E_INVALID
