@@ -17,6 +17,27 @@ sys.path.insert(0, ROOT)
 METRIC = "particle-iters/s & grasps/s at matched final cost: plain vs learned-seeded"
 PEAK_FP32_MFMA = 157.3e12  # MI355X dense fp32 matrix peak, FLOP/s
 FLOP_PER_PAIR = 6          # 3 multiply-adds of |r|^2 - 2 r.s per (query, object point) pair
+# HBM bytes per launch of the forward-NN kernel (dispatch-order XCD placement,
+# per-query chunk test) on the paper-scale workload, from two rocprofv3 --pmc
+# passes: 2.000 x FETCH_SIZE + 1.000 x WRITE_SIZE (KiB per dispatch, factors
+# from a 256 MiB device copy), averaged over the 101 launches of one solve
+# (profiles/nn_forward_counters_paper_scale.md).  Reported only while the
+# kernel's sources hash to the ones measured.
+NN_TRAFFIC = {"bytes": 5632041, "fetch_bytes": 2486313, "write_bytes": 3145728,
+              "sha256": "69099fc82fd0574ccc7c00e3a0c97e56e588bae22722e930cd9f303d5bd6526d",
+              "launch": {"xcd_map": 1, "fine": 1}}
+NN_SOURCES = ("k_nn_forward.hip", "nn_core.h", "asicp_internal.h")
+
+
+def nn_traffic(workload, launch, brute):
+    import hashlib
+    h = hashlib.sha256()
+    for f in NN_SOURCES:
+        with open(os.path.join(ROOT, "paper_2412_08346_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != NN_TRAFFIC["sha256"] or workload != "paper" or brute or launch != NN_TRAFFIC["launch"]:
+        return None
+    return NN_TRAFFIC["bytes"]
 
 
 def cpu_baseline(pb, st, iters=1):
@@ -158,7 +179,8 @@ def main():
                    "contact_points_per_preshape": int(np.diff(pb.s_off)[0]), "preshapes": pb.n_pre},
         "roofline": {"bound": "mfma", "kernel": "k_nn_forward", "achieved": achieved / 1e12,
                      "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA,
-                     "traffic": None, "avg_launch_ms": avg_nn * 1e3, "launches": nn_n,
+                     "traffic": nn_traffic(args.workload, launch, args.brute),
+                     "traffic_unit": "bytes per launch", "avg_launch_ms": avg_nn * 1e3, "launches": nn_n,
                      "pairs_per_launch": pairs, "brute_force_pairs_per_launch": all_pairs,
                      "pruned": not args.brute, "flop_per_pair": FLOP_PER_PAIR,
                      "launch": launch, "autotune_ms_3_stages": launch_ms},
