@@ -265,6 +265,59 @@ void asicp_destroy(asicp_ctx ctx);
 /* Message of the last failed call on this thread ("" if none). */
 const char* asicp_last_error(void);
 
+/* ---------------------------------------------------------------------------
+ * Learned grasp proposal (seeds for the iteration above).  The paper points to
+ * learned priors and data-driven seeding as the way to need fewer
+ * initialisations (Sec. V-A ablation, Sec. VI); this network and its training
+ * are the library's own.  A max-pooled point encoder, 3 -> 64 -> 128 -> 256
+ * per point (BF16 matrix products, FP32 accumulation) and a 256 -> 256 -> 256
+ * -> n_pre * n_seed * 7 head, maps each object cloud to n_seed seed poses per
+ * preshape: t = mean(cloud) + 0.1 o[0:3] (metres), q = o[3:7] / |o[3:7]|.
+ *
+ * Parameters: one FP32 device array of asicp_pn_param_count() floats in the
+ * order W1 (64x3), b1, W2 (128x64), b2, W3 (256x128), b3, W4 (256x256), b4,
+ * W5 (256x256), b5, W6 (O x 256), b6, O = n_pre * n_seed * 7, matrices
+ * row-major (output index first).  Clouds: device SoA x, y, z, concatenated;
+ * off (HOST) [n_obj + 1] point offsets, off[0] = 0, 1..4194304 points each.
+ * The workspace (device, caller-owned, asicp_pn_workspace_bytes) holds every
+ * intermediate; nothing is allocated.  All calls are enqueued on `stream`.
+ * Errors: ASICP_E_INVALID (arguments, checked on the host), ASICP_E_HIP
+ * (launch failures); message in asicp_pn_last_error(). */
+
+/* Parameter floats for n_pre preshapes and n_seed seeds (-1 if
+ * n_pre * n_seed * 7 is not in 7..1024). */
+int64_t asicp_pn_param_count(int32_t n_pre, int32_t n_seed);
+
+/* Workspace bytes for n_obj objects (1..65536). */
+asicp_status asicp_pn_workspace_bytes(int32_t n_obj, int32_t n_pre, int32_t n_seed, size_t* bytes);
+
+/* Forward pass.  seeds (device, may be NULL): [7][n_obj * n_pre * n_seed]
+ * poses (tx ty tz qw qx qy qz, q_w >= 0), particle order (object, preshape,
+ * seed) -- the layout of asicp_problem.theta0.  raw (device, may be NULL):
+ * [n_obj][n_pre * n_seed * 7] network outputs. */
+asicp_status asicp_pn_forward(const float* params, int32_t n_pre, int32_t n_seed, int32_t n_obj,
+                              const int32_t* off, const float* x, const float* y, const float* z,
+                              float* seeds, float* raw, void* workspace, size_t ws_bytes, void* stream);
+
+/* Set loss per object against targets (device [n_obj][n_pre][n_targets][7]
+ * poses, unit q): per preshape the symmetric Chamfer distance
+ * (1/T) sum_g min_a d + (1/S) sum_a min_g d with
+ * d = |t_a - t_g|^2 / 0.01 + (1 - (q_a . q_g)^2), averaged over preshapes ->
+ * loss (device [n_obj]).  grad (device, param_count floats) receives the
+ * gradient of the mean loss over the objects, summed in a fixed order. */
+asicp_status asicp_pn_loss_grad(const float* params, int32_t n_pre, int32_t n_seed, int32_t n_obj,
+                                const int32_t* off, const float* x, const float* y, const float* z,
+                                const float* targets, int32_t n_targets, float* loss, float* grad,
+                                void* workspace, size_t ws_bytes, void* stream);
+
+/* One Adam step (Kingma and Ba, 2015) on `count` parameters, step >= 1 (bias
+ * corrections 1 - beta^step); m and v are the caller's moment buffers. */
+asicp_status asicp_pn_adam(float* params, float* m, float* v, const float* grad, int64_t count, float lr,
+                           float beta1, float beta2, float eps, int32_t step, void* stream);
+
+/* Message of the last failed asicp_pn_* call on this thread. */
+const char* asicp_pn_last_error(void);
+
 #ifdef __cplusplus
 }
 #endif

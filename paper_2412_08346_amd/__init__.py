@@ -24,7 +24,9 @@ ASICP_FLAG_DEBUG, ASICP_FLAG_TIMING, ASICP_FLAG_NO_PRUNE = 1, 2, 4
 
 EXPORTS = ("asicp_workspace_bytes", "asicp_create", "asicp_step", "asicp_solve", "asicp_replay",
            "asicp_cost_grad", "asicp_result", "asicp_kernel_time", "asicp_get_launch",
-           "asicp_set_launch", "asicp_autotune", "asicp_destroy", "asicp_last_error")
+           "asicp_set_launch", "asicp_autotune", "asicp_destroy", "asicp_last_error",
+           "asicp_pn_param_count", "asicp_pn_workspace_bytes", "asicp_pn_forward",
+           "asicp_pn_loss_grad", "asicp_pn_adam", "asicp_pn_last_error")
 
 
 class AsicpError(RuntimeError):
@@ -104,6 +106,19 @@ def load():
         L.asicp_set_launch.restype = i32
         L.asicp_autotune.argtypes = [vp, i32, vp, vp, vp]
         L.asicp_autotune.restype = i32
+        L.asicp_pn_param_count.argtypes = [i32, i32]
+        L.asicp_pn_param_count.restype = C.c_int64
+        L.asicp_pn_workspace_bytes.argtypes = [i32, i32, i32, C.POINTER(C.c_size_t)]
+        L.asicp_pn_workspace_bytes.restype = i32
+        L.asicp_pn_forward.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]
+        L.asicp_pn_forward.restype = i32
+        L.asicp_pn_loss_grad.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, vp, i32, vp, vp, vp, C.c_size_t, vp]
+        L.asicp_pn_loss_grad.restype = i32
+        L.asicp_pn_adam.argtypes = [vp, vp, vp, vp, C.c_int64, C.c_float, C.c_float, C.c_float, C.c_float,
+                                    i32, vp]
+        L.asicp_pn_adam.restype = i32
+        L.asicp_pn_last_error.argtypes = []
+        L.asicp_pn_last_error.restype = C.c_char_p
         L.asicp_destroy.argtypes = [vp]
         L.asicp_destroy.restype = None
         L.asicp_last_error.argtypes = []
@@ -187,6 +202,42 @@ def asicp_autotune(ctx, reps: int, stream: int):
 
 def asicp_destroy(ctx):
     load().asicp_destroy(ctx)
+
+
+def _pn_check(st):
+    if st != ASICP_OK:
+        raise AsicpError(st, load().asicp_pn_last_error().decode())
+    return st
+
+
+def asicp_pn_param_count(n_pre: int, n_seed: int) -> int:
+    n = int(load().asicp_pn_param_count(int(n_pre), int(n_seed)))
+    if n < 0:
+        raise AsicpError(ASICP_E_INVALID, "n_pre * n_seed * 7 must be in 7..1024")
+    return n
+
+
+def asicp_pn_workspace_bytes(n_obj: int, n_pre: int, n_seed: int) -> int:
+    out = C.c_size_t(0)
+    _pn_check(load().asicp_pn_workspace_bytes(int(n_obj), int(n_pre), int(n_seed), C.byref(out)))
+    return int(out.value)
+
+
+def asicp_pn_forward(params, n_pre, n_seed, n_obj, off, x, y, z, seeds, raw, ws, ws_bytes, stream):
+    return _pn_check(load().asicp_pn_forward(params, int(n_pre), int(n_seed), int(n_obj), off, x, y, z,
+                                             seeds, raw, ws, int(ws_bytes), C.c_void_p(stream)))
+
+
+def asicp_pn_loss_grad(params, n_pre, n_seed, n_obj, off, x, y, z, targets, n_targets, loss, grad, ws,
+                       ws_bytes, stream):
+    return _pn_check(load().asicp_pn_loss_grad(params, int(n_pre), int(n_seed), int(n_obj), off, x, y, z,
+                                               targets, int(n_targets), loss, grad, ws, int(ws_bytes),
+                                               C.c_void_p(stream)))
+
+
+def asicp_pn_adam(params, m, v, grad, count, lr, beta1, beta2, eps, step, stream):
+    return _pn_check(load().asicp_pn_adam(params, m, v, grad, int(count), float(lr), float(beta1),
+                                          float(beta2), float(eps), int(step), C.c_void_p(stream)))
 
 
 def make_config(st: "synth.Settings", flags: int = 0) -> asicp_config:

@@ -1,0 +1,719 @@
+// k_proposal.hip -- learned grasp proposal: a max-pooled point-cloud encoder
+// (PointNet style) that maps an object cloud to S seed poses per preshape for
+// the AS-ICP iteration.  The paper points to learned priors and data-driven
+// seeding as the way to need fewer initialisations (Sec. V-A ablation,
+// Sec. VI); the network, its loss and its training are this library's.
+//
+//   x_m  = (r_m - mean r) / 0.1
+//   h1_m = relu(W1 x_m + b1)          3 -> 64      (VALU, FP32)
+//   h2_m = relu(W2 h1_m + b2)        64 -> 128     (BF16 MFMA, FP32 accumulate)
+//   h3_m = relu(W3 h2_m + b3)       128 -> 256     (BF16 MFMA, FP32 accumulate)
+//   g    = max_m h3_m                (lowest m on ties)
+//   u = relu(W4 g + b4), v = relu(W5 u + b5), o = W6 v + b6   (FP32)
+//   seed (p, s): t = mean r + 0.1 o[0:3], q = o[3:7] / |o[3:7]|
+//
+// Loss per (object, preshape) against T target poses (t_g, q_g):
+//   d(a, g) = |t_a - t_g|^2 / 0.01 + (1 - (q_a . q_g)^2),
+//   L = (1/T) sum_g min_a d + (1/S) sum_a min_g d, averaged over preshapes and
+//   objects.  The max-pool routes each channel's gradient to one point, so
+//   the encoder's backward touches at most 256 points per object: it is a
+//   set of matrix-vector products, done in FP32 on the vector units.
+// Every sum runs in a fixed order: no float atomics.
+#include <algorithm>
+#include <cmath>
+#include <string>
+
+#include "asicp_internal.h"
+
+namespace asicp {
+
+namespace pn {
+
+constexpr int H1 = 64, H2 = 128, H3 = 256, HH = 256;
+constexpr float kUnit = 0.1f;
+constexpr int kPts = 64;  // points per forward workgroup
+
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+struct Params {  // offsets (floats) into the flat parameter array
+  int W1, b1, W2, b2, W3, b3, W4, b4, W5, b5, W6, b6, total, O;
+};
+
+__host__ __device__ inline Params layout(int n_pre, int n_seed) {
+  Params p;
+  int o = 0;
+  p.O = n_pre * n_seed * 7;
+  p.W1 = o; o += H1 * 3;
+  p.b1 = o; o += H1;
+  p.W2 = o; o += H2 * H1;
+  p.b2 = o; o += H2;
+  p.W3 = o; o += H3 * H2;
+  p.b3 = o; o += H3;
+  p.W4 = o; o += HH * H3;
+  p.b4 = o; o += HH;
+  p.W5 = o; o += HH * HH;
+  p.b5 = o; o += HH;
+  p.W6 = o; o += p.O * HH;
+  p.b6 = o; o += p.O;
+  p.total = o;
+  return p;
+}
+
+// FP32 -> BF16, round to nearest even (finite inputs)
+__device__ __forceinline__ unsigned short to_bf16(float f) {
+  const unsigned u = __float_as_uint(f);
+  return (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float from_bf16(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+
+struct Net {
+  const float* prm;           // flat FP32 parameters
+  unsigned short* w2h;        // BF16 copy of W2 [128][64]
+  unsigned short* w3h;        // BF16 copy of W3 [256][128]
+  const int32_t* off;         // [n_obj + 1] point offsets
+  const float *x, *y, *z;     // clouds, SoA
+  float* com;                 // [n_obj][4] centroid
+  unsigned long long* pool;   // [n_obj][256] (value bits << 32) | ~index, max
+  float* head;                // [n_obj][4][256] g, u, v (post-activation), spare
+  float* out;                 // [n_obj][O] raw outputs
+  float* dout;                // [n_obj][O] dL/do
+  float* dhead;               // [n_obj][3][256] dzv, dzu, dg
+  float* part;                // [n_obj][n_enc] per-object encoder gradient
+  int n_obj, n_pre, n_seed, n_tgt;
+  Params P;
+};
+
+constexpr int kEnc = H1 * 3 + H1 + H2 * H1 + H2 + H3 * H2 + H3;  // encoder parameters
+
+// ---------------------------------------------------------------------------
+// set-up: BF16 weights, pool reset, centroids (FP64 in a fixed order)
+__global__ __launch_bounds__(256) void k_pn_prep(Net n) {
+  const int tid = threadIdx.x, bid = blockIdx.x;
+  if (bid == 0) {
+    for (int i = tid; i < H2 * H1; i += 256) n.w2h[i] = to_bf16(n.prm[n.P.W2 + i]);
+    for (int i = tid; i < H3 * H2; i += 256) n.w3h[i] = to_bf16(n.prm[n.P.W3 + i]);
+    return;
+  }
+  const int o = bid - 1;
+  if (o >= n.n_obj) return;
+  __shared__ double s[3][256];
+  const int a = n.off[o], b = n.off[o + 1];
+  double sx = 0, sy = 0, sz = 0;
+  for (int i = a + tid; i < b; i += 256) { sx += n.x[i]; sy += n.y[i]; sz += n.z[i]; }
+  s[0][tid] = sx; s[1][tid] = sy; s[2][tid] = sz;
+  n.pool[(size_t)o * H3 + tid] = 0ull;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (tid < st)
+      for (int c = 0; c < 3; ++c) s[c][tid] += s[c][tid + st];
+    __syncthreads();
+  }
+  if (tid < 3) n.com[o * 4 + tid] = (float)(s[tid][0] / (double)(b - a));
+}
+
+// ---------------------------------------------------------------------------
+// forward of the point MLP for 64 points of one object and the max-pool
+__global__ __launch_bounds__(256) void k_pn_point_fwd(Net n, int chunks_per_obj) {
+  __shared__ unsigned short a1[kPts][H1 + 4];   // BF16 h1, row = point (padded rows)
+  __shared__ unsigned short a2[kPts][H2 + 4];   // BF16 h2
+  __shared__ float xs[kPts][3];
+  const int o = blockIdx.x / chunks_per_obj, ch = blockIdx.x - o * chunks_per_obj;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int a = n.off[o], b = n.off[o + 1];
+  const int p0 = a + ch * kPts;
+  if (p0 >= b) return;  // uniform over the workgroup
+  const int np = min(kPts, b - p0);
+  if (tid < kPts) {
+    // rows past the cloud repeat its first point of this chunk: they take part
+    // in the products but never in the max (masked below)
+    const int i = p0 + (tid < np ? tid : 0);
+    xs[tid][0] = (n.x[i] - n.com[o * 4 + 0]) / kUnit;
+    xs[tid][1] = (n.y[i] - n.com[o * 4 + 1]) / kUnit;
+    xs[tid][2] = (n.z[i] - n.com[o * 4 + 2]) / kUnit;
+  }
+  __syncthreads();
+  // layer 1: 64 points x 64 channels, 16 per thread
+  for (int e = tid; e < kPts * H1; e += 256) {
+    const int m = e / H1, c = e - m * H1;
+    const float* W1 = n.prm + n.P.W1 + c * 3;
+    float zz = n.prm[n.P.b1 + c];
+    zz = __builtin_fmaf(W1[0], xs[m][0], zz);
+    zz = __builtin_fmaf(W1[1], xs[m][1], zz);
+    zz = __builtin_fmaf(W1[2], xs[m][2], zz);
+    a1[m][c] = to_bf16(fmaxf(zz, 0.f));
+  }
+  __syncthreads();
+  const int row = lane & 15, kq = lane >> 4;  // A: row m, k block kq; B: column n, k block kq
+  // layer 2: [64 x 64] . [64 x 128]; wave w takes output column tiles 2w, 2w+1
+  for (int nt = 2 * w; nt < 2 * w + 2; ++nt) {
+    for (int mt = 0; mt < kPts / 16; ++mt) {
+      f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int k0 = 0; k0 < H1; k0 += 16) {
+        s4 av, bv;
+        const unsigned short* ap = &a1[mt * 16 + row][k0 + 4 * kq];
+        const unsigned short* bp = n.w2h + (size_t)(nt * 16 + row) * H1 + k0 + 4 * kq;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) { av[j] = (short)ap[j]; bv[j] = (short)bp[j]; }
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+      }
+      // D[row = 4 kq + v][col = lane % 16]: point mt*16 + 4kq + v, channel nt*16 + lane%16
+      const int c = nt * 16 + row;
+      const float bias = n.prm[n.P.b2 + c];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) a2[mt * 16 + 4 * kq + v][c] = to_bf16(fmaxf(acc[v] + bias, 0.f));
+    }
+  }
+  __syncthreads();
+  // layer 3: [64 x 128] . [128 x 256] and the max over the chunk's points;
+  // wave w takes output column tiles 4w .. 4w+3
+  for (int nt = 4 * w; nt < 4 * w + 4; ++nt) {
+    const int c = nt * 16 + row;
+    const float bias = n.prm[n.P.b3 + c];
+    unsigned long long best = 0ull;
+    for (int mt = 0; mt < kPts / 16; ++mt) {
+      f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int k0 = 0; k0 < H2; k0 += 16) {
+        s4 av, bv;
+        const unsigned short* ap = &a2[mt * 16 + row][k0 + 4 * kq];
+        const unsigned short* bp = n.w3h + (size_t)(nt * 16 + row) * H2 + k0 + 4 * kq;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) { av[j] = (short)ap[j]; bv[j] = (short)bp[j]; }
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = mt * 16 + 4 * kq + v;
+        if (m < np) {
+          const float h = fmaxf(acc[v] + bias, 0.f);
+          // larger value wins; on equal values the lower point index
+          const unsigned long long key =
+              ((unsigned long long)__float_as_uint(h) << 32) | (0xFFFFFFFFu - (unsigned)(p0 + m - a));
+          best = key > best ? key : best;
+        }
+      }
+    }
+    // combine the four lane groups (rows) of each column
+#pragma unroll
+    for (int off = 16; off < 64; off <<= 1) {
+      const unsigned long long other = __shfl_xor(best, off, 64);
+      best = other > best ? other : best;
+    }
+    if (lane < 16 && best) atomicMax(n.pool + (size_t)o * H3 + c, best);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// head: g -> u -> v -> o, and the seed poses (SoA, solver order)
+__global__ __launch_bounds__(256) void k_pn_head_fwd(Net n, float* seeds, int Ktot) {
+  __shared__ float g[H3], u[HH], v[HH];
+  const int o = blockIdx.x, tid = threadIdx.x;
+  const unsigned long long key = n.pool[(size_t)o * H3 + tid];
+  g[tid] = __uint_as_float((unsigned)(key >> 32));
+  __syncthreads();
+  {
+    const float* W = n.prm + n.P.W4 + (size_t)tid * H3;
+    float acc = n.prm[n.P.b4 + tid];
+    for (int k = 0; k < H3; ++k) acc = __builtin_fmaf(W[k], g[k], acc);
+    u[tid] = fmaxf(acc, 0.f);
+  }
+  __syncthreads();
+  {
+    const float* W = n.prm + n.P.W5 + (size_t)tid * HH;
+    float acc = n.prm[n.P.b5 + tid];
+    for (int k = 0; k < HH; ++k) acc = __builtin_fmaf(W[k], u[k], acc);
+    v[tid] = fmaxf(acc, 0.f);
+  }
+  __syncthreads();
+  float* hd = n.head + (size_t)o * 4 * 256;
+  hd[tid] = g[tid];
+  hd[256 + tid] = u[tid];
+  hd[512 + tid] = v[tid];
+  const int O = n.P.O;
+  for (int r = tid; r < O; r += 256) {
+    const float* W = n.prm + n.P.W6 + (size_t)r * HH;
+    float acc = n.prm[n.P.b6 + r];
+    for (int k = 0; k < HH; ++k) acc = __builtin_fmaf(W[k], v[k], acc);
+    n.out[(size_t)o * O + r] = acc;
+  }
+  if (!seeds) return;
+  __syncthreads();
+  const int ns = n.n_pre * n.n_seed;
+  for (int j = tid; j < ns; j += 256) {
+    const float* r = n.out + (size_t)o * O + (size_t)j * 7;
+    const int i = o * ns + j;  // particle index: (object, preshape, seed)
+    for (int a = 0; a < 3; ++a) seeds[(size_t)a * Ktot + i] = n.com[o * 4 + a] + kUnit * r[a];
+    float qw = r[3], qx = r[4], qy = r[5], qz = r[6];
+    const float nrm = sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
+    const float s = (qw < 0.f ? -1.f : 1.f) / (nrm > 0.f ? nrm : 1.f);
+    seeds[(size_t)3 * Ktot + i] = nrm > 0.f ? qw * s : 1.f;
+    seeds[(size_t)4 * Ktot + i] = qx * s;
+    seeds[(size_t)5 * Ktot + i] = qy * s;
+    seeds[(size_t)6 * Ktot + i] = qz * s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// set loss and dL/do: one thread per (object, preshape)
+__global__ __launch_bounds__(64) void k_pn_loss(Net n, const float* tgt, float* lpart) {
+  const int j = blockIdx.x * 64 + threadIdx.x;
+  if (j >= n.n_obj * n.n_pre) return;
+  const int o = j / n.n_pre, p = j - o * n.n_pre;
+  const int S = n.n_seed, T = n.n_tgt, O = n.P.O;
+  const float* a = n.out + (size_t)o * O + (size_t)p * S * 7;
+  float* da = n.dout + (size_t)o * O + (size_t)p * S * 7;
+  const float* tg = tgt + ((size_t)o * n.n_pre + p) * T * 7;
+  const float cx = n.com[o * 4], cy = n.com[o * 4 + 1], cz = n.com[o * 4 + 2];
+  for (int i = 0; i < S * 7; ++i) da[i] = 0.f;
+  auto dist = [&](int s, int g, float* c_out) {
+    const float* r = a + s * 7;
+    const float* t = tg + g * 7;
+    const float dx = cx + kUnit * r[0] - t[0], dy = cy + kUnit * r[1] - t[1], dz = cz + kUnit * r[2] - t[2];
+    const float nq = sqrtf(r[3] * r[3] + r[4] * r[4] + r[5] * r[5] + r[6] * r[6]);
+    const float c = (r[3] * t[3] + r[4] * t[4] + r[5] * t[5] + r[6] * t[6]) / nq;
+    *c_out = c;
+    return (dx * dx + dy * dy + dz * dz) / (kUnit * kUnit) + (1.f - c * c);
+  };
+  // adds w * dd(s, g)/d(raw seed s)
+  auto grad = [&](int s, int g, float wgt) {
+    const float* r = a + s * 7;
+    const float* t = tg + g * 7;
+    float* d = da + s * 7;
+    const float dx = cx + kUnit * r[0] - t[0], dy = cy + kUnit * r[1] - t[1], dz = cz + kUnit * r[2] - t[2];
+    const float f = wgt * 2.f / kUnit;  // d/d raw t = 2 dt / UNIT^2 * UNIT
+    d[0] += f * dx; d[1] += f * dy; d[2] += f * dz;
+    const float nq = sqrtf(r[3] * r[3] + r[4] * r[4] + r[5] * r[5] + r[6] * r[6]);
+    float q[4] = {r[3] / nq, r[4] / nq, r[5] / nq, r[6] / nq};
+    const float c = q[0] * t[3] + q[1] * t[4] + q[2] * t[5] + q[3] * t[6];
+    const float k = -2.f * wgt * c / nq;
+    for (int e = 0; e < 4; ++e) d[3 + e] += k * (t[3 + e] - c * q[e]);
+  };
+  float L = 0.f, c;
+  for (int g = 0; g < T; ++g) {  // nearest seed of each target (lowest index)
+    int bs = 0;
+    float bd = dist(0, g, &c);
+    for (int s = 1; s < S; ++s) {
+      const float dd = dist(s, g, &c);
+      if (dd < bd) { bd = dd; bs = s; }
+    }
+    L += bd / (float)T;
+    grad(bs, g, 1.f / (float)T / (float)n.n_pre);
+  }
+  for (int s = 0; s < S; ++s) {  // nearest target of each seed
+    int bg = 0;
+    float bd = dist(s, 0, &c);
+    for (int g = 1; g < T; ++g) {
+      const float dd = dist(s, g, &c);
+      if (dd < bd) { bd = dd; bg = g; }
+    }
+    L += bd / (float)S;
+    grad(s, bg, 1.f / (float)S / (float)n.n_pre);
+  }
+  lpart[j] = L / (float)n.n_pre;
+}
+
+// per object: loss over preshapes (fixed order)
+__global__ void k_pn_loss_sum(Net n, const float* lpart, float* loss) {
+  const int o = blockIdx.x * 64 + threadIdx.x;
+  if (o >= n.n_obj) return;
+  float L = 0.f;
+  for (int p = 0; p < n.n_pre; ++p) L += lpart[o * n.n_pre + p];
+  loss[o] = L;
+}
+
+// ---------------------------------------------------------------------------
+// head backward per object: dzv, dzu, dg
+__global__ __launch_bounds__(256) void k_pn_head_bwd(Net n) {
+  __shared__ float dov[1024];
+  __shared__ float dzv[HH], dzu[HH];
+  const int o = blockIdx.x, tid = threadIdx.x, O = n.P.O;
+  const float* hd = n.head + (size_t)o * 4 * 256;
+  float* dh = n.dhead + (size_t)o * 3 * 256;
+  for (int r = tid; r < O; r += 256) dov[r] = n.dout[(size_t)o * O + r];
+  __syncthreads();
+  {  // dv = W6^T do, through the relu of v
+    float acc = 0.f;
+    for (int r = 0; r < O; ++r) acc = __builtin_fmaf(n.prm[n.P.W6 + (size_t)r * HH + tid], dov[r], acc);
+    dzv[tid] = hd[512 + tid] > 0.f ? acc : 0.f;
+  }
+  __syncthreads();
+  {
+    float acc = 0.f;
+    for (int r = 0; r < HH; ++r) acc = __builtin_fmaf(n.prm[n.P.W5 + (size_t)r * HH + tid], dzv[r], acc);
+    dzu[tid] = hd[256 + tid] > 0.f ? acc : 0.f;
+  }
+  __syncthreads();
+  float acc = 0.f;
+  for (int r = 0; r < HH; ++r) acc = __builtin_fmaf(n.prm[n.P.W4 + (size_t)r * H3 + tid], dzu[r], acc);
+  dh[tid] = dzv[tid];
+  dh[256 + tid] = dzu[tid];
+  dh[512 + tid] = acc;  // dL/dg
+}
+
+// head weight gradients: sums over objects in a fixed order, one element per
+// thread; the result is divided by the number of objects (mean loss)
+__global__ __launch_bounds__(256) void k_pn_head_wgrad(Net n, float* grad) {
+  const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+  const int O = n.P.O;
+  const long long n4 = (long long)HH * H3, n5 = (long long)HH * HH, n6 = (long long)O * HH;
+  const long long tot = n4 + HH + n5 + HH + n6 + O;
+  if (e >= tot) return;
+  const float inv = 1.f / (float)n.n_obj;
+  float acc = 0.f;
+  long long r = e;
+  if (r < n4) {
+    const int i = (int)(r / H3), k = (int)(r - (long long)i * H3);
+    for (int o = 0; o < n.n_obj; ++o)
+      acc = __builtin_fmaf(n.dhead[(size_t)o * 768 + 256 + i], n.head[(size_t)o * 1024 + k], acc);
+    grad[n.P.W4 + r] = acc * inv;
+    return;
+  }
+  r -= n4;
+  if (r < HH) {
+    for (int o = 0; o < n.n_obj; ++o) acc += n.dhead[(size_t)o * 768 + 256 + r];
+    grad[n.P.b4 + r] = acc * inv;
+    return;
+  }
+  r -= HH;
+  if (r < n5) {
+    const int i = (int)(r / HH), k = (int)(r - (long long)i * HH);
+    for (int o = 0; o < n.n_obj; ++o)
+      acc = __builtin_fmaf(n.dhead[(size_t)o * 768 + i], n.head[(size_t)o * 1024 + 256 + k], acc);
+    grad[n.P.W5 + r] = acc * inv;
+    return;
+  }
+  r -= n5;
+  if (r < HH) {
+    for (int o = 0; o < n.n_obj; ++o) acc += n.dhead[(size_t)o * 768 + r];
+    grad[n.P.b5 + r] = acc * inv;
+    return;
+  }
+  r -= HH;
+  if (r < n6) {
+    const int i = (int)(r / HH), k = (int)(r - (long long)i * HH);
+    for (int o = 0; o < n.n_obj; ++o)
+      acc = __builtin_fmaf(n.dout[(size_t)o * O + i], n.head[(size_t)o * 1024 + 512 + k], acc);
+    grad[n.P.W6 + r] = acc * inv;
+    return;
+  }
+  r -= n6;
+  for (int o = 0; o < n.n_obj; ++o) acc += n.dout[(size_t)o * O + r];
+  grad[n.P.b6 + r] = acc * inv;
+}
+
+// ---------------------------------------------------------------------------
+// encoder backward, one workgroup per object.  Channel c's gradient dg_c goes
+// to its argmax point p_c (where h3 = g_c > 0, so the relu passes it).  The
+// channels are sorted by point; each distinct point is processed in that
+// order by the whole workgroup: its forward up to h2 is recomputed (same
+// BF16 roundings as the forward), then dh2 = W3^T dz3, dz2, dh1 = W2^T dz2,
+// dz1, and the outer products into this object's gradient record.
+__global__ __launch_bounds__(256) void k_pn_point_bwd(Net n) {
+  __shared__ unsigned int keyp[H3];   // (point << 8) | channel, sorted
+  __shared__ float dgs[H3];
+  __shared__ float xp[3], z1[H1], a1f[H1], z2[H2], a2f[H2], dz2[H2], dz1[H1];
+  __shared__ float red[4][H2];
+  const int o = blockIdx.x, tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int a = n.off[o];
+  float* part = n.part + (size_t)o * kEnc;
+  // encoder record layout: W1, b1, W2, b2, W3, b3 (as in the parameters)
+  const int oW1 = 0, ob1 = H1 * 3, oW2 = ob1 + H1, ob2 = oW2 + H2 * H1, oW3 = ob2 + H2, ob3 = oW3 + H3 * H2;
+  for (int i = tid; i < kEnc; i += 256) part[i] = 0.f;
+  {
+    const unsigned long long key = n.pool[(size_t)o * H3 + tid];
+    const float gval = __uint_as_float((unsigned)(key >> 32));
+    const float dg = n.dhead[(size_t)o * 768 + 512 + tid];
+    const bool live = key != 0ull && gval > 0.f && dg != 0.f;
+    const unsigned pt = 0xFFFFFFFFu - (unsigned)(key & 0xFFFFFFFFull);
+    keyp[tid] = live ? ((pt << 8) | (unsigned)tid) : 0xFFFFFFFFu;
+    dgs[tid] = dg;
+  }
+  __syncthreads();
+  // bitonic sort of the 256 keys (point major, channel minor)
+  for (int size = 2; size <= H3; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      const int i = tid, j = i ^ stride;
+      if (j > i) {
+        const bool asc = (i & size) == 0;
+        const unsigned ki = keyp[i], kj = keyp[j];
+        if ((ki > kj) == asc) { keyp[i] = kj; keyp[j] = ki; }
+      }
+      __syncthreads();
+    }
+  }
+  int s0 = 0;
+  while (s0 < H3) {
+    const unsigned k0 = keyp[s0];
+    if (k0 == 0xFFFFFFFFu) break;  // uniform: every thread reads the same LDS word
+    const unsigned pt = k0 >> 8;
+    int s1 = s0 + 1;
+    while (s1 < H3 && (keyp[s1] >> 8) == pt) ++s1;
+    // recompute the point's forward up to h2
+    const int gi = a + (int)pt;
+    if (tid < 3) {
+      const float* src = tid == 0 ? n.x : (tid == 1 ? n.y : n.z);
+      xp[tid] = (src[gi] - n.com[o * 4 + tid]) / kUnit;
+    }
+    __syncthreads();
+    if (tid < H1) {
+      const float* W1 = n.prm + n.P.W1 + tid * 3;
+      float zz = n.prm[n.P.b1 + tid];
+      zz = __builtin_fmaf(W1[0], xp[0], zz);
+      zz = __builtin_fmaf(W1[1], xp[1], zz);
+      zz = __builtin_fmaf(W1[2], xp[2], zz);
+      z1[tid] = zz;
+      a1f[tid] = from_bf16(to_bf16(fmaxf(zz, 0.f)));
+    }
+    __syncthreads();
+    if (tid < H2) {
+      float acc = 0.f;
+      for (int k = 0; k < H1; ++k) acc = __builtin_fmaf(from_bf16(n.w2h[(size_t)tid * H1 + k]), a1f[k], acc);
+      z2[tid] = acc + n.prm[n.P.b2 + tid];
+      a2f[tid] = from_bf16(to_bf16(fmaxf(z2[tid], 0.f)));
+    }
+    __syncthreads();
+    // dW3 rows and db3 of this point's channels (each channel has one point)
+    for (int s = s0; s < s1; ++s) {
+      const int c = (int)(keyp[s] & 255u);
+      const float dg = dgs[c];
+      if (tid < H2) part[oW3 + c * H2 + tid] = dg * a2f[tid];
+      if (tid == 0) part[ob3 + c] = dg;
+    }
+    // dh2 = W3^T dz3 over the point's channels, the 4 waves split them
+    {
+      float acc0 = 0.f, acc1 = 0.f;
+      for (int s = s0 + w; s < s1; s += 4) {
+        const int c = (int)(keyp[s] & 255u);
+        const float dg = dgs[c];
+        acc0 = __builtin_fmaf(from_bf16(n.w3h[(size_t)c * H2 + lane]), dg, acc0);
+        acc1 = __builtin_fmaf(from_bf16(n.w3h[(size_t)c * H2 + 64 + lane]), dg, acc1);
+      }
+      red[w][lane] = acc0;
+      red[w][64 + lane] = acc1;
+    }
+    __syncthreads();
+    if (tid < H2) {
+      const float dh2 = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
+      dz2[tid] = z2[tid] > 0.f ? dh2 : 0.f;
+    }
+    __syncthreads();
+    if (tid < H1) {
+      float acc = 0.f;
+      for (int k = 0; k < H2; ++k) acc = __builtin_fmaf(from_bf16(n.w2h[(size_t)k * H1 + tid]), dz2[k], acc);
+      dz1[tid] = z1[tid] > 0.f ? acc : 0.f;
+    }
+    __syncthreads();
+    // dW2 += dz2 (x) a1, db2 += dz2; dW1 += dz1 (x) x, db1 += dz1
+    for (int e = tid; e < H2 * H1; e += 256) {
+      const int i = e / H1, k = e - i * H1;
+      part[oW2 + e] += dz2[i] * a1f[k];
+    }
+    if (tid < H2) part[ob2 + tid] += dz2[tid];
+    if (tid < H1) {
+      part[oW1 + tid * 3 + 0] += dz1[tid] * xp[0];
+      part[oW1 + tid * 3 + 1] += dz1[tid] * xp[1];
+      part[oW1 + tid * 3 + 2] += dz1[tid] * xp[2];
+      part[ob1 + tid] += dz1[tid];
+    }
+    __syncthreads();
+    s0 = s1;
+  }
+}
+
+// encoder gradient: fixed-order sum of the per-object records
+__global__ __launch_bounds__(256) void k_pn_reduce(Net n, float* grad) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= kEnc) return;
+  float acc = 0.f;
+  for (int o = 0; o < n.n_obj; ++o) acc += n.part[(size_t)o * kEnc + e];
+  grad[e] = acc / (float)n.n_obj;  // the encoder parameters come first in the flat array
+}
+
+__global__ __launch_bounds__(256) void k_pn_adam(float* p, float* m, float* v, const float* g, long long cnt,
+                                                  float lr, float b1, float b2, float eps, float c1, float c2) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= cnt) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+}  // namespace pn
+
+}  // namespace asicp
+
+// ---------------------------------------------------------------------------
+// C ABI
+namespace {
+
+using namespace asicp;
+using namespace asicp::pn;
+
+thread_local std::string pn_err;
+asicp_status pn_fail(asicp_status st, const std::string& m) {
+  pn_err = m;
+  return st;
+}
+
+struct PnLayout {
+  size_t w2h, w3h, off, com, pool, head, out, dout, dhead, part, lpart, total;
+};
+
+PnLayout pn_layout(int n_obj, int n_pre, int n_seed) {
+  const Params P = layout(n_pre, n_seed);
+  PnLayout L;
+  size_t c = 0;
+  auto bump = [&c](size_t bytes) { const size_t o = c; c += (bytes + 255) & ~(size_t)255; return o; };
+  L.w2h = bump(2 * (size_t)H2 * H1);
+  L.w3h = bump(2 * (size_t)H3 * H2);
+  L.off = bump(4 * (size_t)(n_obj + 1));
+  L.com = bump(16 * (size_t)n_obj);
+  L.pool = bump(8 * (size_t)n_obj * H3);
+  L.head = bump(4 * (size_t)n_obj * 1024);
+  L.out = bump(4 * (size_t)n_obj * P.O);
+  L.dout = bump(4 * (size_t)n_obj * P.O);
+  L.dhead = bump(4 * (size_t)n_obj * 768);
+  L.part = bump(4 * (size_t)n_obj * kEnc);
+  L.lpart = bump(4 * (size_t)n_obj * n_pre);
+  L.total = c;
+  return L;
+}
+
+asicp_status pn_check(int n_obj, int n_pre, int n_seed) {
+  if (n_obj < 1 || n_obj > 65536) return pn_fail(ASICP_E_INVALID, "n_obj must be in 1..65536");
+  if (n_pre < 1 || n_seed < 1 || n_pre * n_seed * 7 > 1024)
+    return pn_fail(ASICP_E_INVALID, "n_pre * n_seed * 7 must be in 7..1024");
+  return ASICP_OK;
+}
+
+// validates the offsets (host) and fills the network descriptor; uploads the
+// offsets with the library's kernel-argument uploader
+asicp_status pn_setup(Net& n, const float* params, int n_pre, int n_seed, int n_obj, const int32_t* off,
+                      const float* x, const float* y, const float* z, void* ws, size_t ws_bytes,
+                      hipStream_t hs, int* max_chunks) {
+  asicp_status st = pn_check(n_obj, n_pre, n_seed);
+  if (st != ASICP_OK) return st;
+  if (!params || !off || !x || !y || !z || !ws) return pn_fail(ASICP_E_INVALID, "NULL pointer argument");
+  if (off[0] != 0) return pn_fail(ASICP_E_INVALID, "offsets must start at 0");
+  int mc = 0;
+  for (int o = 0; o < n_obj; ++o) {
+    const long long m = (long long)off[o + 1] - off[o];
+    if (m < 1 || m > (1 << 22)) return pn_fail(ASICP_E_INVALID, "object " + std::to_string(o) + " must have 1..4194304 points");
+    mc = std::max(mc, (int)((m + kPts - 1) / kPts));
+  }
+  const PnLayout L = pn_layout(n_obj, n_pre, n_seed);
+  if (ws_bytes < L.total) return pn_fail(ASICP_E_INVALID, "workspace too small");
+  char* b = static_cast<char*>(ws);
+  n.prm = params;
+  n.w2h = reinterpret_cast<unsigned short*>(b + L.w2h);
+  n.w3h = reinterpret_cast<unsigned short*>(b + L.w3h);
+  n.off = reinterpret_cast<const int32_t*>(b + L.off);
+  n.x = x; n.y = y; n.z = z;
+  n.com = reinterpret_cast<float*>(b + L.com);
+  n.pool = reinterpret_cast<unsigned long long*>(b + L.pool);
+  n.head = reinterpret_cast<float*>(b + L.head);
+  n.out = reinterpret_cast<float*>(b + L.out);
+  n.dout = reinterpret_cast<float*>(b + L.dout);
+  n.dhead = reinterpret_cast<float*>(b + L.dhead);
+  n.part = reinterpret_cast<float*>(b + L.part);
+  n.n_obj = n_obj; n.n_pre = n_pre; n.n_seed = n_seed; n.n_tgt = 0;
+  n.P = layout(n_pre, n_seed);
+  (void)hipGetLastError();
+  upload_words(b + L.off, off, 4 * (size_t)(n_obj + 1), hs);
+  *max_chunks = mc;
+  return ASICP_OK;
+}
+
+void pn_forward(const Net& n, int mc, float* seeds, hipStream_t hs) {
+  hipLaunchKernelGGL(k_pn_prep, dim3(n.n_obj + 1), dim3(256), 0, hs, n);
+  hipLaunchKernelGGL(k_pn_point_fwd, dim3(n.n_obj * mc), dim3(256), 0, hs, n, mc);
+  hipLaunchKernelGGL(k_pn_head_fwd, dim3(n.n_obj), dim3(256), 0, hs, n, seeds, n.n_obj * n.n_pre * n.n_seed);
+}
+
+asicp_status pn_launched(const char* what) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return pn_fail(ASICP_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+  return ASICP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* asicp_pn_last_error(void) { return pn_err.c_str(); }
+
+int64_t asicp_pn_param_count(int32_t n_pre, int32_t n_seed) {
+  if (n_pre < 1 || n_seed < 1 || n_pre * n_seed * 7 > 1024) return -1;
+  return layout(n_pre, n_seed).total;
+}
+
+asicp_status asicp_pn_workspace_bytes(int32_t n_obj, int32_t n_pre, int32_t n_seed, size_t* bytes) {
+  pn_err.clear();
+  if (!bytes) return pn_fail(ASICP_E_INVALID, "bytes must not be NULL");
+  const asicp_status st = pn_check(n_obj, n_pre, n_seed);
+  if (st != ASICP_OK) return st;
+  *bytes = pn_layout(n_obj, n_pre, n_seed).total;
+  return ASICP_OK;
+}
+
+asicp_status asicp_pn_forward(const float* params, int32_t n_pre, int32_t n_seed, int32_t n_obj,
+                              const int32_t* off, const float* x, const float* y, const float* z,
+                              float* seeds, float* raw, void* workspace, size_t ws_bytes, void* stream) {
+  pn_err.clear();
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  Net n;
+  int mc = 0;
+  asicp_status st = pn_setup(n, params, n_pre, n_seed, n_obj, off, x, y, z, workspace, ws_bytes, hs, &mc);
+  if (st != ASICP_OK) return st;
+  pn_forward(n, mc, seeds, hs);
+  if ((st = pn_launched("proposal forward")) != ASICP_OK) return st;
+  if (raw && hipMemcpyAsync(raw, n.out, 4 * (size_t)n_obj * n.P.O, hipMemcpyDeviceToDevice, hs) != hipSuccess)
+    return pn_fail(ASICP_E_HIP, "copying the raw outputs failed");
+  return ASICP_OK;
+}
+
+asicp_status asicp_pn_loss_grad(const float* params, int32_t n_pre, int32_t n_seed, int32_t n_obj,
+                                const int32_t* off, const float* x, const float* y, const float* z,
+                                const float* targets, int32_t n_targets, float* loss, float* grad,
+                                void* workspace, size_t ws_bytes, void* stream) {
+  pn_err.clear();
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  if (!targets || !loss || !grad) return pn_fail(ASICP_E_INVALID, "NULL pointer argument");
+  if (n_targets < 1 || n_targets > 4096) return pn_fail(ASICP_E_INVALID, "n_targets must be in 1..4096");
+  Net n;
+  int mc = 0;
+  asicp_status st = pn_setup(n, params, n_pre, n_seed, n_obj, off, x, y, z, workspace, ws_bytes, hs, &mc);
+  if (st != ASICP_OK) return st;
+  n.n_tgt = n_targets;
+  pn_forward(n, mc, nullptr, hs);
+  float* lpart = reinterpret_cast<float*>(static_cast<char*>(workspace) + pn_layout(n_obj, n_pre, n_seed).lpart);
+  const int pairs = n_obj * n_pre;
+  hipLaunchKernelGGL(k_pn_loss, dim3((pairs + 63) / 64), dim3(64), 0, hs, n, targets, lpart);
+  hipLaunchKernelGGL(k_pn_loss_sum, dim3((n_obj + 63) / 64), dim3(64), 0, hs, n, lpart, loss);
+  hipLaunchKernelGGL(k_pn_head_bwd, dim3(n_obj), dim3(256), 0, hs, n);
+  const long long head_elems = (long long)HH * H3 + HH + (long long)HH * HH + HH + (long long)n.P.O * HH + n.P.O;
+  hipLaunchKernelGGL(k_pn_head_wgrad, dim3((unsigned)((head_elems + 255) / 256)), dim3(256), 0, hs, n, grad);
+  hipLaunchKernelGGL(k_pn_point_bwd, dim3(n_obj), dim3(256), 0, hs, n);
+  hipLaunchKernelGGL(k_pn_reduce, dim3((kEnc + 255) / 256), dim3(256), 0, hs, n, grad);
+  return pn_launched("proposal loss and gradient");
+}
+
+asicp_status asicp_pn_adam(float* params, float* m, float* v, const float* grad, int64_t count, float lr,
+                           float beta1, float beta2, float eps, int32_t step, void* stream) {
+  pn_err.clear();
+  if (!params || !m || !v || !grad) return pn_fail(ASICP_E_INVALID, "NULL pointer argument");
+  if (count < 1 || step < 1 || !(lr > 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) ||
+      !(eps > 0.f))
+    return pn_fail(ASICP_E_INVALID, "bad Adam settings");
+  const float c1 = 1.f - std::pow(beta1, (float)step), c2 = 1.f - std::pow(beta2, (float)step);
+  hipLaunchKernelGGL(k_pn_adam, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, static_cast<hipStream_t>(stream),
+                     params, m, v, grad, (long long)count, lr, beta1, beta2, eps, c1, c2);
+  return pn_launched("Adam step");
+}
+
+}  // extern "C"

@@ -1,0 +1,140 @@
+"""GPU (HIP, gfx950) vs FP64 oracle for the learned grasp proposal.
+
+The oracle runs in its BF16 mode (the operands of the kernel's BF16 matrix
+products rounded the same way), so the remaining differences are FP32 versus
+FP64 accumulation.  No input and no expected value comes from the HIP path."""
+import numpy as np
+import pytest
+
+from oracle import proposal as OP
+import paper_2412_08346_amd.proposal as PP
+
+pytestmark = pytest.mark.gpu
+NPRE, NSEED = 3, 8
+
+
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def random_params(rng):
+    th = OP.init_params(NPRE, NSEED, rng)
+    # non-zero biases everywhere, output layer at a useful scale
+    sizes = [int(np.prod(s)) for s in OP.layer_shapes(NPRE, NSEED)]
+    o = 0
+    for k, n in enumerate(sizes):
+        if k % 2 == 1:
+            th[o:o + n] = rng.normal(0.0, 0.1, n)
+        if k == 10:
+            th[o:o + n] *= 30.0
+        o += n
+    return th.astype(np.float32).astype(np.float64)
+
+
+def clouds_for(rng, sizes):
+    return [(rng.standard_normal((m, 3)) * [0.04, 0.03, 0.02] + rng.uniform(-0.2, 0.2, 3)).astype(np.float32)
+            for m in sizes]
+
+
+def test_forward_matches_oracle_ragged_objects():
+    torch = _gpu()
+    rng = np.random.default_rng(11)
+    th = random_params(rng)
+    clouds = clouds_for(rng, [1, 63, 64, 65, 300, 5000])
+    net = PP.ProposalNet(NPRE, NSEED, max_obj=len(clouds), params=th.astype(np.float32))
+    seeds, raw = net.forward(clouds)
+    torch.cuda.synchronize()
+    raw = raw.cpu().numpy().astype(np.float64)
+    seeds = seeds.cpu().numpy().astype(np.float64)
+    for i, c in enumerate(clouds):
+        o, I = OP.forward(th, c.astype(np.float64), NPRE, NSEED, bf=True)
+        scale = max(np.abs(o).mean(), 1e-6)
+        err = np.abs(raw[i] - o).max()
+        say(f"[proposal] object {i} ({len(c)} points): max |raw - oracle| {err:.3g}, scale {scale:.3g}")
+        assert err <= 1e-3 * scale
+        s_or = OP.seeds(o, I["com"], NPRE, NSEED).reshape(-1, 7)
+        k = NPRE * NSEED
+        s_gpu = seeds[:, i * k:(i + 1) * k].T
+        assert np.abs(s_gpu[:, :3] - s_or[:, :3]).max() <= 1e-4 * (1 + np.abs(s_or[:, :3]).max())
+        assert np.abs(s_gpu[:, 3:] - s_or[:, 3:]).max() <= 2e-3
+        assert np.all(s_gpu[:, 3] >= 0)
+
+
+def gap_ok(th, c):
+    """True if no channel's max is nearly tied with another point's value
+    (the argmax, and so the gradient's route, would then be ambiguous)."""
+    _, I = OP.forward(th, c.astype(np.float64), NPRE, NSEED, bf=True)
+    h3 = I["h3"]
+    if h3.shape[0] < 2:
+        return True
+    top2 = np.sort(h3, axis=0)[-2:]
+    live = top2[1] > 0
+    gap = (top2[1] - top2[0])[live] / np.maximum(top2[1][live], 1e-30)
+    return bool(np.all(gap > 1e-4))
+
+
+def test_loss_and_gradient_match_oracle():
+    torch = _gpu()
+    rng = np.random.default_rng(12)
+    th = random_params(rng)
+    sizes = [2, 64, 130, 700, 2000]
+    clouds = []
+    while len(clouds) < len(sizes):
+        c = clouds_for(rng, [sizes[len(clouds)]])[0]
+        if gap_ok(th, c):
+            clouds.append(c)
+    T = 5
+    tg = np.concatenate([rng.uniform(-0.3, 0.3, (len(clouds), NPRE, T, 3)),
+                         rng.standard_normal((len(clouds), NPRE, T, 4))], -1)
+    tg[..., 3:] /= np.linalg.norm(tg[..., 3:], axis=-1, keepdims=True)
+    tg = tg.astype(np.float32)
+    net = PP.ProposalNet(NPRE, NSEED, max_obj=8, params=th.astype(np.float32))
+    loss = net.loss_grad(clouds, tg).cpu().numpy().astype(np.float64)
+    g_gpu = net.grad.cpu().numpy().astype(np.float64)
+    g_or = np.zeros_like(th)
+    for i, c in enumerate(clouds):
+        o, I = OP.forward(th, c.astype(np.float64), NPRE, NSEED, bf=True)
+        L, do = OP.loss(o, I["com"], tg[i].astype(np.float64), NPRE, NSEED)
+        assert loss[i] == pytest.approx(L, rel=1e-4, abs=1e-6)
+        g_or += OP.backward(th, I, do, NPRE, NSEED, bf=True) / len(clouds)
+    sizes_l = [int(np.prod(s)) for s in OP.layer_shapes(NPRE, NSEED)]
+    o = 0
+    for k, n in enumerate(sizes_l):
+        a, b = g_gpu[o:o + n], g_or[o:o + n]
+        scale = max(np.abs(b).max(), 1e-12)
+        err = np.abs(a - b).max()
+        say(f"[proposal] grad block {k}: max err {err:.3g} scale {scale:.3g}")
+        assert err <= 2e-3 * scale, k
+        o += n
+    # repeated calls are bitwise identical (fixed-order sums)
+    net.loss_grad(clouds, tg)
+    assert np.array_equal(net.grad.cpu().numpy(), g_gpu.astype(np.float32))
+
+
+def test_adam_step_matches_closed_form():
+    torch = _gpu()
+    rng = np.random.default_rng(13)
+    net = PP.ProposalNet(1, 1, max_obj=1)
+    n = net.n
+    p0 = rng.standard_normal(n).astype(np.float32)
+    g = rng.standard_normal(n).astype(np.float32)
+    m0 = rng.standard_normal(n).astype(np.float32) * 0.1
+    v0 = np.abs(rng.standard_normal(n)).astype(np.float32) * 0.1
+    net.params.copy_(torch.as_tensor(p0))
+    net.grad.copy_(torch.as_tensor(g))
+    net.m.copy_(torch.as_tensor(m0))
+    net.v.copy_(torch.as_tensor(v0))
+    net.step_count = 2
+    net.adam(lr=1e-2, beta1=0.9, beta2=0.99, eps=1e-8)
+    b1, b2, t = 0.9, 0.99, 3
+    m = b1 * m0.astype(np.float64) + (1 - b1) * g
+    v = b2 * v0.astype(np.float64) + (1 - b2) * g.astype(np.float64) ** 2
+    p = p0 - 1e-2 * (m / (1 - b1 ** t)) / (np.sqrt(v / (1 - b2 ** t)) + 1e-8)
+    assert np.allclose(net.params.cpu().numpy(), p, rtol=1e-5, atol=1e-6)
