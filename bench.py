@@ -69,6 +69,10 @@ def main():
     ap.add_argument("--workload", choices=("paper", "batched"), default="paper")
     ap.add_argument("--brute", action="store_true",
                     help="forward NN visits every object chunk (no exact pruning)")
+    ap.add_argument("--learned", action="store_true",
+                    help="plain against learned-seeded AS-ICP at matched final cost: trains the "
+                         "proposal network on grasps the solver finds (a few minutes) and prints one "
+                         "JSON line of the comparison instead of the throughput line")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch choices instead of timing them first")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -87,6 +91,16 @@ def main():
     from paper_2412_08346_amd import synth
 
     torch.cuda.set_device(0)
+    if args.learned:
+        from paper_2412_08346_amd import proposal
+        r = proposal.run_learned(log=lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
+        line = {"metric": METRIC, "value": r["learned"]["grasps_per_s"], "unit": "grasps/s (learned-seeded)",
+                "n_gpus": 1, "higher_is_better": True, "vs_baseline": None, "dtype": "f32",
+                "data": "synthetic", "config": {"workload": "64 held-out random objects (superquadrics and "
+                "box unions, 2k-8k points), 3 box-gripper preshapes x 4096 contact points; plain 256 Fibonacci "
+                "particles x 100 iterations per preshape vs 32 learned seeds x 30 iterations"}, **r}
+        print(json.dumps(line), flush=True)
+        return
     if args.calibrate_copy:
         n = args.calibrate_copy * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")

@@ -293,11 +293,14 @@ asicp_status asicp_pn_workspace_bytes(int32_t n_obj, int32_t n_pre, int32_t n_se
 
 /* Forward pass.  seeds (device, may be NULL): [7][n_obj * n_pre * n_seed]
  * poses (tx ty tz qw qx qy qz, q_w >= 0), particle order (object, preshape,
- * seed) -- the layout of asicp_problem.theta0.  raw (device, may be NULL):
- * [n_obj][n_pre * n_seed * 7] network outputs. */
+ * seed) -- the layout of asicp_problem.theta0 -- each backed off by
+ * `retract` metres along its approach axis (the gripper's +z, R(q) e_z), so
+ * that a seed predicted on the surface starts clear of it.  raw (device,
+ * may be NULL): [n_obj][n_pre * n_seed * 7] network outputs. */
 asicp_status asicp_pn_forward(const float* params, int32_t n_pre, int32_t n_seed, int32_t n_obj,
                               const int32_t* off, const float* x, const float* y, const float* z,
-                              float* seeds, float* raw, void* workspace, size_t ws_bytes, void* stream);
+                              float retract, float* seeds, float* raw, void* workspace, size_t ws_bytes,
+                              void* stream);
 
 /* Set loss per object against targets (device [n_obj][n_pre][n_targets][7]
  * poses, unit q): per preshape the symmetric Chamfer distance

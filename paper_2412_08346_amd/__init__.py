@@ -110,7 +110,7 @@ def load():
         L.asicp_pn_param_count.restype = C.c_int64
         L.asicp_pn_workspace_bytes.argtypes = [i32, i32, i32, C.POINTER(C.c_size_t)]
         L.asicp_pn_workspace_bytes.restype = i32
-        L.asicp_pn_forward.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]
+        L.asicp_pn_forward.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, C.c_float, vp, vp, vp, C.c_size_t, vp]
         L.asicp_pn_forward.restype = i32
         L.asicp_pn_loss_grad.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, vp, i32, vp, vp, vp, C.c_size_t, vp]
         L.asicp_pn_loss_grad.restype = i32
@@ -223,9 +223,9 @@ def asicp_pn_workspace_bytes(n_obj: int, n_pre: int, n_seed: int) -> int:
     return int(out.value)
 
 
-def asicp_pn_forward(params, n_pre, n_seed, n_obj, off, x, y, z, seeds, raw, ws, ws_bytes, stream):
+def asicp_pn_forward(params, n_pre, n_seed, n_obj, off, x, y, z, retract, seeds, raw, ws, ws_bytes, stream):
     return _pn_check(load().asicp_pn_forward(params, int(n_pre), int(n_seed), int(n_obj), off, x, y, z,
-                                             seeds, raw, ws, int(ws_bytes), C.c_void_p(stream)))
+                                             float(retract), seeds, raw, ws, int(ws_bytes), C.c_void_p(stream)))
 
 
 def asicp_pn_loss_grad(params, n_pre, n_seed, n_obj, off, x, y, z, targets, n_targets, loss, grad, ws,

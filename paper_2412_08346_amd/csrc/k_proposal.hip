@@ -207,7 +207,7 @@ __global__ __launch_bounds__(256) void k_pn_point_fwd(Net n, int chunks_per_obj)
 
 // ---------------------------------------------------------------------------
 // head: g -> u -> v -> o, and the seed poses (SoA, solver order)
-__global__ __launch_bounds__(256) void k_pn_head_fwd(Net n, float* seeds, int Ktot) {
+__global__ __launch_bounds__(256) void k_pn_head_fwd(Net n, float* seeds, int Ktot, float retract) {
   __shared__ float g[H3], u[HH], v[HH];
   const int o = blockIdx.x, tid = threadIdx.x;
   const unsigned long long key = n.pool[(size_t)o * H3 + tid];
@@ -248,10 +248,20 @@ __global__ __launch_bounds__(256) void k_pn_head_fwd(Net n, float* seeds, int Kt
     float qw = r[3], qx = r[4], qy = r[5], qz = r[6];
     const float nrm = sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
     const float s = (qw < 0.f ? -1.f : 1.f) / (nrm > 0.f ? nrm : 1.f);
-    seeds[(size_t)3 * Ktot + i] = nrm > 0.f ? qw * s : 1.f;
-    seeds[(size_t)4 * Ktot + i] = qx * s;
-    seeds[(size_t)5 * Ktot + i] = qy * s;
-    seeds[(size_t)6 * Ktot + i] = qz * s;
+    if (nrm > 0.f) {
+      qw *= s; qx *= s; qy *= s; qz *= s;
+    } else {
+      qw = 1.f; qx = qy = qz = 0.f;
+    }
+    seeds[(size_t)3 * Ktot + i] = qw;
+    seeds[(size_t)4 * Ktot + i] = qx;
+    seeds[(size_t)5 * Ktot + i] = qy;
+    seeds[(size_t)6 * Ktot + i] = qz;
+    // back the gripper off along its approach axis (third column of R(q))
+    const float ax = 2.f * (qx * qz + qw * qy), ay = 2.f * (qy * qz - qw * qx), az = 1.f - 2.f * (qx * qx + qy * qy);
+    seeds[(size_t)0 * Ktot + i] -= retract * ax;
+    seeds[(size_t)1 * Ktot + i] -= retract * ay;
+    seeds[(size_t)2 * Ktot + i] -= retract * az;
   }
 }
 
@@ -629,10 +639,11 @@ asicp_status pn_setup(Net& n, const float* params, int n_pre, int n_seed, int n_
   return ASICP_OK;
 }
 
-void pn_forward(const Net& n, int mc, float* seeds, hipStream_t hs) {
+void pn_forward(const Net& n, int mc, float* seeds, float retract, hipStream_t hs) {
   hipLaunchKernelGGL(k_pn_prep, dim3(n.n_obj + 1), dim3(256), 0, hs, n);
   hipLaunchKernelGGL(k_pn_point_fwd, dim3(n.n_obj * mc), dim3(256), 0, hs, n, mc);
-  hipLaunchKernelGGL(k_pn_head_fwd, dim3(n.n_obj), dim3(256), 0, hs, n, seeds, n.n_obj * n.n_pre * n.n_seed);
+  hipLaunchKernelGGL(k_pn_head_fwd, dim3(n.n_obj), dim3(256), 0, hs, n, seeds, n.n_obj * n.n_pre * n.n_seed,
+                     retract);
 }
 
 asicp_status pn_launched(const char* what) {
@@ -663,14 +674,16 @@ asicp_status asicp_pn_workspace_bytes(int32_t n_obj, int32_t n_pre, int32_t n_se
 
 asicp_status asicp_pn_forward(const float* params, int32_t n_pre, int32_t n_seed, int32_t n_obj,
                               const int32_t* off, const float* x, const float* y, const float* z,
-                              float* seeds, float* raw, void* workspace, size_t ws_bytes, void* stream) {
+                              float retract, float* seeds, float* raw, void* workspace, size_t ws_bytes,
+                              void* stream) {
   pn_err.clear();
   hipStream_t hs = static_cast<hipStream_t>(stream);
+  if (!std::isfinite(retract)) return pn_fail(ASICP_E_INVALID, "retract must be finite");
   Net n;
   int mc = 0;
   asicp_status st = pn_setup(n, params, n_pre, n_seed, n_obj, off, x, y, z, workspace, ws_bytes, hs, &mc);
   if (st != ASICP_OK) return st;
-  pn_forward(n, mc, seeds, hs);
+  pn_forward(n, mc, seeds, retract, hs);
   if ((st = pn_launched("proposal forward")) != ASICP_OK) return st;
   if (raw && hipMemcpyAsync(raw, n.out, 4 * (size_t)n_obj * n.P.O, hipMemcpyDeviceToDevice, hs) != hipSuccess)
     return pn_fail(ASICP_E_HIP, "copying the raw outputs failed");
@@ -690,7 +703,7 @@ asicp_status asicp_pn_loss_grad(const float* params, int32_t n_pre, int32_t n_se
   asicp_status st = pn_setup(n, params, n_pre, n_seed, n_obj, off, x, y, z, workspace, ws_bytes, hs, &mc);
   if (st != ASICP_OK) return st;
   n.n_tgt = n_targets;
-  pn_forward(n, mc, nullptr, hs);
+  pn_forward(n, mc, nullptr, 0.f, hs);
   float* lpart = reinterpret_cast<float*>(static_cast<char*>(workspace) + pn_layout(n_obj, n_pre, n_seed).lpart);
   const int pairs = n_obj * n_pre;
   hipLaunchKernelGGL(k_pn_loss, dim3((pairs + 63) / 64), dim3(64), 0, hs, n, targets, lpart);

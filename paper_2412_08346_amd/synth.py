@@ -442,16 +442,34 @@ def workload_batched(n_obj: int = 64, K: int = 128, k_max: int = 100, m_lo: int 
     """Many objects of uneven size in one batch: point counts log-uniform in
     [m_lo, m_hi], superquadrics and unions of 1-3 boxes alternating, 1 mm
     noise; the three preshapes of the paper-scale workload; K particles each."""
+    objs = random_objects(n_obj, m_lo, m_hi, seed)
+    return workload_objects(objs, K, k_max, n, grid_n), Settings(k_max=k_max, k_stein=k_max)
+
+
+def random_objects(n_obj: int, m_lo: int, m_hi: int, seed: int) -> list:
+    """n_obj clouds of log-uniform size in [m_lo, m_hi]: superquadrics and
+    unions of 1-3 boxes alternating, 1 mm noise."""
     rng = np.random.default_rng(seed)
     objs = []
     for o in range(n_obj):
         m = int(round(math.exp(rng.uniform(math.log(m_lo), math.log(m_hi)))))
         objs.append(superquadric(m, rng) if o % 2 == 0 else box_union_object(m, rng))
+    return objs
+
+
+def workload_objects(objs: list, K: int, k_max: int = 100, n: int = 4096, grid_n: int = 128,
+                     theta0: np.ndarray | None = None) -> Problem:
+    """The given object clouds with the three preshapes of the paper-scale
+    workload (finger gaps 4 / 6 / 8 cm, n contact points, grid_n^3 SDF at
+    1.5 mm) and K Fibonacci particles per (object, preshape), or the poses
+    theta0 (7, n_obj * 3 * K) when given."""
     gaps = (0.04, 0.06, 0.08)
     pre = [gripper_contact_cloud(g, n, np.random.default_rng((3, i))) for i, g in enumerate(gaps)]
     grids = [gripper_sdf_grid(g, grid_n, 0.0015) for g in gaps]
     pb = _assemble(objs, pre, grids, K, [standoff(o) for o in objs])
-    return pb, Settings(k_max=k_max, k_stein=k_max)
+    if theta0 is not None:
+        pb.theta0 = np.ascontiguousarray(theta0, np.float32)
+    return pb
 
 
 def random_poses(k: int, anchor: np.ndarray, radius: float, rng: np.random.Generator) -> np.ndarray:
