@@ -272,6 +272,15 @@ def run_learned(n_train: int = 1024, n_eval: int = 64, steps: int = 3000, n_seed
     seeds, _ = net.forward(eval_objs, retract=retract)
     torch.cuda.synchronize()
     t_fwd = time.perf_counter() - t0
+    iters_list = seeded_iters if isinstance(seeded_iters, (list, tuple)) else [seeded_iters]
+    extra = {}
+    for it in iters_list[1:]:
+        pb_x, r_x, w_x = solve(eval_objs, K=n_seed, k_max=it, theta0=seeds.cpu().numpy())
+        rx = best_per_object(pb_x, r_x) / best_p
+        extra[f"learned_{it}_iterations"] = {"solve_s": w_x, "grasps_per_s": n_eval / (w_x + t_fwd),
+                                             "median_cost_ratio": float(np.median(rx)),
+                                             "matched_fraction": float(np.mean(rx <= 1.02))}
+    seeded_iters = iters_list[0]
     pb_l, r_l, w_l = solve(eval_objs, K=n_seed, k_max=seeded_iters, theta0=seeds.cpu().numpy())
     best_l = best_per_object(pb_l, r_l)
     pb_f, r_f, w_f = solve(eval_objs, K=n_seed, k_max=seeded_iters)
@@ -296,5 +305,6 @@ def run_learned(n_train: int = 1024, n_eval: int = 64, steps: int = 3000, n_seed
                     "particle_iters_per_s": n_eval * P * n_seed * seeded_iters / w_l, **cmp(best_l)},
         "fibonacci_same_budget": {"particles_per_preshape": n_seed, "iterations": seeded_iters, "solve_s": w_f,
                                   "grasps_per_s": n_eval / w_f, **cmp(best_f)},
+        **extra,
     }
     return out
