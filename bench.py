@@ -98,7 +98,8 @@ def main():
                 "n_gpus": 1, "higher_is_better": True, "vs_baseline": None, "dtype": "f32",
                 "data": "synthetic", "config": {"workload": "64 held-out random objects (superquadrics and "
                 "box unions, 2k-8k points), 3 box-gripper preshapes x 4096 contact points; plain 256 Fibonacci "
-                "particles x 100 iterations per preshape vs 32 learned seeds x 30 iterations"}, **r}
+                "particles x 100 annealed Stein iterations per preshape vs 32 learned seeds x 50 SGD-ICP "
+                "iterations"}, **r}
         print(json.dumps(line), flush=True)
         return
     if args.calibrate_copy:

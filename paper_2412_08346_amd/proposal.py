@@ -116,14 +116,14 @@ class ProposalNet:
 # self-supervised data, training and evaluation
 
 def solve(objs, K: int, k_max: int, theta0=None, T0: float = 1.0, T1: float = 0.01, launch=None,
-          warm: bool = True):
+          warm: bool = True, k_stein: int | None = None):
     """Plain (Fibonacci) or seeded AS-ICP on the objects with the paper-scale
     preshapes; returns (problem, per-particle result, wall seconds of the
     timed solve).  With warm, one untimed solve runs first."""
     import time
     import torch
     pb = synth.workload_objects(objs, K, k_max, theta0=theta0)
-    st = synth.Settings(k_max=k_max, k_stein=k_max, T0=T0, T1=T1)
+    st = synth.Settings(k_max=k_max, k_stein=k_max if k_stein is None else k_stein, T0=T0, T1=T1)
     s = Solver(pb, st)
     if launch is not None:
         s.set_launch(**launch)
@@ -229,7 +229,8 @@ def best_per_object(pb, r):
 
 
 def run_learned(n_train: int = 1024, n_eval: int = 64, steps: int = 3000, n_seed: int = 32,
-                seeded_iters: int = 30, retract: float = 0.02, m_lo: int = 2048, m_hi: int = 8192,
+                seeded_iters: int = 50, seeded_k_stein: int = 0, retract: float = 0.03,
+                m_lo: int = 2048, m_hi: int = 8192,
                 plain_k: int = 256, plain_iters: int = 100, n_targets: int = 16, seed: int = 0, log=None):
     """Self-supervised pipeline and the comparison at matched final cost.
 
@@ -239,8 +240,11 @@ def run_learned(n_train: int = 1024, n_eval: int = 64, steps: int = 3000, n_seed
     2. Training: Adam with rotation augmentation.
     3. Held-out objects: plain AS-ICP (plain_k particles x plain_iters
        iterations per preshape) against learned seeds (n_seed x
-       seeded_iters) and against the same small budget from Fibonacci seeds
-       (no network).  Per object the lowest collision-free cost; a run is
+       seeded_iters, backed off `retract`) and against the same small budget
+       from Fibonacci seeds (no network).  The seeded runs refine with the
+       first seeded_k_stein iterations Stein and the rest SGD-ICP (eq. 3,
+       with the convergence freeze): good seeds need local refinement, not
+       exploration.  Per object the lowest collision-free cost; a run is
        matched when it is within 2 % of plain's.
     Returns a dict of the measured numbers."""
     import time
@@ -275,15 +279,16 @@ def run_learned(n_train: int = 1024, n_eval: int = 64, steps: int = 3000, n_seed
     iters_list = seeded_iters if isinstance(seeded_iters, (list, tuple)) else [seeded_iters]
     extra = {}
     for it in iters_list[1:]:
-        pb_x, r_x, w_x = solve(eval_objs, K=n_seed, k_max=it, theta0=seeds.cpu().numpy())
+        pb_x, r_x, w_x = solve(eval_objs, K=n_seed, k_max=it, theta0=seeds.cpu().numpy(), k_stein=seeded_k_stein)
         rx = best_per_object(pb_x, r_x) / best_p
         extra[f"learned_{it}_iterations"] = {"solve_s": w_x, "grasps_per_s": n_eval / (w_x + t_fwd),
                                              "median_cost_ratio": float(np.median(rx)),
                                              "matched_fraction": float(np.mean(rx <= 1.02))}
     seeded_iters = iters_list[0]
-    pb_l, r_l, w_l = solve(eval_objs, K=n_seed, k_max=seeded_iters, theta0=seeds.cpu().numpy())
+    pb_l, r_l, w_l = solve(eval_objs, K=n_seed, k_max=seeded_iters, theta0=seeds.cpu().numpy(),
+                           k_stein=seeded_k_stein)
     best_l = best_per_object(pb_l, r_l)
-    pb_f, r_f, w_f = solve(eval_objs, K=n_seed, k_max=seeded_iters)
+    pb_f, r_f, w_f = solve(eval_objs, K=n_seed, k_max=seeded_iters, k_stein=seeded_k_stein)
     best_f = best_per_object(pb_f, r_f)
 
     def cmp(best):
@@ -300,10 +305,12 @@ def run_learned(n_train: int = 1024, n_eval: int = 64, steps: int = 3000, n_seed
                   "grasps_per_s": n_eval / w_p,
                   "particle_iters_per_s": n_eval * P * plain_k * plain_iters / w_p,
                   "collision_free_objects": int(np.isfinite(best_p).sum())},
-        "learned": {"particles_per_preshape": n_seed, "iterations": seeded_iters, "retract_m": retract,
+        "learned": {"particles_per_preshape": n_seed, "iterations": seeded_iters, "stein_iterations": seeded_k_stein,
+                    "retract_m": retract,
                     "solve_s": w_l, "forward_s": t_fwd, "grasps_per_s": n_eval / (w_l + t_fwd),
                     "particle_iters_per_s": n_eval * P * n_seed * seeded_iters / w_l, **cmp(best_l)},
-        "fibonacci_same_budget": {"particles_per_preshape": n_seed, "iterations": seeded_iters, "solve_s": w_f,
+        "fibonacci_same_budget": {"particles_per_preshape": n_seed, "iterations": seeded_iters,
+                                  "stein_iterations": seeded_k_stein, "solve_s": w_f,
                                   "grasps_per_s": n_eval / w_f, **cmp(best_f)},
         **extra,
     }
