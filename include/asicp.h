@@ -239,7 +239,8 @@ asicp_status asicp_set_launch(asicp_ctx ctx, const asicp_launch_t* in);
  * events on `stream`), keep the fastest and return it in `chosen` (may be
  * NULL); ms_out (host, may be NULL) receives the average time per
  * evaluation of each choice, index 2 * xcd_map + fine.  Synchronises
- * `stream`.  The solve's state and its pair counter are left as they were;
+ * `stream`.  The solve's state is left as it was (tuning launches are not
+ * counted by asicp_kernel_time);
  * a captured asicp_replay graph is discarded.  Results never depend on the
  * choice, so tuning cannot change what a solve returns. */
 asicp_status asicp_autotune(asicp_ctx ctx, int32_t reps, void* stream, asicp_launch_t* chosen,
@@ -255,8 +256,9 @@ asicp_status asicp_result(asicp_ctx ctx, asicp_result_t* out, void* stream);
  * launches enqueued so far by asicp_step / asicp_solve / asicp_cost_grad,
  * from HIP events recorded on the launch stream
  * around each launch, and (nn_pairs, may be NULL) the number of (contact
- * point, object point) distances those launches evaluated.  Synchronises on
- * the events. */
+ * point, object point) distances those launches evaluated (each forward
+ * wave counts into a slot of its own, summed here on the host).
+ * Synchronises on the events. */
 asicp_status asicp_kernel_time(asicp_ctx ctx, double* total_ms, int32_t* launches, double* nn_pairs);
 
 /* Release the context (host memory and HIP events only). NULL is a no-op. */

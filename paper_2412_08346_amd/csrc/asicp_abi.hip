@@ -26,7 +26,7 @@ constexpr int kMaxGroups = 1 << 16;
 
 struct Layout {
   size_t groups, objs, pres, obj_prep, pre_prep, obj_pts, pre_pts, obj_perm, pre_perm, obj_box, pre_box;
-  size_t sort_keys, counters, obj_com, pre_const, col_pts, col_perm, obj_prep_mb, batch_mark, prior;
+  size_t sort_keys, wave_pairs, obj_com, pre_const, col_pts, col_perm, obj_prep_mb, batch_mark, prior;
   size_t theta, cost, col_cost, prev_cost, ncol, converged, grad, grad_ct, grad_col, phi, h, bw_hist, bw_state;
   size_t nn_part, col_part, pen_part, best, best_theta, flags, dbg_nn, dbg_rev;
   size_t total;
@@ -43,6 +43,7 @@ struct Shape {
   bool prior;
   long long total_waves, total_gate_wgs;
   bool debug;
+  bool timing;
 };
 
 size_t bump(size_t& cur, size_t bytes) {
@@ -72,7 +73,7 @@ Layout layout_of(const Shape& s) {
   L.batch_mark = s.minibatch ? bump(c, (size_t)s.r_total) : 0;
   L.prior = s.prior ? bump(c, 48 * (size_t)s.G) : 0;
   L.col_perm = bump(c, (size_t)(s.c_total > 0 ? s.c_total : 1) * 4);
-  L.counters = bump(c, 16);
+  L.wave_pairs = s.timing ? bump(c, 8 * (size_t)s.total_waves) : 0;
   L.obj_com = bump(c, 16 * (size_t)s.n_obj);
   L.pre_const = bump(c, 32 * (size_t)s.n_pre);
   L.theta = bump(c, 4 * 7 * K);
@@ -230,6 +231,7 @@ asicp_status validate(const asicp_problem* pb, const asicp_config* cfg, Shape& s
     }
   }
   s.debug = (cfg->flags & ASICP_FLAG_DEBUG) != 0;
+  s.timing = (cfg->flags & ASICP_FLAG_TIMING) != 0;
   return ASICP_OK;
 }
 
@@ -240,8 +242,6 @@ asicp_status check_launch(const char* what) {
 }
 
 }  // namespace
-
-__global__ void k_set_u64(unsigned long long* dst, unsigned long long v) { *dst = v; }
 
 __global__ void k_set_theta(float* dst, const float* src, int n) {
   const int i = blockIdx.x * 256 + threadIdx.x;
@@ -385,7 +385,7 @@ asicp_status asicp_create(const asicp_problem* pb, const asicp_config* cfg, void
   d.sort_keys = reinterpret_cast<unsigned long long*>(ws + L.sort_keys);
   d.col_pts = reinterpret_cast<float4*>(ws + L.col_pts);
   d.col_perm = reinterpret_cast<int32_t*>(ws + L.col_perm);
-  d.counters = reinterpret_cast<unsigned long long*>(ws + L.counters);
+  d.wave_pairs = s.timing ? reinterpret_cast<unsigned long long*>(ws + L.wave_pairs) : nullptr;
   d.prune = (cfg->flags & ASICP_FLAG_NO_PRUNE) ? 0 : 1;
   d.obj_com = reinterpret_cast<float*>(ws + L.obj_com);
   d.pre_const = reinterpret_cast<float*>(ws + L.pre_const);
@@ -706,11 +706,13 @@ asicp_status asicp_kernel_time(asicp_ctx c, double* total_ms, int32_t* launches,
       return fail(ASICP_E_HIP, "hipEventElapsedTime failed");
     tot += ms;
   }
-  if (nn_pairs) {
-    unsigned long long cnt = 0;
-    if (c->n_timed > 0 && hipMemcpy(&cnt, c->d.counters, sizeof cnt, hipMemcpyDeviceToHost) != hipSuccess)
-      return fail(ASICP_E_HIP, "reading the pair counter failed");
-    *nn_pairs = (double)cnt;
+  if (nn_pairs) {  // one slot per forward wave (no shared counter to contend for)
+    std::vector<unsigned long long> per((size_t)c->d.total_waves, 0ull);
+    if (c->n_timed > 0 && hipMemcpy(per.data(), c->d.wave_pairs, 8 * per.size(), hipMemcpyDeviceToHost) != hipSuccess)
+      return fail(ASICP_E_HIP, "reading the pair counts failed");
+    double cnt = 0.0;
+    for (unsigned long long v : per) cnt += (double)v;
+    *nn_pairs = cnt;
   }
   *total_ms = tot;
   *launches = c->n_timed;
@@ -752,10 +754,6 @@ asicp_status asicp_autotune(asicp_ctx c, int32_t reps, void* stream, asicp_launc
     const double full = 2.0 * (double)c->cfg.k_max / 3.0;
     launch_minibatch(c->d, k, ((double)k < full ? (double)k : full) / full, hs);
   }
-  unsigned long long cnt0 = 0;
-  if (hipMemcpyAsync(&cnt0, c->d.counters, sizeof cnt0, hipMemcpyDeviceToHost, hs) != hipSuccess ||
-      hipStreamSynchronize(hs) != hipSuccess)
-    return fail(ASICP_E_HIP, "reading the pair counter failed");
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     if (e0) (void)hipEventDestroy(e0);
@@ -772,6 +770,7 @@ asicp_status asicp_autotune(asicp_ctx c, int32_t reps, void* stream, asicp_launc
   bool ok = true;
   for (int v = 0; v < 4 && ok; ++v) {  // v = 2 * xcd_map + fine
     Dev dv = c->d;
+    dv.wave_pairs = nullptr;  // tuning launches are not counted
     dv.xcd_map = v >> 1;
     dv.fine = v & 1;
     ok = timed([&] { launch_nn_forward(dv, hs); }, &nn_ms[v]);
@@ -780,8 +779,7 @@ asicp_status asicp_autotune(asicp_ctx c, int32_t reps, void* stream, asicp_launc
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (!ok) return fail(ASICP_E_HIP, "timing a launch variant failed");
-  hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, hs, c->d.counters, cnt0);
-  asicp_status st = check_launch("autotune");
+  const asicp_status st = check_launch("autotune");
   if (st != ASICP_OK) return st;
   int bestv = 2 * c->d.xcd_map + c->d.fine;  // keep the current choice unless another is faster
   for (int v = 0; v < 4; ++v) {

@@ -92,7 +92,8 @@ struct Dev {
   float4* col_pts;    // collision clouds in Morton order (offsets as the input's)
   int32_t* col_perm;
   unsigned long long* sort_keys;
-  unsigned long long* counters;  // [0]: forward-NN distance evaluations
+  unsigned long long* wave_pairs;  // [total_waves] distances evaluated per forward wave,
+                                   //   summed over launches (ASICP_FLAG_TIMING only, else NULL)
   int32_t prune;                 // skip object chunks that cannot hold a nearest neighbour
   float* obj_com;   // [n_obj][4]
   float* pre_const; // [n_pre][8]: tcp xyz, rho2, a_t, a_w, -, -

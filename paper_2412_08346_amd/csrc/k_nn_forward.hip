@@ -128,7 +128,9 @@ __device__ __forceinline__ void nn_forward_body(const Dev& d) {
     float* out = d.nn_part + ((size_t)i * d.max_waves_pp + chunk) * kPartStride;
     out[0] = e2; out[1] = ex; out[2] = ey; out[3] = ez;
     out[4] = mx; out[5] = my_; out[6] = mz; out[7] = cnt;
-    atomicAdd(d.counters, (unsigned long long)pairs);
+    // the wave's own slot: launches are ordered on the stream, so a plain
+    // read-modify-write accumulates over them without contention
+    if (d.wave_pairs) d.wave_pairs[wave] += (unsigned long long)pairs;
   }
 }
 

@@ -277,7 +277,8 @@ __global__ __launch_bounds__(256) void k_setup_state(Dev d, const float* theta0,
   }
   for (int w = i; w < d.G * 256; w += gridDim.x * 256) d.bw_hist[w] = 0u;
   if (i < 4) d.flags[i] = 0;
-  if (i < 2) d.counters[i] = 0ull;
+  if (d.wave_pairs)
+    for (int w = i; w < d.total_waves; w += gridDim.x * 256) d.wave_pairs[w] = 0ull;
   if (i >= d.Ktot) return;
   const int K = d.Ktot;
   for (int a = 0; a < 7; ++a) d.theta[a * K + i] = theta0[a * K + i];
