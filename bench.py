@@ -17,15 +17,14 @@ sys.path.insert(0, ROOT)
 METRIC = "particle-iters/s & grasps/s at matched final cost: plain vs learned-seeded"
 PEAK_FP32_MFMA = 157.3e12  # MI355X dense fp32 matrix peak, FLOP/s
 FLOP_PER_PAIR = 6          # 3 multiply-adds of |r|^2 - 2 r.s per (query, object point) pair
-# HBM bytes per launch of the forward-NN kernel (dispatch-order XCD placement,
-# per-query chunk test) on the paper-scale workload, from two rocprofv3 --pmc
-# passes: 2.000 x FETCH_SIZE + 1.000 x WRITE_SIZE (KiB per dispatch, factors
-# from a 256 MiB device copy), averaged over the 101 launches of one solve
+# HBM bytes per launch of the forward-NN kernel on the paper-scale workload,
+# per launch choice, from two rocprofv3 --pmc passes: 2.000 x FETCH_SIZE +
+# 1.000 x WRITE_SIZE (KiB per dispatch, factors from a 256 MiB device copy),
+# averaged over the 101 launches of one solve
 # (profiles/nn_forward_counters_paper_scale.md).  Reported only while the
 # kernel's sources hash to the ones measured.
-NN_TRAFFIC = {"bytes": 5632041, "fetch_bytes": 2486313, "write_bytes": 3145728,
-              "sha256": "69099fc82fd0574ccc7c00e3a0c97e56e588bae22722e930cd9f303d5bd6526d",
-              "launch": {"xcd_map": 1, "fine": 1}}
+NN_TRAFFIC = {"sha256": "ecbb779fade74d0e55dd0272cfc28fa7762d98edb5bcb7e8b139a347bbccc13d",
+              "bytes": {"1,0": 6023150, "1,1": 6051705}}  # launch "map,fine" -> bytes per launch
 NN_SOURCES = ("k_nn_forward.hip", "nn_core.h", "asicp_internal.h")
 
 
@@ -35,9 +34,9 @@ def nn_traffic(workload, launch, brute):
     for f in NN_SOURCES:
         with open(os.path.join(ROOT, "paper_2412_08346_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
-    if h.hexdigest() != NN_TRAFFIC["sha256"] or workload != "paper" or brute or launch != NN_TRAFFIC["launch"]:
+    if h.hexdigest() != NN_TRAFFIC["sha256"] or workload != "paper" or brute:
         return None
-    return NN_TRAFFIC["bytes"]
+    return NN_TRAFFIC["bytes"].get(f"{launch['xcd_map']},{launch['fine']}")
 
 
 def cpu_baseline(pb, st, iters=1):
@@ -73,6 +72,9 @@ def main():
                     help="plain against learned-seeded AS-ICP at matched final cost: trains the "
                          "proposal network on grasps the solver finds (a few minutes) and prints one "
                          "JSON line of the comparison instead of the throughput line")
+    ap.add_argument("--launch", default=None, metavar="MAP,FINE",
+                    help="use this launch choice (XCD placement 0/1, per-query chunk test 0/1) "
+                         "instead of tuning")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch choices instead of timing them first")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -139,7 +141,10 @@ def main():
     # time them outside the timed region on the poses at k = 0, k_max/3 and
     # 2 k_max/3 of a solve, and use the fastest in total for every timed solve
     solver.reset()
-    if args.no_autotune:
+    if args.launch:
+        mp, fn = (int(v) for v in args.launch.split(","))
+        launch, launch_ms = {"xcd_map": mp, "fine": fn}, None
+    elif args.no_autotune:
         launch, launch_ms = solver.launch(), None
     else:
         launch_ms = [0.0] * 4
