@@ -3,7 +3,9 @@
 //   k_bw_pass     x4: h of the RBF kernel (eq. 9), the lower median of
 //                 |t_i - t_j|^2 over pairs i < j divided by ln K and floored,
 //                 found exactly by a radix select over the FP32 bit patterns
-//                 (monotone for non-negative floats), 8 bits per pass;
+//                 (monotone for non-negative floats), 8 bits per pass
+//                 (k_bw_fused instead: all four passes in one workgroup per
+//                 group when K <= 256);
 //   k_svgd_phi    Stein direction in the 6-D tangent: kernel-weighted mean of
 //                 the preconditioned driving terms -gamma A g_j (g_j minus the
 //                 log-prior gradient when a prior is given, eq. 8) plus tau times
@@ -118,6 +120,105 @@ __global__ __launch_bounds__(256) void k_bw_pass(Dev d, int pass, float inv_log_
     for (int r = 0; r < 4; ++r) ghist[4 * tid + r] = 0u;
     if (tid == 0) state[3] = 0u;
   }
+}
+
+// The same radix select in one workgroup of 1024 threads per group, for
+// K (K - 1) / 2 <= 32768 unordered pairs (K <= 256): each thread keeps the bit
+// patterns of its (at most 32) pairs in registers, so the distances are formed
+// once and the four passes only rebuild the LDS histogram and pick a digit,
+// with no global histogram, no last-workgroup hand-off and one launch instead
+// of four.  Pair slot s is {i, (i + d) mod K} with i = s mod K, d = s / K + 1:
+// d runs over 1 .. floor((K - 1) / 2) for every i, and for even K the slots
+// d = K / 2, i < K / 2 follow, so each unordered pair appears once.
+constexpr int kBwRegs = 32;
+__global__ __launch_bounds__(1024) void k_bw_fused(Dev d, float inv_log_k) {
+  __shared__ float st[256 * 3];
+  __shared__ unsigned int hist[256];
+  __shared__ unsigned int s_sel[3];  // prefix, mask, rank
+  const int g = blockIdx.x, tid = threadIdx.x, lane = tid & 63, K = d.K, Kt = d.Ktot;
+  for (int j = tid; j < 3 * K; j += 1024) {
+    const int a = j / K, p = j - a * K;
+    st[3 * p + a] = d.theta[a * Kt + g * K + p];
+  }
+  if (tid < 256) hist[tid] = 0u;
+  __syncthreads();
+  const int P = K * (K - 1) / 2;
+  const int step_d = 1024 / K, step_i = 1024 - step_d * K;
+  int pi = tid % K, pd = tid / K + 1;
+  unsigned int bits[kBwRegs];
+  // distances, and the first-pass histogram (sign and exponent bits: few
+  // distinct digits per wave, so one atomic per digit and wave)
+#pragma unroll
+  for (int r = 0; r < kBwRegs; ++r) {
+    bits[r] = 0u;
+    if (r * 1024 < P) {
+      bool act = r * 1024 + tid < P;
+      if (act) {
+        int pj = pi + pd;
+        pj -= pj >= K ? K : 0;
+        const float dx = st[3 * pi] - st[3 * pj], dy = st[3 * pi + 1] - st[3 * pj + 1],
+                    dz = st[3 * pi + 2] - st[3 * pj + 2];
+        bits[r] = __float_as_uint(__builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx)));
+      }
+      const unsigned int dig = bits[r] >> 24;
+      unsigned long long pending = __ballot(act);
+      while (pending) {
+        const int leader = __builtin_ctzll(pending);
+        const unsigned int b = __builtin_amdgcn_readlane(dig, leader);
+        const unsigned long long same = __ballot(act && dig == b);
+        if (lane == leader) atomicAdd(&hist[b], (unsigned int)__popcll(same));
+        act = act && dig != b;
+        pending &= ~same;
+      }
+      pi += step_i;
+      pd += step_d;
+      if (pi >= K) {
+        pi -= K;
+        pd += 1;
+      }
+    }
+  }
+  unsigned int prefix = 0u, mask = 0u, rank = (unsigned int)(P - 1) / 2u;
+  for (int pass = 0; pass < 4; ++pass) {
+    const int shift = 24 - 8 * pass;
+    if (pass > 0) {
+#pragma unroll
+      for (int r = 0; r < kBwRegs; ++r)
+        if (r * 1024 + tid < P && (bits[r] & mask) == prefix) atomicAdd(&hist[(bits[r] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    if (tid < 64) {
+      unsigned int c[4], run = 0u;
+      for (int r = 0; r < 4; ++r) {
+        c[r] = hist[4 * tid + r];
+        run += c[r];
+      }
+      unsigned int incl = run;
+      for (int off = 1; off < 64; off <<= 1) {
+        const unsigned int o = __shfl_up(incl, off, 64);
+        if (tid >= off) incl += o;
+      }
+      const unsigned int excl = incl - run;
+      if (rank >= excl && rank < incl) {
+        unsigned int cum = excl;
+        for (int r = 0; r < 4; ++r) {
+          if (rank < cum + c[r]) {
+            s_sel[0] = prefix | ((unsigned int)(4 * tid + r) << shift);
+            s_sel[1] = mask | (255u << shift);
+            s_sel[2] = rank - cum;
+            break;
+          }
+          cum += c[r];
+        }
+      }
+      for (int r = 0; r < 4; ++r) hist[4 * tid + r] = 0u;
+    }
+    __syncthreads();
+    prefix = s_sel[0];
+    mask = s_sel[1];
+    rank = s_sel[2];  // rewritten only after the next pass's first barrier
+  }
+  if (tid == 0) d.h[g] = fmaxf(__uint_as_float(prefix) * inv_log_k, d.h_min);
 }
 
 // bandwidth without a median: fixed h, or h = 1 for a single particle
@@ -241,9 +342,12 @@ __global__ __launch_bounds__(256) void k_svgd_apply(Dev d) {
 
 void launch_svgd(const Dev& d, float gamma, float tau, float inv_log_k, hipStream_t s) {
   if (d.K >= 2 && d.bw_mode == ASICP_BW_MEDIAN) {
-    const int slices = kBwSlices;
-    for (int pass = 0; pass < 4; ++pass)
-      hipLaunchKernelGGL(k_bw_pass, dim3(slices, d.G), dim3(256), 0, s, d, pass, inv_log_k);
+    if (d.K * (d.K - 1) / 2 <= kBwRegs * 1024) {
+      hipLaunchKernelGGL(k_bw_fused, dim3(d.G), dim3(1024), 0, s, d, inv_log_k);
+    } else {
+      for (int pass = 0; pass < 4; ++pass)
+        hipLaunchKernelGGL(k_bw_pass, dim3(kBwSlices, d.G), dim3(256), 0, s, d, pass, inv_log_k);
+    }
   } else {
     hipLaunchKernelGGL(k_bw_const, dim3((d.G + 255) / 256), dim3(256), 0, s, d);
   }

@@ -195,6 +195,18 @@ def test_small_first_step():
     say("[parity] small first step", out)
 
 
+@pytest.mark.parametrize("K", [2, 255, 256, 257, 300])
+def test_bandwidth_on_both_sides_of_one_workgroup(K):
+    """The median bandwidth (eq. 9) comes from one workgroup per group up to
+    K = 256 and from the sliced four-launch select above; both must give the
+    oracle's lower median.  Checked on the first step and one later step."""
+    pb, st = synth.workload_small(K=K)
+    out = compare_step(pb, st, pb.theta0, 0, label=f"bandwidth K={K}")
+    say(f"[parity] bandwidth K={K}", out)
+    th, pc, cv = oracle_trajectory(pb, st, [3])[3]
+    compare_step(pb, st, th, 3, pc, cv, label=f"bandwidth K={K} k=3")
+
+
 def test_small_teacher_forced_steps():
     pb, st = synth.workload_small()
     ks = [1, 5, 9, 14, 20, 29]
