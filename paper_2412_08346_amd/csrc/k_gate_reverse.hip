@@ -5,7 +5,7 @@
 // point is moved into the gripper frame, c' = R^T (c - t), and looked up in
 // the preshape's SDF by trilinear interpolation; it collides when it lies in
 // the node box and the value is strictly negative.  Colliding points are
-// compacted in a fixed order and paired with their nearest contact point in
+// compacted in the cloud's order and paired with their nearest contact point in
 // the gripper frame (a rigid motion preserves distances, so this is the
 // nearest transformed contact point of eq. (18)).  Partial sums, gripper
 // frame: [sum |s - c'|^2, sum (s - c') (3), sum s x (s - c') (3), count].
@@ -19,6 +19,7 @@
 namespace asicp {
 
 constexpr int kPerThread = kGateChunk / 256;
+constexpr int kGateBatch = 4;  // points whose SDF node values are in flight together
 
 // Workgroup placement over the XCDs, as for the forward kernel (MAP 0:
 // contiguous work per XCD, MAP 1: dispatch order); changes no result.
@@ -29,11 +30,12 @@ __device__ __forceinline__ int xcd_logical_g(int b, int nwg) {
   return (b & 7) * per + (b >> 3);
 }
 
-// Trilinear SDF at a gripper-frame point.  Returns true if the point
-// collides (inside the node box, value strictly negative); then *phi holds
-// the value and, if grad is given, grad the interpolant's gradient.
-__device__ __forceinline__ bool sdf_collides(const PreInfo& pi, float px, float py, float pz,
-                                             float* phi = nullptr, float* grad = nullptr) {
+// Cell of a gripper-frame point for the trilinear SDF: false if the point
+// lies outside the node box or in a cell without a negative corner (it cannot
+// collide); otherwise off = index of the cell's lowest node and f = the
+// point's fractions within the cell.  No memory is read.
+__device__ __forceinline__ bool sdf_cell(const PreInfo& pi, float px, float py, float pz, int& off,
+                                         float f[3]) {
   const float ux = (px - pi.ox) * pi.inv_cell;
   const float uy = (py - pi.oy) * pi.inv_cell;
   const float uz = (pz - pi.oz) * pi.inv_cell;
@@ -46,11 +48,27 @@ __device__ __forceinline__ bool sdf_collides(const PreInfo& pi, float px, float 
   if (ix < pi.neg_lo[0] - 1 || ix > pi.neg_hi[0] || iy < pi.neg_lo[1] - 1 || iy > pi.neg_hi[1] ||
       iz < pi.neg_lo[2] - 1 || iz > pi.neg_hi[2])
     return false;
-  const float fx = ux - (float)ix, fy = uy - (float)iy, fz = uz - (float)iz;
-  const size_t sx = 1, sy = (size_t)pi.nx, sz = (size_t)pi.nx * pi.ny;
-  const float* v = pi.sdf + (size_t)iz * sz + (size_t)iy * sy + ix;
-  const float v000 = v[0], v100 = v[sx], v010 = v[sy], v110 = v[sy + sx];
-  const float v001 = v[sz], v101 = v[sz + sx], v011 = v[sz + sy], v111 = v[sz + sy + sx];
+  f[0] = ux - (float)ix;
+  f[1] = uy - (float)iy;
+  f[2] = uz - (float)iz;
+  off = (iz * pi.ny + iy) * pi.nx + ix;
+  return true;
+}
+
+// The cell's 8 node values, v[4 dz + 2 dy + dx].
+__device__ __forceinline__ void sdf_corners(const PreInfo& pi, int off, float v[8]) {
+  const int sy = pi.nx, sz = pi.nx * pi.ny;
+  const float* g = pi.sdf + off;
+  v[0] = g[0]; v[1] = g[1]; v[2] = g[sy]; v[3] = g[sy + 1];
+  v[4] = g[sz]; v[5] = g[sz + 1]; v[6] = g[sz + sy]; v[7] = g[sz + sy + 1];
+}
+
+// Trilinear value at fractions f from the cell's node values, and, if grad is
+// given, the interpolant's gradient (world units).
+__device__ __forceinline__ float sdf_interp(const float v[8], const float f[3], float inv_cell, float* grad) {
+  const float fx = f[0], fy = f[1], fz = f[2];
+  const float v000 = v[0], v100 = v[1], v010 = v[2], v110 = v[3];
+  const float v001 = v[4], v101 = v[5], v011 = v[6], v111 = v[7];
   const float c00 = (1.f - fx) * v000 + fx * v100;
   const float c10 = (1.f - fx) * v010 + fx * v110;
   const float c01 = (1.f - fx) * v001 + fx * v101;
@@ -58,18 +76,16 @@ __device__ __forceinline__ bool sdf_collides(const PreInfo& pi, float px, float 
   const float c0 = (1.f - fy) * c00 + fy * c10;
   const float c1 = (1.f - fy) * c01 + fy * c11;
   const float val = (1.f - fz) * c0 + fz * c1;
-  if (!(val < 0.f)) return false;
-  if (phi) *phi = val;
   if (grad) {
     const float gx = (1.f - fy) * (1.f - fz) * (v100 - v000) + fy * (1.f - fz) * (v110 - v010) +
                      (1.f - fy) * fz * (v101 - v001) + fy * fz * (v111 - v011);
     const float gy = (1.f - fx) * (1.f - fz) * (v010 - v000) + fx * (1.f - fz) * (v110 - v100) +
                      (1.f - fx) * fz * (v011 - v001) + fx * fz * (v111 - v101);
-    grad[0] = gx * pi.inv_cell;
-    grad[1] = gy * pi.inv_cell;
-    grad[2] = (c1 - c0) * pi.inv_cell;
+    grad[0] = gx * inv_cell;
+    grad[1] = gy * inv_cell;
+    grad[2] = (c1 - c0) * inv_cell;
   }
-  return true;
+  return val;
 }
 
 // Can any point of the cloud's bounding box reach a cell with a negative
@@ -127,7 +143,7 @@ template <int MAP>
 __global__ __launch_bounds__(256) void k_gate_reverse(Dev d) {
   __shared__ float lx[kGateChunk], ly[kGateChunk], lz[kGateChunk];
   __shared__ int lm[kGateChunk];
-  __shared__ int wtot[4];
+  __shared__ int wcnt[kPerThread][4];
   __shared__ float wpart[4][kPartStride];
 
   const int nwg = d.total_gate_wgs;
@@ -173,20 +189,39 @@ __global__ __launch_bounds__(256) void k_gate_reverse(Dev d) {
   // penetration sums (gripper frame): phi^2, -2 phi grad, 2 phi grad x c'
   float pn[7] = {0, 0, 0, 0, 0, 0, 0};
   const bool want_pen = d.w_pen > 0.f;
+  // all eight points are loaded and moved first, and the node values of a
+  // batch of kGateBatch points are requested together before any is used,
+  // so their memory latencies overlap
 #pragma unroll
   for (int r = 0; r < kPerThread; ++r) {
     const int m = cc * kGateChunk + r * 256 + tid;
-    px[r] = py[r] = pz[r] = 0.f;
-    if (m < oi.mc) {
-      const float4 c = d.col_pts[oi.c_begin + m];
-      const float dx = c.x - t[0];
-      const float dy = c.y - t[1];
-      const float dz = c.z - t[2];
-      px[r] = R[0] * dx + R[3] * dy + R[6] * dz;
-      py[r] = R[1] * dx + R[4] * dy + R[7] * dz;
-      pz[r] = R[2] * dx + R[5] * dy + R[8] * dz;
-      float phi, gr[3];
-      const bool col = sdf_collides(pi, px[r], py[r], pz[r], &phi, want_pen ? gr : nullptr);
+    const float4 c = d.col_pts[oi.c_begin + max(0, min(m, oi.mc - 1))];
+    const float dx = c.x - t[0];
+    const float dy = c.y - t[1];
+    const float dz = c.z - t[2];
+    px[r] = R[0] * dx + R[3] * dy + R[6] * dz;
+    py[r] = R[1] * dx + R[4] * dy + R[7] * dz;
+    pz[r] = R[2] * dx + R[5] * dy + R[8] * dz;
+  }
+#pragma unroll
+  for (int r0 = 0; r0 < kPerThread; r0 += kGateBatch) {
+    bool cand[kGateBatch];
+    int off[kGateBatch];
+    float fr[kGateBatch][3], v[kGateBatch][8];
+#pragma unroll
+    for (int u = 0; u < kGateBatch; ++u) {
+      const int r = r0 + u;
+      off[u] = 0;
+      cand[u] = cc * kGateChunk + r * 256 + tid < oi.mc && sdf_cell(pi, px[r], py[r], pz[r], off[u], fr[u]);
+      if (cand[u]) sdf_corners(pi, off[u], v[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < kGateBatch; ++u) {
+      const int r = r0 + u;
+      const int m = cc * kGateChunk + r * 256 + tid;
+      if (m >= oi.mc) continue;
+      float phi = 0.f, gr[3];
+      const bool col = cand[u] && (phi = sdf_interp(v[u], fr[u], pi.inv_cell, want_pen ? gr : nullptr)) < 0.f;
       if (col && want_pen) {
         pn[0] += phi * phi;
         pn[1] -= 2.f * phi * gr[0];
@@ -200,22 +235,27 @@ __global__ __launch_bounds__(256) void k_gate_reverse(Dev d) {
       else if (d.dbg_rev) d.dbg_rev[(size_t)i * d.mc_max + d.col_perm[oi.c_begin + m]] = -1;
     }
   }
-  // workgroup exclusive scan of the per-thread counts (thread order)
-  const int cnt = __popc(bits);
-  int incl = cnt;
-  for (int off = 1; off < 64; off <<= 1) {
-    const int o = __shfl_up(incl, off, 64);
-    if (lane >= off) incl += o;
-  }
-  if (lane == 63) wtot[w] = incl;
-  __syncthreads();
-  int base = 0, total = 0;
+  // compaction in the cloud's (Morton) order, point m = cc*2048 + r*256 + tid:
+  // slot r's ballot ranks the lane within its wave, and the per-slot wave
+  // counts place the wave, so a block of 16 consecutive colliding points is
+  // spatially compact and the reverse scan's chunk bounds stay tight
+  int rank[kPerThread];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    base += (k < w) ? wtot[k] : 0;
-    total += wtot[k];
+  for (int r = 0; r < kPerThread; ++r) {
+    const unsigned long long bal = __ballot((bits >> r) & 1u);
+    rank[r] = __builtin_amdgcn_mbcnt_hi((unsigned)(bal >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
+    if (lane == 0) wcnt[r][w] = __popcll(bal);
   }
-  int pos = base + incl - cnt;
+  __syncthreads();
+  int total = 0;
+#pragma unroll
+  for (int r = 0; r < kPerThread; ++r) {
+    int before = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) before += (k < w) ? wcnt[r][k] : 0;
+    rank[r] += total + before;
+    total += (wcnt[r][0] + wcnt[r][1]) + (wcnt[r][2] + wcnt[r][3]);
+  }
   if (want_pen) {  // fixed-order workgroup sums of the penetration terms
 #pragma unroll
     for (int a = 0; a < 7; ++a) pn[a] = wave_sum(pn[a]);
@@ -230,9 +270,9 @@ __global__ __launch_bounds__(256) void k_gate_reverse(Dev d) {
 #pragma unroll
   for (int r = 0; r < kPerThread; ++r) {
     if (bits & (1u << r)) {
+      const int pos = rank[r];
       lx[pos] = px[r]; ly[pos] = py[r]; lz[pos] = pz[r];
       lm[pos] = cc * kGateChunk + r * 256 + tid;
-      ++pos;
     }
   }
   __syncthreads();
