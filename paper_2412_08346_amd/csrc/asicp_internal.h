@@ -229,6 +229,45 @@ __device__ __forceinline__ float row_min(float v) {
   return fminf(v, dppf<kDppMirror>(v));
 }
 
+// Minimum over the 64 lanes of a wave (unsigned); every lane gets it.
+__device__ __forceinline__ unsigned wave_min_u(unsigned v) {
+  v = min(v, (unsigned)dppi<kDppXor1>((int)v));
+  v = min(v, (unsigned)dppi<kDppXor2>((int)v));
+  v = min(v, (unsigned)dppi<kDppHalfMirror>((int)v));
+  v = min(v, (unsigned)dppi<kDppMirror>((int)v));
+  const auto a = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+  v = min(a[0], a[1]);
+  const auto b = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+  return min(b[0], b[1]);
+}
+
+// Eight sums over the 64 lanes of a wave at once, in a fixed order: register
+// pairs are folded through the 32-lane swap (a[k] keeps the low half's sums of
+// a[k], the high half's of a[k+4]), then the 16-lane swap, then within rows.
+// Afterwards lane 8k (k = 0..7) holds the total of a[k].
+__device__ __forceinline__ float wave_sum8(const float a[8]) {
+  float b[4], c[2];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a[k]), __float_as_uint(a[k + 4]), false, false);
+    b[k] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(b[k]), __float_as_uint(b[k + 2]), false, false);
+    c[k] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+  // row r: c[0] holds a[2r]'s partial sums, c[1] a[2r+1]'s; fold each row's
+  // halves so lanes 0-7 carry c[0] and lanes 8-15 carry c[1]
+  const float t0 = c[0] + dppf<kDppMirror>(c[0]);
+  const float t1 = c[1] + dppf<kDppMirror>(c[1]);
+  float v = (threadIdx.x & 8) ? t1 : t0;
+  v += dppf<kDppHalfMirror>(v);
+  v += dppf<kDppXor2>(v);
+  v += dppf<kDppXor1>(v);
+  return v;
+}
+
 // Sum over the 64 lanes of a wave in a fixed order; every lane gets the total.
 __device__ __forceinline__ float wave_sum(float v) {
   v += dppf<kDppXor1>(v);

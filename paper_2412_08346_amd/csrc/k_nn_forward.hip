@@ -116,22 +116,12 @@ __device__ __forceinline__ void nn_forward_body(const Dev& d) {
       d.dbg_nn[(size_t)i * d.n_max + n_orig] = d.obj_perm[(size_t)oi.prep_tg_begin * 64 + my];
     }
   }
-  e2 = wave_sum(e2);
-  ex = wave_sum(ex);
-  ey = wave_sum(ey);
-  ez = wave_sum(ez);
-  mx = wave_sum(mx);
-  my_ = wave_sum(my_);
-  mz = wave_sum(mz);
-  cnt = wave_sum(cnt);
-  if (lane == 0) {
-    float* out = d.nn_part + ((size_t)i * d.max_waves_pp + chunk) * kPartStride;
-    out[0] = e2; out[1] = ex; out[2] = ey; out[3] = ez;
-    out[4] = mx; out[5] = my_; out[6] = mz; out[7] = cnt;
-    // the wave's own slot: launches are ordered on the stream, so a plain
-    // read-modify-write accumulates over them without contention
-    if (d.wave_pairs) d.wave_pairs[wave] += (unsigned long long)pairs;
-  }
+  const float sums[8] = {e2, ex, ey, ez, mx, my_, mz, cnt};
+  const float tot = wave_sum8(sums);  // lane 8k holds sums[k]
+  if ((lane & 7) == 0) d.nn_part[((size_t)i * d.max_waves_pp + chunk) * kPartStride + (lane >> 3)] = tot;
+  // the wave's own slot: launches are ordered on the stream, so a plain
+  // read-modify-write accumulates over them without contention
+  if (lane == 0 && d.wave_pairs) d.wave_pairs[wave] += (unsigned long long)pairs;
 }
 
 // The pruned scan keeps fewer registers live per wavefront and gains from

@@ -326,23 +326,32 @@ __device__ __forceinline__ long long nn_scan_pruned(const float4* __restrict__ p
       uhi[a] = fmaxf(uhi[a], qhi[q][a]);
     }
   }
-  unsigned long long near = ~0ull;
+  // (smallest gap, then lowest index; gaps are non-negative, so their bit
+  // patterns order like their values; a lane without a chunk never wins)
+  unsigned gbest = 0xffffffffu;
+  int cbest = 0x7fffffff;
   for (int c = lane; c < nch; c += 64) {
-    const unsigned long long key =
-        ((unsigned long long)__float_as_uint(box_gap2(box + (size_t)c * 8, ulo, uhi)) << 32) | (unsigned)c;
-    near = key < near ? key : near;
+    const unsigned g = __float_as_uint(box_gap2(box + (size_t)c * 8, ulo, uhi));
+    if (c == lane || g < gbest) {
+      gbest = g;
+      cbest = c;
+    }
   }
-  for (int off = 1; off < 64; off <<= 1) {
-    const unsigned long long o = __shfl_xor(near, off, 64);
-    near = o < near ? o : near;
-  }
-  const int c0 = __builtin_amdgcn_readfirstlane((int)(near & 0xffffffffull));  // same in every lane
+  const unsigned gmin = wave_min_u(gbest);
+  const int c0 = __builtin_amdgcn_readfirstlane(
+      min((int)wave_min_u(gbest == gmin ? (unsigned)cbest : 0x7fffffffu), nch - 1));  // same in every lane
+  // pair count (a statistic): every operand is wave-uniform, so it stays in
+  // scalar registers
+  const int mu = __builtin_amdgcn_readfirstlane(m);
+  int vqu[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) vqu[q] = __builtin_amdgcn_readfirstlane(vq[q]);
   long long pairs = 0;
   {
-    const int pts = max(0, min(128, m - 128 * c0));
+    const int pts = max(0, min(128, mu - 128 * c0));
     chunk_step<Q>(load_tg(rs, 2 * c0, lo), load_tg(rs, 2 * c0 + 1, lo), b, best, bch, c0);
 #pragma unroll
-    for (int q = 0; q < Q; ++q) pairs += (long long)pts * vq[q];
+    for (int q = 0; q < Q; ++q) pairs += (long long)(pts * vqu[q]);
   }
   refresh();
   int since = 0;
@@ -359,15 +368,18 @@ __device__ __forceinline__ long long nn_scan_pruned(const float4* __restrict__ p
       cand |= mq[q];
     }
     // candidates in index order; the next candidate's data is loaded while
-    // the current one is compared
+    // the current one is compared.  One step compares chunk cl (held in cur)
+    // and loads the next candidate into nxt; two steps per iteration swap the
+    // roles of the register pairs, so no copy is made between them.
     int cl = cand ? __ffsll((long long)cand) - 1 : 0;
-    float4 x0 = load_tg(rs, 2 * (blk + cl), lo), x1 = load_tg(rs, 2 * (blk + cl) + 1, lo);
-    while (cand) {
+    float4 x0 = load_tg(rs, 2 * (blk + cl), lo), x1 = load_tg(rs, 2 * (blk + cl) + 1, lo), y0, y1;
+    auto step = [&](const float4& cur0, const float4& cur1, float4& nxt0, float4& nxt1) {
       const int cc = blk + cl;
       cand &= cand - 1;
       const int nl = cand ? __ffsll((long long)cand) - 1 : cl;
-      const float4 y0 = load_tg(rs, 2 * (blk + nl), lo), y1 = load_tg(rs, 2 * (blk + nl) + 1, lo);
-      const int pts = max(0, min(128, m - 128 * cc));
+      nxt0 = load_tg(rs, 2 * (blk + nl), lo);
+      nxt1 = load_tg(rs, 2 * (blk + nl) + 1, lo);
+      const int pts = max(0, min(128, mu - 128 * cc));
       // block q is compared only if chunk cc is still in its mask (a scalar
       // bit test) and, with FINE, some query of the block may improve
       bool need[Q];
@@ -376,9 +388,9 @@ __device__ __forceinline__ long long nn_scan_pruned(const float4* __restrict__ p
       for (int q = 0; q < Q; ++q) {
         need[q] = (mq[q] >> cl) & 1ull;
         if (FINE && need[q]) need[q] = __ballot(point_box2(qc + 3 * q, bx) <= qb[q]) != 0ull;
-        pairs += need[q] ? (long long)pts * vq[q] : 0ll;
+        pairs += need[q] ? (long long)(pts * vqu[q]) : 0ll;
       }
-      chunk_step<Q>(x0, x1, b, best, bch, cc, need);
+      chunk_step<Q>(cur0, cur1, b, best, bch, cc, need);
       if (++since == ASICP_NN_REFRESH) {
         since = 0;
         refresh();
@@ -390,13 +402,16 @@ __device__ __forceinline__ long long nn_scan_pruned(const float4* __restrict__ p
         }
         cand &= keep;
       }
-      x0 = y0;
-      x1 = y1;
       cl = cand ? __ffsll((long long)cand) - 1 : cl;
       if (cl != nl) {  // the prefetched chunk was dropped by the refresh
-        x0 = load_tg(rs, 2 * (blk + cl), lo);
-        x1 = load_tg(rs, 2 * (blk + cl) + 1, lo);
+        nxt0 = load_tg(rs, 2 * (blk + cl), lo);
+        nxt1 = load_tg(rs, 2 * (blk + cl) + 1, lo);
       }
+    };
+    while (cand) {
+      step(x0, x1, y0, y1);
+      if (!cand) break;
+      step(y0, y1, x0, x1);
     }
   }
   nn_rescan<Q, BATCH_RESCAN>(prep, rs, b, qc, best, bch, idx, miss);
