@@ -16,7 +16,7 @@ constexpr int kTileGroup = 64;     // points per MFMA-ready tile group (4 tiles 
 #define ASICP_NN_Q 4
 #endif
 #ifndef ASICP_NN_WPE
-#define ASICP_NN_WPE 5
+#define ASICP_NN_WPE 6
 #endif
 #ifndef ASICP_NN_SPLIT
 #define ASICP_NN_SPLIT 0

@@ -34,7 +34,7 @@ __device__ __forceinline__ void nn_forward_body(const Dev& d) {
   const int nwg = (d.total_waves + 3) >> 2;
   const int logical = xcd_logical<MAP>(blockIdx.x, nwg);
   if (logical >= nwg) return;
-  const int wave = logical * 4 + (threadIdx.x >> 6);
+  const int wave = __builtin_amdgcn_readfirstlane(logical * 4 + (int)(threadIdx.x >> 6));
   if (wave >= d.total_waves) return;
   const int lane = threadIdx.x & 63;
 
