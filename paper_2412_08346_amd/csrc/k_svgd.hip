@@ -10,8 +10,8 @@
 //                 the preconditioned driving terms -gamma A g_j (g_j minus the
 //                 log-prior gradient when a prior is given, eq. 8) plus tau times
 //                 the kernel gradient with respect to particle j (translation
-//                 part scaled by h/2); 64 particles per workgroup, 4 lanes per
-//                 particle;
+//                 part scaled by h/2); 16 particles per workgroup, 16 lanes
+//                 per particle;
 //   k_svgd_apply  t += eta phi_t, q <- canon(normalize(Exp(eta phi_w) (x) q)).
 // Every phi is computed from the poses of the same iteration: poses are only
 // written by the last launch.
@@ -243,6 +243,8 @@ __device__ __forceinline__ void log_prior_grad(const float* pr, const float* t, 
   gp[5] = c * (q[0] * mz - mw * q[3] - (mx * q[2] - my * q[1]));
 }
 
+constexpr int kPhiLanes = 16;              // lanes per particle (one row of a wave)
+constexpr int kPhiPer = 256 / kPhiLanes;   // particles per workgroup
 __global__ __launch_bounds__(256) void k_svgd_phi(Dev d, float gamma, float tau) {
   __shared__ float st[kMaxK * 3];
   __shared__ float sq[kMaxK * 4];
@@ -261,7 +263,7 @@ __global__ __launch_bounds__(256) void k_svgd_phi(Dev d, float gamma, float tau)
     }
   }
   __syncthreads();
-  const int ii = blockIdx.y * 64 + (tid >> 2), part = tid & 3;
+  const int ii = blockIdx.y * kPhiPer + tid / kPhiLanes, part = tid % kPhiLanes;
   const float h = d.h[g];
   const float inv_h = 1.0f / h;
   const GroupInfo gi = d.groups[g];
@@ -272,7 +274,7 @@ __global__ __launch_bounds__(256) void k_svgd_phi(Dev d, float gamma, float tau)
   if (ii < K) {
     const float tix = st[3 * ii], tiy = st[3 * ii + 1], tiz = st[3 * ii + 2];
     const float qw = sq[4 * ii], qx = sq[4 * ii + 1], qy = sq[4 * ii + 2], qz = sq[4 * ii + 3];
-    for (int j = part; j < K; j += 4) {
+    for (int j = part; j < K; j += kPhiLanes) {
       const float dx = tix - st[3 * j], dy = tiy - st[3 * j + 1], dz = tiz - st[3 * j + 2];
       const float kt = expf(-__builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx)) * inv_h);
       const float pw = sq[4 * j], px = sq[4 * j + 1], py = sq[4 * j + 2], pz = sq[4 * j + 3];
@@ -298,10 +300,13 @@ __global__ __launch_bounds__(256) void k_svgd_phi(Dev d, float gamma, float tau)
       acc[5] += wdw * (-ga_w * gj[5]) + tau * wrw * 0.5f * vz;
     }
   }
+  // sum over the particle's 16 lanes (one row): every lane gets the total
 #pragma unroll
   for (int a = 0; a < 6; ++a) {
-    acc[a] += __shfl_xor(acc[a], 1, 64);
-    acc[a] += __shfl_xor(acc[a], 2, 64);
+    acc[a] += dppf<kDppXor1>(acc[a]);
+    acc[a] += dppf<kDppXor2>(acc[a]);
+    acc[a] += dppf<kDppHalfMirror>(acc[a]);
+    acc[a] += dppf<kDppMirror>(acc[a]);
   }
   if (ii < K && part == 0) {
     const float invK = 1.0f / (float)K;
@@ -351,7 +356,7 @@ void launch_svgd(const Dev& d, float gamma, float tau, float inv_log_k, hipStrea
   } else {
     hipLaunchKernelGGL(k_bw_const, dim3((d.G + 255) / 256), dim3(256), 0, s, d);
   }
-  hipLaunchKernelGGL(k_svgd_phi, dim3(d.G, (d.K + 63) / 64), dim3(256), 0, s, d, gamma, tau);
+  hipLaunchKernelGGL(k_svgd_phi, dim3(d.G, (d.K + kPhiPer - 1) / kPhiPer), dim3(256), 0, s, d, gamma, tau);
   hipLaunchKernelGGL(k_svgd_apply, dim3((d.Ktot + 255) / 256), dim3(256), 0, s, d);
 }
 
