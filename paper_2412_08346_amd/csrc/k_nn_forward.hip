@@ -98,14 +98,20 @@ __device__ __forceinline__ void nn_forward_body(const Dev& d) {
       atomicOr(d.flags + 1, 2);
       my = oi.m - 1;
     }
-    const float4 s = spts[n];
-    const float ux = R[0] * s.x + R[1] * s.y + R[2] * s.z;
-    const float uy = R[3] * s.x + R[4] * s.y + R[5] * s.z;
-    const float uz = R[6] * s.x + R[7] * s.y + R[8] * s.z;
+    // the lane's transformed contact point s' is its query of block comp
+    float px = qc[0], py = qc[1], pz = qc[2];
+#pragma unroll
+    for (int q = 1; q < Q; ++q)
+      if (comp == q) {
+        px = qc[3 * q];
+        py = qc[3 * q + 1];
+        pz = qc[3 * q + 2];
+      }
+    const float ux = px - t[0], uy = py - t[1], uz = pz - t[2];  // R s
     const float4 r = d.obj_pts[(size_t)oi.prep_tg_begin * 64 + my];
-    ex = ux + t[0] - r.x;
-    ey = uy + t[1] - r.y;
-    ez = uz + t[2] - r.z;
+    ex = px - r.x;
+    ey = py - r.y;
+    ez = pz - r.z;
     e2 = ex * ex + ey * ey + ez * ez;
     mx = uy * ez - uz * ey;
     my_ = uz * ex - ux * ez;
