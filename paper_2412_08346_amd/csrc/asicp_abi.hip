@@ -271,6 +271,11 @@ struct asicp_ctx_s {
   hipGraphExec_t graph;         // whole-solve graph of asicp_replay
   hipStream_t cap_stream;       // private stream the graph is captured on
   bool capturing;               // no timing events inside a captured graph
+  // Side stream of an evaluation: the bandwidth select and the collision
+  // gate depend only on the poses, so they run beside the forward NN launch
+  // (fork after the caller's preceding work, join before the finaliser).
+  hipStream_t side;
+  hipEvent_t fork_ev, join_ev;
 };
 
 extern "C" {
@@ -472,6 +477,15 @@ asicp_status asicp_create(const asicp_problem* pb, const asicp_config* cfg, void
   c->final_done = false;
   c->inv_log_k = s.K >= 2 ? (float)(1.0 / std::log((double)s.K)) : 1.0f;
   c->n_timed = 0;
+  c->side = nullptr;
+  c->fork_ev = c->join_ev = nullptr;
+  // default priority, like every stream here
+  if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming) != hipSuccess) {
+    asicp_destroy(c);
+    return fail(ASICP_E_HIP, "creating the side stream or its events failed");
+  }
   *out = c;
   return ASICP_OK;
 }
@@ -513,7 +527,11 @@ static asicp_status nn_forward_timed(asicp_ctx c, hipStream_t hs) {
   return ASICP_OK;
 }
 
-static asicp_status evaluate(asicp_ctx c, int k, int final_eval, hipStream_t hs) {
+// One evaluation at the current poses (and, with bandwidth, the kernel
+// bandwidth of the Stein update that follows): the forward NN on the caller's
+// stream, the bandwidth select and the collision gate on the side stream,
+// joined before the finaliser.
+static asicp_status evaluate(asicp_ctx c, int k, int final_eval, bool bandwidth, hipStream_t hs) {
   asicp_status st;
   if (c->d.minibatch) {  // Table I: batch size grows linearly to the whole cloud at 2 k_max / 3
     const double full = 2.0 * (double)c->cfg.k_max / 3.0;
@@ -521,12 +539,31 @@ static asicp_status evaluate(asicp_ctx c, int k, int final_eval, hipStream_t hs)
     launch_minibatch(c->d, k, frac, hs);
     if ((st = check_launch("minibatch")) != ASICP_OK) return st;
   }
+  if (hipEventRecord(c->fork_ev, hs) != hipSuccess || hipStreamWaitEvent(c->side, c->fork_ev, 0) != hipSuccess)
+    return fail(ASICP_E_HIP, "fork to the side stream failed");
+  if (bandwidth) {
+    launch_bandwidth(c->d, c->inv_log_k, c->side);
+    if ((st = check_launch("bandwidth")) != ASICP_OK) return st;
+  }
+  launch_gate_reverse(c->d, c->side);
+  if ((st = check_launch("gate_reverse")) != ASICP_OK) return st;
   st = nn_forward_timed(c, hs);
   if (st != ASICP_OK) return st;
-  launch_gate_reverse(c->d, hs);
-  if ((st = check_launch("gate_reverse")) != ASICP_OK) return st;
+  if (hipEventRecord(c->join_ev, c->side) != hipSuccess || hipStreamWaitEvent(hs, c->join_ev, 0) != hipSuccess)
+    return fail(ASICP_E_HIP, "join of the side stream failed");
   launch_finalize(c->d, k, final_eval, hs);
   return check_launch("finalize");
+}
+
+// Iteration k: evaluation, then (in the Stein phase) the Stein update.
+static asicp_status iterate(asicp_ctx c, int k, hipStream_t hs) {
+  const bool stein = k < c->cfg.k_stein;
+  asicp_status st = evaluate(c, k, 0, stein, hs);
+  if (st != ASICP_OK || !stein) return st;
+  float gamma, tau;
+  schedule_of(c->cfg, k, &gamma, &tau);
+  launch_stein(c->d, gamma, tau, hs);
+  return check_launch("svgd");
 }
 
 asicp_status asicp_step(asicp_ctx c, int32_t n_iters, void* stream) {
@@ -538,15 +575,8 @@ asicp_status asicp_step(asicp_ctx c, int32_t n_iters, void* stream) {
     return fail(ASICP_E_STATE, "stepping past k_max (" + std::to_string(c->cfg.k_max) + ")");
   hipStream_t hs = static_cast<hipStream_t>(stream);
   for (int it = 0; it < n_iters; ++it) {
-    const int k = c->k;
-    asicp_status st = evaluate(c, k, 0, hs);
+    const asicp_status st = iterate(c, c->k, hs);
     if (st != ASICP_OK) return st;
-    if (k < c->cfg.k_stein) {
-      float gamma, tau;
-      schedule_of(c->cfg, k, &gamma, &tau);
-      launch_svgd(c->d, gamma, tau, c->inv_log_k, hs);
-      if ((st = check_launch("svgd")) != ASICP_OK) return st;
-    }
     ++c->k;
   }
   return ASICP_OK;
@@ -559,7 +589,7 @@ asicp_status asicp_solve(asicp_ctx c, void* stream) {
   asicp_status st = asicp_step(c, c->cfg.k_max - c->k, stream);
   if (st != ASICP_OK) return st;
   hipStream_t hs = static_cast<hipStream_t>(stream);
-  if ((st = evaluate(c, c->k, 1, hs)) != ASICP_OK) return st;
+  if ((st = evaluate(c, c->k, 1, false, hs)) != ASICP_OK) return st;
   launch_select(c->d, hs);
   if ((st = check_launch("select")) != ASICP_OK) return st;
   c->final_done = true;
@@ -569,16 +599,9 @@ asicp_status asicp_solve(asicp_ctx c, void* stream) {
 // Enqueue iterations k0 .. k_max-1, the final evaluation and the selection.
 static asicp_status enqueue_rest(asicp_ctx c, int k0, hipStream_t hs) {
   asicp_status st;
-  for (int k = k0; k < c->cfg.k_max; ++k) {
-    if ((st = evaluate(c, k, 0, hs)) != ASICP_OK) return st;
-    if (k < c->cfg.k_stein) {
-      float gamma, tau;
-      schedule_of(c->cfg, k, &gamma, &tau);
-      launch_svgd(c->d, gamma, tau, c->inv_log_k, hs);
-      if ((st = check_launch("svgd")) != ASICP_OK) return st;
-    }
-  }
-  if ((st = evaluate(c, c->cfg.k_max, 1, hs)) != ASICP_OK) return st;
+  for (int k = k0; k < c->cfg.k_max; ++k)
+    if ((st = iterate(c, k, hs)) != ASICP_OK) return st;
+  if ((st = evaluate(c, c->cfg.k_max, 1, false, hs)) != ASICP_OK) return st;
   launch_select(c->d, hs);
   return check_launch("select");
 }
@@ -592,7 +615,7 @@ asicp_status asicp_cost_grad(asicp_ctx c, const float* theta, float* cost_out, f
   hipLaunchKernelGGL(k_set_theta, dim3((7 * K + 255) / 256), dim3(256), 0, hs, c->d.theta, theta, 7 * K);
   asicp_status st = check_launch("set theta");
   if (st != ASICP_OK) return st;
-  if ((st = evaluate(c, c->cfg.k_max, 1, hs)) != ASICP_OK) return st;
+  if ((st = evaluate(c, c->cfg.k_max, 1, false, hs)) != ASICP_OK) return st;
   hipLaunchKernelGGL(k_get_cost_grad, dim3((K + 255) / 256), dim3(256), 0, hs, c->d.cost, c->d.grad_ct,
                      cost_out, grad_out, K);
   return check_launch("cost/grad copy");
@@ -801,6 +824,9 @@ void asicp_destroy(asicp_ctx c) {
   if (!c) return;
   if (c->graph) (void)hipGraphExecDestroy(c->graph);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  if (c->side) (void)hipStreamDestroy(c->side);
+  if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
+  if (c->join_ev) (void)hipEventDestroy(c->join_ev);
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   delete c;
 }

@@ -286,7 +286,8 @@ void launch_setup(const Dev& d, const float* theta0, const float* prev_cost0,
 void launch_nn_forward(const Dev& d, hipStream_t s);
 void launch_gate_reverse(const Dev& d, hipStream_t s);
 void launch_finalize(const Dev& d, int k, int final_eval, hipStream_t s);
-void launch_svgd(const Dev& d, float gamma, float tau, float inv_log_k, hipStream_t s);
+void launch_bandwidth(const Dev& d, float inv_log_k, hipStream_t s);  // h of eq. (9), from the poses only
+void launch_stein(const Dev& d, float gamma, float tau, hipStream_t s);  // phi and the pose update
 void launch_select(const Dev& d, hipStream_t s);
 void launch_minibatch(const Dev& d, int k, double frac, hipStream_t s);
 void upload_words(void* dst, const void* src, size_t bytes, hipStream_t s);

@@ -345,7 +345,7 @@ __global__ __launch_bounds__(256) void k_svgd_apply(Dev d) {
   d.theta[6 * Kt + i] = nz * inv;
 }
 
-void launch_svgd(const Dev& d, float gamma, float tau, float inv_log_k, hipStream_t s) {
+void launch_bandwidth(const Dev& d, float inv_log_k, hipStream_t s) {
   if (d.K >= 2 && d.bw_mode == ASICP_BW_MEDIAN) {
     if (d.K * (d.K - 1) / 2 <= kBwRegs * 1024) {
       hipLaunchKernelGGL(k_bw_fused, dim3(d.G), dim3(1024), 0, s, d, inv_log_k);
@@ -356,6 +356,9 @@ void launch_svgd(const Dev& d, float gamma, float tau, float inv_log_k, hipStrea
   } else {
     hipLaunchKernelGGL(k_bw_const, dim3((d.G + 255) / 256), dim3(256), 0, s, d);
   }
+}
+
+void launch_stein(const Dev& d, float gamma, float tau, hipStream_t s) {
   hipLaunchKernelGGL(k_svgd_phi, dim3(d.G, (d.K + kPhiPer - 1) / kPhiPer), dim3(256), 0, s, d, gamma, tau);
   hipLaunchKernelGGL(k_svgd_apply, dim3((d.Ktot + 255) / 256), dim3(256), 0, s, d);
 }
