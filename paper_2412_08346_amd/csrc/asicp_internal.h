@@ -159,6 +159,12 @@ __device__ __forceinline__ void load_pose(const float* theta, int Ktot, int i, f
   q[3] = theta[6 * Ktot + i];
 }
 
+// The lane's index in its wavefront, from the execution mask (two VALU
+// instructions that the compiler can repeat instead of keeping a register).
+__device__ __forceinline__ int lane_id() {
+  return (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+
 // Cross-lane helpers built from VALU lane permutes only (no LDS crossbar):
 // DPP within a row of 16 lanes, and gfx950's permlane16/32 swaps across rows.
 template <int CTRL>
@@ -261,7 +267,7 @@ __device__ __forceinline__ float wave_sum8(const float a[8]) {
   // halves so lanes 0-7 carry c[0] and lanes 8-15 carry c[1]
   const float t0 = c[0] + dppf<kDppMirror>(c[0]);
   const float t1 = c[1] + dppf<kDppMirror>(c[1]);
-  float v = (threadIdx.x & 8) ? t1 : t0;
+  float v = (lane_id() & 8) ? t1 : t0;
   v += dppf<kDppHalfMirror>(v);
   v += dppf<kDppXor2>(v);
   v += dppf<kDppXor1>(v);

@@ -36,7 +36,7 @@ __device__ __forceinline__ void nn_forward_body(const Dev& d) {
   if (logical >= nwg) return;
   const int wave = __builtin_amdgcn_readfirstlane(logical * 4 + (int)(threadIdx.x >> 6));
   if (wave >= d.total_waves) return;
-  const int lane = threadIdx.x & 63;
+  const int lane = lane_id();
 
   int lo = 0, hi = d.G - 1;
   while (lo < hi) {

@@ -90,12 +90,17 @@ __device__ __forceinline__ void tile_group(const float4& a, const float* b, floa
   }
 }
 
+// Fold one chunk (two tile groups) into each lane's running minimum.  The
+// chunk's own minimum is folded first, so that the chunk recorded with the
+// running minimum is the lowest-index chunk holding it whatever order the
+// chunks are visited in: a chunk with a smaller value replaces it, one with
+// an equal value only if its index is lower.
 template <int Q>
 __device__ __forceinline__ void chunk_step(const float4& a0, const float4& a1, const float* b,
                                            float* best, int* bch, int c, const bool* need = nullptr) {
   float m[Q];
 #pragma unroll
-  for (int q = 0; q < Q; ++q) m[q] = best[q];
+  for (int q = 0; q < Q; ++q) m[q] = __builtin_inff();
   tile_group<Q>(a0, b, m, need);
 #if ASICP_NN_SPLIT
   __builtin_amdgcn_sched_barrier(0);  // keep one tile group's MFMA results live at a time
@@ -103,8 +108,9 @@ __device__ __forceinline__ void chunk_step(const float4& a0, const float4& a1, c
   tile_group<Q>(a1, b, m, need);
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    bch[q] = (m[q] != best[q]) ? c : bch[q];
-    best[q] = m[q];
+    if (need && !need[q]) continue;  // wave-uniform
+    bch[q] = (m[q] < best[q] || (m[q] == best[q] && c < bch[q])) ? c : bch[q];
+    best[q] = fminf(best[q], m[q]);
   }
 }
 
@@ -128,7 +134,7 @@ template <int Q, bool BATCH>
 __device__ __forceinline__ void nn_rescan(const float4* __restrict__ prep, __amdgpu_buffer_rsrc_t rs,
                                           const float* b, const float* qc, const float* best,
                                           const int* bch, int* idx, int32_t* miss) {
-  const int lane = threadIdx.x & 63;
+  const int lane = lane_id();
   const int grp = lane >> 4;
   const float* pf = reinterpret_cast<const float*>(prep);
   const int j = lane & 15;
@@ -210,7 +216,7 @@ __device__ __forceinline__ void nn_rescan(const float4* __restrict__ prep, __amd
 template <int Q>
 __device__ __forceinline__ void nn_scan(const float4* __restrict__ prep, int ntg, const float* bq,
                                         const float* qc, int* idx, int32_t* miss) {
-  const int lane = threadIdx.x & 63;
+  const int lane = lane_id();
   float b[Q], best[Q];
   int bch[Q];
 #pragma unroll
@@ -235,6 +241,19 @@ __device__ __forceinline__ void nn_scan(const float4* __restrict__ prep, int ntg
   }
   nn_rescan<Q, true>(prep, rs, b, qc, best, bch, idx, miss);
 }
+
+// Q non-negative floats packed as FP16 pairs with rounding toward zero, so an
+// unpacked value never exceeds the original (lower bounds stay lower bounds;
+// +inf stays +inf).
+template <int Q>
+struct LbPack {
+  __attribute__((ext_vector_type(2))) __fp16 h[(Q + 1) / 2];
+  __device__ __forceinline__ void set(int q, float v) {
+    if (q & 1) h[q >> 1] = __builtin_amdgcn_cvt_pkrtz(h[q >> 1][0], v);
+    else h[q >> 1] = __builtin_amdgcn_cvt_pkrtz(v, 0.0f);
+  }
+  __device__ __forceinline__ float get(int q) const { return (float)h[q >> 1][q & 1]; }
+};
 
 // Squared distance from the box [lo, hi] to the box [qlo, qhi] (0 if they
 // overlap): a lower bound of |s - r|^2 for any query s in the query box and
@@ -283,7 +302,7 @@ __device__ __forceinline__ long long nn_scan_pruned(const float4* __restrict__ p
                                                     const float* __restrict__ box, const float* bq,
                                                     const float* snorm, const float* qc, const int* vq,
                                                     int* idx, int32_t* miss) {
-  const int lane = threadIdx.x & 63;
+  const int lane = lane_id();
   float b[Q], best[Q];
   int bch[Q];
   float qlo[Q][3], qhi[Q][3];
@@ -305,7 +324,7 @@ __device__ __forceinline__ long long nn_scan_pruned(const float4* __restrict__ p
   const __amdgpu_buffer_rsrc_t rs = cloud_rsrc(prep, ntg);
   // qb[q]: the lane's query's current best squared distance (block q), with
   // slack; ub[q]: the largest of them over the block
-  float ub[Q], qb[Q];
+  float ub[Q], qb[Q], ubmax;
   auto refresh = [&]() {
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
@@ -313,6 +332,9 @@ __device__ __forceinline__ long long nn_scan_pruned(const float4* __restrict__ p
       // every row holds the same 16 queries, so the row maximum is uniform
       ub[q] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(row_max(qb[q]))));
     }
+    ubmax = ub[0];
+#pragma unroll
+    for (int q = 1; q < Q; ++q) ubmax = fmaxf(ubmax, ub[q]);
   };
   // nearest chunk to the union of the blocks' boxes
   float ulo[3], uhi[3];
@@ -357,28 +379,57 @@ __device__ __forceinline__ long long nn_scan_pruned(const float4* __restrict__ p
   int since = 0;
   for (int blk = 0; blk < nch; blk += 64) {
     const int c = blk + lane;
-    float lb[Q];
-    // mq[q]: candidate chunks of this 64-chunk block that block q of the
-    // queries may still need (wave-uniform masks)
-    unsigned long long mq[Q], cand = 0ull;
+    // lb(q): lower bound of the squared distance between block q's queries
+    // and the lane's chunk, kept as FP16 pairs rounded toward zero (still
+    // lower bounds, in half the registers)
+    LbPack<Q> lbp;
+    // in[q]: the lane's chunk may still be needed by block q of the queries;
+    // mq[q]: the same as a wave-uniform mask over the 64 chunks of the block
+    bool in[Q];
+    unsigned long long mq[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      lb[q] = c < nch ? box_gap2(box + (size_t)c * 8, qlo[q], qhi[q]) : __builtin_inff();
-      mq[q] = __ballot(c < nch && c != c0 && lb[q] <= ub[q]);
-      cand |= mq[q];
+      const float g = c < nch ? box_gap2(box + (size_t)c * 8, qlo[q], qhi[q]) : __builtin_inff();
+      lbp.set(q, g);
+      in[q] = c < nch && c != c0 && g <= ub[q];
+      mq[q] = __ballot(in[q]);
     }
-    // candidates in index order; the next candidate's data is loaded while
-    // the current one is compared.  One step compares chunk cl (held in cur)
-    // and loads the next candidate into nxt; two steps per iteration swap the
-    // roles of the register pairs, so no copy is made between them.
-    int cl = cand ? __ffsll((long long)cand) - 1 : 0;
+    auto lb = [&](int q) { return lbp.get(q); };
+    // Candidates are visited nearest first: the key of the lane's chunk is its
+    // smallest lower bound over the blocks that may need it, with the lane in
+    // the low 6 bits (unique keys, rounded down, so the exit test below stays
+    // conservative).  Taken chunks and chunks no block needs have no key.
+    bool taken = false;
+    auto key_of = [&]() -> unsigned {
+      float k = __builtin_inff();
+#pragma unroll
+      for (int q = 0; q < Q; ++q) k = in[q] ? fminf(k, lb(q)) : k;
+      return (taken || !(k < __builtin_inff())) ? 0xffffffffu : ((__float_as_uint(k) & ~63u) | (unsigned)lane);
+    };
+    unsigned key = key_of();
+    // the next chunk, or -1 once every remaining lower bound exceeds every
+    // block's bound (then no remaining chunk can hold a nearer point)
+    auto pick = [&]() -> int {
+      const unsigned mk = __builtin_amdgcn_readfirstlane(wave_min_u(key));
+      if (mk == 0xffffffffu || __uint_as_float(mk & ~63u) > ubmax) return -1;
+      const int l = (int)(mk & 63u);
+      taken = taken || lane == l;
+      key = lane == l ? 0xffffffffu : key;
+      return l;
+    };
+    int cl = pick();
+    if (cl < 0) continue;
+    // One step compares chunk cl (held in cur) and loads the next candidate
+    // into nxt while it does; two steps per iteration swap the roles of the
+    // register pairs, so no copy is made between them.
     float4 x0 = load_tg(rs, 2 * (blk + cl), lo), x1 = load_tg(rs, 2 * (blk + cl) + 1, lo), y0, y1;
     auto step = [&](const float4& cur0, const float4& cur1, float4& nxt0, float4& nxt1) {
       const int cc = blk + cl;
-      cand &= cand - 1;
-      const int nl = cand ? __ffsll((long long)cand) - 1 : cl;
-      nxt0 = load_tg(rs, 2 * (blk + nl), lo);
-      nxt1 = load_tg(rs, 2 * (blk + nl) + 1, lo);
+      int nl = pick();
+      if (nl >= 0) {
+        nxt0 = load_tg(rs, 2 * (blk + nl), lo);
+        nxt1 = load_tg(rs, 2 * (blk + nl) + 1, lo);
+      }
       const int pts = max(0, min(128, mu - 128 * cc));
       // block q is compared only if chunk cc is still in its mask (a scalar
       // bit test) and, with FINE, some query of the block may improve
@@ -394,23 +445,34 @@ __device__ __forceinline__ long long nn_scan_pruned(const float4* __restrict__ p
       if (++since == ASICP_NN_REFRESH) {
         since = 0;
         refresh();
-        unsigned long long keep = 0ull;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
-          mq[q] &= __ballot(lb[q] <= ub[q]);
-          keep |= mq[q];
+          in[q] = in[q] && lb(q) <= ub[q];
+          mq[q] = __ballot(in[q]);
         }
-        cand &= keep;
+        // the prefetched chunk stays taken; the rest are re-keyed
+        if (nl >= 0) {
+          const bool was = lane == nl;
+          taken = taken && !was;
+          key = key_of();
+          const int n2 = pick();
+          if (n2 != nl) {  // the prefetched chunk is no longer the nearest needed one
+            if (was) key = key_of();  // hand it back to the pool
+            nl = n2;
+            if (nl >= 0) {
+              nxt0 = load_tg(rs, 2 * (blk + nl), lo);
+              nxt1 = load_tg(rs, 2 * (blk + nl) + 1, lo);
+            }
+          }
+        } else {
+          key = key_of();
+        }
       }
-      cl = cand ? __ffsll((long long)cand) - 1 : cl;
-      if (cl != nl) {  // the prefetched chunk was dropped by the refresh
-        nxt0 = load_tg(rs, 2 * (blk + cl), lo);
-        nxt1 = load_tg(rs, 2 * (blk + cl) + 1, lo);
-      }
+      cl = nl;
     };
-    while (cand) {
+    while (cl >= 0) {
       step(x0, x1, y0, y1);
-      if (!cand) break;
+      if (cl < 0) break;
       step(y0, y1, x0, x1);
     }
   }

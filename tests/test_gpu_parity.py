@@ -207,6 +207,60 @@ def test_bandwidth_on_both_sides_of_one_workgroup(K):
     compare_step(pb, st, th, 3, pc, cv, label=f"bandwidth K={K} k=3")
 
 
+def test_exact_ties_give_one_valid_nearest_point_for_every_launch():
+    """A mirror-symmetric object seen from its mirror plane: every query's two
+    nearest points (a point and its mirror image, 1024 indices apart and far
+    apart in the Morton order) have bit-identical squared distances, in FP32 as
+    in FP64, so eq. (1) has two minimisers.  The oracle takes the lowest
+    original index (the first copy); the GPU takes the lowest index of the
+    prepared (Morton-sorted) cloud, which is the other copy as often as not.
+    Both are valid: the GPU's point must lie at exactly the oracle's minimal
+    distance, and every launch choice, pruned or not, must return the same
+    index whatever order it visits the chunks in."""
+    A, torch = _gpu()
+    rng = np.random.default_rng(5)
+    half = synth.ellipsoid(1024, (0.04, 0.03, 0.02), rng)
+    half[:, 0] = np.abs(half[:, 0]) + 1e-3  # no point on the plane itself
+    obj = np.concatenate([half, half * np.array([-1.0, 1.0, 1.0], np.float32)]).astype(np.float32)
+    S = synth.gripper_contact_cloud(0.06, 512, np.random.default_rng(2))
+    S[:, 0] = 0.0  # the contact points lie in the mirror plane ...
+    grid = synth.gripper_sdf_grid(0.06, 64, 0.002)
+    K = 8
+    pb = synth._assemble([obj], [S], [grid], K, [0.10])
+    th = np.zeros((7, K), np.float32)
+    th[1] = rng.uniform(-0.03, 0.03, K)
+    th[2] = rng.uniform(-0.03, 0.03, K)
+    th[3] = 1.0  # ... and stay there: identity rotation, no x translation
+    pb.theta0 = th
+    st = synth.Settings(k_max=3, k_stein=3)
+    r = oracle.Oracle(pb, st).step(0, th.astype(np.float64), full=True)
+    n = len(S)
+    ref = np.asarray(r["nn_idx"])[:, :n]
+    assert (ref < len(half)).all(), "the oracle must pick the first copy"
+    sp = S.astype(np.float64)[None, :, :] + th[:3].T.astype(np.float64)[:, None, :]  # (K, n, 3)
+    R = obj.astype(np.float64)
+    d_ref = ((sp - R[ref]) ** 2).sum(-1)
+    first = None
+    for prune in (True, False):
+        for xcd_map, fine in ((0, 0), (0, 1), (1, 0), (1, 1)):
+            if not prune and fine:
+                continue
+            sol = A.Solver(pb, st, debug=True, theta0=th, prune=prune)
+            sol.set_launch(xcd_map, fine)
+            sol.step(1)
+            g = sol.result()
+            sol.close()
+            got = np.asarray(g["nn_idx"])[:, :n]
+            assert ((got >= 0) & (got < len(obj))).all()
+            d_got = ((sp - R[got]) ** 2).sum(-1)
+            mirror = int((got != ref).sum())
+            say(f"[ties] prune={prune} launch=({xcd_map},{fine}): other copy for {mirror} of {got.size}")
+            assert np.array_equal(d_got, d_ref), "not a nearest point"
+            if first is None:
+                first = got
+            assert np.array_equal(got, first), "launch choices disagree on a tie"
+
+
 def test_small_teacher_forced_steps():
     pb, st = synth.workload_small()
     ks = [1, 5, 9, 14, 20, 29]
