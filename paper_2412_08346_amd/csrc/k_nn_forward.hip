@@ -57,7 +57,7 @@ __device__ __forceinline__ void nn_forward_body(const Dev& d) {
   constexpr int Q = kNnQ, QPW = kQueriesPerWave;
   const float4* spts = d.pre_pts + (size_t)pi.prep_tg_begin * 64;  // Morton-sorted contact cloud
   const int comp = lane >> 4, j = lane & 15;
-  float bq[Q], snorm[Q], qc[3 * Q];
+  float bq[Q], qc[3 * Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     int n = chunk * QPW + q * 16 + j;
@@ -67,7 +67,6 @@ __device__ __forceinline__ void nn_forward_body(const Dev& d) {
     const float py = R[3] * s.x + R[4] * s.y + R[5] * s.z + t[1];
     const float pz = R[6] * s.x + R[7] * s.y + R[8] * s.z + t[2];
     bq[q] = comp == 0 ? px : comp == 1 ? py : comp == 2 ? pz : 1.0f;
-    snorm[q] = px * px + py * py + pz * pz;
     qc[3 * q] = px;
     qc[3 * q + 1] = py;
     qc[3 * q + 2] = pz;
@@ -80,7 +79,7 @@ __device__ __forceinline__ void nn_forward_body(const Dev& d) {
 #pragma unroll
     for (int q = 0; q < Q; ++q) vq[q] = max(0, min(16, pi.n - (chunk * QPW + q * 16)));
     pairs = nn_scan_pruned<Q, true, FINE>(prep, oi.ntg, oi.m, d.obj_box + (size_t)oi.prep_tg_begin / kChunkTG * 8,
-                                    bq, snorm, qc, vq, idx, d.flags + 1);
+                                    bq, nullptr, qc, vq, idx, d.flags + 1);
   } else {
     nn_scan<Q>(prep, oi.ntg, bq, qc, idx, d.flags + 1);
     pairs = (long long)oi.m * min(QPW, pi.n - chunk * QPW);

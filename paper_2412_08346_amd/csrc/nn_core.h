@@ -292,7 +292,8 @@ __device__ __forceinline__ float point_box2(const float* p, const float* bx) {
 // lane's query).  Neither test can drop a chunk holding a value equal to a
 // final minimum, so the results do not depend on them.
 // snorm[q] = |s|^2 of the lane's query in block q (turns the reduced value
-// |r|^2 - 2 r.s into a squared distance); box = the cloud's chunk boxes;
+// |r|^2 - 2 r.s into a squared distance; with BATCH_RESCAN it is computed
+// from qc instead and snorm may be null); box = the cloud's chunk boxes;
 // m = real points of the cloud; vq[q] = real queries of block q.  Returns the
 // number of (query, point) distances evaluated (wave-uniform).  Every bound
 // carries a slack of 1e-4 relative plus 1e-7 (squared length units) for the
@@ -328,7 +329,16 @@ __device__ __forceinline__ long long nn_scan_pruned(const float4* __restrict__ p
   auto refresh = [&]() {
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      qb[q] = (rows_min(best[q]) + snorm[q]) * 1.0001f + 1e-7f;
+      float sn = snorm ? snorm[q] : 0.0f;
+      if (BATCH_RESCAN) {
+        // |s|^2 from the query's coordinates, recomputed here rather than
+        // kept in registers through the scan (the empty constraints keep the
+        // compiler from hoisting it out of the loop)
+        float x = qc[3 * q], y = qc[3 * q + 1], z = qc[3 * q + 2];
+        __asm__("" : "+v"(x), "+v"(y), "+v"(z));
+        sn = __builtin_fmaf(z, z, __builtin_fmaf(y, y, x * x));
+      }
+      qb[q] = (rows_min(best[q]) + sn) * 1.0001f + 1e-7f;
       // every row holds the same 16 queries, so the row maximum is uniform
       ub[q] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(row_max(qb[q]))));
     }
