@@ -285,12 +285,16 @@ __device__ __forceinline__ float point_box2(const float* p, const float* bx) {
 // spatially coherent for this to pay (contact clouds are Morton sorted).
 //
 // The chunk nearest to the wave's query box is scanned first; the other
-// candidates follow in index order.  A block of queries takes a candidate
-// chunk only while the box-to-box lower bound is within the block's bound
-// (refreshed every ASICP_NN_REFRESH chunks) and, with FINE, only if some
-// query's point-to-box distance is within that query's own best (qc holds the
-// lane's query).  Neither test can drop a chunk holding a value equal to a
-// final minimum, so the results do not depend on them.
+// candidates follow nearest first (smallest box-to-box lower bound over the
+// blocks that may need them), and the scan of a 64-chunk block stops once
+// every remaining lower bound exceeds every block's bound.  A block of
+// queries takes a candidate chunk only while the box-to-box lower bound is
+// within the block's bound (refreshed every ASICP_NN_REFRESH chunks) and,
+// with FINE, only if some query's point-to-box distance is within that
+// query's own best (qc holds the lane's query).  None of these tests can drop
+// a chunk holding a value equal to a final minimum, and the chunk record of
+// chunk_step does not depend on the visiting order, so the results do not
+// depend on them.
 // snorm[q] = |s|^2 of the lane's query in block q (turns the reduced value
 // |r|^2 - 2 r.s into a squared distance; with BATCH_RESCAN it is computed
 // from qc instead and snorm may be null); box = the cloud's chunk boxes;
