@@ -502,31 +502,6 @@ static void schedule_of(const asicp_config& cfg, int k, float* gamma, float* tau
   }
 }
 
-static asicp_status nn_forward_timed(asicp_ctx c, hipStream_t hs) {
-  const bool timing = (c->cfg.flags & ASICP_FLAG_TIMING) != 0 && !c->capturing;
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (timing) {
-    if ((size_t)(2 * c->n_timed + 2) > c->ev.size()) {
-      hipEvent_t a, b;
-      if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
-        return fail(ASICP_E_HIP, "hipEventCreate failed");
-      c->ev.push_back(a);
-      c->ev.push_back(b);
-    }
-    e0 = c->ev[2 * c->n_timed];
-    e1 = c->ev[2 * c->n_timed + 1];
-    if (hipEventRecord(e0, hs) != hipSuccess) return fail(ASICP_E_HIP, "hipEventRecord failed");
-  }
-  launch_nn_forward(c->d, hs);
-  asicp_status st = check_launch("nn_forward");
-  if (st != ASICP_OK) return st;
-  if (timing) {
-    if (hipEventRecord(e1, hs) != hipSuccess) return fail(ASICP_E_HIP, "hipEventRecord failed");
-    ++c->n_timed;
-  }
-  return ASICP_OK;
-}
-
 // One evaluation at the current poses (and, with bandwidth, the kernel
 // bandwidth of the Stein update that follows): the forward NN on the caller's
 // stream, the bandwidth select and the collision gate on the side stream,
@@ -539,7 +514,23 @@ static asicp_status evaluate(asicp_ctx c, int k, int final_eval, bool bandwidth,
     launch_minibatch(c->d, k, frac, hs);
     if ((st = check_launch("minibatch")) != ASICP_OK) return st;
   }
-  if (hipEventRecord(c->fork_ev, hs) != hipSuccess || hipStreamWaitEvent(c->side, c->fork_ev, 0) != hipSuccess)
+  // With timing on (never inside a captured graph), the event that starts the
+  // forward NN's timed interval is also the fork signal, so the caller's
+  // stream records one event before the launch instead of two.
+  const bool timing = (c->cfg.flags & ASICP_FLAG_TIMING) != 0 && !c->capturing;
+  hipEvent_t e0 = c->fork_ev, e1 = nullptr;
+  if (timing) {
+    if ((size_t)(2 * c->n_timed + 2) > c->ev.size()) {
+      hipEvent_t x, y;
+      if (hipEventCreate(&x) != hipSuccess || hipEventCreate(&y) != hipSuccess)
+        return fail(ASICP_E_HIP, "hipEventCreate failed");
+      c->ev.push_back(x);
+      c->ev.push_back(y);
+    }
+    e0 = c->ev[2 * c->n_timed];
+    e1 = c->ev[2 * c->n_timed + 1];
+  }
+  if (hipEventRecord(e0, hs) != hipSuccess || hipStreamWaitEvent(c->side, e0, 0) != hipSuccess)
     return fail(ASICP_E_HIP, "fork to the side stream failed");
   if (bandwidth) {
     launch_bandwidth(c->d, c->inv_log_k, c->side);
@@ -547,8 +538,12 @@ static asicp_status evaluate(asicp_ctx c, int k, int final_eval, bool bandwidth,
   }
   launch_gate_reverse(c->d, c->side);
   if ((st = check_launch("gate_reverse")) != ASICP_OK) return st;
-  st = nn_forward_timed(c, hs);
-  if (st != ASICP_OK) return st;
+  launch_nn_forward(c->d, hs);
+  if ((st = check_launch("nn_forward")) != ASICP_OK) return st;
+  if (timing) {
+    if (hipEventRecord(e1, hs) != hipSuccess) return fail(ASICP_E_HIP, "hipEventRecord failed");
+    ++c->n_timed;
+  }
   if (hipEventRecord(c->join_ev, c->side) != hipSuccess || hipStreamWaitEvent(hs, c->join_ev, 0) != hipSuccess)
     return fail(ASICP_E_HIP, "join of the side stream failed");
   launch_finalize(c->d, k, final_eval, hs);
