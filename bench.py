@@ -24,7 +24,7 @@ FLOP_PER_PAIR = 6          # 3 multiply-adds of |r|^2 - 2 r.s per (query, object
 # (profiles/nn_forward_counters_paper_scale.md).  Reported only while the
 # kernel's sources hash to the ones measured.
 NN_TRAFFIC = {"sha256": "09f2abff3e00eb5b4ae9f880251535ef29bbbc5ee5eeabaaafb658032b4f52d8",
-              "bytes": {"1,0": 6294146, "1,1": 6303825}}  # launch "map,fine" -> bytes per launch
+              "bytes": {"0,0": 4872721, "0,1": 4899543, "1,0": 6292331, "1,1": 6305217}}  # launch "map,fine" -> bytes per launch
 NN_SOURCES = ("k_nn_forward.hip", "nn_core.h", "asicp_internal.h")
 
 
