@@ -25,6 +25,10 @@ constexpr int kTileGroup = 64;     // points per MFMA-ready tile group (4 tiles 
 #ifndef ASICP_NN_REFRESH
 #define ASICP_NN_REFRESH 4
 #endif
+// Tile groups (64 points each) per pruning chunk: 1 or 2.
+#ifndef ASICP_NN_CHUNK_TG
+#define ASICP_NN_CHUNK_TG 2
+#endif
 constexpr int kNnQ = ASICP_NN_Q;
 constexpr int kQueriesPerWave = 16 * kNnQ;
 constexpr int kGateChunk = 2048;   // collision points per gate workgroup (8 per thread)

@@ -222,13 +222,14 @@ __global__ __launch_bounds__(1024) void k_sort_cloud(Dev d) {
     }
   }
   __syncthreads();
-  // chunk boxes (128 points per chunk; an all-padding chunk gets an empty box)
+  // chunk boxes (kChunkPts points per chunk; an all-padding chunk gets an
+  // empty box)
   const int nch = ntg / kChunkTG;
   for (int c = tid; c < nch; c += 1024) {
     float bb[6] = {__builtin_inff(), __builtin_inff(), __builtin_inff(),
                    -__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
-    const int k1 = min(n, (c + 1) * 128);
-    for (int k = c * 128; k < k1; ++k) {
+    const int k1 = min(n, (c + 1) * kChunkPts);
+    for (int k = c * kChunkPts; k < k1; ++k) {
       const float4 p = pts[base + k];
       bb[0] = fminf(bb[0], p.x); bb[1] = fminf(bb[1], p.y); bb[2] = fminf(bb[2], p.z);
       bb[3] = fmaxf(bb[3], p.x); bb[4] = fmaxf(bb[4], p.y); bb[5] = fmaxf(bb[5], p.z);

@@ -51,6 +51,10 @@ __device__ __forceinline__ float2 load_f2(__amdgpu_buffer_rsrc_t r, unsigned byt
   return f;
 }
 
+__device__ __forceinline__ float load_f1(__amdgpu_buffer_rsrc_t r, unsigned byte_off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0));
+}
+
 __device__ __forceinline__ float4 load_tg(__amdgpu_buffer_rsrc_t r, int tg, unsigned lane_off) {
   const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, lane_off, tg * 1024, 0);
   float4 f;
@@ -58,9 +62,12 @@ __device__ __forceinline__ float4 load_tg(__amdgpu_buffer_rsrc_t r, int tg, unsi
   return f;
 }
 
-// Chunk = 2 tile groups = 128 points; prepared clouds are padded to a whole
-// number of chunk pairs (256 points) so the main loop runs without a tail.
-constexpr int kChunkTG = 2;
+// Chunk = kChunkTG tile groups (64 or 128 points), the unit of spatial
+// pruning; prepared clouds are padded to a multiple of 256 points, a whole
+// number of chunk pairs, so the full scan's loop runs without a tail.
+constexpr int kChunkTG = ASICP_NN_CHUNK_TG;
+static_assert(kChunkTG == 1 || kChunkTG == 2, "a chunk is one or two tile groups");
+constexpr int kChunkPts = 64 * kChunkTG;
 constexpr int kPadPoints = 256;
 
 // Fold the 16 distances a lane holds for one query and one tile group into
@@ -90,22 +97,24 @@ __device__ __forceinline__ void tile_group(const float4& a, const float* b, floa
   }
 }
 
-// Fold one chunk (two tile groups) into each lane's running minimum.  The
+// Fold one chunk (kChunkTG tile groups) into each lane's running minimum.  The
 // chunk's own minimum is folded first, so that the chunk recorded with the
 // running minimum is the lowest-index chunk holding it whatever order the
 // chunks are visited in: a chunk with a smaller value replaces it, one with
 // an equal value only if its index is lower.
 template <int Q>
-__device__ __forceinline__ void chunk_step(const float4& a0, const float4& a1, const float* b,
-                                           float* best, int* bch, int c, const bool* need = nullptr) {
+__device__ __forceinline__ void chunk_step(const float4 (&a)[kChunkTG], const float* b, float* best, int* bch,
+                                           int c, const bool* need = nullptr) {
   float m[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) m[q] = __builtin_inff();
-  tile_group<Q>(a0, b, m, need);
+#pragma unroll
+  for (int t = 0; t < kChunkTG; ++t) {
 #if ASICP_NN_SPLIT
-  __builtin_amdgcn_sched_barrier(0);  // keep one tile group's MFMA results live at a time
+    if (t) __builtin_amdgcn_sched_barrier(0);  // keep one tile group's MFMA results live at a time
 #endif
-  tile_group<Q>(a1, b, m, need);
+    tile_group<Q>(a[t], b, m, need);
+  }
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     if (need && !need[q]) continue;  // wave-uniform
@@ -123,13 +132,13 @@ __device__ __forceinline__ void chunk_step(const float4& a0, const float4& a1, c
 // performs.
 //
 // With BATCH, when one lane group wins (the usual case), the query's four
-// lanes test that group's 4 rows in all 8 tiles of the chunk: lane group g
-// takes tile group g/2 and its sub-tiles 2(g%2) and 2(g%2)+1, whose values
-// are adjacent in the prepared cloud, so 16 eight-byte buffer loads with
-// immediate offsets fetch all 32 operands at once; qc holds the lane's query
+// lanes test that group's 4 rows in all 4 kChunkTG tiles of the chunk: lane
+// group g takes tiles g kChunkTG .. g kChunkTG + kChunkTG - 1 (sub-tiles of
+// one tile group, adjacent in the prepared cloud), so 16 buffer loads with
+// immediate offsets fetch all operands at once; qc holds the lane's query
 // (x, y, z per block) from the caller.  Otherwise (or on ties between lane
-// groups, which test all 16 rows) the lanes split the 8 tiles and test row
-// by row, reading the query from the B operand.
+// groups, which test all 16 rows) the lanes split the tiles and test row by
+// row, reading the query from the B operand.
 template <int Q, bool BATCH>
 __device__ __forceinline__ void nn_rescan(const float4* __restrict__ prep, __amdgpu_buffer_rsrc_t rs,
                                           const float* b, const float* qc, const float* best,
@@ -150,37 +159,40 @@ __device__ __forceinline__ void nn_rescan(const float4* __restrict__ prep, __amd
     if (cmin != 0x7fffffff) {
       if (BATCH && ng == 1) {
         const float s0 = qc[3 * q], s1 = qc[3 * q + 1], s2 = qc[3 * q + 2];
-        const int tgi = grp >> 1, u0 = (grp & 1) * 2, r0 = 4 * gw;
+        const int t0 = grp * kChunkTG;  // first tile of the lane group within the chunk
+        const int tgi = t0 >> 2, u0 = t0 & 3, r0 = 4 * gw;
         const unsigned voff = 4u * (unsigned)((cmin * kChunkTG + tgi) * 256 + r0 * 4 + u0);
-        float2 a[4][4];  // [component][row]: sub-tiles u0 and u0 + 1
+        float a[4][4][kChunkTG];  // [component][row][sub-tile]
 #pragma unroll
         for (int k = 0; k < 4; ++k)
 #pragma unroll
-          for (int ii = 0; ii < 4; ++ii) a[k][ii] = load_f2(rs, voff + 16u * (unsigned)(k * 16 + ii));
-        const int tbase = ((cmin * kChunkTG + tgi) * 4 + u0) * 16 + r0;
+          for (int ii = 0; ii < 4; ++ii) {
+            if (kChunkTG == 2) {
+              const float2 v = load_f2(rs, voff + 16u * (unsigned)(k * 16 + ii));
+              a[k][ii][0] = v.x;
+              a[k][ii][kChunkTG - 1] = v.y;
+            } else {
+              a[k][ii][0] = load_f1(rs, voff + 16u * (unsigned)(k * 16 + ii));
+            }
+          }
+        const int tbase = (cmin * kChunkTG * 4 + t0) * 16 + r0;
 #pragma unroll
-        for (int ii = 3; ii >= 0; --ii) {  // the lowest index is tested last, so it wins
-          float acc = __builtin_fmaf(a[0][ii].y, s0, 0.0f);
-          acc = __builtin_fmaf(a[1][ii].y, s1, acc);
-          acc = __builtin_fmaf(a[2][ii].y, s2, acc);
-          acc = __builtin_fmaf(a[3][ii].y, 1.0f, acc);
-          if (acc == vmin) cand = tbase + 16 + ii;
-        }
+        for (int u = kChunkTG - 1; u >= 0; --u)
 #pragma unroll
-        for (int ii = 3; ii >= 0; --ii) {
-          float acc = __builtin_fmaf(a[0][ii].x, s0, 0.0f);
-          acc = __builtin_fmaf(a[1][ii].x, s1, acc);
-          acc = __builtin_fmaf(a[2][ii].x, s2, acc);
-          acc = __builtin_fmaf(a[3][ii].x, 1.0f, acc);
-          if (acc == vmin) cand = tbase + ii;
-        }
+          for (int ii = 3; ii >= 0; --ii) {  // the lowest index is tested last, so it wins
+            float acc = __builtin_fmaf(a[0][ii][u], s0, 0.0f);
+            acc = __builtin_fmaf(a[1][ii][u], s1, acc);
+            acc = __builtin_fmaf(a[2][ii][u], s2, acc);
+            acc = __builtin_fmaf(a[3][ii][u], 1.0f, acc);
+            if (acc == vmin) cand = tbase + 16 * u + ii;
+          }
       } else {
         const float s0 = __shfl(b[q], j, 64);
         const float s1 = __shfl(b[q], j + 16, 64);
         const float s2 = __shfl(b[q], j + 32, 64);
         const float s3 = __shfl(b[q], j + 48, 64);
         const int r0 = (ng > 1) ? 0 : 4 * gw, r1 = (ng > 1) ? 16 : 4 * gw + 4;
-        for (int tt = 0; tt < 2 && cand == 0x7fffffff; ++tt) {
+        for (int tt = 0; tt < kChunkTG && cand == 0x7fffffff; ++tt) {
           const int t = grp + 4 * tt;  // tile within the chunk: tile group t/4, sub-tile t%4
           const float* base = pf + (size_t)(cmin * kChunkTG + (t >> 2)) * 256 + (t & 3);
           for (int i = r0; i < r1; ++i) {
@@ -228,16 +240,18 @@ __device__ __forceinline__ void nn_scan(const float4* __restrict__ prep, int ntg
   const int nch = ntg / kChunkTG;  // even
   const unsigned lo = 16u * (unsigned)lane;
   const __amdgpu_buffer_rsrc_t rs = cloud_rsrc(prep, ntg);
-  float4 x0 = load_tg(rs, 0, lo), x1 = load_tg(rs, 1, lo);
+  float4 x[kChunkTG], y[kChunkTG];
+#pragma unroll
+  for (int t = 0; t < kChunkTG; ++t) x[t] = load_tg(rs, t, lo);
   for (int c = 0; c < nch; c += 2) {
-    const float4 y0 = load_tg(rs, 2 * c + 2, lo);
-    const float4 y1 = load_tg(rs, 2 * c + 3, lo);
-    chunk_step<Q>(x0, x1, b, best, bch, c);
+#pragma unroll
+    for (int t = 0; t < kChunkTG; ++t) y[t] = load_tg(rs, (c + 1) * kChunkTG + t, lo);
+    chunk_step<Q>(x, b, best, bch, c);
     if (c + 2 < nch) {
-      x0 = load_tg(rs, 2 * c + 4, lo);
-      x1 = load_tg(rs, 2 * c + 5, lo);
+#pragma unroll
+      for (int t = 0; t < kChunkTG; ++t) x[t] = load_tg(rs, (c + 2) * kChunkTG + t, lo);
     }
-    chunk_step<Q>(y0, y1, b, best, bch, c + 1);
+    chunk_step<Q>(y, b, best, bch, c + 1);
   }
   nn_rescan<Q, true>(prep, rs, b, qc, best, bch, idx, miss);
 }
@@ -384,8 +398,11 @@ __device__ __forceinline__ long long nn_scan_pruned(const float4* __restrict__ p
   for (int q = 0; q < Q; ++q) vqu[q] = __builtin_amdgcn_readfirstlane(vq[q]);
   long long pairs = 0;
   {
-    const int pts = max(0, min(128, mu - 128 * c0));
-    chunk_step<Q>(load_tg(rs, 2 * c0, lo), load_tg(rs, 2 * c0 + 1, lo), b, best, bch, c0);
+    const int pts = max(0, min(kChunkPts, mu - kChunkPts * c0));
+    float4 x0[kChunkTG];
+#pragma unroll
+    for (int t = 0; t < kChunkTG; ++t) x0[t] = load_tg(rs, c0 * kChunkTG + t, lo);
+    chunk_step<Q>(x0, b, best, bch, c0);
 #pragma unroll
     for (int q = 0; q < Q; ++q) pairs += (long long)(pts * vqu[q]);
   }
@@ -436,15 +453,17 @@ __device__ __forceinline__ long long nn_scan_pruned(const float4* __restrict__ p
     // One step compares chunk cl (held in cur) and loads the next candidate
     // into nxt while it does; two steps per iteration swap the roles of the
     // register pairs, so no copy is made between them.
-    float4 x0 = load_tg(rs, 2 * (blk + cl), lo), x1 = load_tg(rs, 2 * (blk + cl) + 1, lo), y0, y1;
-    auto step = [&](const float4& cur0, const float4& cur1, float4& nxt0, float4& nxt1) {
+    float4 x[kChunkTG], y[kChunkTG];
+    auto fetch = [&](float4 (&dst)[kChunkTG], int l) {
+#pragma unroll
+      for (int t = 0; t < kChunkTG; ++t) dst[t] = load_tg(rs, (blk + l) * kChunkTG + t, lo);
+    };
+    fetch(x, cl);
+    auto step = [&](const float4 (&cur)[kChunkTG], float4 (&nxt)[kChunkTG]) {
       const int cc = blk + cl;
       int nl = pick();
-      if (nl >= 0) {
-        nxt0 = load_tg(rs, 2 * (blk + nl), lo);
-        nxt1 = load_tg(rs, 2 * (blk + nl) + 1, lo);
-      }
-      const int pts = max(0, min(128, mu - 128 * cc));
+      if (nl >= 0) fetch(nxt, nl);
+      const int pts = max(0, min(kChunkPts, mu - kChunkPts * cc));
       // block q is compared only if chunk cc is still in its mask (a scalar
       // bit test) and, with FINE, some query of the block may improve
       bool need[Q];
@@ -455,7 +474,7 @@ __device__ __forceinline__ long long nn_scan_pruned(const float4* __restrict__ p
         if (FINE && need[q]) need[q] = __ballot(point_box2(qc + 3 * q, bx) <= qb[q]) != 0ull;
         pairs += need[q] ? (long long)(pts * vqu[q]) : 0ll;
       }
-      chunk_step<Q>(cur0, cur1, b, best, bch, cc, need);
+      chunk_step<Q>(cur, b, best, bch, cc, need);
       if (++since == ASICP_NN_REFRESH) {
         since = 0;
         refresh();
@@ -473,10 +492,7 @@ __device__ __forceinline__ long long nn_scan_pruned(const float4* __restrict__ p
           if (n2 != nl) {  // the prefetched chunk is no longer the nearest needed one
             if (was) key = key_of();  // hand it back to the pool
             nl = n2;
-            if (nl >= 0) {
-              nxt0 = load_tg(rs, 2 * (blk + nl), lo);
-              nxt1 = load_tg(rs, 2 * (blk + nl) + 1, lo);
-            }
+            if (nl >= 0) fetch(nxt, nl);
           }
         } else {
           key = key_of();
@@ -485,9 +501,9 @@ __device__ __forceinline__ long long nn_scan_pruned(const float4* __restrict__ p
       cl = nl;
     };
     while (cl >= 0) {
-      step(x0, x1, y0, y1);
+      step(x, y);
       if (cl < 0) break;
-      step(y0, y1, x0, x1);
+      step(y, x);
     }
   }
   nn_rescan<Q, BATCH_RESCAN>(prep, rs, b, qc, best, bch, idx, miss);
