@@ -20,6 +20,10 @@ namespace asicp {
 
 constexpr int kPerThread = kGateChunk / 256;
 constexpr int kGateBatch = 4;  // points whose SDF node values are in flight together
+#ifndef ASICP_REV_Q
+#define ASICP_REV_Q 2
+#endif
+constexpr int kRevQ = ASICP_REV_Q;  // blocks of 16 colliding points per reverse scan (1, 2 or 4)
 
 // Workgroup placement over the XCDs, as for the forward kernel (MAP 0:
 // contiguous work per XCD, MAP 1: dispatch order); changes no result.
@@ -281,33 +285,33 @@ __global__ __launch_bounds__(256) void k_gate_reverse(Dev d) {
     return;
   }
   // reverse NN: blocks of 16 colliding points; wave w takes blocks w, w+4, ...
-  // in batches of up to 4 blocks per scan of the contact cloud
+  // in batches of up to kRevQ blocks per scan of the contact cloud (few
+  // blocks per scan keep the kernel's registers within what one retiring
+  // forward-NN workgroup frees, so it can run beside that launch)
   const int nb = (total + 15) >> 4;
   const int nbw = (nb > w) ? (nb - w + 3) >> 2 : 0;
   const int comp = lane >> 4;
   float e2 = 0.f, ex = 0.f, ey = 0.f, ez = 0.f, mx = 0.f, my = 0.f, mz = 0.f;
-  for (int k0 = 0; k0 < nbw; k0 += 4) {
-    const int qn = min(4, nbw - k0);
-    float bq[4];
+  for (int k0 = 0; k0 < nbw; k0 += kRevQ) {
+    const int qn = min(kRevQ, nbw - k0);
+    float bq[kRevQ];
     const int pfirst = (w + 4 * k0) * 16;  // a colliding point of this batch
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < kRevQ; ++q) {
       int p = (w + 4 * (k0 + q)) * 16 + (lane & 15);
       if (!(q < qn && p < total)) p = pfirst;  // padding queries repeat it
       const float v = comp == 0 ? lx[p] : comp == 1 ? ly[p] : lz[p];
       bq[q] = comp == 3 ? 1.0f : v;
     }
-    int idx[4] = {0, 0, 0, 0};
-    switch (qn) {
-      case 1: rev_scan<1>(d, pi, bq, idx); break;
-      case 2: rev_scan<2>(d, pi, bq, idx); break;
-      case 3: rev_scan<3>(d, pi, bq, idx); break;
-      default: rev_scan<4>(d, pi, bq, idx); break;
-    }
+    int idx[kRevQ];
+#pragma unroll
+    for (int q = 0; q < kRevQ; ++q) idx[q] = 0;
+    if (kRevQ == 1 || qn == 1) rev_scan<1>(d, pi, bq, idx);
+    else rev_scan<kRevQ>(d, pi, bq, idx);
     int my_idx = idx[0];
-    if (comp == 1) my_idx = idx[1];
-    if (comp == 2) my_idx = idx[2];
-    if (comp == 3) my_idx = idx[3];
+#pragma unroll
+    for (int q = 1; q < kRevQ; ++q)
+      if (comp == q) my_idx = idx[q];
     const int p = (w + 4 * (k0 + comp)) * 16 + (lane & 15);
     if (comp < qn && p < total) {
       if (my_idx >= pi.n) {

@@ -122,9 +122,11 @@ __global__ __launch_bounds__(256) void k_bw_pass(Dev d, int pass, float inv_log_
   }
 }
 
-// The same radix select in one workgroup of 1024 threads per group, for
-// K (K - 1) / 2 <= 32768 unordered pairs (K <= 256): each thread keeps the bit
-// patterns of its (at most 32) pairs in registers, so the distances are formed
+// The same radix select in one workgroup per group of 256, 512 or 1024
+// threads (the fewest that hold K (K - 1) / 2 <= 32768 unordered pairs, so
+// K <= 256, at 32 per thread: smaller workgroups find room on CUs busy with
+// the forward NN launch beside them): each thread keeps the bit patterns of
+// its (at most 32) pairs in registers, so the distances are formed
 // once and the four passes only rebuild the LDS histogram and pick a digit,
 // with no global histogram, no last-workgroup hand-off and one launch instead
 // of four.  Pair slot s is {i, (i + d) mod K} with i = s mod K, d = s / K + 1:
@@ -136,14 +138,15 @@ __global__ __launch_bounds__(1024) void k_bw_fused(Dev d, float inv_log_k) {
   __shared__ unsigned int hist[256];
   __shared__ unsigned int s_sel[3];  // prefix, mask, rank
   const int g = blockIdx.x, tid = threadIdx.x, lane = tid & 63, K = d.K, Kt = d.Ktot;
-  for (int j = tid; j < 3 * K; j += 1024) {
+  const int nt = blockDim.x;  // 256, 512 or 1024
+  for (int j = tid; j < 3 * K; j += nt) {
     const int a = j / K, p = j - a * K;
     st[3 * p + a] = d.theta[a * Kt + g * K + p];
   }
   if (tid < 256) hist[tid] = 0u;
   __syncthreads();
   const int P = K * (K - 1) / 2;
-  const int step_d = 1024 / K, step_i = 1024 - step_d * K;
+  const int step_d = nt / K, step_i = nt - step_d * K;
   int pi = tid % K, pd = tid / K + 1;
   unsigned int bits[kBwRegs];
   // distances, and the first-pass histogram (sign and exponent bits: few
@@ -151,8 +154,8 @@ __global__ __launch_bounds__(1024) void k_bw_fused(Dev d, float inv_log_k) {
 #pragma unroll
   for (int r = 0; r < kBwRegs; ++r) {
     bits[r] = 0u;
-    if (r * 1024 < P) {
-      bool act = r * 1024 + tid < P;
+    if (r * nt < P) {
+      bool act = r * nt + tid < P;
       if (act) {
         int pj = pi + pd;
         pj -= pj >= K ? K : 0;
@@ -184,7 +187,7 @@ __global__ __launch_bounds__(1024) void k_bw_fused(Dev d, float inv_log_k) {
     if (pass > 0) {
 #pragma unroll
       for (int r = 0; r < kBwRegs; ++r)
-        if (r * 1024 + tid < P && (bits[r] & mask) == prefix) atomicAdd(&hist[(bits[r] >> shift) & 255u], 1u);
+        if (r * nt + tid < P && (bits[r] & mask) == prefix) atomicAdd(&hist[(bits[r] >> shift) & 255u], 1u);
     }
     __syncthreads();
     if (tid < 64) {
@@ -347,8 +350,11 @@ __global__ __launch_bounds__(256) void k_svgd_apply(Dev d) {
 
 void launch_bandwidth(const Dev& d, float inv_log_k, hipStream_t s) {
   if (d.K >= 2 && d.bw_mode == ASICP_BW_MEDIAN) {
-    if (d.K * (d.K - 1) / 2 <= kBwRegs * 1024) {
-      hipLaunchKernelGGL(k_bw_fused, dim3(d.G), dim3(1024), 0, s, d, inv_log_k);
+    const int pairs = d.K * (d.K - 1) / 2;
+    if (pairs <= kBwRegs * 1024) {
+      int nt = 256;
+      while (nt * kBwRegs < pairs) nt *= 2;
+      hipLaunchKernelGGL(k_bw_fused, dim3(d.G), dim3(nt), 0, s, d, inv_log_k);
     } else {
       for (int pass = 0; pass < 4; ++pass)
         hipLaunchKernelGGL(k_bw_pass, dim3(kBwSlices, d.G), dim3(256), 0, s, d, pass, inv_log_k);
