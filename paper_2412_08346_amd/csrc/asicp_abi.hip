@@ -25,7 +25,7 @@ constexpr int kMaxPoints = 1 << 22;   // per object / collision cloud / preshape
 constexpr int kMaxGroups = 1 << 16;
 
 struct Layout {
-  size_t groups, objs, pres, obj_prep, pre_prep, obj_pts, pre_pts, obj_perm, pre_perm, obj_box, pre_box;
+  size_t groups, objs, pres, obj_prep, pre_prep, obj_pts, pre_pts, obj_perm, pre_perm, obj_box, pre_box, col_box;
   size_t sort_keys, wave_pairs, obj_com, pre_const, col_pts, col_perm, obj_prep_mb, batch_mark, prior;
   size_t theta, cost, col_cost, prev_cost, ncol, converged, grad, grad_ct, grad_col, phi, h, bw_hist, bw_state;
   size_t nn_part, col_part, pen_part, best, best_theta, flags, dbg_nn, dbg_rev;
@@ -35,6 +35,7 @@ struct Layout {
 struct Shape {
   int n_obj, n_pre, K, G, Ktot;
   int obj_tg, pre_tg, max_waves_pp, max_gate_chunks, n_max, mc_max;
+  long long gate_chunks;  // over all objects
   long long sort_keys;  // total power-of-two padded cloud sizes
   long long c_total;    // collision points over all objects
   long long r_total;    // object points over all objects
@@ -67,6 +68,7 @@ Layout layout_of(const Shape& s) {
   L.pre_perm = bump(c, (size_t)s.pre_tg * 64 * 4);
   L.obj_box = bump(c, (size_t)s.obj_tg / kChunkTG * 32);
   L.pre_box = bump(c, (size_t)s.pre_tg / kChunkTG * 32);
+  L.col_box = bump(c, 32 * (size_t)(s.gate_chunks > 0 ? s.gate_chunks : 1));
   L.sort_keys = bump(c, (size_t)s.sort_keys * 8);
   L.col_pts = bump(c, (size_t)(s.c_total > 0 ? s.c_total : 1) * 16);
   L.obj_prep_mb = s.minibatch ? bump(c, (size_t)s.obj_tg * 64 * 16) : 0;
@@ -136,6 +138,7 @@ asicp_status validate(const asicp_problem* pb, const asicp_config* cfg, Shape& s
   s.n_max = s.mc_max = 0;
   s.max_waves_pp = 0;
   s.max_gate_chunks = 0;
+  s.gate_chunks = 0;
   bool any_c = false;
   for (int o = 0; o < s.n_obj; ++o) {
     const long long m = (long long)pb->r_off[o + 1] - pb->r_off[o];
@@ -147,6 +150,7 @@ asicp_status validate(const asicp_problem* pb, const asicp_config* cfg, Shape& s
     if (mc > 0) s.sort_keys += pow2_at_least((long long)mc);
     s.mc_max = std::max(s.mc_max, (int)mc);
     s.max_gate_chunks = std::max(s.max_gate_chunks, (int)((mc + kGateChunk - 1) / kGateChunk));
+    s.gate_chunks += (mc + kGateChunk - 1) / kGateChunk;
     any_c = any_c || mc > 0;
   }
   if (any_c && (!pb->cx || !pb->cy || !pb->cz))
@@ -312,9 +316,10 @@ asicp_status asicp_create(const asicp_problem* pb, const asicp_config* cfg, void
   std::vector<PreInfo> pres(s.n_pre);
   int tg = 0;
   long long key_off = 0;
+  int gbox = 0;
   for (int o = 0; o < s.n_obj; ++o) {
     ObjInfo& oi = objs[o];
-    std::memset(&oi, 0, sizeof oi);  // the cloud's bounding box is filled in on the device
+    std::memset(&oi, 0, sizeof oi);
     oi.r_begin = pb->r_off[o];
     oi.m = pb->r_off[o + 1] - pb->r_off[o];
     oi.c_begin = pb->c_off[o];
@@ -322,6 +327,8 @@ asicp_status asicp_create(const asicp_problem* pb, const asicp_config* cfg, void
     oi.prep_tg_begin = tg;
     oi.ntg = ((oi.m + kPadPoints - 1) / kPadPoints) * (kPadPoints / 64);
     oi.gate_chunks = (oi.mc + kGateChunk - 1) / kGateChunk;
+    oi.gbox_begin = gbox;
+    gbox += oi.gate_chunks;
     oi.key_off = (int32_t)key_off;
     key_off += pow2_at_least(oi.m);
     oi.c_key_off = (int32_t)key_off;
@@ -387,6 +394,7 @@ asicp_status asicp_create(const asicp_problem* pb, const asicp_config* cfg, void
   d.pre_perm = reinterpret_cast<int32_t*>(ws + L.pre_perm);
   d.obj_box = reinterpret_cast<float*>(ws + L.obj_box);
   d.pre_box = reinterpret_cast<float*>(ws + L.pre_box);
+  d.col_box = reinterpret_cast<float*>(ws + L.col_box);
   d.sort_keys = reinterpret_cast<unsigned long long*>(ws + L.sort_keys);
   d.col_pts = reinterpret_cast<float4*>(ws + L.col_pts);
   d.col_perm = reinterpret_cast<int32_t*>(ws + L.col_perm);

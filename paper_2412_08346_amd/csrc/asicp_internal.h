@@ -51,9 +51,8 @@ struct ObjInfo {
   int32_t ntg;             // tile groups (ceil(m / 64))
   int32_t gate_chunks;     // ceil(mc / kGateChunk)
   int32_t key_off;         // offset of this cloud's sort keys (uint64) in the scratch
-  float cmin[3], cmax[3];  // bounding box of the collision cloud (set on the device)
   int32_t c_key_off;       // sort keys of the collision cloud
-  int32_t pad2;
+  int32_t gbox_begin;      // first of this cloud's gate-chunk boxes
 };
 
 // Per-preshape descriptor.
@@ -93,6 +92,7 @@ struct Dev {
   int32_t* pre_perm;
   float* obj_box;
   float* pre_box;
+  float* col_box;  // [gate chunks][8]: box of each kGateChunk points of the sorted collision clouds
   float4* col_pts;    // collision clouds in Morton order (offsets as the input's)
   int32_t* col_perm;
   unsigned long long* sort_keys;

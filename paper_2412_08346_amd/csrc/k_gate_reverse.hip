@@ -12,8 +12,9 @@
 //
 // Trilinear weights are non-negative, so a point can only collide inside a
 // cell with a negative corner: the box of such cells (from the negative SDF
-// nodes) culls whole workgroups (transformed bounding box of the cloud) and
-// single points without reading the grid.  Both tests are exact.
+// nodes) culls whole workgroups (the transformed box of the workgroup's own
+// 2048 points, compact because the cloud is Morton sorted) and single points
+// without reading the grid.  Both tests are exact.
 #include "nn_core.h"
 
 namespace asicp {
@@ -92,18 +93,19 @@ __device__ __forceinline__ float sdf_interp(const float v[8], const float f[3], 
   return val;
 }
 
-// Can any point of the cloud's bounding box reach a cell with a negative
-// corner?  Box corners are moved into the gripper frame; a 10 um margin covers
-// the rounding of the per-point transform.
-__device__ __forceinline__ bool box_may_collide(const PreInfo& pi, const ObjInfo& oi, const float R[9],
+// Can any point of a box of collision points (lo = bx[0..2], hi = bx[4..6])
+// reach a cell with a negative corner?  Box corners are moved into the
+// gripper frame; a 10 um margin covers the rounding of the per-point
+// transform.
+__device__ __forceinline__ bool box_may_collide(const PreInfo& pi, const float* bx, const float R[9],
                                                 const float t[3]) {
   if (pi.neg_hi[0] < 0) return false;  // no negative node at all
   float lo[3] = {__builtin_inff(), __builtin_inff(), __builtin_inff()};
   float hi[3] = {-__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
   for (int c = 0; c < 8; ++c) {
-    const float dx = ((c & 1) ? oi.cmax[0] : oi.cmin[0]) - t[0];
-    const float dy = ((c & 2) ? oi.cmax[1] : oi.cmin[1]) - t[1];
-    const float dz = ((c & 4) ? oi.cmax[2] : oi.cmin[2]) - t[2];
+    const float dx = ((c & 1) ? bx[4] : bx[0]) - t[0];
+    const float dy = ((c & 2) ? bx[5] : bx[1]) - t[1];
+    const float dz = ((c & 4) ? bx[6] : bx[2]) - t[2];
     const float p[3] = {R[0] * dx + R[3] * dy + R[6] * dz, R[1] * dx + R[4] * dy + R[7] * dz,
                         R[2] * dx + R[5] * dy + R[8] * dz};
     for (int a = 0; a < 3; ++a) {
@@ -173,7 +175,9 @@ __global__ __launch_bounds__(256) void k_gate_reverse(Dev d) {
   quat_to_rot(qv[0], qv[1], qv[2], qv[3], R);
 
   float* pout = d.pen_part + ((size_t)i * d.max_gate_chunks + cc) * kPartStride;
-  if (!box_may_collide(pi, oi, R, t)) {
+  // the box of this workgroup's 2048 points (spatially compact: the cloud is
+  // Morton sorted), not of the whole cloud, so most far chunks stop here
+  if (!box_may_collide(pi, d.col_box + (size_t)(oi.gbox_begin + cc) * 8, R, t)) {
     if (tid < kPartStride) {
       out[tid] = 0.f;
       pout[tid] = 0.f;

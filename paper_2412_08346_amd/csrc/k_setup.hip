@@ -25,7 +25,6 @@ __device__ void block_sum4(double v[4], double (*sh)[4]) {
 // one workgroup per object
 __global__ __launch_bounds__(256) void k_setup_obj(Dev d) {
   __shared__ double sh[256][4];
-  __shared__ float sb[256][6];
   const int o = blockIdx.x, tid = threadIdx.x;
   const ObjInfo oi = d.objs[o];
   double v[4] = {0, 0, 0, 0};
@@ -38,30 +37,6 @@ __global__ __launch_bounds__(256) void k_setup_obj(Dev d) {
   if (tid == 0) {
     for (int a = 0; a < 3; ++a) d.obj_com[4 * o + a] = (float)(v[a] / (double)oi.m);
     d.obj_com[4 * o + 3] = 0.f;
-  }
-  // bounding box of the collision cloud
-  float b[6] = {__builtin_inff(), __builtin_inff(), __builtin_inff(),
-                -__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
-  for (int m = tid; m < oi.mc; m += 256) {
-    const float x = d.cx[oi.c_begin + m], y = d.cy[oi.c_begin + m], z = d.cz[oi.c_begin + m];
-    b[0] = fminf(b[0], x); b[1] = fminf(b[1], y); b[2] = fminf(b[2], z);
-    b[3] = fmaxf(b[3], x); b[4] = fmaxf(b[4], y); b[5] = fmaxf(b[5], z);
-  }
-  for (int a = 0; a < 6; ++a) sb[tid][a] = b[a];
-  __syncthreads();
-  for (int off = 128; off >= 1; off >>= 1) {
-    if (tid < off) {
-      for (int a = 0; a < 3; ++a) sb[tid][a] = fminf(sb[tid][a], sb[tid + off][a]);
-      for (int a = 3; a < 6; ++a) sb[tid][a] = fmaxf(sb[tid][a], sb[tid + off][a]);
-    }
-    __syncthreads();
-  }
-  if (tid == 0) {
-    ObjInfo* w = const_cast<ObjInfo*>(d.objs) + o;
-    for (int a = 0; a < 3; ++a) {
-      w->cmin[a] = sb[0][a];
-      w->cmax[a] = sb[0][3 + a];
-    }
   }
 }
 
@@ -104,11 +79,13 @@ __device__ __forceinline__ unsigned int spread10(unsigned int v) {
 
 // One workgroup (1024 threads) per cloud: blocks [0, n_obj) sort object
 // clouds, blocks [n_obj, n_obj + n_pre) contact clouds, the last n_obj blocks
-// collision clouds (only a sorted copy and the original index for those).  Points are ordered by
-// the Morton code of their position in the cloud's bounding box (ties by
-// original index: the keys are unique, so the order is deterministic), then
-// written as MFMA-ready float4, plain float4, the original index, and one
-// bounding box per 128-point chunk.  Padding points carry |r|^2 = 1e30.
+// collision clouds.  Points are ordered by the Morton code of their position
+// in the cloud's bounding box (ties by original index: the keys are unique,
+// so the order is deterministic), then written as MFMA-ready float4, plain
+// float4, the original index, and one bounding box per pruning chunk; a
+// collision cloud gets a plain copy, the original index and one box per
+// kGateChunk points (one gate workgroup's share).  Padding points carry
+// |r|^2 = 1e30.
 __global__ __launch_bounds__(1024) void k_sort_cloud(Dev d) {
   __shared__ float sb[1024][6];
   __shared__ float s_box[6];
@@ -203,6 +180,30 @@ __global__ __launch_bounds__(1024) void k_sort_cloud(Dev d) {
       const int orig = (int)(keys[k] & 0xffffffffull);
       pts[base + k] = make_float4(sx[orig], sy[orig], sz[orig], 0.f);
       perm[base + k] = orig;
+    }
+    // the box of every kGateChunk consecutive sorted points (one gate
+    // workgroup's share), read back from the unsorted inputs
+    const ObjInfo& oi = d.objs[blockIdx.x - d.n_obj - d.n_pre];
+    for (int c = 0; c < oi.gate_chunks; ++c) {
+      float e[6] = {__builtin_inff(), __builtin_inff(), __builtin_inff(),
+                    -__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
+      for (int k = c * kGateChunk + tid; k < min(n, (c + 1) * kGateChunk); k += 1024) {
+        const int orig = (int)(keys[k] & 0xffffffffull);
+        const float x = sx[orig], y = sy[orig], z = sz[orig];
+        e[0] = fminf(e[0], x); e[1] = fminf(e[1], y); e[2] = fminf(e[2], z);
+        e[3] = fmaxf(e[3], x); e[4] = fmaxf(e[4], y); e[5] = fmaxf(e[5], z);
+      }
+      __syncthreads();  // sb is reused
+      for (int a = 0; a < 6; ++a) sb[tid][a] = e[a];
+      __syncthreads();
+      for (int off = 512; off >= 1; off >>= 1) {
+        if (tid < off) {
+          for (int a = 0; a < 3; ++a) sb[tid][a] = fminf(sb[tid][a], sb[tid + off][a]);
+          for (int a = 3; a < 6; ++a) sb[tid][a] = fmaxf(sb[tid][a], sb[tid + off][a]);
+        }
+        __syncthreads();
+      }
+      if (tid < 8) d.col_box[(size_t)(oi.gbox_begin + c) * 8 + tid] = tid == 3 || tid == 7 ? 0.f : sb[0][tid < 3 ? tid : tid - 1];
     }
     return;
   }
