@@ -241,7 +241,8 @@ def run_learned(n_train: int = 1024, n_eval: int = 64, steps: int = 3000, n_seed
     3. Held-out objects: plain AS-ICP (plain_k particles x plain_iters
        iterations per preshape) against learned seeds (n_seed x
        seeded_iters, backed off `retract`) and against the same small budget
-       from Fibonacci seeds (no network).  The seeded runs refine with the
+       from Fibonacci seeds (no network), and the two seed sets together in
+       one run (2 n_seed per preshape).  The seeded runs refine with the
        first seeded_k_stein iterations Stein and the rest SGD-ICP (eq. 3,
        with the convergence freeze): good seeds need local refinement, not
        exploration.  Per object the lowest collision-free cost; a run is
@@ -290,6 +291,14 @@ def run_learned(n_train: int = 1024, n_eval: int = 64, steps: int = 3000, n_seed
     best_l = best_per_object(pb_l, r_l)
     pb_f, r_f, w_f = solve(eval_objs, K=n_seed, k_max=seeded_iters, k_stein=seeded_k_stein)
     best_f = best_per_object(pb_f, r_f)
+    # hybrid: each group starts from its learned seeds and its Fibonacci
+    # particles together (twice the particles of either)
+    G = pb_f.theta0.shape[1] // n_seed
+    th_l = seeds.cpu().numpy().reshape(7, G, n_seed)
+    th_f = np.asarray(pb_f.theta0, np.float32).reshape(7, G, n_seed)
+    th_h = np.ascontiguousarray(np.concatenate([th_l, th_f], axis=2).reshape(7, G * 2 * n_seed))
+    pb_h, r_h, w_h = solve(eval_objs, K=2 * n_seed, k_max=seeded_iters, theta0=th_h, k_stein=seeded_k_stein)
+    best_h = best_per_object(pb_h, r_h)
 
     def cmp(best):
         ratio = best / best_p
@@ -312,6 +321,9 @@ def run_learned(n_train: int = 1024, n_eval: int = 64, steps: int = 3000, n_seed
         "fibonacci_same_budget": {"particles_per_preshape": n_seed, "iterations": seeded_iters,
                                   "stein_iterations": seeded_k_stein, "solve_s": w_f,
                                   "grasps_per_s": n_eval / w_f, **cmp(best_f)},
+        "learned_plus_fibonacci": {"particles_per_preshape": 2 * n_seed, "iterations": seeded_iters,
+                                   "stein_iterations": seeded_k_stein, "solve_s": w_h,
+                                   "grasps_per_s": n_eval / (w_h + t_fwd), **cmp(best_h)},
         **extra,
     }
     return out
