@@ -83,7 +83,8 @@ struct Dev {
   int32_t max_m, max_m_pad;  // largest object cloud, and padded to whole tile groups
   // clouds in Morton order (index = prep_tg_begin*64 + k): MFMA-ready float4
   // (A-operand order), plain float4 (x, y, z, 0), original index (-1 for
-  // padding), and one bounding box per 128-point chunk (lo xyz, -, hi xyz, -)
+  // padding), and one bounding box per pruning chunk of kChunkTG tile groups
+  // (lo xyz, -, hi xyz, -)
   float4* obj_prep;
   float4* pre_prep;
   float4* obj_pts;
