@@ -82,7 +82,7 @@ def main():
                          "kernel that scales rocprofv3 FETCH_SIZE / WRITE_SIZE to bytes")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (objects and groups are "
+        print("bench.py measures one GPU: the library has no multi-GPU path (objects and groups are "
               "independent and would shard across GPUs without communication)", file=sys.stderr)
         sys.exit(2)
 
