@@ -44,6 +44,8 @@ typedef int32_t asicp_status;
 #define ASICP_E_STATE (-2)   /* call not allowed in the context's current state           */
 #define ASICP_E_HIP (-3)     /* a HIP runtime call or kernel launch failed                 */
 #define ASICP_E_NUMERIC (-4) /* a pose, cost or gradient became NaN / Inf on the device    */
+#define ASICP_E_HOST (-5)    /* host-side failure (out of host memory); no C++ exception    */
+                             /* ever crosses this interface                               */
 
 /* Preconditioner A of the SGD-ICP update, eq. (3). */
 #define ASICP_PRECOND_GN_DIAG 0  /* 1/(1+lambda) on t, 3/(2(rho^2 + lambda |TCP|^2)) on rotation */

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -19,6 +20,23 @@ thread_local std::string g_err;
 asicp_status fail(asicp_status st, const std::string& msg) {
   g_err = msg;
   return st;
+}
+
+// Runs the body of an entry point so that no C++ exception crosses the C ABI:
+// host memory exhaustion in a container or a message string becomes
+// ASICP_E_HOST.
+template <class F>
+asicp_status guarded(F&& body) noexcept {
+  try {
+    return body();
+  } catch (...) {
+    g_err.clear();
+    try {
+      g_err = "host-side failure (out of host memory)";
+    } catch (...) {
+    }
+    return ASICP_E_HOST;
+  }
 }
 
 constexpr int kMaxPoints = 1 << 22;   // per object / collision cloud / preshape
@@ -287,215 +305,220 @@ extern "C" {
 const char* asicp_last_error(void) { return g_err.c_str(); }
 
 asicp_status asicp_workspace_bytes(const asicp_problem* pb, const asicp_config* cfg, size_t* bytes) {
-  g_err.clear();
-  if (!bytes) return fail(ASICP_E_INVALID, "bytes must not be NULL");
-  Shape s;
-  const asicp_status st = validate(pb, cfg, s);
-  if (st != ASICP_OK) return st;
-  *bytes = layout_of(s).total;
-  return ASICP_OK;
+  return guarded([&]() -> asicp_status {
+    g_err.clear();
+    if (!bytes) return fail(ASICP_E_INVALID, "bytes must not be NULL");
+    Shape s;
+    const asicp_status st = validate(pb, cfg, s);
+    if (st != ASICP_OK) return st;
+    *bytes = layout_of(s).total;
+    return ASICP_OK;
+  });
 }
 
 asicp_status asicp_create(const asicp_problem* pb, const asicp_config* cfg, void* workspace,
                           size_t workspace_bytes, void* stream, asicp_ctx* out) {
-  g_err.clear();
-  if (!out) return fail(ASICP_E_INVALID, "out must not be NULL");
-  *out = nullptr;
-  Shape s;
-  asicp_status st = validate(pb, cfg, s);
-  if (st != ASICP_OK) return st;
-  const Layout L = layout_of(s);
-  if (!workspace) return fail(ASICP_E_INVALID, "workspace must not be NULL");
-  if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return fail(ASICP_E_INVALID, "workspace must be 256-byte aligned");
-  if (workspace_bytes < L.total)
-    return fail(ASICP_E_INVALID, "workspace too small: need " + std::to_string(L.total) + " bytes");
+  return guarded([&]() -> asicp_status {
+    g_err.clear();
+    if (!out) return fail(ASICP_E_INVALID, "out must not be NULL");
+    *out = nullptr;
+    Shape s;
+    asicp_status st = validate(pb, cfg, s);
+    if (st != ASICP_OK) return st;
+    const Layout L = layout_of(s);
+    if (!workspace) return fail(ASICP_E_INVALID, "workspace must not be NULL");
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return fail(ASICP_E_INVALID, "workspace must be 256-byte aligned");
+    if (workspace_bytes < L.total)
+      return fail(ASICP_E_INVALID, "workspace too small: need " + std::to_string(L.total) + " bytes");
 
-  // host tables
-  std::vector<GroupInfo> groups(s.G);
-  std::vector<ObjInfo> objs(s.n_obj);
-  std::vector<PreInfo> pres(s.n_pre);
-  int tg = 0;
-  long long key_off = 0;
-  int gbox = 0;
-  for (int o = 0; o < s.n_obj; ++o) {
-    ObjInfo& oi = objs[o];
-    std::memset(&oi, 0, sizeof oi);
-    oi.r_begin = pb->r_off[o];
-    oi.m = pb->r_off[o + 1] - pb->r_off[o];
-    oi.c_begin = pb->c_off[o];
-    oi.mc = pb->c_off[o + 1] - pb->c_off[o];
-    oi.prep_tg_begin = tg;
-    oi.ntg = ((oi.m + kPadPoints - 1) / kPadPoints) * (kPadPoints / 64);
-    oi.gate_chunks = (oi.mc + kGateChunk - 1) / kGateChunk;
-    oi.gbox_begin = gbox;
-    gbox += oi.gate_chunks;
-    oi.key_off = (int32_t)key_off;
-    key_off += pow2_at_least(oi.m);
-    oi.c_key_off = (int32_t)key_off;
-    if (oi.mc > 0) key_off += pow2_at_least(oi.mc);
-    tg += oi.ntg;
-  }
-  tg = 0;
-  for (int p = 0; p < s.n_pre; ++p) {
-    PreInfo& pi = pres[p];
-    std::memset(&pi, 0, sizeof pi);
-    pi.s_begin = pb->s_off[p];
-    pi.n = pb->s_off[p + 1] - pb->s_off[p];
-    pi.prep_tg_begin = tg;
-    pi.ntg = ((pi.n + kPadPoints - 1) / kPadPoints) * (kPadPoints / 64);
-    pi.waves = (pi.n + kQueriesPerWave - 1) / kQueriesPerWave;
-    pi.key_off = (int32_t)key_off;
-    key_off += pow2_at_least(pi.n);
-    tg += pi.ntg;
-    const asicp_sdf& g = pb->sdf[p];
-    pi.nx = g.nx; pi.ny = g.ny; pi.nz = g.nz;
-    pi.sdf = g.values;
-    pi.ox = g.origin[0]; pi.oy = g.origin[1]; pi.oz = g.origin[2];
-    pi.cell = g.cell;
-    pi.inv_cell = (float)(1.0 / (double)g.cell);
-    for (int ax = 0; ax < 3; ++ax) {
-      pi.neg_lo[ax] = 0x7fffffff;  // reduced on the device by the set-up
-      pi.neg_hi[ax] = -1;
+    // host tables
+    std::vector<GroupInfo> groups(s.G);
+    std::vector<ObjInfo> objs(s.n_obj);
+    std::vector<PreInfo> pres(s.n_pre);
+    int tg = 0;
+    long long key_off = 0;
+    int gbox = 0;
+    for (int o = 0; o < s.n_obj; ++o) {
+      ObjInfo& oi = objs[o];
+      std::memset(&oi, 0, sizeof oi);
+      oi.r_begin = pb->r_off[o];
+      oi.m = pb->r_off[o + 1] - pb->r_off[o];
+      oi.c_begin = pb->c_off[o];
+      oi.mc = pb->c_off[o + 1] - pb->c_off[o];
+      oi.prep_tg_begin = tg;
+      oi.ntg = ((oi.m + kPadPoints - 1) / kPadPoints) * (kPadPoints / 64);
+      oi.gate_chunks = (oi.mc + kGateChunk - 1) / kGateChunk;
+      oi.gbox_begin = gbox;
+      gbox += oi.gate_chunks;
+      oi.key_off = (int32_t)key_off;
+      key_off += pow2_at_least(oi.m);
+      oi.c_key_off = (int32_t)key_off;
+      if (oi.mc > 0) key_off += pow2_at_least(oi.mc);
+      tg += oi.ntg;
     }
-  }
-  int wave_off = 0, gate_off = 0;
-  for (int o = 0; o < s.n_obj; ++o)
+    tg = 0;
     for (int p = 0; p < s.n_pre; ++p) {
-      GroupInfo& gi = groups[o * s.n_pre + p];
-      gi.obj = o;
-      gi.pre = p;
-      gi.wave_off = wave_off;
-      gi.gate_off = gate_off;
-      wave_off += s.K * pres[p].waves;
-      gate_off += s.K * objs[o].gate_chunks;
+      PreInfo& pi = pres[p];
+      std::memset(&pi, 0, sizeof pi);
+      pi.s_begin = pb->s_off[p];
+      pi.n = pb->s_off[p + 1] - pb->s_off[p];
+      pi.prep_tg_begin = tg;
+      pi.ntg = ((pi.n + kPadPoints - 1) / kPadPoints) * (kPadPoints / 64);
+      pi.waves = (pi.n + kQueriesPerWave - 1) / kQueriesPerWave;
+      pi.key_off = (int32_t)key_off;
+      key_off += pow2_at_least(pi.n);
+      tg += pi.ntg;
+      const asicp_sdf& g = pb->sdf[p];
+      pi.nx = g.nx; pi.ny = g.ny; pi.nz = g.nz;
+      pi.sdf = g.values;
+      pi.ox = g.origin[0]; pi.oy = g.origin[1]; pi.oz = g.origin[2];
+      pi.cell = g.cell;
+      pi.inv_cell = (float)(1.0 / (double)g.cell);
+      for (int ax = 0; ax < 3; ++ax) {
+        pi.neg_lo[ax] = 0x7fffffff;  // reduced on the device by the set-up
+        pi.neg_hi[ax] = -1;
+      }
+    }
+    int wave_off = 0, gate_off = 0;
+    for (int o = 0; o < s.n_obj; ++o)
+      for (int p = 0; p < s.n_pre; ++p) {
+        GroupInfo& gi = groups[o * s.n_pre + p];
+        gi.obj = o;
+        gi.pre = p;
+        gi.wave_off = wave_off;
+        gi.gate_off = gate_off;
+        wave_off += s.K * pres[p].waves;
+        gate_off += s.K * objs[o].gate_chunks;
+      }
+
+    char* ws = static_cast<char*>(workspace);
+    Dev d;
+    std::memset(&d, 0, sizeof d);
+    d.rx = pb->rx; d.ry = pb->ry; d.rz = pb->rz;
+    d.cx = pb->cx; d.cy = pb->cy; d.cz = pb->cz;
+    d.sx = pb->sx; d.sy = pb->sy; d.sz = pb->sz;
+    d.groups = reinterpret_cast<const GroupInfo*>(ws + L.groups);
+    d.objs = reinterpret_cast<const ObjInfo*>(ws + L.objs);
+    d.pres = reinterpret_cast<const PreInfo*>(ws + L.pres);
+    d.n_obj = s.n_obj; d.n_pre = s.n_pre; d.K = s.K; d.G = s.G; d.Ktot = s.Ktot;
+    d.total_waves = (int)s.total_waves;
+    d.total_gate_wgs = (int)s.total_gate_wgs;
+    d.max_waves_pp = s.max_waves_pp;
+    d.max_gate_chunks = s.max_gate_chunks > 0 ? s.max_gate_chunks : 1;
+    d.n_max = s.n_max;
+    d.mc_max = s.mc_max > 0 ? s.mc_max : 1;
+    d.obj_prep = reinterpret_cast<float4*>(ws + L.obj_prep);
+    d.pre_prep = reinterpret_cast<float4*>(ws + L.pre_prep);
+    d.obj_pts = reinterpret_cast<float4*>(ws + L.obj_pts);
+    d.pre_pts = reinterpret_cast<float4*>(ws + L.pre_pts);
+    d.obj_perm = reinterpret_cast<int32_t*>(ws + L.obj_perm);
+    d.pre_perm = reinterpret_cast<int32_t*>(ws + L.pre_perm);
+    d.obj_box = reinterpret_cast<float*>(ws + L.obj_box);
+    d.pre_box = reinterpret_cast<float*>(ws + L.pre_box);
+    d.col_box = reinterpret_cast<float*>(ws + L.col_box);
+    d.sort_keys = reinterpret_cast<unsigned long long*>(ws + L.sort_keys);
+    d.col_pts = reinterpret_cast<float4*>(ws + L.col_pts);
+    d.col_perm = reinterpret_cast<int32_t*>(ws + L.col_perm);
+    d.wave_pairs = s.timing ? reinterpret_cast<unsigned long long*>(ws + L.wave_pairs) : nullptr;
+    d.prune = (cfg->flags & ASICP_FLAG_NO_PRUNE) ? 0 : 1;
+    d.obj_com = reinterpret_cast<float*>(ws + L.obj_com);
+    d.pre_const = reinterpret_cast<float*>(ws + L.pre_const);
+    d.theta = reinterpret_cast<float*>(ws + L.theta);
+    d.cost = reinterpret_cast<float*>(ws + L.cost);
+    d.col_cost = reinterpret_cast<float*>(ws + L.col_cost);
+    d.prev_cost = reinterpret_cast<float*>(ws + L.prev_cost);
+    d.ncol = reinterpret_cast<int32_t*>(ws + L.ncol);
+    d.converged = reinterpret_cast<int32_t*>(ws + L.converged);
+    d.grad = reinterpret_cast<float*>(ws + L.grad);
+    d.grad_ct = reinterpret_cast<float*>(ws + L.grad_ct);
+    d.grad_col = reinterpret_cast<float*>(ws + L.grad_col);
+    d.phi = reinterpret_cast<float*>(ws + L.phi);
+    d.h = reinterpret_cast<float*>(ws + L.h);
+    d.bw_hist = reinterpret_cast<unsigned int*>(ws + L.bw_hist);
+    d.bw_state = reinterpret_cast<unsigned int*>(ws + L.bw_state);
+    d.nn_part = reinterpret_cast<float*>(ws + L.nn_part);
+    d.col_part = reinterpret_cast<float*>(ws + L.col_part);
+    d.pen_part = reinterpret_cast<float*>(ws + L.pen_part);
+    d.best = reinterpret_cast<int32_t*>(ws + L.best);
+    d.best_theta = reinterpret_cast<float*>(ws + L.best_theta);
+    d.flags = reinterpret_cast<int32_t*>(ws + L.flags);
+    d.dbg_nn = s.debug ? reinterpret_cast<int32_t*>(ws + L.dbg_nn) : nullptr;
+    d.dbg_rev = s.debug ? reinterpret_cast<int32_t*>(ws + L.dbg_rev) : nullptr;
+    d.eta = cfg->eta;
+    d.lambda = cfg->lambda;
+    d.k_stein = cfg->k_stein;
+    d.kernel_mode = cfg->kernel_mode;
+    d.bw_mode = cfg->bw_mode;
+    d.precond = cfg->precond;
+    d.h_fixed = cfg->h_fixed;
+    d.h_min = cfg->h_min;
+    d.conv_tol = cfg->conv_tol;
+    d.w_pen = cfg->w_pen;
+    d.minibatch = s.minibatch ? 1 : 0;
+    d.seed = cfg->seed;
+    d.obj_prep_mb = s.minibatch ? reinterpret_cast<float4*>(ws + L.obj_prep_mb) : nullptr;
+    d.batch_mark = s.minibatch ? reinterpret_cast<unsigned char*>(ws + L.batch_mark) : nullptr;
+    d.max_m = s.max_m;
+    d.max_m_pad = s.max_m_pad;
+    d.prior = s.prior ? reinterpret_cast<const float*>(ws + L.prior) : nullptr;
+    d.xcd_map = 1;  // launch defaults (asicp_set_launch / asicp_autotune change them)
+    d.fine = 1;
+    std::vector<float> prior_words;
+    if (s.prior) {
+      prior_words.assign(12 * (size_t)s.G, 0.f);
+      for (int g = 0; g < s.G; ++g) {
+        const float* pr = pb->prior + 9 * (size_t)g;
+        float* w = prior_words.data() + 12 * (size_t)g;
+        const double n = std::sqrt((double)pr[4] * pr[4] + (double)pr[5] * pr[5] + (double)pr[6] * pr[6] +
+                                   (double)pr[7] * pr[7]);
+        for (int a = 0; a < 4; ++a) w[a] = pr[a];
+        for (int a = 0; a < 4; ++a) w[4 + a] = (float)(pr[4 + a] / n);
+        w[8] = pr[8];
+      }
     }
 
-  char* ws = static_cast<char*>(workspace);
-  Dev d;
-  std::memset(&d, 0, sizeof d);
-  d.rx = pb->rx; d.ry = pb->ry; d.rz = pb->rz;
-  d.cx = pb->cx; d.cy = pb->cy; d.cz = pb->cz;
-  d.sx = pb->sx; d.sy = pb->sy; d.sz = pb->sz;
-  d.groups = reinterpret_cast<const GroupInfo*>(ws + L.groups);
-  d.objs = reinterpret_cast<const ObjInfo*>(ws + L.objs);
-  d.pres = reinterpret_cast<const PreInfo*>(ws + L.pres);
-  d.n_obj = s.n_obj; d.n_pre = s.n_pre; d.K = s.K; d.G = s.G; d.Ktot = s.Ktot;
-  d.total_waves = (int)s.total_waves;
-  d.total_gate_wgs = (int)s.total_gate_wgs;
-  d.max_waves_pp = s.max_waves_pp;
-  d.max_gate_chunks = s.max_gate_chunks > 0 ? s.max_gate_chunks : 1;
-  d.n_max = s.n_max;
-  d.mc_max = s.mc_max > 0 ? s.mc_max : 1;
-  d.obj_prep = reinterpret_cast<float4*>(ws + L.obj_prep);
-  d.pre_prep = reinterpret_cast<float4*>(ws + L.pre_prep);
-  d.obj_pts = reinterpret_cast<float4*>(ws + L.obj_pts);
-  d.pre_pts = reinterpret_cast<float4*>(ws + L.pre_pts);
-  d.obj_perm = reinterpret_cast<int32_t*>(ws + L.obj_perm);
-  d.pre_perm = reinterpret_cast<int32_t*>(ws + L.pre_perm);
-  d.obj_box = reinterpret_cast<float*>(ws + L.obj_box);
-  d.pre_box = reinterpret_cast<float*>(ws + L.pre_box);
-  d.col_box = reinterpret_cast<float*>(ws + L.col_box);
-  d.sort_keys = reinterpret_cast<unsigned long long*>(ws + L.sort_keys);
-  d.col_pts = reinterpret_cast<float4*>(ws + L.col_pts);
-  d.col_perm = reinterpret_cast<int32_t*>(ws + L.col_perm);
-  d.wave_pairs = s.timing ? reinterpret_cast<unsigned long long*>(ws + L.wave_pairs) : nullptr;
-  d.prune = (cfg->flags & ASICP_FLAG_NO_PRUNE) ? 0 : 1;
-  d.obj_com = reinterpret_cast<float*>(ws + L.obj_com);
-  d.pre_const = reinterpret_cast<float*>(ws + L.pre_const);
-  d.theta = reinterpret_cast<float*>(ws + L.theta);
-  d.cost = reinterpret_cast<float*>(ws + L.cost);
-  d.col_cost = reinterpret_cast<float*>(ws + L.col_cost);
-  d.prev_cost = reinterpret_cast<float*>(ws + L.prev_cost);
-  d.ncol = reinterpret_cast<int32_t*>(ws + L.ncol);
-  d.converged = reinterpret_cast<int32_t*>(ws + L.converged);
-  d.grad = reinterpret_cast<float*>(ws + L.grad);
-  d.grad_ct = reinterpret_cast<float*>(ws + L.grad_ct);
-  d.grad_col = reinterpret_cast<float*>(ws + L.grad_col);
-  d.phi = reinterpret_cast<float*>(ws + L.phi);
-  d.h = reinterpret_cast<float*>(ws + L.h);
-  d.bw_hist = reinterpret_cast<unsigned int*>(ws + L.bw_hist);
-  d.bw_state = reinterpret_cast<unsigned int*>(ws + L.bw_state);
-  d.nn_part = reinterpret_cast<float*>(ws + L.nn_part);
-  d.col_part = reinterpret_cast<float*>(ws + L.col_part);
-  d.pen_part = reinterpret_cast<float*>(ws + L.pen_part);
-  d.best = reinterpret_cast<int32_t*>(ws + L.best);
-  d.best_theta = reinterpret_cast<float*>(ws + L.best_theta);
-  d.flags = reinterpret_cast<int32_t*>(ws + L.flags);
-  d.dbg_nn = s.debug ? reinterpret_cast<int32_t*>(ws + L.dbg_nn) : nullptr;
-  d.dbg_rev = s.debug ? reinterpret_cast<int32_t*>(ws + L.dbg_rev) : nullptr;
-  d.eta = cfg->eta;
-  d.lambda = cfg->lambda;
-  d.k_stein = cfg->k_stein;
-  d.kernel_mode = cfg->kernel_mode;
-  d.bw_mode = cfg->bw_mode;
-  d.precond = cfg->precond;
-  d.h_fixed = cfg->h_fixed;
-  d.h_min = cfg->h_min;
-  d.conv_tol = cfg->conv_tol;
-  d.w_pen = cfg->w_pen;
-  d.minibatch = s.minibatch ? 1 : 0;
-  d.seed = cfg->seed;
-  d.obj_prep_mb = s.minibatch ? reinterpret_cast<float4*>(ws + L.obj_prep_mb) : nullptr;
-  d.batch_mark = s.minibatch ? reinterpret_cast<unsigned char*>(ws + L.batch_mark) : nullptr;
-  d.max_m = s.max_m;
-  d.max_m_pad = s.max_m_pad;
-  d.prior = s.prior ? reinterpret_cast<const float*>(ws + L.prior) : nullptr;
-  d.xcd_map = 1;  // launch defaults (asicp_set_launch / asicp_autotune change them)
-  d.fine = 1;
-  std::vector<float> prior_words;
-  if (s.prior) {
-    prior_words.assign(12 * (size_t)s.G, 0.f);
-    for (int g = 0; g < s.G; ++g) {
-      const float* pr = pb->prior + 9 * (size_t)g;
-      float* w = prior_words.data() + 12 * (size_t)g;
-      const double n = std::sqrt((double)pr[4] * pr[4] + (double)pr[5] * pr[5] + (double)pr[6] * pr[6] +
-                                 (double)pr[7] * pr[7]);
-      for (int a = 0; a < 4; ++a) w[a] = pr[a];
-      for (int a = 0; a < 4; ++a) w[4 + a] = (float)(pr[4 + a] / n);
-      w[8] = pr[8];
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    (void)hipGetLastError();  // start from a clean error state
+    upload_words(ws + L.groups, groups.data(), sizeof(GroupInfo) * groups.size(), hs);
+    upload_words(ws + L.objs, objs.data(), sizeof(ObjInfo) * objs.size(), hs);
+    upload_words(ws + L.pres, pres.data(), sizeof(PreInfo) * pres.size(), hs);
+    if (s.prior) upload_words(ws + L.prior, prior_words.data(), 4 * prior_words.size(), hs);
+    if ((st = check_launch("table upload")) != ASICP_OK) return st;
+    launch_setup(d, pb->theta0, pb->prev_cost, pb->converged, hs);
+    if ((st = check_launch("setup")) != ASICP_OK) return st;
+    if (s.debug) {
+      if (hipMemsetAsync(d.dbg_nn, 0xff, 4 * (size_t)s.Ktot * s.n_max, hs) != hipSuccess ||
+          hipMemsetAsync(d.dbg_rev, 0xff, 4 * (size_t)s.Ktot * d.mc_max, hs) != hipSuccess)
+        return fail(ASICP_E_HIP, "debug buffer clear failed");
     }
-  }
 
-  hipStream_t hs = static_cast<hipStream_t>(stream);
-  (void)hipGetLastError();  // start from a clean error state
-  upload_words(ws + L.groups, groups.data(), sizeof(GroupInfo) * groups.size(), hs);
-  upload_words(ws + L.objs, objs.data(), sizeof(ObjInfo) * objs.size(), hs);
-  upload_words(ws + L.pres, pres.data(), sizeof(PreInfo) * pres.size(), hs);
-  if (s.prior) upload_words(ws + L.prior, prior_words.data(), 4 * prior_words.size(), hs);
-  if ((st = check_launch("table upload")) != ASICP_OK) return st;
-  launch_setup(d, pb->theta0, pb->prev_cost, pb->converged, hs);
-  if ((st = check_launch("setup")) != ASICP_OK) return st;
-  if (s.debug) {
-    if (hipMemsetAsync(d.dbg_nn, 0xff, 4 * (size_t)s.Ktot * s.n_max, hs) != hipSuccess ||
-        hipMemsetAsync(d.dbg_rev, 0xff, 4 * (size_t)s.Ktot * d.mc_max, hs) != hipSuccess)
-      return fail(ASICP_E_HIP, "debug buffer clear failed");
-  }
-
-  asicp_ctx_s* c = new asicp_ctx_s();
-  c->d = d;
-  c->cfg = *cfg;
-  c->k = pb->k_start;
-  c->k_start = pb->k_start;
-  c->theta0 = pb->theta0;
-  c->prev_cost0 = pb->prev_cost;
-  c->converged0 = pb->converged;
-  c->graph = nullptr;
-  c->cap_stream = nullptr;
-  c->capturing = false;
-  c->final_done = false;
-  c->inv_log_k = s.K >= 2 ? (float)(1.0 / std::log((double)s.K)) : 1.0f;
-  c->n_timed = 0;
-  c->side = nullptr;
-  c->fork_ev = c->join_ev = nullptr;
-  // default priority, like every stream here
-  if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming) != hipSuccess) {
-    asicp_destroy(c);
-    return fail(ASICP_E_HIP, "creating the side stream or its events failed");
-  }
-  *out = c;
-  return ASICP_OK;
+    asicp_ctx_s* c = new (std::nothrow) asicp_ctx_s();  // no exception crosses the C ABI
+    if (!c) return fail(ASICP_E_HOST, "out of host memory for the context");
+    c->d = d;
+    c->cfg = *cfg;
+    c->k = pb->k_start;
+    c->k_start = pb->k_start;
+    c->theta0 = pb->theta0;
+    c->prev_cost0 = pb->prev_cost;
+    c->converged0 = pb->converged;
+    c->graph = nullptr;
+    c->cap_stream = nullptr;
+    c->capturing = false;
+    c->final_done = false;
+    c->inv_log_k = s.K >= 2 ? (float)(1.0 / std::log((double)s.K)) : 1.0f;
+    c->n_timed = 0;
+    c->side = nullptr;
+    c->fork_ev = c->join_ev = nullptr;
+    // default priority, like every stream here
+    if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming) != hipSuccess) {
+      asicp_destroy(c);
+      return fail(ASICP_E_HIP, "creating the side stream or its events failed");
+    }
+    *out = c;
+    return ASICP_OK;
+  });
 }
 
 static void schedule_of(const asicp_config& cfg, int k, float* gamma, float* tau) {
@@ -530,8 +553,11 @@ static asicp_status evaluate(asicp_ctx c, int k, int final_eval, bool bandwidth,
   if (timing) {
     if ((size_t)(2 * c->n_timed + 2) > c->ev.size()) {
       hipEvent_t x, y;
-      if (hipEventCreate(&x) != hipSuccess || hipEventCreate(&y) != hipSuccess)
+      if (hipEventCreate(&x) != hipSuccess) return fail(ASICP_E_HIP, "hipEventCreate failed");
+      if (hipEventCreate(&y) != hipSuccess) {
+        (void)hipEventDestroy(x);
         return fail(ASICP_E_HIP, "hipEventCreate failed");
+      }
       c->ev.push_back(x);
       c->ev.push_back(y);
     }
@@ -570,33 +596,37 @@ static asicp_status iterate(asicp_ctx c, int k, hipStream_t hs) {
 }
 
 asicp_status asicp_step(asicp_ctx c, int32_t n_iters, void* stream) {
-  g_err.clear();
-  if (!c) return fail(ASICP_E_INVALID, "ctx is NULL");
-  if (n_iters < 0) return fail(ASICP_E_INVALID, "n_iters must be >= 0");
-  if (c->final_done) return fail(ASICP_E_STATE, "the solve has already run its final evaluation");
-  if (c->k + n_iters > c->cfg.k_max)
-    return fail(ASICP_E_STATE, "stepping past k_max (" + std::to_string(c->cfg.k_max) + ")");
-  hipStream_t hs = static_cast<hipStream_t>(stream);
-  for (int it = 0; it < n_iters; ++it) {
-    const asicp_status st = iterate(c, c->k, hs);
-    if (st != ASICP_OK) return st;
-    ++c->k;
-  }
-  return ASICP_OK;
+  return guarded([&]() -> asicp_status {
+    g_err.clear();
+    if (!c) return fail(ASICP_E_INVALID, "ctx is NULL");
+    if (n_iters < 0) return fail(ASICP_E_INVALID, "n_iters must be >= 0");
+    if (c->final_done) return fail(ASICP_E_STATE, "the solve has already run its final evaluation");
+    if (c->k + n_iters > c->cfg.k_max)
+      return fail(ASICP_E_STATE, "stepping past k_max (" + std::to_string(c->cfg.k_max) + ")");
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    for (int it = 0; it < n_iters; ++it) {
+      const asicp_status st = iterate(c, c->k, hs);
+      if (st != ASICP_OK) return st;
+      ++c->k;
+    }
+    return ASICP_OK;
+  });
 }
 
 asicp_status asicp_solve(asicp_ctx c, void* stream) {
-  g_err.clear();
-  if (!c) return fail(ASICP_E_INVALID, "ctx is NULL");
-  if (c->final_done) return fail(ASICP_E_STATE, "the solve has already run its final evaluation");
-  asicp_status st = asicp_step(c, c->cfg.k_max - c->k, stream);
-  if (st != ASICP_OK) return st;
-  hipStream_t hs = static_cast<hipStream_t>(stream);
-  if ((st = evaluate(c, c->k, 1, false, hs)) != ASICP_OK) return st;
-  launch_select(c->d, hs);
-  if ((st = check_launch("select")) != ASICP_OK) return st;
-  c->final_done = true;
-  return ASICP_OK;
+  return guarded([&]() -> asicp_status {
+    g_err.clear();
+    if (!c) return fail(ASICP_E_INVALID, "ctx is NULL");
+    if (c->final_done) return fail(ASICP_E_STATE, "the solve has already run its final evaluation");
+    asicp_status st = asicp_step(c, c->cfg.k_max - c->k, stream);
+    if (st != ASICP_OK) return st;
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    if ((st = evaluate(c, c->k, 1, false, hs)) != ASICP_OK) return st;
+    launch_select(c->d, hs);
+    if ((st = check_launch("select")) != ASICP_OK) return st;
+    c->final_done = true;
+    return ASICP_OK;
+  });
 }
 
 // Enqueue iterations k0 .. k_max-1, the final evaluation and the selection.
@@ -610,147 +640,157 @@ static asicp_status enqueue_rest(asicp_ctx c, int k0, hipStream_t hs) {
 }
 
 asicp_status asicp_cost_grad(asicp_ctx c, const float* theta, float* cost_out, float* grad_out, void* stream) {
-  g_err.clear();
-  if (!c || !theta) return fail(ASICP_E_INVALID, "ctx and theta must not be NULL");
-  hipStream_t hs = static_cast<hipStream_t>(stream);
-  const int K = c->d.Ktot;
-  (void)hipGetLastError();
-  hipLaunchKernelGGL(k_set_theta, dim3((7 * K + 255) / 256), dim3(256), 0, hs, c->d.theta, theta, 7 * K);
-  asicp_status st = check_launch("set theta");
-  if (st != ASICP_OK) return st;
-  if ((st = evaluate(c, c->cfg.k_max, 1, false, hs)) != ASICP_OK) return st;
-  hipLaunchKernelGGL(k_get_cost_grad, dim3((K + 255) / 256), dim3(256), 0, hs, c->d.cost, c->d.grad_ct,
-                     cost_out, grad_out, K);
-  return check_launch("cost/grad copy");
+  return guarded([&]() -> asicp_status {
+    g_err.clear();
+    if (!c || !theta) return fail(ASICP_E_INVALID, "ctx and theta must not be NULL");
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    const int K = c->d.Ktot;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_set_theta, dim3((7 * K + 255) / 256), dim3(256), 0, hs, c->d.theta, theta, 7 * K);
+    asicp_status st = check_launch("set theta");
+    if (st != ASICP_OK) return st;
+    if ((st = evaluate(c, c->cfg.k_max, 1, false, hs)) != ASICP_OK) return st;
+    hipLaunchKernelGGL(k_get_cost_grad, dim3((K + 255) / 256), dim3(256), 0, hs, c->d.cost, c->d.grad_ct,
+                       cost_out, grad_out, K);
+    return check_launch("cost/grad copy");
+  });
 }
 
 asicp_status asicp_replay(asicp_ctx c, void* stream) {
-  g_err.clear();
-  if (!c) return fail(ASICP_E_INVALID, "ctx is NULL");
-  if (c->d.dbg_nn) return fail(ASICP_E_STATE, "asicp_replay is not available with ASICP_FLAG_DEBUG");
-  hipStream_t hs = static_cast<hipStream_t>(stream);
-  if (!c->graph) {
-    // Capture on a private stream (the caller's may be the null stream,
-    // which cannot be captured); capturing enqueues nothing.  Default
-    // priority.
-    if (!c->cap_stream && hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
-      c->cap_stream = nullptr;
-      return fail(ASICP_E_HIP, "hipStreamCreateWithFlags failed");
+  return guarded([&]() -> asicp_status {
+    g_err.clear();
+    if (!c) return fail(ASICP_E_INVALID, "ctx is NULL");
+    if (c->d.dbg_nn) return fail(ASICP_E_STATE, "asicp_replay is not available with ASICP_FLAG_DEBUG");
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    if (!c->graph) {
+      // Capture on a private stream (the caller's may be the null stream,
+      // which cannot be captured); capturing enqueues nothing.  Default
+      // priority.
+      if (!c->cap_stream && hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        c->cap_stream = nullptr;
+        return fail(ASICP_E_HIP, "hipStreamCreateWithFlags failed");
+      }
+      hipStream_t cs = c->cap_stream;
+      (void)hipGetLastError();
+      if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return fail(ASICP_E_HIP, "hipStreamBeginCapture failed");
+      c->capturing = true;
+      launch_setup(c->d, c->theta0, c->prev_cost0, c->converged0, cs);
+      asicp_status st = check_launch("setup");
+      if (st == ASICP_OK) st = enqueue_rest(c, c->k_start, cs);
+      c->capturing = false;
+      hipGraph_t g = nullptr;
+      const hipError_t e = hipStreamEndCapture(cs, &g);
+      if (st != ASICP_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+      }
+      if (e != hipSuccess || !g) return fail(ASICP_E_HIP, "hipStreamEndCapture failed");
+      const hipError_t ei = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ei != hipSuccess) {
+        c->graph = nullptr;
+        return fail(ASICP_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+      }
     }
-    hipStream_t cs = c->cap_stream;
-    (void)hipGetLastError();
-    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess)
-      return fail(ASICP_E_HIP, "hipStreamBeginCapture failed");
-    c->capturing = true;
-    launch_setup(c->d, c->theta0, c->prev_cost0, c->converged0, cs);
-    asicp_status st = check_launch("setup");
-    if (st == ASICP_OK) st = enqueue_rest(c, c->k_start, cs);
-    c->capturing = false;
-    hipGraph_t g = nullptr;
-    const hipError_t e = hipStreamEndCapture(cs, &g);
-    if (st != ASICP_OK) {
-      if (g) (void)hipGraphDestroy(g);
-      return st;
-    }
-    if (e != hipSuccess || !g) return fail(ASICP_E_HIP, "hipStreamEndCapture failed");
-    const hipError_t ei = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (ei != hipSuccess) {
-      c->graph = nullptr;
-      return fail(ASICP_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
-    }
-  }
-  if (hipGraphLaunch(c->graph, hs) != hipSuccess) return fail(ASICP_E_HIP, "hipGraphLaunch failed");
-  c->k = c->cfg.k_max;
-  c->final_done = true;
-  return ASICP_OK;
+    if (hipGraphLaunch(c->graph, hs) != hipSuccess) return fail(ASICP_E_HIP, "hipGraphLaunch failed");
+    c->k = c->cfg.k_max;
+    c->final_done = true;
+    return ASICP_OK;
+  });
 }
 
 asicp_status asicp_result(asicp_ctx c, asicp_result_t* out, void* stream) {
-  g_err.clear();
-  if (!c || !out) return fail(ASICP_E_INVALID, "ctx and out must not be NULL");
-  hipStream_t hs = static_cast<hipStream_t>(stream);
-  const Dev& d = c->d;
-  const size_t K = (size_t)d.Ktot;
-  struct Cp { void* dst; const void* src; size_t bytes; };
-  const Cp dev[] = {
-      {out->theta, d.theta, 4 * 7 * K},        {out->cost, d.cost, 4 * K},
-      {out->col_cost, d.col_cost, 4 * K},      {out->ncol, d.ncol, 4 * K},
-      {out->converged, d.converged, 4 * K},    {out->prev_cost, d.prev_cost, 4 * K},
-      {out->grad, d.grad, 4 * 6 * K},          {out->grad_ct, d.grad_ct, 4 * 6 * K},
-      {out->grad_col, d.grad_col, 4 * 6 * K},  {out->phi, d.phi, 4 * 6 * K},
-      {out->h, d.h, 4 * (size_t)d.G},
-  };
-  for (const Cp& x : dev)
-    if (x.dst && hipMemcpyAsync(x.dst, x.src, x.bytes, hipMemcpyDeviceToDevice, hs) != hipSuccess)
-      return fail(ASICP_E_HIP, "device-to-device copy of a result failed");
-  if (out->nn_idx) {
-    if (!d.dbg_nn) return fail(ASICP_E_STATE, "nn_idx needs ASICP_FLAG_DEBUG");
-    if (hipMemcpyAsync(out->nn_idx, d.dbg_nn, 4 * K * d.n_max, hipMemcpyDeviceToDevice, hs) != hipSuccess)
-      return fail(ASICP_E_HIP, "copy of nn_idx failed");
-  }
-  if (out->rev_idx) {
-    if (!d.dbg_rev) return fail(ASICP_E_STATE, "rev_idx needs ASICP_FLAG_DEBUG");
-    if (hipMemcpyAsync(out->rev_idx, d.dbg_rev, 4 * K * d.mc_max, hipMemcpyDeviceToDevice, hs) != hipSuccess)
-      return fail(ASICP_E_HIP, "copy of rev_idx failed");
-  }
-  std::vector<int32_t> best(2 * (size_t)d.n_obj);
-  std::vector<float> bt(8 * (size_t)d.n_obj);
-  int32_t flags[4] = {0, 0, 0, 0};
-  if (hipMemcpyAsync(flags, d.flags, sizeof flags, hipMemcpyDeviceToHost, hs) != hipSuccess)
-    return fail(ASICP_E_HIP, "copy of the device flags failed");
-  if (c->final_done) {
-    if (hipMemcpyAsync(best.data(), d.best, 4 * best.size(), hipMemcpyDeviceToHost, hs) != hipSuccess ||
-        hipMemcpyAsync(bt.data(), d.best_theta, 4 * bt.size(), hipMemcpyDeviceToHost, hs) != hipSuccess)
-      return fail(ASICP_E_HIP, "copy of the selected grasps failed");
-  }
-  const hipError_t e = hipStreamSynchronize(hs);
-  if (e != hipSuccess) return fail(ASICP_E_HIP, std::string("stream synchronisation: ") + hipGetErrorString(e));
-  out->iterations_done = c->k;
-  out->final_evaluated = c->final_done ? 1 : 0;
-  for (int o = 0; o < d.n_obj; ++o) {
-    if (out->best_particle) out->best_particle[o] = c->final_done ? best[2 * o] : -1;
-    if (out->best_free) out->best_free[o] = c->final_done ? best[2 * o + 1] : 0;
-    if (out->best_cost) out->best_cost[o] = c->final_done ? bt[8 * o + 7] : NAN;
-    if (out->best_theta)
-      for (int a = 0; a < 7; ++a) out->best_theta[7 * o + a] = c->final_done ? bt[8 * o + a] : NAN;
-  }
-  if (flags[1] != 0) return fail(ASICP_E_NUMERIC, "nearest-neighbour re-scan missed (non-finite distances)");
-  if (flags[0] != 0) return fail(ASICP_E_NUMERIC, "a pose, cost or gradient became non-finite");
-  return ASICP_OK;
+  return guarded([&]() -> asicp_status {
+    g_err.clear();
+    if (!c || !out) return fail(ASICP_E_INVALID, "ctx and out must not be NULL");
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    const Dev& d = c->d;
+    const size_t K = (size_t)d.Ktot;
+    struct Cp { void* dst; const void* src; size_t bytes; };
+    const Cp dev[] = {
+        {out->theta, d.theta, 4 * 7 * K},        {out->cost, d.cost, 4 * K},
+        {out->col_cost, d.col_cost, 4 * K},      {out->ncol, d.ncol, 4 * K},
+        {out->converged, d.converged, 4 * K},    {out->prev_cost, d.prev_cost, 4 * K},
+        {out->grad, d.grad, 4 * 6 * K},          {out->grad_ct, d.grad_ct, 4 * 6 * K},
+        {out->grad_col, d.grad_col, 4 * 6 * K},  {out->phi, d.phi, 4 * 6 * K},
+        {out->h, d.h, 4 * (size_t)d.G},
+    };
+    for (const Cp& x : dev)
+      if (x.dst && hipMemcpyAsync(x.dst, x.src, x.bytes, hipMemcpyDeviceToDevice, hs) != hipSuccess)
+        return fail(ASICP_E_HIP, "device-to-device copy of a result failed");
+    if (out->nn_idx) {
+      if (!d.dbg_nn) return fail(ASICP_E_STATE, "nn_idx needs ASICP_FLAG_DEBUG");
+      if (hipMemcpyAsync(out->nn_idx, d.dbg_nn, 4 * K * d.n_max, hipMemcpyDeviceToDevice, hs) != hipSuccess)
+        return fail(ASICP_E_HIP, "copy of nn_idx failed");
+    }
+    if (out->rev_idx) {
+      if (!d.dbg_rev) return fail(ASICP_E_STATE, "rev_idx needs ASICP_FLAG_DEBUG");
+      if (hipMemcpyAsync(out->rev_idx, d.dbg_rev, 4 * K * d.mc_max, hipMemcpyDeviceToDevice, hs) != hipSuccess)
+        return fail(ASICP_E_HIP, "copy of rev_idx failed");
+    }
+    std::vector<int32_t> best(2 * (size_t)d.n_obj);
+    std::vector<float> bt(8 * (size_t)d.n_obj);
+    int32_t flags[4] = {0, 0, 0, 0};
+    if (hipMemcpyAsync(flags, d.flags, sizeof flags, hipMemcpyDeviceToHost, hs) != hipSuccess)
+      return fail(ASICP_E_HIP, "copy of the device flags failed");
+    if (c->final_done) {
+      if (hipMemcpyAsync(best.data(), d.best, 4 * best.size(), hipMemcpyDeviceToHost, hs) != hipSuccess ||
+          hipMemcpyAsync(bt.data(), d.best_theta, 4 * bt.size(), hipMemcpyDeviceToHost, hs) != hipSuccess)
+        return fail(ASICP_E_HIP, "copy of the selected grasps failed");
+    }
+    const hipError_t e = hipStreamSynchronize(hs);
+    if (e != hipSuccess) return fail(ASICP_E_HIP, std::string("stream synchronisation: ") + hipGetErrorString(e));
+    out->iterations_done = c->k;
+    out->final_evaluated = c->final_done ? 1 : 0;
+    for (int o = 0; o < d.n_obj; ++o) {
+      if (out->best_particle) out->best_particle[o] = c->final_done ? best[2 * o] : -1;
+      if (out->best_free) out->best_free[o] = c->final_done ? best[2 * o + 1] : 0;
+      if (out->best_cost) out->best_cost[o] = c->final_done ? bt[8 * o + 7] : NAN;
+      if (out->best_theta)
+        for (int a = 0; a < 7; ++a) out->best_theta[7 * o + a] = c->final_done ? bt[8 * o + a] : NAN;
+    }
+    if (flags[1] != 0) return fail(ASICP_E_NUMERIC, "nearest-neighbour re-scan missed (non-finite distances)");
+    if (flags[0] != 0) return fail(ASICP_E_NUMERIC, "a pose, cost or gradient became non-finite");
+    return ASICP_OK;
+  });
 }
 
 asicp_status asicp_kernel_time(asicp_ctx c, double* total_ms, int32_t* launches, double* nn_pairs) {
-  g_err.clear();
-  if (!c || !total_ms || !launches) return fail(ASICP_E_INVALID, "NULL argument");
-  if (!(c->cfg.flags & ASICP_FLAG_TIMING)) return fail(ASICP_E_STATE, "context was created without ASICP_FLAG_TIMING");
-  double tot = 0.0;
-  for (int j = 0; j < c->n_timed; ++j) {
-    if (hipEventSynchronize(c->ev[2 * j + 1]) != hipSuccess) return fail(ASICP_E_HIP, "hipEventSynchronize failed");
-    float ms = 0.f;
-    if (hipEventElapsedTime(&ms, c->ev[2 * j], c->ev[2 * j + 1]) != hipSuccess)
-      return fail(ASICP_E_HIP, "hipEventElapsedTime failed");
-    tot += ms;
-  }
-  if (nn_pairs) {  // one slot per forward wave (no shared counter to contend for)
-    std::vector<unsigned long long> per((size_t)c->d.total_waves, 0ull);
-    if (c->n_timed > 0 && hipMemcpy(per.data(), c->d.wave_pairs, 8 * per.size(), hipMemcpyDeviceToHost) != hipSuccess)
-      return fail(ASICP_E_HIP, "reading the pair counts failed");
-    double cnt = 0.0;
-    for (unsigned long long v : per) cnt += (double)v;
-    *nn_pairs = cnt;
-  }
-  *total_ms = tot;
-  *launches = c->n_timed;
-  return ASICP_OK;
+  return guarded([&]() -> asicp_status {
+    g_err.clear();
+    if (!c || !total_ms || !launches) return fail(ASICP_E_INVALID, "NULL argument");
+    if (!(c->cfg.flags & ASICP_FLAG_TIMING)) return fail(ASICP_E_STATE, "context was created without ASICP_FLAG_TIMING");
+    double tot = 0.0;
+    for (int j = 0; j < c->n_timed; ++j) {
+      if (hipEventSynchronize(c->ev[2 * j + 1]) != hipSuccess) return fail(ASICP_E_HIP, "hipEventSynchronize failed");
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, c->ev[2 * j], c->ev[2 * j + 1]) != hipSuccess)
+        return fail(ASICP_E_HIP, "hipEventElapsedTime failed");
+      tot += ms;
+    }
+    if (nn_pairs) {  // one slot per forward wave (no shared counter to contend for)
+      std::vector<unsigned long long> per((size_t)c->d.total_waves, 0ull);
+      if (c->n_timed > 0 && hipMemcpy(per.data(), c->d.wave_pairs, 8 * per.size(), hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(ASICP_E_HIP, "reading the pair counts failed");
+      double cnt = 0.0;
+      for (unsigned long long v : per) cnt += (double)v;
+      *nn_pairs = cnt;
+    }
+    *total_ms = tot;
+    *launches = c->n_timed;
+    return ASICP_OK;
+  });
 }
 
 asicp_status asicp_get_launch(asicp_ctx c, asicp_launch_t* out) {
-  g_err.clear();
-  if (!c || !out) return fail(ASICP_E_INVALID, "NULL argument");
-  out->xcd_map = c->d.xcd_map;
-  out->fine = c->d.fine;
-  return ASICP_OK;
+  return guarded([&]() -> asicp_status {
+    g_err.clear();
+    if (!c || !out) return fail(ASICP_E_INVALID, "NULL argument");
+    out->xcd_map = c->d.xcd_map;
+    out->fine = c->d.fine;
+    return ASICP_OK;
+  });
 }
 
 static void drop_graph(asicp_ctx c) {  // a captured solve holds the old launch choices
@@ -759,68 +799,72 @@ static void drop_graph(asicp_ctx c) {  // a captured solve holds the old launch 
 }
 
 asicp_status asicp_set_launch(asicp_ctx c, const asicp_launch_t* in) {
-  g_err.clear();
-  if (!c || !in) return fail(ASICP_E_INVALID, "NULL argument");
-  if ((in->xcd_map != 0 && in->xcd_map != 1) || (in->fine != 0 && in->fine != 1))
-    return fail(ASICP_E_INVALID, "xcd_map and fine must be 0 or 1");
-  c->d.xcd_map = in->xcd_map;
-  c->d.fine = in->fine;
-  drop_graph(c);
-  return ASICP_OK;
+  return guarded([&]() -> asicp_status {
+    g_err.clear();
+    if (!c || !in) return fail(ASICP_E_INVALID, "NULL argument");
+    if ((in->xcd_map != 0 && in->xcd_map != 1) || (in->fine != 0 && in->fine != 1))
+      return fail(ASICP_E_INVALID, "xcd_map and fine must be 0 or 1");
+    c->d.xcd_map = in->xcd_map;
+    c->d.fine = in->fine;
+    drop_graph(c);
+    return ASICP_OK;
+  });
 }
 
 asicp_status asicp_autotune(asicp_ctx c, int32_t reps, void* stream, asicp_launch_t* chosen, float* ms_out) {
-  g_err.clear();
-  if (!c) return fail(ASICP_E_INVALID, "ctx is NULL");
-  if (reps < 1 || reps > 1000) return fail(ASICP_E_INVALID, "reps must be in 1..1000");
-  hipStream_t hs = static_cast<hipStream_t>(stream);
-  (void)hipGetLastError();
-  if (c->d.minibatch) {  // the forward kernel reads the current mini-batch operand
-    const int k = std::min(c->k, c->cfg.k_max);
-    const double full = 2.0 * (double)c->cfg.k_max / 3.0;
-    launch_minibatch(c->d, k, ((double)k < full ? (double)k : full) / full, hs);
-  }
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
-    if (e0) (void)hipEventDestroy(e0);
-    return fail(ASICP_E_HIP, "hipEventCreate failed");
-  }
-  auto timed = [&](auto&& launch, float* ms) -> bool {
-    launch();  // warm-up
-    if (hipEventRecord(e0, hs) != hipSuccess) return false;
-    for (int r = 0; r < reps; ++r) launch();
-    if (hipEventRecord(e1, hs) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return false;
-    return hipEventElapsedTime(ms, e0, e1) == hipSuccess;
-  };
-  float nn_ms[4] = {0, 0, 0, 0}, gate_ms[2] = {0, 0};
-  bool ok = true;
-  for (int v = 0; v < 4 && ok; ++v) {  // v = 2 * xcd_map + fine
-    Dev dv = c->d;
-    dv.wave_pairs = nullptr;  // tuning launches are not counted
-    dv.xcd_map = v >> 1;
-    dv.fine = v & 1;
-    ok = timed([&] { launch_nn_forward(dv, hs); }, &nn_ms[v]);
-    if (ok && dv.fine == 0) ok = timed([&] { launch_gate_reverse(dv, hs); }, &gate_ms[dv.xcd_map]);
-  }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  if (!ok) return fail(ASICP_E_HIP, "timing a launch variant failed");
-  const asicp_status st = check_launch("autotune");
-  if (st != ASICP_OK) return st;
-  int bestv = 2 * c->d.xcd_map + c->d.fine;  // keep the current choice unless another is faster
-  for (int v = 0; v < 4; ++v) {
-    const float tv = nn_ms[v] + gate_ms[v >> 1], tb = nn_ms[bestv] + gate_ms[bestv >> 1];
-    if (tv < tb) bestv = v;
-    if (ms_out) ms_out[v] = tv / (float)reps;
-  }
-  c->d.xcd_map = bestv >> 1;
-  c->d.fine = bestv & 1;
-  drop_graph(c);
-  if (chosen) {
-    chosen->xcd_map = c->d.xcd_map;
-    chosen->fine = c->d.fine;
-  }
-  return ASICP_OK;
+  return guarded([&]() -> asicp_status {
+    g_err.clear();
+    if (!c) return fail(ASICP_E_INVALID, "ctx is NULL");
+    if (reps < 1 || reps > 1000) return fail(ASICP_E_INVALID, "reps must be in 1..1000");
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    (void)hipGetLastError();
+    if (c->d.minibatch) {  // the forward kernel reads the current mini-batch operand
+      const int k = std::min(c->k, c->cfg.k_max);
+      const double full = 2.0 * (double)c->cfg.k_max / 3.0;
+      launch_minibatch(c->d, k, ((double)k < full ? (double)k : full) / full, hs);
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+      if (e0) (void)hipEventDestroy(e0);
+      return fail(ASICP_E_HIP, "hipEventCreate failed");
+    }
+    auto timed = [&](auto&& launch, float* ms) -> bool {
+      launch();  // warm-up
+      if (hipEventRecord(e0, hs) != hipSuccess) return false;
+      for (int r = 0; r < reps; ++r) launch();
+      if (hipEventRecord(e1, hs) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return false;
+      return hipEventElapsedTime(ms, e0, e1) == hipSuccess;
+    };
+    float nn_ms[4] = {0, 0, 0, 0}, gate_ms[2] = {0, 0};
+    bool ok = true;
+    for (int v = 0; v < 4 && ok; ++v) {  // v = 2 * xcd_map + fine
+      Dev dv = c->d;
+      dv.wave_pairs = nullptr;  // tuning launches are not counted
+      dv.xcd_map = v >> 1;
+      dv.fine = v & 1;
+      ok = timed([&] { launch_nn_forward(dv, hs); }, &nn_ms[v]);
+      if (ok && dv.fine == 0) ok = timed([&] { launch_gate_reverse(dv, hs); }, &gate_ms[dv.xcd_map]);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (!ok) return fail(ASICP_E_HIP, "timing a launch variant failed");
+    const asicp_status st = check_launch("autotune");
+    if (st != ASICP_OK) return st;
+    int bestv = 2 * c->d.xcd_map + c->d.fine;  // keep the current choice unless another is faster
+    for (int v = 0; v < 4; ++v) {
+      const float tv = nn_ms[v] + gate_ms[v >> 1], tb = nn_ms[bestv] + gate_ms[bestv >> 1];
+      if (tv < tb) bestv = v;
+      if (ms_out) ms_out[v] = tv / (float)reps;
+    }
+    c->d.xcd_map = bestv >> 1;
+    c->d.fine = bestv & 1;
+    drop_graph(c);
+    if (chosen) {
+      chosen->xcd_map = c->d.xcd_map;
+      chosen->fine = c->d.fine;
+    }
+    return ASICP_OK;
+  });
 }
 
 void asicp_destroy(asicp_ctx c) {

@@ -570,6 +570,23 @@ asicp_status pn_fail(asicp_status st, const std::string& m) {
   return st;
 }
 
+// Runs the body of an entry point so that no C++ exception crosses the C ABI:
+// host memory exhaustion in a container or a message string becomes
+// ASICP_E_HOST.
+template <class F>
+asicp_status guarded(F&& body) noexcept {
+  try {
+    return body();
+  } catch (...) {
+    pn_err.clear();
+    try {
+      pn_err = "host-side failure (out of host memory)";
+    } catch (...) {
+    }
+    return ASICP_E_HOST;
+  }
+}
+
 struct PnLayout {
   size_t w2h, w3h, off, com, pool, head, out, dout, dhead, part, lpart, total;
 };
@@ -664,69 +681,77 @@ int64_t asicp_pn_param_count(int32_t n_pre, int32_t n_seed) {
 }
 
 asicp_status asicp_pn_workspace_bytes(int32_t n_obj, int32_t n_pre, int32_t n_seed, size_t* bytes) {
-  pn_err.clear();
-  if (!bytes) return pn_fail(ASICP_E_INVALID, "bytes must not be NULL");
-  const asicp_status st = pn_check(n_obj, n_pre, n_seed);
-  if (st != ASICP_OK) return st;
-  *bytes = pn_layout(n_obj, n_pre, n_seed).total;
-  return ASICP_OK;
+  return guarded([&]() -> asicp_status {
+    pn_err.clear();
+    if (!bytes) return pn_fail(ASICP_E_INVALID, "bytes must not be NULL");
+    const asicp_status st = pn_check(n_obj, n_pre, n_seed);
+    if (st != ASICP_OK) return st;
+    *bytes = pn_layout(n_obj, n_pre, n_seed).total;
+    return ASICP_OK;
+  });
 }
 
 asicp_status asicp_pn_forward(const float* params, int32_t n_pre, int32_t n_seed, int32_t n_obj,
                               const int32_t* off, const float* x, const float* y, const float* z,
                               float retract, float* seeds, float* raw, void* workspace, size_t ws_bytes,
                               void* stream) {
-  pn_err.clear();
-  hipStream_t hs = static_cast<hipStream_t>(stream);
-  if (!std::isfinite(retract)) return pn_fail(ASICP_E_INVALID, "retract must be finite");
-  Net n;
-  int mc = 0;
-  asicp_status st = pn_setup(n, params, n_pre, n_seed, n_obj, off, x, y, z, workspace, ws_bytes, hs, &mc);
-  if (st != ASICP_OK) return st;
-  pn_forward(n, mc, seeds, retract, hs);
-  if ((st = pn_launched("proposal forward")) != ASICP_OK) return st;
-  if (raw && hipMemcpyAsync(raw, n.out, 4 * (size_t)n_obj * n.P.O, hipMemcpyDeviceToDevice, hs) != hipSuccess)
-    return pn_fail(ASICP_E_HIP, "copying the raw outputs failed");
-  return ASICP_OK;
+  return guarded([&]() -> asicp_status {
+    pn_err.clear();
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    if (!std::isfinite(retract)) return pn_fail(ASICP_E_INVALID, "retract must be finite");
+    Net n;
+    int mc = 0;
+    asicp_status st = pn_setup(n, params, n_pre, n_seed, n_obj, off, x, y, z, workspace, ws_bytes, hs, &mc);
+    if (st != ASICP_OK) return st;
+    pn_forward(n, mc, seeds, retract, hs);
+    if ((st = pn_launched("proposal forward")) != ASICP_OK) return st;
+    if (raw && hipMemcpyAsync(raw, n.out, 4 * (size_t)n_obj * n.P.O, hipMemcpyDeviceToDevice, hs) != hipSuccess)
+      return pn_fail(ASICP_E_HIP, "copying the raw outputs failed");
+    return ASICP_OK;
+  });
 }
 
 asicp_status asicp_pn_loss_grad(const float* params, int32_t n_pre, int32_t n_seed, int32_t n_obj,
                                 const int32_t* off, const float* x, const float* y, const float* z,
                                 const float* targets, int32_t n_targets, float* loss, float* grad,
                                 void* workspace, size_t ws_bytes, void* stream) {
-  pn_err.clear();
-  hipStream_t hs = static_cast<hipStream_t>(stream);
-  if (!targets || !loss || !grad) return pn_fail(ASICP_E_INVALID, "NULL pointer argument");
-  if (n_targets < 1 || n_targets > 4096) return pn_fail(ASICP_E_INVALID, "n_targets must be in 1..4096");
-  Net n;
-  int mc = 0;
-  asicp_status st = pn_setup(n, params, n_pre, n_seed, n_obj, off, x, y, z, workspace, ws_bytes, hs, &mc);
-  if (st != ASICP_OK) return st;
-  n.n_tgt = n_targets;
-  pn_forward(n, mc, nullptr, 0.f, hs);
-  float* lpart = reinterpret_cast<float*>(static_cast<char*>(workspace) + pn_layout(n_obj, n_pre, n_seed).lpart);
-  const int pairs = n_obj * n_pre;
-  hipLaunchKernelGGL(k_pn_loss, dim3((pairs + 63) / 64), dim3(64), 0, hs, n, targets, lpart);
-  hipLaunchKernelGGL(k_pn_loss_sum, dim3((n_obj + 63) / 64), dim3(64), 0, hs, n, lpart, loss);
-  hipLaunchKernelGGL(k_pn_head_bwd, dim3(n_obj), dim3(256), 0, hs, n);
-  const long long head_elems = (long long)HH * H3 + HH + (long long)HH * HH + HH + (long long)n.P.O * HH + n.P.O;
-  hipLaunchKernelGGL(k_pn_head_wgrad, dim3((unsigned)((head_elems + 255) / 256)), dim3(256), 0, hs, n, grad);
-  hipLaunchKernelGGL(k_pn_point_bwd, dim3(n_obj), dim3(256), 0, hs, n);
-  hipLaunchKernelGGL(k_pn_reduce, dim3((kEnc + 255) / 256), dim3(256), 0, hs, n, grad);
-  return pn_launched("proposal loss and gradient");
+  return guarded([&]() -> asicp_status {
+    pn_err.clear();
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    if (!targets || !loss || !grad) return pn_fail(ASICP_E_INVALID, "NULL pointer argument");
+    if (n_targets < 1 || n_targets > 4096) return pn_fail(ASICP_E_INVALID, "n_targets must be in 1..4096");
+    Net n;
+    int mc = 0;
+    asicp_status st = pn_setup(n, params, n_pre, n_seed, n_obj, off, x, y, z, workspace, ws_bytes, hs, &mc);
+    if (st != ASICP_OK) return st;
+    n.n_tgt = n_targets;
+    pn_forward(n, mc, nullptr, 0.f, hs);
+    float* lpart = reinterpret_cast<float*>(static_cast<char*>(workspace) + pn_layout(n_obj, n_pre, n_seed).lpart);
+    const int pairs = n_obj * n_pre;
+    hipLaunchKernelGGL(k_pn_loss, dim3((pairs + 63) / 64), dim3(64), 0, hs, n, targets, lpart);
+    hipLaunchKernelGGL(k_pn_loss_sum, dim3((n_obj + 63) / 64), dim3(64), 0, hs, n, lpart, loss);
+    hipLaunchKernelGGL(k_pn_head_bwd, dim3(n_obj), dim3(256), 0, hs, n);
+    const long long head_elems = (long long)HH * H3 + HH + (long long)HH * HH + HH + (long long)n.P.O * HH + n.P.O;
+    hipLaunchKernelGGL(k_pn_head_wgrad, dim3((unsigned)((head_elems + 255) / 256)), dim3(256), 0, hs, n, grad);
+    hipLaunchKernelGGL(k_pn_point_bwd, dim3(n_obj), dim3(256), 0, hs, n);
+    hipLaunchKernelGGL(k_pn_reduce, dim3((kEnc + 255) / 256), dim3(256), 0, hs, n, grad);
+    return pn_launched("proposal loss and gradient");
+  });
 }
 
 asicp_status asicp_pn_adam(float* params, float* m, float* v, const float* grad, int64_t count, float lr,
                            float beta1, float beta2, float eps, int32_t step, void* stream) {
-  pn_err.clear();
-  if (!params || !m || !v || !grad) return pn_fail(ASICP_E_INVALID, "NULL pointer argument");
-  if (count < 1 || step < 1 || !(lr > 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) ||
-      !(eps > 0.f))
-    return pn_fail(ASICP_E_INVALID, "bad Adam settings");
-  const float c1 = 1.f - std::pow(beta1, (float)step), c2 = 1.f - std::pow(beta2, (float)step);
-  hipLaunchKernelGGL(k_pn_adam, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, static_cast<hipStream_t>(stream),
-                     params, m, v, grad, (long long)count, lr, beta1, beta2, eps, c1, c2);
-  return pn_launched("Adam step");
+  return guarded([&]() -> asicp_status {
+    pn_err.clear();
+    if (!params || !m || !v || !grad) return pn_fail(ASICP_E_INVALID, "NULL pointer argument");
+    if (count < 1 || step < 1 || !(lr > 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) ||
+        !(eps > 0.f))
+      return pn_fail(ASICP_E_INVALID, "bad Adam settings");
+    const float c1 = 1.f - std::pow(beta1, (float)step), c2 = 1.f - std::pow(beta2, (float)step);
+    hipLaunchKernelGGL(k_pn_adam, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, static_cast<hipStream_t>(stream),
+                       params, m, v, grad, (long long)count, lr, beta1, beta2, eps, c1, c2);
+    return pn_launched("Adam step");
+  });
 }
 
 }  // extern "C"

@@ -27,6 +27,15 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(L, n), n
 
 
+def test_status_codes_match_the_header():
+    text = open(os.path.join(ROOT, "include", "asicp.h")).read()
+    codes = {k: int(v) for k, v in re.findall(r"#define (ASICP_(?:OK|E_[A-Z]+))\s+\(?(-?\d+)\)?", text)}
+    assert codes == {"ASICP_OK": 0, "ASICP_E_INVALID": -1, "ASICP_E_STATE": -2, "ASICP_E_HIP": -3,
+                     "ASICP_E_NUMERIC": -4, "ASICP_E_HOST": -5}
+    for k, v in codes.items():
+        assert getattr(A, k) == v, k
+
+
 def host_problem(pb, sdf_ok=True):
     """A problem whose device pointers are placeholders: only host-side
     validation and sizing may look at it."""
