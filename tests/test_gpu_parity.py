@@ -195,12 +195,13 @@ def test_small_first_step():
     say("[parity] small first step", out)
 
 
-@pytest.mark.parametrize("K", [2, 128, 160, 255, 256, 257, 300])
+@pytest.mark.parametrize("K", [2, 128, 160, 255, 256, 257, 300, 512, 1024])
 def test_bandwidth_on_both_sides_of_one_workgroup(K):
     """The median bandwidth (eq. 9) comes from one workgroup per group up to
     K = 256 (of 256 threads up to K = 128, 512 up to K = 181, 1024 above) and
-    from the sliced four-launch select above; all must give the oracle's lower
-    median.  Checked on the first step and one later step."""
+    from the sliced four-launch select above, up to the largest group the
+    interface accepts (K = 1024); all must give the oracle's lower median.
+    Checked on the first step and one later step."""
     pb, st = synth.workload_small(K=K)
     out = compare_step(pb, st, pb.theta0, 0, label=f"bandwidth K={K}")
     say(f"[parity] bandwidth K={K}", out)
