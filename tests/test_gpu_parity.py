@@ -70,6 +70,37 @@ def col_scales(pb, theta_soa, or_rev):
     return st, sw, xc, xt, xw
 
 
+def stein_scales(pb, st, k, th64, r, setup, xb_t, xb_w):
+    """Scale of the Stein direction phi per particle: kernel-weighted
+    magnitudes of its driving and repulsion terms (ph_t, ph_w), and the part
+    of it that excused ties (bounds xb_t, xb_w on the gradient) may move
+    (ex_t, ex_w).  r is the oracle's step record at th64."""
+    ph_t = np.zeros(pb.k_tot)
+    ph_w = np.zeros(pb.k_tot)
+    ex_t = np.zeros(pb.k_tot)
+    ex_w = np.zeros(pb.k_tot)
+    gam, tau = oracle.schedule(st, k)
+    # driving gradient: the cost gradient minus the log-prior gradient
+    gdrive = r["g_fin"].copy()
+    if getattr(pb, "prior", None) is not None:
+        for i in range(pb.k_tot):
+            gdrive[i] -= oracle.log_prior(pb.prior[i // pb.K].astype(np.float64), th64[:, i])[1]
+    for gi in range(pb.n_obj * pb.n_pre):
+        p = gi % pb.n_pre
+        sl = slice(gi * pb.K, (gi + 1) * pb.K)
+        aos = th64[:, sl].T
+        _, kmat = oracle.svgd_direction(aos, gdrive[sl], r["h"][gi], gam, tau,
+                                        setup["a_t"][p], setup["a_w"][p], st.kernel_mode)
+        gt = np.abs(gdrive[sl, :3]).max(1)
+        gw = np.abs(gdrive[sl, 3:]).max(1)
+        dt = np.abs(aos[:, None, :3] - aos[None, :, :3]).max(-1)
+        ph_t[sl] = (kmat * (gam * setup["a_t"][p] * gt[None, :] + tau * dt)).mean(1)
+        ph_w[sl] = (kmat * (gam * setup["a_w"][p] * gw[None, :]) + tau).mean(1)
+        ex_t[sl] = (kmat * (gam * setup["a_t"][p] * xb_t[sl][None, :])).mean(1)
+        ex_w[sl] = (kmat * (gam * setup["a_w"][p] * xb_w[sl][None, :])).mean(1)
+    return ph_t, ph_w, ex_t, ex_w
+
+
 def compare_step(pb, st, theta, k, prev_cost=None, converged=None, label=""):
     """One teacher-forced step from float32 `theta` (7, Ktot); returns stats."""
     A, torch = _gpu()
@@ -117,30 +148,7 @@ def compare_step(pb, st, theta, k, prev_cost=None, converged=None, label=""):
     th64 = theta.astype(np.float64)
     if svgd:
         pu.close(g["h"], r["h"], r["h"], what="h")
-        # scale of phi: kernel-weighted magnitudes of driving and repulsion terms
-        ph_t = np.zeros(pb.k_tot)
-        ph_w = np.zeros(pb.k_tot)
-        ex_t = np.zeros(pb.k_tot)
-        ex_w = np.zeros(pb.k_tot)
-        gam, tau = oracle.schedule(st, k)
-        # driving gradient: the cost gradient minus the log-prior gradient
-        gdrive = r["g_fin"].copy()
-        if getattr(pb, "prior", None) is not None:
-            for i in range(pb.k_tot):
-                gdrive[i] -= oracle.log_prior(pb.prior[i // pb.K].astype(np.float64), th64[:, i])[1]
-        for gi in range(pb.n_obj * pb.n_pre):
-            p = gi % pb.n_pre
-            sl = slice(gi * pb.K, (gi + 1) * pb.K)
-            aos = th64[:, sl].T
-            _, kmat = oracle.svgd_direction(aos, gdrive[sl], r["h"][gi], gam, tau,
-                                            setup["a_t"][p], setup["a_w"][p], st.kernel_mode)
-            gt = np.abs(gdrive[sl, :3]).max(1)
-            gw = np.abs(gdrive[sl, 3:]).max(1)
-            dt = np.abs(aos[:, None, :3] - aos[None, :, :3]).max(-1)
-            ph_t[sl] = (kmat * (gam * setup["a_t"][p] * gt[None, :] + tau * dt)).mean(1)
-            ph_w[sl] = (kmat * (gam * setup["a_w"][p] * gw[None, :]) + tau).mean(1)
-            ex_t[sl] = (kmat * (gam * setup["a_t"][p] * xb_t[sl][None, :])).mean(1)
-            ex_w[sl] = (kmat * (gam * setup["a_w"][p] * xb_w[sl][None, :])).mean(1)
+        ph_t, ph_w, ex_t, ex_w = stein_scales(pb, st, k, th64, r, setup, xb_t, xb_w)
         if same.all() and excused == 0:
             pu.close(g["phi"][:3].T, r["phi"][:, :3], ph_t[:, None], what="phi_t", extra=ex_t[:, None])
             pu.close(g["phi"][3:].T, r["phi"][:, 3:], ph_w[:, None], what="phi_w", extra=ex_w[:, None])
@@ -423,6 +431,69 @@ def test_batched_objects_first_steps():
     pb, st = synth.workload_batched(n_obj=4, K=16, k_max=10, m_lo=512, m_hi=4096, n=640, grid_n=64)
     compare_step(pb, st, pb.theta0, 0, label="batched")
     compare_step(pb, st, pulled_in(pb, 0.7), 3, label="batched pulled in")
+
+
+def test_batched_workload_full_size_sampled():
+    """The full batched workload (64 objects of 2k-32k points, 24,576
+    particles, 3 x 4096 contact points) stepped once on the GPU; every particle
+    of its smallest and its largest object is checked against the oracle run
+    on those two objects alone (groups never mix objects, so their step is the
+    same computation).  Poses are pulled 0-70 % of the way towards each
+    object's centre, so both collision-free and colliding particles occur.
+    Without the debug records no tie can be excused, so 99 % of the particles
+    must agree within the tolerances of the other parity tests."""
+    A, torch = _gpu()
+    pb, st = synth.workload_batched()
+    m = np.diff(pb.r_off)
+    sub_objs = [int(np.argmin(m)), int(np.argmax(m))]
+    per_obj = pb.n_pre * pb.K
+    sel = np.concatenate([np.arange(o * per_obj, (o + 1) * per_obj) for o in sub_objs])
+    th = pb.theta0.astype(np.float64)
+    frac = np.linspace(0.0, 0.7, per_obj)
+    for o in range(pb.n_obj):
+        com = pb.R[pb.r_off[o]:pb.r_off[o + 1]].astype(np.float64).mean(0)
+        c = slice(o * per_obj, (o + 1) * per_obj)
+        th[:3, c] += frac * (com[:, None] - th[:3, c])
+    th = th.astype(np.float32)
+    say(f"[parity] batched full size: objects {sub_objs} of {pb.n_obj}, M = {m[sub_objs].tolist()}")
+    sol = A.Solver(pb, st, theta0=th)
+    sol.step(1)
+    g = sol.result()
+    sol.close()
+    assert g["status"] == 0
+    R_parts = [pb.R[pb.r_off[o]:pb.r_off[o + 1]] for o in sub_objs]
+    C_parts = [pb.C[pb.c_off[o]:pb.c_off[o + 1]] for o in sub_objs]
+    sub = synth.Problem(R=np.concatenate(R_parts), r_off=np.cumsum([0] + [len(r) for r in R_parts]).astype(np.int32),
+                        C=np.concatenate(C_parts), c_off=np.cumsum([0] + [len(c) for c in C_parts]).astype(np.int32),
+                        S=pb.S, s_off=pb.s_off, grids=pb.grids, theta0=th[:, sel], K=pb.K)
+    o = oracle.Oracle(sub, st)
+    r = o.step(0, sub.theta0, full=True)
+    say("[parity] batched full size: oracle done")
+    gsel = lambda a: np.asarray(a)[..., sel]
+    n = len(sel)
+    s_t, s_w = pu.scales(sub, sub.theta0, r["nn_idx"], st.lam, o.setup())
+    same_col = gsel(g["ncol"]) == r["ncol"]
+    ok_cost = np.abs(gsel(g["cost"]) - r["cost"]) <= pu.REL * np.abs(r["cost"])
+    gct = gsel(g["grad_ct"]).T
+    ok_gt = (np.abs(gct[:, :3] - r["g_ct"][:, :3]) <= pu.REL * np.maximum(np.abs(r["g_ct"][:, :3]), s_t[:, None])).all(1)
+    ok_gw = (np.abs(gct[:, 3:] - r["g_ct"][:, 3:]) <= pu.REL * np.maximum(np.abs(r["g_ct"][:, 3:]), s_w[:, None])).all(1)
+    # the update, against the scale of the Stein direction's terms (as in the
+    # teacher-forced step tests, with no tie excused)
+    th64 = sub.theta0.astype(np.float64)
+    ph_t, ph_w, _, _ = stein_scales(sub, st, 0, th64, r, o.setup(), np.zeros(n), np.zeros(n))
+    err_t = np.abs(gsel(g["theta"][:3]).astype(np.float64) - r["theta"][:3]).max(0)
+    err_w = pu.angle_between(gsel(g["theta"][3:]), r["theta"][3:])
+    ok_t = err_t <= 1e-4 * st.eta * ph_t + 2e-7 * np.maximum(np.abs(th64[:3]).max(0), 1e-2)
+    ok_w = err_w <= 1e-4 * st.eta * ph_w + 2e-6
+    h_g = np.asarray(g["h"])[np.concatenate([np.arange(o_ * pb.n_pre, (o_ + 1) * pb.n_pre) for o_ in sub_objs])]
+    rates = dict(ncol=same_col.mean(), cost=ok_cost.mean(), g_t=ok_gt.mean(), g_w=ok_gw.mean(),
+                 theta_t=ok_t.mean(), theta_w=ok_w.mean())
+    say("[parity] batched full size:", {k: round(float(v), 4) for k, v in rates.items()},
+        "colliding", int((r["ncol"] > 0).sum()), "of", n)
+    assert 0 < (r["ncol"] > 0).sum() < n
+    pu.close(h_g, r["h"], r["h"], what="h")
+    for k, v in rates.items():
+        assert v >= 0.99, (k, v)
 
 
 def test_determinism_and_resume():
