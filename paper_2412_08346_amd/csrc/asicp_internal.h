@@ -18,9 +18,6 @@ constexpr int kTileGroup = 64;     // points per MFMA-ready tile group (4 tiles 
 #ifndef ASICP_NN_WPE
 #define ASICP_NN_WPE 6
 #endif
-#ifndef ASICP_NN_SPLIT
-#define ASICP_NN_SPLIT 0
-#endif
 // Candidate chunks compared between refreshes of the pruning bound.
 #ifndef ASICP_NN_REFRESH
 #define ASICP_NN_REFRESH 4

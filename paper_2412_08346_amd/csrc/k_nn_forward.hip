@@ -130,14 +130,15 @@ __device__ __forceinline__ void nn_forward_body(const Dev& d) {
 }
 
 // The pruned scan keeps fewer registers live per wavefront and gains from
-// more wavefronts per SIMD to hide its per-chunk loads; the full scan does
-// not (a lower register budget makes it spill).
+// more wavefronts per SIMD to hide its per-chunk loads.  The full scan folds
+// one tile group's MFMA results at a time, which fits 3 wavefronts per SIMD
+// (168 registers; 4 would spill heavily).
 template <int MAP, bool FINE>
 __global__ __launch_bounds__(256) NN_OCCUPANCY void k_nn_forward(Dev d) {
   nn_forward_body<true, MAP, FINE>(d);
 }
 template <int MAP>
-__global__ __launch_bounds__(256) void k_nn_forward_full(Dev d) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_nn_forward_full(Dev d) {
   nn_forward_body<false, MAP, false>(d);
 }
 

@@ -101,8 +101,12 @@ __device__ __forceinline__ void tile_group(const float4& a, const float* b, floa
 // chunk's own minimum is folded first, so that the chunk recorded with the
 // running minimum is the lowest-index chunk holding it whatever order the
 // chunks are visited in: a chunk with a smaller value replaces it, one with
-// an equal value only if its index is lower.
-template <int Q>
+// an equal value only if its index is lower.  ASCENDING (the full scan, which
+// visits chunks in index order) records a chunk only if its value is
+// smaller, which selects the same chunk, and keeps one tile group's MFMA
+// results live at a time (fewer registers, so more wavefronts per SIMD hide
+// the matrix-core latency).
+template <int Q, bool ASCENDING = false>
 __device__ __forceinline__ void chunk_step(const float4 (&a)[kChunkTG], const float* b, float* best, int* bch,
                                            int c, const bool* need = nullptr) {
   float m[Q];
@@ -110,15 +114,16 @@ __device__ __forceinline__ void chunk_step(const float4 (&a)[kChunkTG], const fl
   for (int q = 0; q < Q; ++q) m[q] = __builtin_inff();
 #pragma unroll
   for (int t = 0; t < kChunkTG; ++t) {
-#if ASICP_NN_SPLIT
-    if (t) __builtin_amdgcn_sched_barrier(0);  // keep one tile group's MFMA results live at a time
-#endif
+    if (ASCENDING && t) __builtin_amdgcn_sched_barrier(0);
     tile_group<Q>(a[t], b, m, need);
   }
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     if (need && !need[q]) continue;  // wave-uniform
-    bch[q] = (m[q] < best[q] || (m[q] == best[q] && c < bch[q])) ? c : bch[q];
+    if (ASCENDING)
+      bch[q] = m[q] < best[q] ? c : bch[q];
+    else
+      bch[q] = (m[q] < best[q] || (m[q] == best[q] && c < bch[q])) ? c : bch[q];
     best[q] = fminf(best[q], m[q]);
   }
 }
@@ -246,12 +251,12 @@ __device__ __forceinline__ void nn_scan(const float4* __restrict__ prep, int ntg
   for (int c = 0; c < nch; c += 2) {
 #pragma unroll
     for (int t = 0; t < kChunkTG; ++t) y[t] = load_tg(rs, (c + 1) * kChunkTG + t, lo);
-    chunk_step<Q>(x, b, best, bch, c);
+    chunk_step<Q, true>(x, b, best, bch, c);
     if (c + 2 < nch) {
 #pragma unroll
       for (int t = 0; t < kChunkTG; ++t) x[t] = load_tg(rs, (c + 2) * kChunkTG + t, lo);
     }
-    chunk_step<Q>(y, b, best, bch, c + 1);
+    chunk_step<Q, true>(y, b, best, bch, c + 1);
   }
   nn_rescan<Q, true>(prep, rs, b, qc, best, bch, idx, miss);
 }
