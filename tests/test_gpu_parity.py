@@ -427,6 +427,42 @@ def test_ragged_sizes_and_edges():
     compare_step(pb, st, pulled_in(pb, 0.7), 4, label="K=1 SGD")
 
 
+def test_largest_object_cloud():
+    """An object of 2^22 points, the most the interface accepts per cloud
+    (its collision cloud too), with a ragged 200-point contact cloud: one
+    teacher-forced Stein step of 4 particles against the oracle, and the
+    pruned and full scans give the same nearest points."""
+    A, torch = _gpu()
+    rng = np.random.default_rng(11)
+    m = 1 << 22
+    v = rng.normal(size=(m, 3))
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    obj = (v * 0.035 + rng.normal(scale=0.001, size=(m, 3))).astype(np.float32)  # a 3.5 cm shell
+    pre = [synth.gripper_contact_cloud(0.06, 200, rng)]
+    grids = [synth.gripper_sdf_grid(0.06, 48, 0.003)]
+    pb = synth._assemble([obj], pre, grids, 4, [0.07])
+    st = synth.Settings(k_max=4, k_stein=2)
+    th = pulled_in(pb, 0.6)
+    out = compare_step(pb, st, th, 0, label="largest object cloud")
+    say("[parity] largest object cloud", out)
+    assert out["ncol"] > 0
+    res = []
+    for prune in (True, False):
+        s = A.Solver(pb, st, debug=True, theta0=th, prune=prune)
+        s.step(1)
+        res.append(s.result())
+        s.close()
+    a, b = res[0]["nn_idx"], res[1]["nn_idx"]
+    diff = np.argwhere(a != b)
+    say("[parity] largest object cloud, pruned vs plain index differences:", len(diff))
+    S = pb.S.astype(np.float64)
+    R = pb.R.astype(np.float64)
+    th64 = th.astype(np.float64)
+    for i, n in diff:
+        sp = oracle.quat_to_rot(th64[3:, i]) @ S[n] + th64[:3, i]
+        assert abs(((sp - R[a[i, n]]) ** 2).sum() - ((sp - R[b[i, n]]) ** 2).sum()) <= 1e-8
+
+
 def test_batched_objects_first_steps():
     pb, st = synth.workload_batched(n_obj=4, K=16, k_max=10, m_lo=512, m_hi=4096, n=640, grid_n=64)
     compare_step(pb, st, pb.theta0, 0, label="batched")
