@@ -236,9 +236,11 @@ typedef struct {
 asicp_status asicp_get_launch(asicp_ctx ctx, asicp_launch_t* out);
 asicp_status asicp_set_launch(asicp_ctx ctx, const asicp_launch_t* in);
 
-/* Time every launch choice on the context's current poses (the forward NN
- * and the collision kernel, `reps` launches each after one warm-up, HIP
- * events on `stream`), keep the fastest and return it in `chosen` (may be
+/* Time every launch choice on the context's current poses (`reps`
+ * evaluations each after one warm-up, HIP events on `stream`; an evaluation
+ * runs the forward NN on `stream` beside the bandwidth select, in the Stein
+ * phase, and the collision kernel on the context's side stream, as an
+ * iteration does), keep the fastest and return it in `chosen` (may be
  * NULL); ms_out (host, may be NULL) receives the average time per
  * evaluation of each choice, index 2 * xcd_map + fine.  Synchronises
  * `stream`.  The solve's state is left as it was (tuning launches are not

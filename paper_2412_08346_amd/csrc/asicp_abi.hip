@@ -835,26 +835,37 @@ asicp_status asicp_autotune(asicp_ctx c, int32_t reps, void* stream, asicp_launc
       if (hipEventRecord(e1, hs) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return false;
       return hipEventElapsedTime(ms, e0, e1) == hipSuccess;
     };
-    float nn_ms[4] = {0, 0, 0, 0}, gate_ms[2] = {0, 0};
-    bool ok = true;
+    // Each choice is timed on one evaluation as an iteration runs it: the
+    // side stream forks from `stream`, runs the bandwidth select (in the Stein
+    // phase) and the collision kernel while the forward NN runs on `stream`,
+    // and joins; how the three share the GPU depends on the choice.
+    const bool bandwidth = c->k < c->cfg.k_stein;
+    float ev_ms[4] = {0, 0, 0, 0};
+    bool ok = true, streams_ok = true;
     for (int v = 0; v < 4 && ok; ++v) {  // v = 2 * xcd_map + fine
       Dev dv = c->d;
       dv.wave_pairs = nullptr;  // tuning launches are not counted
       dv.xcd_map = v >> 1;
       dv.fine = v & 1;
-      ok = timed([&] { launch_nn_forward(dv, hs); }, &nn_ms[v]);
-      if (ok && dv.fine == 0) ok = timed([&] { launch_gate_reverse(dv, hs); }, &gate_ms[dv.xcd_map]);
+      ok = timed([&] {
+        streams_ok = streams_ok && hipEventRecord(c->fork_ev, hs) == hipSuccess &&
+                     hipStreamWaitEvent(c->side, c->fork_ev, 0) == hipSuccess;
+        if (bandwidth) launch_bandwidth(dv, c->inv_log_k, c->side);
+        launch_gate_reverse(dv, c->side);
+        launch_nn_forward(dv, hs);
+        streams_ok = streams_ok && hipEventRecord(c->join_ev, c->side) == hipSuccess &&
+                     hipStreamWaitEvent(hs, c->join_ev, 0) == hipSuccess;
+      }, &ev_ms[v]);
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    if (!ok) return fail(ASICP_E_HIP, "timing a launch variant failed");
+    if (!ok || !streams_ok) return fail(ASICP_E_HIP, "timing a launch variant failed");
     const asicp_status st = check_launch("autotune");
     if (st != ASICP_OK) return st;
     int bestv = 2 * c->d.xcd_map + c->d.fine;  // keep the current choice unless another is faster
     for (int v = 0; v < 4; ++v) {
-      const float tv = nn_ms[v] + gate_ms[v >> 1], tb = nn_ms[bestv] + gate_ms[bestv >> 1];
-      if (tv < tb) bestv = v;
-      if (ms_out) ms_out[v] = tv / (float)reps;
+      if (ev_ms[v] < ev_ms[bestv]) bestv = v;
+      if (ms_out) ms_out[v] = ev_ms[v] / (float)reps;
     }
     c->d.xcd_map = bestv >> 1;
     c->d.fine = bestv & 1;
