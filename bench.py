@@ -39,18 +39,21 @@ def nn_traffic(workload, launch, brute):
     return NN_TRAFFIC["bytes"].get(f"{launch['xcd_map']},{launch['fine']}")
 
 
-def cpu_baseline(pb, st, iters=1):
-    """The FP64 oracle, untuned, on a bounded sample: `iters` iteration(s) of
-    every particle of the same workload (evaluation + Stein update)."""
+def cpu_baseline(pb, st, seconds=10.0):
+    """The FP64 oracle, untuned, on a bounded sample of the same workload:
+    whole iterations of every particle (evaluation + Stein update) from the
+    initial poses, as many as start within `seconds`."""
     import numpy as np
     import oracle
     o = oracle.Oracle(pb, st)
     th = pb.theta0.astype(np.float64)
     t0 = time.perf_counter()
     pc = cv = None
-    for k in range(iters):
-        r = o.step(k, th, pc, cv)
+    iters = 0
+    while iters < st.k_max and (iters == 0 or time.perf_counter() - t0 < seconds):
+        r = o.step(iters, th, pc, cv)
         th, pc, cv = r["theta"], r["prev_cost"], r["converged"]
+        iters += 1
     dt = time.perf_counter() - t0
     return {"value": pb.k_tot * iters / dt, "unit": "particle-iters/s", "cores": oracle.threads(),
             "kind": "oracle",
