@@ -1,0 +1,47 @@
+"""Host-side parts of the measurement in bench.py: the CPU-baseline leg and
+the HBM-traffic record of the forward-NN kernel.  No GPU is needed."""
+import hashlib
+import os
+import subprocess
+import sys
+
+import oracle
+from paper_2412_08346_amd import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_cpu_baseline_fields_and_bounded_sample():
+    pb, st = synth.workload_small(k_max=6)
+    cb = bench.cpu_baseline(pb, st, seconds=0.0)  # one whole iteration
+    assert set(cb) == {"value", "unit", "cores", "kind", "sample"}
+    assert cb["kind"] == "oracle" and cb["unit"] == "particle-iters/s"
+    assert cb["cores"] == oracle.threads() and cb["value"] > 0
+    assert cb["sample"].startswith(f"1 iteration(s) of all {pb.k_tot} particles")
+    cb = bench.cpu_baseline(pb, st, seconds=1e9)  # capped by k_max
+    assert cb["sample"].startswith(f"{st.k_max} iteration(s)")
+
+
+def test_traffic_record_follows_the_kernel_source():
+    h = hashlib.sha256()
+    for f in bench.NN_SOURCES:
+        with open(os.path.join(ROOT, "paper_2412_08346_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    # the committed record was measured on the committed kernel source
+    assert h.hexdigest() == bench.NN_TRAFFIC["sha256"]
+    assert set(bench.NN_TRAFFIC["bytes"]) == {"0,0", "0,1", "1,0", "1,1"}
+    for mp in (0, 1):
+        for fn in (0, 1):
+            b = bench.nn_traffic("paper", {"xcd_map": mp, "fine": fn}, False)
+            assert b == bench.NN_TRAFFIC["bytes"][f"{mp},{fn}"]
+            # other workloads and the full scan were not measured: null
+            assert bench.nn_traffic("batched", {"xcd_map": mp, "fine": fn}, False) is None
+            assert bench.nn_traffic("paper", {"xcd_map": mp, "fine": fn}, True) is None
+
+
+def test_more_than_one_gpu_exits_with_a_message():
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert p.returncode != 0 and "one GPU" in p.stderr
