@@ -17,10 +17,15 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "asicp_oracle.c")
 _LIB = os.path.join(_HERE, "libasicp_oracle.so")
+# A test may point the face at a library built from a deliberately altered copy
+# of the source, to show that the pins catch the alteration.
+_VARIANT = os.environ.get("ASICP_ORACLE_VARIANT_LIB")
 
 
 def build(force: bool = False) -> str:
     """Compile the oracle with the system C compiler (plain -O2, OpenMP)."""
+    if _VARIANT:
+        return _VARIANT
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall",
@@ -57,8 +62,7 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        build()
-        L = C.CDLL(_LIB)
+        L = C.CDLL(build())
         vp, i32, f64 = C.c_void_p, C.c_int32, C.c_double
         L.or_quat_to_rot.argtypes = [vp, vp]
         L.or_quat_mul.argtypes = [vp, vp, vp]

@@ -428,6 +428,185 @@ def test_single_particle_zero_temperature_is_gradient_descent():
         assert not np.allclose(svgd["theta"], pb.theta0, atol=1e-6)
 
 
+# ---------------------------------------------------------------------------
+# preconditioner A of eq. (3): the reciprocal of the Gauss-Newton diagonal
+# ---------------------------------------------------------------------------
+
+def no_collision(pb):
+    for g in pb.grids:
+        g.values[:] = 1.0
+    return pb
+
+
+@pytest.mark.parametrize("lam", [0.6, 2.5])
+def test_translation_step_lands_on_the_minimiser_of_the_cost_in_t(lam):
+    # With the pairs held, C is a quadratic in t whose minimiser is
+    #   t* = (mean(r_hat) + lambda CoM) / (1 + lambda) - R TCP
+    # (set dC/dt = mean(R s + t - r_hat) + lambda (R TCP + t - CoM) = 0).  One SGD
+    # step with eta = 1 and the GN-diagonal A must land exactly there.
+    pb, st = tiny_problem(seed=21, lam=lam)
+    no_collision(pb)
+    st.k_stein = 0
+    o = oracle.Oracle(pb, st)
+    r = o.step(0, pb.theta0, full=True)
+    S = pb.S.astype(np.float64)
+    R = pb.R.astype(np.float64)
+    com, tcp = R.mean(0), S.mean(0)
+    for i in range(pb.k_tot):
+        Rq = oracle.quat_to_rot(pb.theta0[3:, i].astype(np.float64))
+        rhat = R[r["nn_idx"][i]].mean(0)
+        tstar = (rhat + lam * com) / (1.0 + lam) - Rq @ tcp
+        assert np.allclose(r["theta"][:3, i], tstar, rtol=0, atol=1e-15), (i, r["theta"][:3, i], tstar)
+
+
+def isotropic_hessian_cloud(lam, a=0.03, vz=0.01):
+    """Six points v +- a e_x, v +- a e_y, v +- b e_z with v = (0, 0, vz).  Their
+    second moment about the origin is M2 = diag(a^2/3, a^2/3, b^2/3 + vz^2);
+    with b^2 = a^2 - 3 (1 + lambda) vz^2, M2 + lambda v v^T = (a^2/3) I, so the
+    Gauss-Newton Hessian of C in the rotation vector at zero residual,
+    tr(M2) I - M2 + lambda (|v|^2 I - v v^T), is the isotropic (2 a^2/3) I."""
+    b = math.sqrt(a * a - 3.0 * (1.0 + lam) * vz * vz)
+    v = np.array([0.0, 0.0, vz])
+    pts = [v + s * a * e for e in np.eye(3)[:2] for s in (1, -1)] + [v + s * b * np.eye(3)[2] for s in (1, -1)]
+    return np.array(pts)
+
+
+@pytest.mark.parametrize("lam", [1.0, 0.25])
+def test_rotation_step_undoes_a_small_rotation_to_first_order(lam):
+    # S = R (so TCP = CoM and every residual is zero at the identity pose), a
+    # contact cloud whose rotation Hessian is isotropic with TCP != 0.  From a
+    # small rotation w0 one SGD step (eta = 1) must return the rotation to the
+    # identity up to O(|w0|^2): a_w equals 1 / (2 a^2 / 3) only if it is
+    # 3 / (2 (rho^2 + lambda |TCP|^2)).
+    pts = isotropic_hessian_cloud(lam).astype(np.float32)
+    rng = np.random.default_rng(3)
+    K = 4
+    pb, st = tiny_problem(seed=22, lam=lam, R=pts, S=pts, K=K)
+    no_collision(pb)
+    st.k_stein = 0
+    th = np.zeros((7, K))
+    w0s = []
+    for i in range(K):
+        ax = rng.standard_normal(3)
+        w0 = 1e-3 * ax / np.linalg.norm(ax)
+        w0s.append(w0)
+        th[3:, i] = oracle.quat_exp(w0)
+    r = oracle.Oracle(pb, st).step(0, th, full=True)
+    assert (r["nn_idx"][:, :6] == np.arange(6)).all()
+    for i in range(K):
+        ang = 2.0 * math.asin(min(1.0, np.linalg.norm(r["theta"][4:, i])))
+        assert ang <= 1e-3 * np.linalg.norm(w0s[i]), (i, ang)
+
+
+def test_preconditioner_is_the_reciprocal_gauss_newton_diagonal():
+    # At zero residual (S = R at the identity pose) the Hessian of C equals its
+    # Gauss-Newton Hessian.  Central second differences of the oracle's own cost
+    # give its diagonal: (1 + lambda) on each translation axis, and a rotation
+    # trace; A = diag(a_t I, a_w I) must be 1/(1+lambda) and 3 / trace.
+    rng = np.random.default_rng(9)
+    pts = (rng.uniform(-0.03, 0.03, (40, 3)) + [0.004, -0.006, 0.02]).astype(np.float32)
+    for lam in (0.0, 0.7, 3.0):
+        pb, st = tiny_problem(seed=23, lam=lam, R=pts, S=pts, K=1)
+        no_collision(pb)
+        o = oracle.Oracle(pb, st)
+        th = np.zeros((7, 1))
+        th[3, 0] = 1.0
+        base = o.evaluate(th)
+        assert base["cost"][0] == 0.0
+        hess = []
+        for ax in range(6):
+            h = 1e-4
+            ep = o.evaluate(perturb(th, 0, ax, h))
+            em = o.evaluate(perturb(th, 0, ax, -h))
+            assert (ep["nn_idx"][0] == np.arange(40)).all() and (em["nn_idx"][0] == np.arange(40)).all()
+            hess.append((ep["cost"][0] + em["cost"][0] - 2.0 * base["cost"][0]) / (h * h))
+        setup = o.setup()
+        assert np.allclose(hess[:3], 1.0 + lam, rtol=1e-6)
+        assert setup["a_t"][0] * (1.0 + lam) == pytest.approx(1.0, rel=1e-12)
+        assert setup["a_w"][0] * sum(hess[3:]) / 3.0 == pytest.approx(1.0, rel=1e-6)
+    # the identity preconditioner is A = I whatever lambda is
+    st.precond = synth.PRECOND_IDENTITY
+    s1 = oracle.Oracle(pb, st).setup()
+    assert s1["a_t"][0] == 1.0 and s1["a_w"][0] == 1.0
+
+
+# ---------------------------------------------------------------------------
+# the driving term of eq. (8) with K > 1
+# ---------------------------------------------------------------------------
+
+def three_particle_group():
+    """t0 = 0, t1 = 5 cm along x, t2 = 8 cm along y; q0 = identity, q1 a turn of
+    0.8 rad about z, q2 a turn of 1.1 rad about x.  With h = 0.01 m^2:
+    RBF kt_ij = exp(-|t_i - t_j|^2 / h) and rotation kernel kr_ij = |q_i . q_j|
+    are kt01 = e^-0.25, kt02 = e^-0.64, kt12 = e^-0.89, kr01 = cos 0.4,
+    kr02 = cos 0.55, kr12 = cos 0.4 cos 0.55."""
+    th = np.zeros((3, 7))
+    th[1, 0] = 0.05
+    th[2, 1] = 0.08
+    th[0, 3] = 1.0
+    th[1, 3:] = [math.cos(0.4), 0.0, 0.0, math.sin(0.4)]
+    th[2, 3:] = [math.cos(0.55), math.sin(0.55), 0.0, 0.0]
+    kt = np.array([[1.0, math.exp(-0.25), math.exp(-0.64)],
+                   [math.exp(-0.25), 1.0, math.exp(-0.89)],
+                   [math.exp(-0.64), math.exp(-0.89), 1.0]])
+    kr = np.array([[1.0, math.cos(0.4), math.cos(0.55)],
+                   [math.cos(0.4), 1.0, math.cos(0.4) * math.cos(0.55)],
+                   [math.cos(0.55), math.cos(0.4) * math.cos(0.55), 1.0]])
+    return th, kt, kr
+
+
+@pytest.mark.parametrize("mode", [synth.KERNEL_PRODUCT, synth.KERNEL_BLOCK])
+@pytest.mark.parametrize("gamma", [1.0, 0.35])
+def test_stein_driving_term_three_particles_by_hand(mode, gamma):
+    # tau = 0 leaves the driving term alone: phi_i = (1/K) sum_j k_ij (-gamma A g_j)
+    # (eq. 8, expectation form).  The product kernel weighs every row by
+    # kt kr; the block kernel weighs translation rows by kt and rotation rows by kr.
+    th, kt, kr = three_particle_group()
+    g = np.array([[0.3, -0.2, 0.5, 0.01, -0.04, 0.02],
+                  [-0.7, 0.1, 0.2, -0.03, 0.05, 0.06],
+                  [0.4, 0.9, -0.6, 0.08, 0.02, -0.07]]) * 1e-2
+    a_t, a_w = 0.5, 300.0
+    phi, kmat = oracle.svgd_direction(th, g, h=0.01, gamma=gamma, tau=0.0, a_t=a_t, a_w=a_w,
+                                      kernel_mode=mode)
+    assert np.allclose(kmat, kt * kr, rtol=1e-14)
+    if mode == synth.KERNEL_PRODUCT:
+        wt, ww = kt * kr, kt * kr
+    else:
+        wt, ww = kt, kr
+    expect = np.zeros((3, 6))
+    for i in range(3):
+        for j in range(3):
+            expect[i, :3] += wt[i, j] * (-gamma * a_t * g[j, :3]) / 3.0
+            expect[i, 3:] += ww[i, j] * (-gamma * a_w * g[j, 3:]) / 3.0
+    assert np.allclose(phi, expect, rtol=1e-13, atol=1e-18)
+
+
+@pytest.mark.parametrize("mode", [synth.KERNEL_PRODUCT, synth.KERNEL_BLOCK])
+def test_stein_driving_term_moves_neighbours_of_the_only_particle_with_a_gradient(mode):
+    # The driving term is linear in the gradients.  If only particle m has a
+    # gradient, every particle i moves along -gamma A g_m, weighted by its
+    # kernel value with m; particles far from m barely move, and the sum over
+    # such single-particle cases is the full direction (superposition).
+    K, gamma, a_t, a_w, h = 6, 0.8, 0.4, 250.0, 0.004
+    th, g = random_group(K, 17)
+    t, q = th[:, :3], th[:, 3:]
+    kt = np.exp(-((t[:, None] - t[None]) ** 2).sum(-1) / h)
+    kr = np.abs(q @ q.T)
+    wt, ww = (kt * kr, kt * kr) if mode == synth.KERNEL_PRODUCT else (kt, kr)
+    total = np.zeros((K, 6))
+    for m in range(K):
+        gm = np.zeros((K, 6))
+        gm[m] = g[m]
+        phi, _ = oracle.svgd_direction(th, gm, h=h, gamma=gamma, tau=0.0, a_t=a_t, a_w=a_w,
+                                       kernel_mode=mode)
+        total += phi
+        for i in range(K):
+            assert np.allclose(phi[i, :3], -gamma * a_t * wt[i, m] * g[m, :3] / K, rtol=1e-12, atol=1e-20)
+            assert np.allclose(phi[i, 3:], -gamma * a_w * ww[i, m] * g[m, 3:] / K, rtol=1e-12, atol=1e-20)
+    full, _ = oracle.svgd_direction(th, g, h=h, gamma=gamma, tau=0.0, a_t=a_t, a_w=a_w, kernel_mode=mode)
+    assert np.allclose(full, total, rtol=1e-12, atol=1e-20)
+
+
 def test_median_bandwidth_unit_square():
     th = np.zeros((4, 7))
     th[:, 3] = 1
