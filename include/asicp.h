@@ -8,7 +8,7 @@
  * complete gripper cloud G), the initial particles Theta_0, k_stein and
  * k_max (Sec. IV-A, Algorithm 1 inputs) -- and returns, per object, the pose
  * theta that minimises the grasp loss among collision-free particles
- * (Algorithm 1 return; Sec. V-A).  Every iteration of every particle runs in
+ * (Algorithm 1 return; Sec. VI-A).  Every iteration of every particle runs in
  * hand-written HIP kernels on the stream the caller passes.
  *
  * Conventions (all calls)
@@ -102,7 +102,7 @@ typedef struct {
   const int32_t* converged;    /*   previous iteration, converged flags)             */
   int32_t k_start;             /* first iteration to run (0 .. k_max)                */
   const float* prior;          /* HOST, optional (NULL: none), [n_objects*n_preshapes][9]
-                                  per group, Sec. III-B / eq. (8): mean translation
+                                  per group, Sec. III-C / eq. (8): mean translation
                                   mu_t[3], translation precision w_t = 1/sigma^2
                                   (>= 0), mean rotation mu_q[4] (w, x, y, z; unit
                                   within 1e-3, normalised on use), von Mises
@@ -274,7 +274,7 @@ const char* asicp_last_error(void);
 /* ---------------------------------------------------------------------------
  * Learned grasp proposal (seeds for the iteration above).  The paper points to
  * learned priors and data-driven seeding as the way to need fewer
- * initialisations (Sec. V-A ablation, Sec. VI); this network and its training
+ * initialisations (Sec. V, the ablation; Sec. VII); this network and its training
  * are the library's own.  A max-pooled point encoder, 3 -> 64 -> 128 -> 256
  * per point (BF16 matrix products, FP32 accumulation) and a 256 -> 256 -> 256
  * -> n_pre * n_seed * 7 head, maps each object cloud to n_seed seed poses per

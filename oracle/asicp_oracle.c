@@ -686,7 +686,7 @@ int32_t or_step(const or_problem* pb, const or_config* cfg, int32_t k, double* t
   return 0;
 }
 
-/* Log prior of a pose (Sec. III-B: Gaussian in translation, von Mises in
+/* Log prior of a pose (Sec. III-C: Gaussian in translation, von Mises in
  * rotation), up to a constant, and its gradient in the 6-D tangent (t, world
  * rotation vector).  Translation: -w_t/2 |t - mu_t|^2.  Rotation: the matrix
  * von Mises-Fisher density on SO(3), kappa tr(R(mu_q)^T R(q)); its rotation
@@ -718,7 +718,7 @@ double or_log_prior(const double pr[9], const double theta[7], double grad[6]) {
   return lp;
 }
 
-/* Returned grasp (Algorithm 1 return; Sec. V-A): per object, the particle
+/* Returned grasp (Algorithm 1 return; Sec. VI-A): per object, the particle
  * with the lowest cost among those whose final pose does not collide, lowest
  * index on ties.  If every particle collides the lowest-cost particle overall
  * is returned with best_free = 0. */

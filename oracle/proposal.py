@@ -2,7 +2,7 @@
 
 A point-cloud encoder in the style of PointNet (the paper points to learned
 priors and data-driven seeding as ways to need fewer initialisations,
-Sec. V-A ablation and Sec. VI) maps an object cloud to S seed poses per
+Sec. V, the ablation, and Sec. VII) maps an object cloud to S seed poses per
 preshape, which then start the AS-ICP iteration of Algorithm 1:
 
   x_m   = (r_m - mean(r)) / 0.1                       centred, 10 cm units

@@ -1,8 +1,8 @@
 // k_proposal.hip -- learned grasp proposal: a max-pooled point-cloud encoder
 // (PointNet style) that maps an object cloud to S seed poses per preshape for
 // the AS-ICP iteration.  The paper points to learned priors and data-driven
-// seeding as the way to need fewer initialisations (Sec. V-A ablation,
-// Sec. VI); the network, its loss and its training are this library's.
+// seeding as the way to need fewer initialisations (Sec. V, the
+// ablation; Sec. VII); the network, its loss and its training are this library's.
 //
 //   x_m  = (r_m - mean r) / 0.1
 //   h1_m = relu(W1 x_m + b1)          3 -> 64      (VALU, FP32)

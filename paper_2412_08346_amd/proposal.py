@@ -2,7 +2,7 @@
 encoder (kernels in csrc/k_proposal.hip, C calls asicp_pn_*).
 
 The paper points to learned priors and data-driven seeding as the way to
-need fewer initialisations (Sec. V-A ablation, Sec. VI).  Here a max-pooled
+need fewer initialisations (Sec. V, the ablation; Sec. VII).  Here a max-pooled
 point encoder is trained on grasps the solver itself finds: each training
 object is solved with plain Fibonacci AS-ICP, and the lowest-cost
 collision-free final poses per preshape are the targets of a set loss.  The

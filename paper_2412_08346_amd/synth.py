@@ -315,7 +315,7 @@ def _poses(dirs, anchor, tip, dist, rolls=None) -> np.ndarray:
 
 def fibonacci_poses(k: int, anchor: np.ndarray, tip: np.ndarray, dist: float) -> np.ndarray:
     """k poses on a Fibonacci sphere around `anchor` (the paper initialises
-    with the Fibonacci sequence, Sec. III-C): direction u_j, the gripper's +z
+    with the Fibonacci sequence, Sec. V): direction u_j, the gripper's +z
     axis pointing back at the anchor and the gripper-frame point `tip` at
     distance `dist` from the anchor.  Returns (7, k) float32."""
     return _poses(_fibonacci_dirs(k), anchor, tip, dist)
@@ -323,7 +323,7 @@ def fibonacci_poses(k: int, anchor: np.ndarray, tip: np.ndarray, dist: float) ->
 
 def quarter_sphere_dirs(k: int, arm=(-1.0, 0.0, 0.0)) -> np.ndarray:
     """Exactly k Fibonacci directions on the quarter sphere that faces the
-    robot arm (Sec. V-A, Fig. 4(b)): above the table (u_z >= 0) and on the
+    robot arm (Sec. V, Fig. 4(b); Sec. VI-A): above the table (u_z >= 0) and on the
     arm's side (u . arm >= 0).  The Fibonacci count is the smallest whose
     quarter holds k points."""
     a = np.asarray(arm, np.float64)
@@ -337,7 +337,7 @@ def quarter_sphere_dirs(k: int, arm=(-1.0, 0.0, 0.0)) -> np.ndarray:
 
 
 def top_poses(k: int, anchor: np.ndarray, tip: np.ndarray, dist: float) -> np.ndarray:
-    """k poses straight above the object (Sec. V-A adds six of them): gripper
+    """k poses straight above the object (Sec. VI-A adds six of them): gripper
     +z pointing down, rolls j*pi/k, j < k (a parallel gripper repeats itself
     after half a turn)."""
     dirs = np.tile([0.0, 0.0, 1.0], (k, 1))
@@ -346,7 +346,7 @@ def top_poses(k: int, anchor: np.ndarray, tip: np.ndarray, dist: float) -> np.nd
 
 def tabletop_poses(k: int, anchor: np.ndarray, tip: np.ndarray, dist: float, n_top: int = 6,
                    arm=(-1.0, 0.0, 0.0)) -> np.ndarray:
-    """The paper's simulation initialisation (Sec. V-A): k - n_top
+    """The paper's simulation initialisation (Sec. VI-A): k - n_top
     quarter-sphere Fibonacci poses plus n_top poses from above."""
     quarter = _poses(quarter_sphere_dirs(k - n_top, arm), anchor, tip, dist)
     return np.concatenate([quarter, top_poses(n_top, anchor, tip, dist)], axis=1)
@@ -354,7 +354,7 @@ def tabletop_poses(k: int, anchor: np.ndarray, tip: np.ndarray, dist: float, n_t
 
 def gmm_poses(k: int, anchor: np.ndarray, tip: np.ndarray, dist: float, means, sigma: float,
               rng: np.random.Generator) -> np.ndarray:
-    """Initialisation from a mixture of Gaussians (Fig. 4(a), Sec. III-C):
+    """Initialisation from a mixture of Gaussians (Fig. 4(a), Sec. V):
     approach directions drawn from equal-weight isotropic Gaussians of
     standard deviation `sigma` around the unit directions `means`, projected
     to the unit sphere; the gripper looks at the anchor from `dist`."""
@@ -503,7 +503,7 @@ def workload_adjoint(n_obj: int = 16, K: int = 512, m: int = 4096, n: int = 4096
 
 
 def grasp_prior(pb: Problem, sigma: float = 0.03, kappa: float = 5.0, sigma_n: float = 0.005) -> np.ndarray:
-    """A prior per group (Sec. III-B names Gaussian translation and von Mises
+    """A prior per group (Sec. III-C names Gaussian translation and von Mises
     rotation priors without parameters): the translation mean places the
     contact cloud's centroid on the object's mean point from straight above,
     the rotation mean points the gripper down.  sigma (m) is the translation
@@ -524,7 +524,7 @@ def grasp_prior(pb: Problem, sigma: float = 0.03, kappa: float = 5.0, sigma_n: f
 
 def workload_tabletop(n_pre: int = 10, K: int = 30, m: int = 800, n: int = 96, grid_n: int = 64,
                       seed: int = 8, init: str = "quarter"):
-    """The paper's simulation set-up (Sec. V-A, Table I) at its own scale: a
+    """The paper's simulation set-up (Sec. VI-A, Table I) at its own scale: a
     superquadric of m points resting on a table; the collision cloud C is the
     object plus a 5 mm table grid 2 cm beyond its footprint (about 1100-1900
     points in all); n_pre preshapes of a parallel gripper with finger gaps

@@ -297,7 +297,7 @@ def test_paper_preset_sgd_phase_with_collisions():
 
 @pytest.mark.parametrize("init", ["quarter", "gmm"])
 def test_tabletop_paper_setup(init):
-    """Sec. V-A set-up: collision cloud = object + table (C differs from R),
+    """Sec. VI-A set-up: collision cloud = object + table (C differs from R),
     10 preshapes of 96 points, 30 poses each, Table I schedule with the
     mini-batch."""
     pb, st = synth.workload_tabletop(init=init)

@@ -1,5 +1,5 @@
 """Host checks of the seeded input generators for the paper's simulation
-set-up (Sec. V-A, Table I, Fig. 4): quarter-sphere Fibonacci poses plus poses
+set-up (Sec. VI-A, Table I; Sec. V, Fig. 4): quarter-sphere Fibonacci poses plus poses
 from above, Gaussian-mixture initialisation, and the table in the collision
 cloud.  These generators hold none of the method's arithmetic."""
 import math

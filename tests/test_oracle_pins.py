@@ -895,7 +895,7 @@ def test_minibatch_full_size_equals_whole_cloud(small_workload):
 
 
 # ---------------------------------------------------------------------------
-# priors (Sec. III-B: Gaussian in translation, von Mises in rotation)
+# priors (Sec. III-C: Gaussian in translation, von Mises in rotation)
 # ---------------------------------------------------------------------------
 
 def axis_angle_quat(v):
