@@ -308,6 +308,22 @@ asicp_status asicp_pn_forward(const float* params, int32_t n_pre, int32_t n_seed
                               float retract, float* seeds, float* raw, void* workspace, size_t ws_bytes,
                               void* stream);
 
+/* asicp_pn_forward without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments, kernels and results as
+ * asicp_pn_forward; every intermediate lives in a device array inside the
+ * library instead (1 MiB per device, held by each device the library runs
+ * on until the process ends).  Nothing is allocated: no hipMalloc, hipFree
+ * or allocating library routine.  Limit: at most 64 objects per call
+ * (ASICP_E_INVALID beyond it, checked on the host before any device work).
+ * Every call on one device shares that device's array, which keeps the last
+ * call's contents (the pass clears what it accumulates into): calls that
+ * overlap on one device -- on different streams or host threads without
+ * ordering between them -- race and give undefined results. */
+asicp_status asicp_pn_forward_noalloc(const float* params, int32_t n_pre, int32_t n_seed, int32_t n_obj,
+                                      const int32_t* off, const float* x, const float* y, const float* z,
+                                      float retract, float* seeds, float* raw, void* stream);
+
 /* Set loss per object against targets (device [n_obj][n_pre][n_targets][7]
  * poses, unit q): per preshape the symmetric Chamfer distance
  * (1/T) sum_g min_a d + (1/S) sum_a min_g d with

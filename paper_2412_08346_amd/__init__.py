@@ -26,7 +26,7 @@ EXPORTS = ("asicp_workspace_bytes", "asicp_create", "asicp_step", "asicp_solve",
            "asicp_cost_grad", "asicp_result", "asicp_kernel_time", "asicp_get_launch",
            "asicp_set_launch", "asicp_autotune", "asicp_destroy", "asicp_last_error",
            "asicp_pn_param_count", "asicp_pn_workspace_bytes", "asicp_pn_forward",
-           "asicp_pn_loss_grad", "asicp_pn_adam", "asicp_pn_last_error")
+           "asicp_pn_loss_grad", "asicp_pn_adam", "asicp_pn_last_error", "asicp_pn_forward_noalloc")
 
 
 class AsicpError(RuntimeError):
@@ -112,6 +112,8 @@ def load():
         L.asicp_pn_workspace_bytes.restype = i32
         L.asicp_pn_forward.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, C.c_float, vp, vp, vp, C.c_size_t, vp]
         L.asicp_pn_forward.restype = i32
+        L.asicp_pn_forward_noalloc.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, C.c_float, vp, vp, vp]
+        L.asicp_pn_forward_noalloc.restype = i32
         L.asicp_pn_loss_grad.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, vp, i32, vp, vp, vp, C.c_size_t, vp]
         L.asicp_pn_loss_grad.restype = i32
         L.asicp_pn_adam.argtypes = [vp, vp, vp, vp, C.c_int64, C.c_float, C.c_float, C.c_float, C.c_float,
@@ -226,6 +228,11 @@ def asicp_pn_workspace_bytes(n_obj: int, n_pre: int, n_seed: int) -> int:
 def asicp_pn_forward(params, n_pre, n_seed, n_obj, off, x, y, z, retract, seeds, raw, ws, ws_bytes, stream):
     return _pn_check(load().asicp_pn_forward(params, int(n_pre), int(n_seed), int(n_obj), off, x, y, z,
                                              float(retract), seeds, raw, ws, int(ws_bytes), C.c_void_p(stream)))
+
+
+def asicp_pn_forward_noalloc(params, n_pre, n_seed, n_obj, off, x, y, z, retract, seeds, raw, stream):
+    return _pn_check(load().asicp_pn_forward_noalloc(params, int(n_pre), int(n_seed), int(n_obj), off, x, y, z,
+                                                     float(retract), seeds, raw, C.c_void_p(stream)))
 
 
 def asicp_pn_loss_grad(params, n_pre, n_seed, n_obj, off, x, y, z, targets, n_targets, loss, grad, ws,

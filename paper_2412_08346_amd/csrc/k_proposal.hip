@@ -21,6 +21,7 @@
 // Every sum runs in a fixed order: no float atomics.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <string>
 
 #include "asicp_internal.h"
@@ -587,8 +588,9 @@ asicp_status guarded(F&& body) noexcept {
   }
 }
 
+// The forward pass uses only the buffers up to `out`; fwd_total is their size.
 struct PnLayout {
-  size_t w2h, w3h, off, com, pool, head, out, dout, dhead, part, lpart, total;
+  size_t w2h, w3h, off, com, pool, head, out, dout, dhead, part, lpart, fwd_total, total;
 };
 
 PnLayout pn_layout(int n_obj, int n_pre, int n_seed) {
@@ -603,6 +605,7 @@ PnLayout pn_layout(int n_obj, int n_pre, int n_seed) {
   L.pool = bump(8 * (size_t)n_obj * H3);
   L.head = bump(4 * (size_t)n_obj * 1024);
   L.out = bump(4 * (size_t)n_obj * P.O);
+  L.fwd_total = c;
   L.dout = bump(4 * (size_t)n_obj * P.O);
   L.dhead = bump(4 * (size_t)n_obj * 768);
   L.part = bump(4 * (size_t)n_obj * kEnc);
@@ -622,7 +625,7 @@ asicp_status pn_check(int n_obj, int n_pre, int n_seed) {
 // offsets with the library's kernel-argument uploader
 asicp_status pn_setup(Net& n, const float* params, int n_pre, int n_seed, int n_obj, const int32_t* off,
                       const float* x, const float* y, const float* z, void* ws, size_t ws_bytes,
-                      hipStream_t hs, int* max_chunks) {
+                      hipStream_t hs, int* max_chunks, bool forward_only = false) {
   asicp_status st = pn_check(n_obj, n_pre, n_seed);
   if (st != ASICP_OK) return st;
   if (!params || !off || !x || !y || !z || !ws) return pn_fail(ASICP_E_INVALID, "NULL pointer argument");
@@ -634,7 +637,7 @@ asicp_status pn_setup(Net& n, const float* params, int n_pre, int n_seed, int n_
     mc = std::max(mc, (int)((m + kPts - 1) / kPts));
   }
   const PnLayout L = pn_layout(n_obj, n_pre, n_seed);
-  if (ws_bytes < L.total) return pn_fail(ASICP_E_INVALID, "workspace too small");
+  if (ws_bytes < (forward_only ? L.fwd_total : L.total)) return pn_fail(ASICP_E_INVALID, "workspace too small");
   char* b = static_cast<char*>(ws);
   n.prm = params;
   n.w2h = reinterpret_cast<unsigned short*>(b + L.w2h);
@@ -645,9 +648,9 @@ asicp_status pn_setup(Net& n, const float* params, int n_pre, int n_seed, int n_
   n.pool = reinterpret_cast<unsigned long long*>(b + L.pool);
   n.head = reinterpret_cast<float*>(b + L.head);
   n.out = reinterpret_cast<float*>(b + L.out);
-  n.dout = reinterpret_cast<float*>(b + L.dout);
-  n.dhead = reinterpret_cast<float*>(b + L.dhead);
-  n.part = reinterpret_cast<float*>(b + L.part);
+  n.dout = forward_only ? nullptr : reinterpret_cast<float*>(b + L.dout);
+  n.dhead = forward_only ? nullptr : reinterpret_cast<float*>(b + L.dhead);
+  n.part = forward_only ? nullptr : reinterpret_cast<float*>(b + L.part);
   n.n_obj = n_obj; n.n_pre = n_pre; n.n_seed = n_seed; n.n_tgt = 0;
   n.P = layout(n_pre, n_seed);
   (void)hipGetLastError();
@@ -666,6 +669,53 @@ void pn_forward(const Net& n, int mc, float* seeds, float retract, hipStream_t h
 asicp_status pn_launched(const char* what) {
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return pn_fail(ASICP_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+  return ASICP_OK;
+}
+
+// Forward pass and the optional copy of the raw outputs, on a workspace the
+// caller or the library provides.
+asicp_status pn_forward_call(const float* params, int n_pre, int n_seed, int n_obj, const int32_t* off,
+                             const float* x, const float* y, const float* z, float retract, float* seeds,
+                             float* raw, void* ws, size_t ws_bytes, bool forward_only, hipStream_t hs) {
+  if (!std::isfinite(retract)) return pn_fail(ASICP_E_INVALID, "retract must be finite");
+  Net n;
+  int mc = 0;
+  asicp_status st = pn_setup(n, params, n_pre, n_seed, n_obj, off, x, y, z, ws, ws_bytes, hs, &mc, forward_only);
+  if (st != ASICP_OK) return st;
+  pn_forward(n, mc, seeds, retract, hs);
+  if ((st = pn_launched("proposal forward")) != ASICP_OK) return st;
+  if (raw && hipMemcpyAsync(raw, n.out, 4 * (size_t)n_obj * n.P.O, hipMemcpyDeviceToDevice, hs) != hipSuccess)
+    return pn_fail(ASICP_E_HIP, "copying the raw outputs failed");
+  return ASICP_OK;
+}
+
+// Device-resident workspace of asicp_pn_forward_noalloc: every intermediate
+// of a forward pass of up to kNoAllocObjects objects.  Each device the
+// library runs on holds its own copy until the process ends.  Host code never
+// uses the symbol itself (on the host it names a stand-in, not device
+// memory): it uses the device address that hipGetSymbolAddress returns,
+// looked up once per device and kept in scratch_addr.
+constexpr int kNoAllocObjects = 64;
+constexpr size_t kNoAllocBytes = 1u << 20;
+__device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void* scratch_addr[kMaxDevices] = {};
+
+asicp_status scratch_for_current_device(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return pn_fail(ASICP_E_HIP, "hipGetDevice failed");
+  if (dev >= kMaxDevices) return pn_fail(ASICP_E_INVALID, "device index beyond the library's table (64)");
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_addr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return pn_fail(ASICP_E_HIP, std::string("hipGetSymbolAddress of the scratch array: ") + hipGetErrorString(e));
+    scratch_addr[dev] = p;
+  }
+  *out = scratch_addr[dev];
   return ASICP_OK;
 }
 
@@ -697,17 +747,27 @@ asicp_status asicp_pn_forward(const float* params, int32_t n_pre, int32_t n_seed
                               void* stream) {
   return guarded([&]() -> asicp_status {
     pn_err.clear();
-    hipStream_t hs = static_cast<hipStream_t>(stream);
-    if (!std::isfinite(retract)) return pn_fail(ASICP_E_INVALID, "retract must be finite");
-    Net n;
-    int mc = 0;
-    asicp_status st = pn_setup(n, params, n_pre, n_seed, n_obj, off, x, y, z, workspace, ws_bytes, hs, &mc);
+    return pn_forward_call(params, n_pre, n_seed, n_obj, off, x, y, z, retract, seeds, raw, workspace, ws_bytes,
+                           false, static_cast<hipStream_t>(stream));
+  });
+}
+
+asicp_status asicp_pn_forward_noalloc(const float* params, int32_t n_pre, int32_t n_seed, int32_t n_obj,
+                                      const int32_t* off, const float* x, const float* y, const float* z,
+                                      float retract, float* seeds, float* raw, void* stream) {
+  return guarded([&]() -> asicp_status {
+    pn_err.clear();
+    asicp_status st = pn_check(n_obj, n_pre, n_seed);
     if (st != ASICP_OK) return st;
-    pn_forward(n, mc, seeds, retract, hs);
-    if ((st = pn_launched("proposal forward")) != ASICP_OK) return st;
-    if (raw && hipMemcpyAsync(raw, n.out, 4 * (size_t)n_obj * n.P.O, hipMemcpyDeviceToDevice, hs) != hipSuccess)
-      return pn_fail(ASICP_E_HIP, "copying the raw outputs failed");
-    return ASICP_OK;
+    if (n_obj > kNoAllocObjects)
+      return pn_fail(ASICP_E_INVALID, "asicp_pn_forward_noalloc takes at most 64 objects per call");
+    const size_t need = pn_layout(n_obj, n_pre, n_seed).fwd_total;
+    if (need > kNoAllocBytes)
+      return pn_fail(ASICP_E_INVALID, "forward pass needs more than the 1 MiB device scratch");
+    void* ws = nullptr;
+    if ((st = scratch_for_current_device(&ws)) != ASICP_OK) return st;
+    return pn_forward_call(params, n_pre, n_seed, n_obj, off, x, y, z, retract, seeds, raw, ws, kNoAllocBytes,
+                           true, static_cast<hipStream_t>(stream));
   });
 }
 
