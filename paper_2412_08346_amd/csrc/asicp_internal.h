@@ -81,7 +81,8 @@ struct Dev {
   // clouds in Morton order (index = prep_tg_begin*64 + k): MFMA-ready float4
   // (A-operand order), plain float4 (x, y, z, 0), original index (-1 for
   // padding), and one bounding box per pruning chunk of kChunkTG tile groups
-  // (lo xyz, -, hi xyz, -)
+  // (lo xyz, -, hi xyz, -).  Object and collision clouds are stored relative
+  // to their object's centroid, contact clouds in the gripper frame.
   float4* obj_prep;
   float4* pre_prep;
   float4* obj_pts;
@@ -97,8 +98,8 @@ struct Dev {
   unsigned long long* wave_pairs;  // [total_waves] distances evaluated per forward wave,
                                    //   summed over launches (ASICP_FLAG_TIMING only, else NULL)
   int32_t prune;                 // skip object chunks that cannot hold a nearest neighbour
-  float* obj_com;   // [n_obj][4]
-  float* pre_const; // [n_pre][8]: tcp xyz, rho2, a_t, a_w, -, -
+  float* obj_com;   // [n_obj][4]: centroid xyz, largest |r - centroid|^2
+  float* pre_const; // [n_pre][8]: tcp xyz, rho2, a_t, a_w, largest |s|^2, -
   // state
   float* theta;     // [7][Ktot]
   float* cost;

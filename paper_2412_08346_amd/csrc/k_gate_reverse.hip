@@ -127,7 +127,7 @@ __device__ __forceinline__ bool box_may_collide(const PreInfo& pi, const float* 
 // Morton-sorted contact cloud, skipping contact chunks that cannot hold a
 // nearest point (same exact result as scanning them all).
 template <int Q>
-__device__ __forceinline__ void rev_scan(const Dev& d, const PreInfo& pi, const float* bq, int* idx) {
+__device__ __forceinline__ void rev_scan(const Dev& d, const PreInfo& pi, int gi_pre, const float* bq, int* idx) {
   const int lane = threadIdx.x & 63;
   float snorm[Q];
   int vq[Q];
@@ -141,8 +141,8 @@ __device__ __forceinline__ void rev_scan(const Dev& d, const PreInfo& pi, const 
     vq[q] = 16;
   }
   nn_scan_pruned<Q, false, false>(d.pre_prep + (size_t)pi.prep_tg_begin * 64, pi.ntg, pi.n,
-                    d.pre_box + (size_t)pi.prep_tg_begin / kChunkTG * 8, bq, snorm, nullptr, vq, idx,
-                    d.flags + 1);
+                                  d.pre_box + (size_t)pi.prep_tg_begin / kChunkTG * 8, bq, snorm, nullptr, vq,
+                                  d.pre_const[8 * gi_pre + 6], idx, d.flags + 1);
 }
 
 template <int MAP>
@@ -170,9 +170,17 @@ __global__ __launch_bounds__(256) void k_gate_reverse(Dev d) {
   const int i = lo * d.K + pj;
   float* out = d.col_part + ((size_t)i * d.max_gate_chunks + cc) * kPartStride;
 
+  // the pose relative to the object's centroid, like the stored collision
+  // cloud: c' = R^T ((c - com) - (t - com))
   float t[3], qv[4], R[9];
   load_pose(d.theta, d.Ktot, i, t, qv);
   quat_to_rot(qv[0], qv[1], qv[2], qv[3], R);
+  {
+    const float* com = d.obj_com + 4 * gi.obj;
+    t[0] -= com[0];
+    t[1] -= com[1];
+    t[2] -= com[2];
+  }
 
   float* pout = d.pen_part + ((size_t)i * d.max_gate_chunks + cc) * kPartStride;
   // the box of this workgroup's 2048 points (spatially compact: the cloud is
@@ -310,8 +318,8 @@ __global__ __launch_bounds__(256) void k_gate_reverse(Dev d) {
     int idx[kRevQ];
 #pragma unroll
     for (int q = 0; q < kRevQ; ++q) idx[q] = 0;
-    if (kRevQ == 1 || qn == 1) rev_scan<1>(d, pi, bq, idx);
-    else rev_scan<kRevQ>(d, pi, bq, idx);
+    if (kRevQ == 1 || qn == 1) rev_scan<1>(d, pi, gi.pre, bq, idx);
+    else rev_scan<kRevQ>(d, pi, gi.pre, bq, idx);
     int my_idx = idx[0];
 #pragma unroll
     for (int q = 1; q < kRevQ; ++q)

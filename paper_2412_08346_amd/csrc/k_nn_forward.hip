@@ -6,8 +6,10 @@
 // Morton-sorted contact cloud, so spatially close), matched against the object
 // cloud of its group with the MFMA core.  By default object chunks that
 // provably cannot hold any of the wave's nearest neighbours are skipped.
-// Partial sums per wavefront: [sum |e|^2, sum e (3), sum (R s) x e (3),
-// points], e = s' - r_nn.
+// Partial sums per wavefront: [sum |e|^2, sum e (3), sum s' x e (3),
+// points], e = s' - r_nn, s' relative to the object's centroid (the
+// finaliser turns the moment into sum (R s) x e = sum s' x e - (t - CoM) x
+// sum e, so no pose value stays live through the scan).
 #include "nn_core.h"
 
 namespace asicp {
@@ -50,9 +52,15 @@ __device__ __forceinline__ void nn_forward_body(const Dev& d) {
   const int pj = local / pi.waves, chunk = local - pj * pi.waves;
   const int i = lo * d.K + pj;
 
+  // the pose relative to the object's centroid: the object cloud is stored
+  // relative to it, so every value below is centroid-relative
   float t[3], qv[4], R[9];
   load_pose(d.theta, d.Ktot, i, t, qv);
   quat_to_rot(qv[0], qv[1], qv[2], qv[3], R);
+  const float* com = d.obj_com + 4 * gi.obj;
+  t[0] -= com[0];
+  t[1] -= com[1];
+  t[2] -= com[2];
 
   constexpr int Q = kNnQ, QPW = kQueriesPerWave;
   const float4* spts = d.pre_pts + (size_t)pi.prep_tg_begin * 64;  // Morton-sorted contact cloud
@@ -79,7 +87,7 @@ __device__ __forceinline__ void nn_forward_body(const Dev& d) {
 #pragma unroll
     for (int q = 0; q < Q; ++q) vq[q] = max(0, min(16, pi.n - (chunk * QPW + q * 16)));
     pairs = nn_scan_pruned<Q, true, FINE>(prep, oi.ntg, oi.m, d.obj_box + (size_t)oi.prep_tg_begin / kChunkTG * 8,
-                                    bq, nullptr, qc, vq, idx, d.flags + 1);
+                                          bq, nullptr, qc, vq, com[3], idx, d.flags + 1);
   } else {
     nn_scan<Q>(prep, oi.ntg, bq, qc, idx, d.flags + 1);
     pairs = (long long)oi.m * min(QPW, pi.n - chunk * QPW);
@@ -106,15 +114,14 @@ __device__ __forceinline__ void nn_forward_body(const Dev& d) {
         py = qc[3 * q + 1];
         pz = qc[3 * q + 2];
       }
-    const float ux = px - t[0], uy = py - t[1], uz = pz - t[2];  // R s
     const float4 r = d.obj_pts[(size_t)oi.prep_tg_begin * 64 + my];
     ex = px - r.x;
     ey = py - r.y;
     ez = pz - r.z;
     e2 = ex * ex + ey * ey + ez * ez;
-    mx = uy * ez - uz * ey;
-    my_ = uz * ex - ux * ez;
-    mz = ux * ey - uy * ex;
+    mx = py * ez - pz * ey;
+    my_ = pz * ex - px * ez;
+    mz = px * ey - py * ex;
     cnt = 1.f;
     if (d.dbg_nn) {
       const int n_orig = d.pre_perm[(size_t)pi.prep_tg_begin * 64 + n];

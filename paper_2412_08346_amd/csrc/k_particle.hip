@@ -75,7 +75,14 @@ __global__ __launch_bounds__(256) void k_finalize(Dev d, int k, int final_eval) 
   const float uTx = R[0] * pc[0] + R[1] * pc[1] + R[2] * pc[2];
   const float uTy = R[3] * pc[0] + R[4] * pc[1] + R[5] * pc[2];
   const float uTz = R[6] * pc[0] + R[7] * pc[1] + R[8] * pc[2];
-  const float eTx = uTx + t[0] - com[0], eTy = uTy + t[1] - com[1], eTz = uTz + t[2] - com[2];
+  // the pose relative to the centroid: t and CoM may both be far from the
+  // origin, their difference is small
+  const float tcx = t[0] - com[0], tcy = t[1] - com[1], tcz = t[2] - com[2];
+  const float eTx = uTx + tcx, eTy = uTy + tcy, eTz = uTz + tcz;
+  // contact moment: the records hold sum s' x e with s' = R s + (t - CoM)
+  s[4] -= tcy * s[3] - tcz * s[2];
+  s[5] -= tcz * s[1] - tcx * s[3];
+  s[6] -= tcx * s[2] - tcy * s[1];
   const float lam = d.lambda;
   const float cost_ct = 0.5f * (s[0] * invN + lam * (eTx * eTx + eTy * eTy + eTz * eTz));
   float cost_pen = 0.f;

@@ -22,9 +22,26 @@ __device__ void block_sum4(double v[4], double (*sh)[4]) {
   __syncthreads();
 }
 
-// one workgroup per object
+__device__ float block_max(float v, float* sh) {
+  const int tid = threadIdx.x;
+  sh[tid] = v;
+  __syncthreads();
+  for (int off = 128; off >= 1; off >>= 1) {
+    if (tid < off) sh[tid] = fmaxf(sh[tid], sh[tid + off]);
+    __syncthreads();
+  }
+  v = sh[0];
+  __syncthreads();
+  return v;
+}
+
+// One workgroup per object: the centroid (the CoM of Sec. IV-B), and the
+// largest squared distance of a point from it.  Every kernel works on the
+// object's clouds and the poses relative to this centroid, so FP32 rounding
+// scales with the object's size rather than its distance from the origin.
 __global__ __launch_bounds__(256) void k_setup_obj(Dev d) {
   __shared__ double sh[256][4];
+  __shared__ float shm[256];
   const int o = blockIdx.x, tid = threadIdx.x;
   const ObjInfo oi = d.objs[o];
   double v[4] = {0, 0, 0, 0};
@@ -34,24 +51,38 @@ __global__ __launch_bounds__(256) void k_setup_obj(Dev d) {
     v[2] += d.rz[oi.r_begin + m];
   }
   block_sum4(v, sh);
+  float com[3];
+  for (int a = 0; a < 3; ++a) com[a] = (float)(v[a] / (double)oi.m);
+  float r2 = 0.f;
+  for (int m = tid; m < oi.m; m += 256) {
+    const float x = d.rx[oi.r_begin + m] - com[0], y = d.ry[oi.r_begin + m] - com[1],
+                z = d.rz[oi.r_begin + m] - com[2];
+    r2 = fmaxf(r2, __builtin_fmaf(z, z, __builtin_fmaf(y, y, x * x)));
+  }
+  r2 = block_max(r2, shm);
   if (tid == 0) {
-    for (int a = 0; a < 3; ++a) d.obj_com[4 * o + a] = (float)(v[a] / (double)oi.m);
-    d.obj_com[4 * o + 3] = 0.f;
+    for (int a = 0; a < 3; ++a) d.obj_com[4 * o + a] = com[a];
+    d.obj_com[4 * o + 3] = r2;
   }
 }
 
 // one workgroup per preshape
 __global__ __launch_bounds__(256) void k_setup_pre(Dev d) {
   __shared__ double sh[256][4];
+  __shared__ float shm[256];
   const int p = blockIdx.x, tid = threadIdx.x;
   const PreInfo pi = d.pres[p];
   double v[4] = {0, 0, 0, 0};
+  float s2 = 0.f;  // largest |s|^2 (gripper frame)
   for (int n = tid; n < pi.n; n += 256) {
-    const double x = d.sx[pi.s_begin + n], y = d.sy[pi.s_begin + n], z = d.sz[pi.s_begin + n];
+    const float fx = d.sx[pi.s_begin + n], fy = d.sy[pi.s_begin + n], fz = d.sz[pi.s_begin + n];
+    const double x = fx, y = fy, z = fz;
     v[0] += x; v[1] += y; v[2] += z;
     v[3] += x * x + y * y + z * z;
+    s2 = fmaxf(s2, __builtin_fmaf(fz, fz, __builtin_fmaf(fy, fy, fx * fx)));
   }
   block_sum4(v, sh);
+  s2 = block_max(s2, shm);
   if (tid == 0) {
     const double inv = 1.0 / (double)pi.n;
     const double tx = v[0] * inv, ty = v[1] * inv, tz = v[2] * inv, rho2 = v[3] * inv;
@@ -63,7 +94,7 @@ __global__ __launch_bounds__(256) void k_setup_pre(Dev d) {
     }
     float* pc = d.pre_const + 8 * p;
     pc[0] = (float)tx; pc[1] = (float)ty; pc[2] = (float)tz; pc[3] = (float)rho2;
-    pc[4] = (float)at; pc[5] = (float)aw; pc[6] = 0.f; pc[7] = 0.f;
+    pc[4] = (float)at; pc[5] = (float)aw; pc[6] = s2; pc[7] = 0.f;
   }
 }
 
@@ -79,7 +110,8 @@ __device__ __forceinline__ unsigned int spread10(unsigned int v) {
 
 // One workgroup (1024 threads) per cloud: blocks [0, n_obj) sort object
 // clouds, blocks [n_obj, n_obj + n_pre) contact clouds, the last n_obj blocks
-// collision clouds.  Points are ordered by the Morton code of their position
+// collision clouds (object and collision clouds relative to the object's
+// centroid).  Points are ordered by the Morton code of their position
 // in the cloud's bounding box (ties by original index: the keys are unique,
 // so the order is deterministic), then written as MFMA-ready float4, plain
 // float4, the original index, and one bounding box per pruning chunk; a
@@ -98,6 +130,14 @@ __global__ __launch_bounds__(1024) void k_sort_cloud(Dev d) {
   int32_t* perm;
   float* box = nullptr;
   size_t base;  // first output index
+  // object and collision clouds are stored relative to the object's centroid
+  // (written by k_setup_obj earlier on the stream); contact clouds stay in
+  // the gripper frame
+  float c0 = 0.f, c1 = 0.f, c2 = 0.f;
+  if (kind != 1) {
+    const float* com = d.obj_com + 4 * (kind == 0 ? blockIdx.x : blockIdx.x - d.n_obj - d.n_pre);
+    c0 = com[0]; c1 = com[1]; c2 = com[2];
+  }
   if (kind == 0) {
     const ObjInfo& oi = d.objs[blockIdx.x];
     sx = d.rx + oi.r_begin; sy = d.ry + oi.r_begin; sz = d.rz + oi.r_begin;
@@ -178,7 +218,7 @@ __global__ __launch_bounds__(1024) void k_sort_cloud(Dev d) {
   if (kind == 2) {
     for (int k = tid; k < n; k += 1024) {
       const int orig = (int)(keys[k] & 0xffffffffull);
-      pts[base + k] = make_float4(sx[orig], sy[orig], sz[orig], 0.f);
+      pts[base + k] = make_float4(sx[orig] - c0, sy[orig] - c1, sz[orig] - c2, 0.f);
       perm[base + k] = orig;
     }
     // the box of every kGateChunk consecutive sorted points (one gate
@@ -189,7 +229,7 @@ __global__ __launch_bounds__(1024) void k_sort_cloud(Dev d) {
                     -__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
       for (int k = c * kGateChunk + tid; k < min(n, (c + 1) * kGateChunk); k += 1024) {
         const int orig = (int)(keys[k] & 0xffffffffull);
-        const float x = sx[orig], y = sy[orig], z = sz[orig];
+        const float x = sx[orig] - c0, y = sy[orig] - c1, z = sz[orig] - c2;
         e[0] = fminf(e[0], x); e[1] = fminf(e[1], y); e[2] = fminf(e[2], z);
         e[3] = fmaxf(e[3], x); e[4] = fmaxf(e[4], y); e[5] = fmaxf(e[5], z);
       }
@@ -212,7 +252,7 @@ __global__ __launch_bounds__(1024) void k_sort_cloud(Dev d) {
     const size_t g = base + k;
     if (k < n) {
       const int orig = (int)(keys[k] & 0xffffffffull);
-      const float x = sx[orig], y = sy[orig], z = sz[orig];
+      const float x = sx[orig] - c0, y = sy[orig] - c1, z = sz[orig] - c2;
       prep_store(pf, k, -2.f * x, -2.f * y, -2.f * z, __builtin_fmaf(z, z, __builtin_fmaf(y, y, x * x)));
       pts[g] = make_float4(x, y, z, 0.f);
       perm[g] = orig;

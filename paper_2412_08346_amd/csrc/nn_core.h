@@ -274,6 +274,24 @@ struct LbPack {
   __device__ __forceinline__ float get(int q) const { return (float)h[q >> 1][q & 1]; }
 };
 
+// Chunk boxes as a raw buffer (like cloud_rsrc): box c is read with the
+// lane's 32-bit byte offset c * 32, no 64-bit address per lane; boxes beyond
+// the buffer read as zeros.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t box_rsrc(const float* __restrict__ box, int nch) {
+  const unsigned long long a = reinterpret_cast<unsigned long long>(box);
+  const unsigned long long lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)a);
+  const unsigned long long hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(a >> 32));
+  void* base = reinterpret_cast<void*>((hi << 32) | lo);
+  return __builtin_amdgcn_make_buffer_rsrc(base, (short)0, __builtin_amdgcn_readfirstlane(nch) * 32, 0x00020000);
+}
+
+__device__ __forceinline__ void load_box(__amdgpu_buffer_rsrc_t r, int c, float bx[8]) {
+  const auto a = __builtin_amdgcn_raw_buffer_load_b128(r, (unsigned)c * 32u, 0, 0);
+  const auto b = __builtin_amdgcn_raw_buffer_load_b128(r, (unsigned)c * 32u + 16u, 0, 0);
+  __builtin_memcpy(bx, &a, 16);
+  __builtin_memcpy(bx + 4, &b, 16);
+}
+
 // Squared distance from the box [lo, hi] to the box [qlo, qhi] (0 if they
 // overlap): a lower bound of |s - r|^2 for any query s in the query box and
 // any point r in the chunk box.
@@ -317,15 +335,18 @@ __device__ __forceinline__ float point_box2(const float* p, const float* bx) {
 // snorm[q] = |s|^2 of the lane's query in block q (turns the reduced value
 // |r|^2 - 2 r.s into a squared distance; with BATCH_RESCAN it is computed
 // from qc instead and snorm may be null); box = the cloud's chunk boxes;
-// m = real points of the cloud; vq[q] = real queries of block q.  Returns the
-// number of (query, point) distances evaluated (wave-uniform).  Every bound
-// carries a slack of 1e-4 relative plus 1e-7 (squared length units) for the
-// FP32 rounding of the distances it is compared with.
+// m = real points of the cloud; vq[q] = real queries of block q; r2max = the
+// largest |r|^2 of the cloud.  Returns the number of (query, point) distances
+// evaluated (wave-uniform).  Every bound carries a slack for the FP32
+// rounding of the distances it is compared with: 1e-4 relative, plus
+// 5e-7 (r2max + |s|^2) (the rounding of the fused chain |r|^2 - 2 r.s is
+// at most a few units of 2^-24 times |r|^2 + 2 |r| |s| <= 2 (|r|^2 + |s|^2)),
+// plus 1e-7 (squared length units).
 template <int Q, bool BATCH_RESCAN, bool FINE>
 __device__ __forceinline__ long long nn_scan_pruned(const float4* __restrict__ prep, int ntg, int m,
                                                     const float* __restrict__ box, const float* bq,
                                                     const float* snorm, const float* qc, const int* vq,
-                                                    int* idx, int32_t* miss) {
+                                                    float r2max, int* idx, int32_t* miss) {
   const int lane = lane_id();
   float b[Q], best[Q];
   int bch[Q];
@@ -361,7 +382,7 @@ __device__ __forceinline__ long long nn_scan_pruned(const float4* __restrict__ p
         __asm__("" : "+v"(x), "+v"(y), "+v"(z));
         sn = __builtin_fmaf(z, z, __builtin_fmaf(y, y, x * x));
       }
-      qb[q] = (rows_min(best[q]) + sn) * 1.0001f + 1e-7f;
+      qb[q] = __builtin_fmaf(rows_min(best[q]) + sn, 1.0001f, __builtin_fmaf(5e-7f, r2max + sn, 1e-7f));
       // every row holds the same 16 queries, so the row maximum is uniform
       ub[q] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(row_max(qb[q]))));
     }
@@ -383,10 +404,13 @@ __device__ __forceinline__ long long nn_scan_pruned(const float4* __restrict__ p
   }
   // (smallest gap, then lowest index; gaps are non-negative, so their bit
   // patterns order like their values; a lane without a chunk never wins)
+  const __amdgpu_buffer_rsrc_t rb = box_rsrc(box, nch);
   unsigned gbest = 0xffffffffu;
   int cbest = 0x7fffffff;
   for (int c = lane; c < nch; c += 64) {
-    const unsigned g = __float_as_uint(box_gap2(box + (size_t)c * 8, ulo, uhi));
+    float cb[8];
+    load_box(rb, c, cb);
+    const unsigned g = __float_as_uint(box_gap2(cb, ulo, uhi));
     if (c == lane || g < gbest) {
       gbest = g;
       cbest = c;
@@ -423,9 +447,11 @@ __device__ __forceinline__ long long nn_scan_pruned(const float4* __restrict__ p
     // mq[q]: the same as a wave-uniform mask over the 64 chunks of the block
     bool in[Q];
     unsigned long long mq[Q];
+    float cb[8];
+    load_box(rb, c, cb);  // zeros beyond the last chunk (not used there)
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      const float g = c < nch ? box_gap2(box + (size_t)c * 8, qlo[q], qhi[q]) : __builtin_inff();
+      const float g = c < nch ? box_gap2(cb, qlo[q], qhi[q]) : __builtin_inff();
       lbp.set(q, g);
       in[q] = c < nch && c != c0 && g <= ub[q];
       mq[q] = __ballot(in[q]);
