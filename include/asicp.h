@@ -196,16 +196,29 @@ asicp_status asicp_step(asicp_ctx ctx, int32_t n_iters, void* stream);
  * the selection of the returned grasp per object. */
 asicp_status asicp_solve(asicp_ctx ctx, void* stream);
 
+/* Gradient forms of asicp_cost_grad. */
+#define ASICP_GRAD_TANGENT 0 /* [6][Ktot]: d/dt, then d/dw for the world rotation vector w  */
+                             /*   about the gripper origin (q <- Exp(w) q), eqs. (16)-(17)  */
+#define ASICP_GRAD_POSE 1    /* [7][Ktot]: d/dt, then d/dq with the cost a function of the  */
+                             /*   unit quaternion q / |q|: 2 M(q) g_w, M(q) = [-q_v^T ;     */
+                             /*   q_w I - [q_v]x] (the tangent of unit quaternions, eq. 17) */
+
 /* Per-particle cost and its gradient at arbitrary poses: the adjoint of the
- * iteration's cost with respect to each 6-DoF pose.  `theta` (device
- * [7][Ktot]) replaces the context's poses; the cost C = 1/2 (L_ct + lambda
- * L_com) of eqs. (13)-(15), plus the penetration term when w_pen > 0, and its
- * gradient with respect to (translation, world rotation vector about the
- * gripper origin), with nearest-neighbour pairs and gate decisions held at
- * `theta`, go to cost_out (device [Ktot]) and grad_out (device [6][Ktot]);
- * either may be NULL.  Enqueued on `stream`. */
+ * iteration's cost with respect to each pose.  `theta` (device [7][Ktot])
+ * replaces the context's poses; the cost C = 1/2 (L_ct + lambda L_com) of
+ * eqs. (13)-(15), plus the penetration term when w_pen > 0, and its gradient
+ * in the form `grad_form` (ASICP_GRAD_*), with nearest-neighbour pairs and
+ * gate decisions held at `theta`, go to cost_out (device [Ktot]) and grad_out
+ * (device, [6][Ktot] or [7][Ktot]); either may be NULL.  Enqueued on
+ * `stream`. */
 asicp_status asicp_cost_grad(asicp_ctx ctx, const float* theta, float* cost_out, float* grad_out,
-                             void* stream);
+                             int32_t grad_form, void* stream);
+
+/* Vector-Jacobian product of the per-particle costs for reverse-mode
+ * differentiation: dtheta[a][i] = gout[i] * grad[a][i] for a < 7 (device
+ * arrays; grad from asicp_cost_grad with ASICP_GRAD_POSE, gout [Ktot], dtheta
+ * [7][Ktot], which may alias grad).  ktot >= 0.  Enqueued on `stream`. */
+asicp_status asicp_pose_vjp(const float* grad, const float* gout, float* dtheta, int32_t ktot, void* stream);
 
 /* Run the whole solve again as one HIP graph on `stream`: set-up from the
  * borrowed inputs (which the caller may have rewritten in place: a new object

@@ -26,7 +26,9 @@ EXPORTS = ("asicp_workspace_bytes", "asicp_create", "asicp_step", "asicp_solve",
            "asicp_cost_grad", "asicp_result", "asicp_kernel_time", "asicp_get_launch",
            "asicp_set_launch", "asicp_autotune", "asicp_destroy", "asicp_last_error",
            "asicp_pn_param_count", "asicp_pn_workspace_bytes", "asicp_pn_forward",
-           "asicp_pn_loss_grad", "asicp_pn_adam", "asicp_pn_last_error", "asicp_pn_forward_noalloc")
+           "asicp_pn_loss_grad", "asicp_pn_adam", "asicp_pn_last_error", "asicp_pn_forward_noalloc",
+           "asicp_pose_vjp")
+ASICP_GRAD_TANGENT, ASICP_GRAD_POSE = 0, 1
 
 
 class AsicpError(RuntimeError):
@@ -92,8 +94,10 @@ def load():
         L.asicp_step.restype = i32
         L.asicp_solve.argtypes = [vp, vp]
         L.asicp_solve.restype = i32
-        L.asicp_cost_grad.argtypes = [vp, vp, vp, vp, vp]
+        L.asicp_cost_grad.argtypes = [vp, vp, vp, vp, i32, vp]
         L.asicp_cost_grad.restype = i32
+        L.asicp_pose_vjp.argtypes = [vp, vp, vp, i32, vp]
+        L.asicp_pose_vjp.restype = i32
         L.asicp_replay.argtypes = [vp, vp]
         L.asicp_replay.restype = i32
         L.asicp_result.argtypes = [vp, vp, vp]
@@ -160,9 +164,14 @@ def asicp_solve(ctx, stream: int):
     return _check(load().asicp_solve(ctx, C.c_void_p(stream)))
 
 
-def asicp_cost_grad(ctx, theta_ptr: int, cost_ptr, grad_ptr, stream: int):
+def asicp_cost_grad(ctx, theta_ptr: int, cost_ptr, grad_ptr, stream: int, grad_form: int = ASICP_GRAD_TANGENT):
     return _check(load().asicp_cost_grad(ctx, C.c_void_p(theta_ptr), C.c_void_p(cost_ptr),
-                                         C.c_void_p(grad_ptr), C.c_void_p(stream)))
+                                         C.c_void_p(grad_ptr), int(grad_form), C.c_void_p(stream)))
+
+
+def asicp_pose_vjp(grad_ptr: int, gout_ptr: int, dtheta_ptr: int, ktot: int, stream: int):
+    return _check(load().asicp_pose_vjp(C.c_void_p(grad_ptr), C.c_void_p(gout_ptr), C.c_void_p(dtheta_ptr),
+                                        int(ktot), C.c_void_p(stream)))
 
 
 def asicp_replay(ctx, stream: int):
@@ -341,14 +350,17 @@ class Solver:
     def solve(self, stream=None):
         asicp_solve(self.ctx, self._stream(stream))
 
-    def cost_grad(self, theta, stream=None):
-        """Cost and 6-D gradient per particle at poses `theta` (7, Ktot) on the
-        device (the adjoint of the cost; pairs and gates held at theta)."""
+    def cost_grad(self, theta, stream=None, pose: bool = False):
+        """Cost and gradient per particle at poses `theta` (7, Ktot) on the
+        device (the adjoint of the cost; pairs and gates held at theta): the
+        6-D tangent gradient (6, Ktot), or with `pose` the gradient with
+        respect to the 7 pose numbers (7, Ktot)."""
         torch = self.torch
         th = torch.as_tensor(theta, dtype=torch.float32, device=self.dev).contiguous()
         cost = torch.empty(self.k_tot, device=self.dev)
-        grad = torch.empty((6, self.k_tot), device=self.dev)
-        asicp_cost_grad(self.ctx, th.data_ptr(), cost.data_ptr(), grad.data_ptr(), self._stream(stream))
+        grad = torch.empty((7 if pose else 6, self.k_tot), device=self.dev)
+        asicp_cost_grad(self.ctx, th.data_ptr(), cost.data_ptr(), grad.data_ptr(), self._stream(stream),
+                        ASICP_GRAD_POSE if pose else ASICP_GRAD_TANGENT)
         return cost, grad
 
     def replay(self, stream=None):
@@ -419,31 +431,25 @@ def _pose_autograd():
         """cost_i(theta_i) of the grasp iteration with a hand-written backward.
 
         Input: poses (7, Ktot) on the device (translation, unit quaternion).
-        Forward runs the library's kernels (asicp_cost_grad); backward maps
-        the 6-D gradient (translation, world rotation vector) to the pose
-        parameters: d/dt = g_t, d/dq = 2 M(q) g_w with
-        M(q) = [-q_v^T ; q_w I - [q_v]x] (the tangent of unit quaternions)."""
+        Forward runs the library's kernels (asicp_cost_grad, pose form: the
+        gradient with respect to the 7 pose numbers); backward is the
+        library's vector-Jacobian product (asicp_pose_vjp)."""
 
         @staticmethod
         def forward(ctx, theta, solver):
-            cost, grad = solver.cost_grad(theta.detach())
-            ctx.save_for_backward(theta.detach(), grad)
+            cost, grad = solver.cost_grad(theta.detach(), pose=True)
+            ctx.save_for_backward(grad)
+            ctx.solver = solver
             return cost
 
         @staticmethod
         def backward(ctx, gout):
-            theta, grad = ctx.saved_tensors
-            q = theta[3:]
-            gw = grad[3:]
-            w, x, y, z = q[0], q[1], q[2], q[3]
-            # 2 M(q) g_w, M = [-q_v^T ; w I - [q_v]x]
-            dq = torch.stack([
-                -(x * gw[0] + y * gw[1] + z * gw[2]),
-                w * gw[0] + z * gw[1] - y * gw[2],
-                -z * gw[0] + w * gw[1] + x * gw[2],
-                y * gw[0] - x * gw[1] + w * gw[2],
-            ]) * 2.0
-            dtheta = torch.cat([grad[:3], dq], 0) * gout[None, :]
+            (grad,) = ctx.saved_tensors
+            solver = ctx.solver
+            gout = gout.to(torch.float32).contiguous()
+            dtheta = torch.empty_like(grad)
+            asicp_pose_vjp(grad.data_ptr(), gout.data_ptr(), dtheta.data_ptr(), grad.shape[1],
+                           solver._stream(None))
             return dtheta, None
 
     return PoseCost

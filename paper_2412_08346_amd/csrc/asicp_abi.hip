@@ -270,12 +270,35 @@ __global__ void k_set_theta(float* dst, const float* src, int n) {
   if (i < n) dst[i] = src[i];
 }
 
-__global__ void k_get_cost_grad(const float* cost, const float* grad_ct, float* cost_out, float* grad_out, int K) {
+// Cost and gradient of asicp_cost_grad.  ASICP_GRAD_POSE maps the rotation
+// part g_w (world rotation vector) to the unit quaternion's parameters by
+// eq. (17)'s tangent map: d/dq = 2 M(q) g_w, M(q) = [-q_v^T ; q_w I - [q_v]x].
+__global__ void k_get_cost_grad(const float* theta, const float* cost, const float* grad_ct, float* cost_out,
+                                float* grad_out, int form, int K) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= K) return;
   if (cost_out) cost_out[i] = cost[i];
-  if (grad_out)
-    for (int a = 0; a < 6; ++a) grad_out[a * K + i] = grad_ct[a * K + i];
+  if (!grad_out) return;
+  for (int a = 0; a < 3; ++a) grad_out[a * K + i] = grad_ct[a * K + i];
+  const float gx = grad_ct[3 * K + i], gy = grad_ct[4 * K + i], gz = grad_ct[5 * K + i];
+  if (form == ASICP_GRAD_TANGENT) {
+    grad_out[3 * K + i] = gx;
+    grad_out[4 * K + i] = gy;
+    grad_out[5 * K + i] = gz;
+    return;
+  }
+  const float w = theta[3 * K + i], x = theta[4 * K + i], y = theta[5 * K + i], z = theta[6 * K + i];
+  grad_out[3 * K + i] = -2.f * (x * gx + y * gy + z * gz);
+  grad_out[4 * K + i] = 2.f * (w * gx + z * gy - y * gz);
+  grad_out[5 * K + i] = 2.f * (-z * gx + w * gy + x * gz);
+  grad_out[6 * K + i] = 2.f * (y * gx - x * gy + w * gz);
+}
+
+__global__ void k_pose_vjp(const float* grad, const float* gout, float* dtheta, int K) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= K) return;
+  const float s = gout[i];
+  for (int a = 0; a < 7; ++a) dtheta[a * K + i] = s * grad[a * K + i];
 }
 
 struct asicp_ctx_s {
@@ -639,10 +662,13 @@ static asicp_status enqueue_rest(asicp_ctx c, int k0, hipStream_t hs) {
   return check_launch("select");
 }
 
-asicp_status asicp_cost_grad(asicp_ctx c, const float* theta, float* cost_out, float* grad_out, void* stream) {
+asicp_status asicp_cost_grad(asicp_ctx c, const float* theta, float* cost_out, float* grad_out, int32_t grad_form,
+                             void* stream) {
   return guarded([&]() -> asicp_status {
     g_err.clear();
     if (!c || !theta) return fail(ASICP_E_INVALID, "ctx and theta must not be NULL");
+    if (grad_form != ASICP_GRAD_TANGENT && grad_form != ASICP_GRAD_POSE)
+      return fail(ASICP_E_INVALID, "grad_form must be ASICP_GRAD_TANGENT or ASICP_GRAD_POSE");
     hipStream_t hs = static_cast<hipStream_t>(stream);
     const int K = c->d.Ktot;
     (void)hipGetLastError();
@@ -650,9 +676,22 @@ asicp_status asicp_cost_grad(asicp_ctx c, const float* theta, float* cost_out, f
     asicp_status st = check_launch("set theta");
     if (st != ASICP_OK) return st;
     if ((st = evaluate(c, c->cfg.k_max, 1, false, hs)) != ASICP_OK) return st;
-    hipLaunchKernelGGL(k_get_cost_grad, dim3((K + 255) / 256), dim3(256), 0, hs, c->d.cost, c->d.grad_ct,
-                       cost_out, grad_out, K);
+    hipLaunchKernelGGL(k_get_cost_grad, dim3((K + 255) / 256), dim3(256), 0, hs, c->d.theta, c->d.cost,
+                       c->d.grad_ct, cost_out, grad_out, (int)grad_form, K);
     return check_launch("cost/grad copy");
+  });
+}
+
+asicp_status asicp_pose_vjp(const float* grad, const float* gout, float* dtheta, int32_t ktot, void* stream) {
+  return guarded([&]() -> asicp_status {
+    g_err.clear();
+    if (ktot < 0) return fail(ASICP_E_INVALID, "ktot must be >= 0");
+    if (ktot == 0) return ASICP_OK;
+    if (!grad || !gout || !dtheta) return fail(ASICP_E_INVALID, "grad, gout and dtheta must not be NULL");
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_pose_vjp, dim3((unsigned)((ktot + 255) / 256)), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), grad, gout, dtheta, (int)ktot);
+    return check_launch("pose vjp");
   });
 }
 
