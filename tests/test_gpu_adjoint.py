@@ -41,16 +41,10 @@ def pen_scales(pb, theta, ev, w_pen):
     return st, sw
 
 
-def check(pb, st, theta):
-    A, torch = _gpu()
-    sol = A.Solver(pb, st, debug=True, theta0=theta)
-    cost, grad = sol.cost_grad(torch.as_tensor(theta))
-    # the same evaluation's NN and gate records, for the tie bounds
-    sol2 = A.Solver(pb, st, debug=True, theta0=theta)
-    sol2.step(1)
-    rec = sol2.result()
-    sol2.close()
-    cost, grad = cost.cpu().numpy(), grad.cpu().numpy()
+def check_records(pb, st, theta, cost, grad, rec):
+    """The GPU's cost and 6-D gradient at `theta`, with the NN and gate
+    records of the same evaluation, against the oracle: ties and gate
+    decisions within 1e-6 m of phi = 0 excused exactly."""
     o = oracle.Oracle(pb, st)
     ev = o.evaluate(theta)
     setup = o.setup()
@@ -61,12 +55,24 @@ def check(pb, st, theta):
     b_t, b_w = pu.tie_bounds(pb, theta, rec["nn_idx"], ev["nn_idx"])
     ok = np.ones(pb.k_tot, bool)
     if excused:  # a gate decision within 1e-6 m of phi = 0 changes the penetration sum slightly
-        gg = (rec["rev_idx"] >= 0)
-        ok = np.array([np.array_equal(gg[i], ev["gate"][i] > 0) for i in range(pb.k_tot)])
+        mcs = np.diff(pb.c_off)
+        obj = (np.arange(pb.k_tot) // pb.K) // pb.n_pre
+        ok = np.array([np.array_equal(rec["rev_idx"][i, :mcs[obj[i]]] >= 0, ev["gate"][i, :mcs[obj[i]]] > 0)
+                       for i in range(pb.k_tot)])
     pu.close(cost[ok], ev["cost"][ok], ev["cost"][ok], what="cost")
     pu.close(grad[:3].T[ok], ev["g_ct"][ok, :3], (s_t + p_t)[ok, None], what="g_t", extra=b_t[ok, None])
-    pu.close(grad[3:].T[ok], ev["g_ct"][ok, 3:], (s_w + p_w)[ok, None], what="g_w", extra=b_w[ok, None])
+    pu.close(grad[3:6].T[ok], ev["g_ct"][ok, 3:], (s_w + p_w)[ok, None], what="g_w", extra=b_w[ok, None])
+    return ev, dict(ok=ok, s_t=s_t + p_t, s_w=s_w + p_w, b_t=b_t, b_w=b_w, excused=excused)
+
+
+def check(pb, st, theta):
+    A, torch = _gpu()
+    sol = A.Solver(pb, st, debug=True, theta0=theta)
+    cost, grad = sol.cost_grad(torch.as_tensor(theta))
+    rec = sol.result()  # the debug records of that evaluation
     sol.close()
+    cost, grad = cost.cpu().numpy(), grad.cpu().numpy()
+    ev, _ = check_records(pb, st, theta, cost, grad, rec)
     return cost, grad, ev
 
 
@@ -78,46 +84,47 @@ def test_cost_grad_matches_oracle_with_penetration():
 
 def test_cost_grad_full_size_sampled():
     """The full adjoint workload (16 objects x 4096 points, 512 particles
-    each): every particle of two objects checked against the oracle."""
+    each) evaluated in one launch with the per-point records; every particle
+    of two objects is held to the bar above (exact tie and gate excusal)
+    against the oracle run on those two objects alone."""
     A, torch = _gpu()
     pb, st = synth.workload_adjoint()
     sub_objs = [0, 7]
-    # oracle on the two objects only (same clouds, same poses)
     R_parts = [pb.R[pb.r_off[o]:pb.r_off[o + 1]] for o in sub_objs]
+    cols = np.concatenate([np.arange(o * pb.K, (o + 1) * pb.K) for o in sub_objs])
     sub = synth.Problem(R=np.concatenate(R_parts), r_off=np.cumsum([0] + [len(r) for r in R_parts]).astype(np.int32),
                         C=np.concatenate(R_parts), c_off=np.cumsum([0] + [len(r) for r in R_parts]).astype(np.int32),
                         S=pb.S, s_off=pb.s_off, grids=pb.grids,
-                        theta0=np.concatenate([pb.theta0[:, o * pb.K:(o + 1) * pb.K] for o in sub_objs], 1), K=pb.K)
-    sol = A.Solver(pb, st)
+                        theta0=np.ascontiguousarray(pb.theta0[:, cols]), K=pb.K)
+    sol = A.Solver(pb, st, debug=True)
     cost, grad = sol.cost_grad(torch.as_tensor(pb.theta0))
+    rec = sol.result()
     sol.close()
-    cost, grad = cost.cpu().numpy(), grad.cpu().numpy()
-    ev = oracle.Oracle(sub, st).evaluate(sub.theta0)
-    cols = np.concatenate([np.arange(o * pb.K, (o + 1) * pb.K) for o in sub_objs])
-    s_t, s_w = pu.scales(sub, sub.theta0, ev["nn_idx"], st.lam, oracle.Oracle(sub, st).setup())
-    p_t, p_w = pen_scales(sub, sub.theta0, ev, st.w_pen)
-    # ties or gate decisions at phi ~ 0 may shift a few particles slightly: require 99 %
-    tol_t = 1e-4 * np.maximum(np.abs(ev["g_ct"][:, :3]), (s_t + p_t)[:, None]) + 1e-7
-    tol_w = 1e-4 * np.maximum(np.abs(ev["g_ct"][:, 3:]), (s_w + p_w)[:, None]) + 1e-7
-    good = ((np.abs(grad[:3].T[cols] - ev["g_ct"][:, :3]) <= tol_t).all(1) &
-            (np.abs(grad[3:].T[cols] - ev["g_ct"][:, 3:]) <= tol_w).all(1) &
-            (np.abs(cost[cols] - ev["cost"]) <= 1e-4 * ev["cost"]))
-    assert good.mean() >= 0.99, good.mean()
+    cost, grad = cost.cpu().numpy()[cols], grad.cpu().numpy()[:, cols]
+    rec = {k: np.asarray(rec[k])[cols] for k in ("nn_idx", "rev_idx")}
+    ev, info = check_records(sub, st, sub.theta0, cost, grad, rec)
+    print(f"[adjoint] full size: {len(cols)} particles, gate decisions excused: {info['excused']}", flush=True)
 
 
 def test_autograd_function_backward():
+    """d/dtheta of sum_i w_i C_i through the torch.autograd.Function: the
+    library's pose-form gradient (d/dt, 2 M(q) g_w) scaled by w_i, against
+    the oracle's gradient mapped the same way.  |2 M(q) v|_inf <= 2 |v|_2 <=
+    2 sqrt(3) |v|_inf (M(q)^T M(q) = I for a unit q), so the rotation bound
+    of the cost_grad bar carries over with that factor."""
     A, torch = _gpu()
     pb, st = synth.workload_adjoint(n_obj=2, K=32, m=1024, n=512, grid_n=64)
-    sol = A.Solver(pb, st)
+    sol = A.Solver(pb, st, debug=True)
     theta = torch.as_tensor(pb.theta0, device="cuda").clone().requires_grad_(True)
     w = torch.linspace(0.5, 1.5, pb.k_tot, device="cuda")
     loss = (A.pose_cost(theta, sol) * w).sum()
     loss.backward()
     g = theta.grad.cpu().numpy().astype(np.float64)
+    rec = sol.result()  # the records of the evaluation the forward ran
+    cost6, grad6 = sol.cost_grad(torch.as_tensor(pb.theta0))
     sol.close()
-    ev = oracle.Oracle(pb, st).evaluate(pb.theta0)
+    ev, info = check_records(pb, st, pb.theta0, cost6.cpu().numpy(), grad6.cpu().numpy(), rec)
     wn = w.cpu().numpy().astype(np.float64)
-    # expected: w_i * (g_t, 2 M(q) g_w) from the oracle gradient
     q = pb.theta0[3:].astype(np.float64)
     exp = np.zeros((7, pb.k_tot))
     for i in range(pb.k_tot):
@@ -126,8 +133,12 @@ def test_autograd_function_backward():
         M = np.vstack([-qv[None, :], qw * np.eye(3) - vx])
         exp[:3, i] = wn[i] * ev["g_ct"][i, :3]
         exp[3:, i] = wn[i] * 2 * M @ ev["g_ct"][i, 3:]
-    scale = np.abs(exp).max(0) + 1e-9
-    rel = np.abs(g - exp).max(0) / scale
-    assert np.median(rel) < 1e-3 and (rel < 5e-2).mean() >= 0.95
+    ok = info["ok"]
+    tol_t = wn * (1e-4 * np.maximum(np.abs(ev["g_ct"][:, :3]).max(1), info["s_t"]) + info["b_t"])
+    tol_q = wn * 2 * np.sqrt(3) * (1e-4 * np.maximum(np.abs(ev["g_ct"][:, 3:]).max(1), info["s_w"]) + info["b_w"])
+    err_t = np.abs(g[:3] - exp[:3]).max(0)
+    err_q = np.abs(g[3:] - exp[3:]).max(0)
+    assert (err_t[ok] <= tol_t[ok]).all(), f"d/dt: worst {(err_t / tol_t)[ok].max():.3g}x tol"
+    assert (err_q[ok] <= tol_q[ok]).all(), f"d/dq: worst {(err_q / tol_q)[ok].max():.3g}x tol"
     # the rotation part of d/dq is tangent to the unit sphere
     assert np.abs((g[3:] * q).sum(0)).max() <= 1e-5 * np.abs(g[3:]).max()
