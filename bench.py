@@ -61,6 +61,123 @@ def cpu_baseline(pb, st, seconds=10.0):
                       f"(FP64, {dt:.1f} s)"}
 
 
+def nn_roofline(ms, n, pairs):
+    """Achieved FLOP/s of the forward-NN launches from their HIP-event time
+    and the distances they evaluated."""
+    avg = ms / max(n, 1) / 1e3
+    per = pairs / max(n, 1)
+    ach = FLOP_PER_PAIR * per / avg if avg > 0 else 0.0
+    return {"achieved": ach / 1e12, "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s", "frac": ach / PEAK_FP32_MFMA,
+            "avg_launch_ms": avg * 1e3, "launches": n, "pairs_per_launch": per}
+
+
+def batched_leg(A, synth, log, solves=2):
+    """The batched workload (64 objects of 2k-32k points x 3 preshapes x 128
+    particles, 100 iterations): one launch per kernel for all objects, launch
+    choice by the library's tuner, `solves` timed whole solves."""
+    import numpy as np
+    import torch
+    pb, st = synth.workload_batched()
+    s = A.Solver(pb, st, timing=True)
+    launch, ms_choice = s.autotune(reps=2)
+    s.reset()
+    s.solve()
+    s.result(per_particle=False)
+    log(f"batched: workload ready (Ktot={pb.k_tot}), launch {launch}")
+    walls, nn = [], [0.0, 0, 0.0]
+    for _ in range(solves):
+        s.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.solve()
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t0)
+        ms, n, pr = s.kernel_time()
+        nn = [nn[0] + ms, nn[1] + n, nn[2] + pr]
+    res = s.result(per_particle=False)
+    s.close()
+    wall = float(np.median(walls))
+    out = {"workload": "64 objects (superquadrics and unions of 1-3 boxes, 2k-32k points, log-uniform) x 3 "
+                       "box-gripper preshapes x 4096 contact points x 128 Fibonacci particles, 100 iterations, "
+                       "one launch per kernel for all objects",
+           "particle_iters_per_s": pb.k_tot * st.k_max / wall, "grasps_per_s": pb.n_obj / wall,
+           "ms_per_solve": 1e3 * wall, "solves": solves, "launch": launch,
+           "collision_free_objects": int(res["best_free"].sum()),
+           "nn_roofline": nn_roofline(*nn)}
+    return out
+
+
+def small_replay_leg(A, synth, log, replays=50):
+    """The small workload (1 object of 1024 points, 1 preshape of 512 contact
+    points, 32 particles, 30 iterations) as one captured HIP graph per solve
+    (asicp_replay), against the same solve enqueued kernel by kernel."""
+    import torch
+    pb, st = synth.workload_small()
+    s = A.Solver(pb, st)
+    s.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(replays):
+        s.replay()
+    torch.cuda.synchronize()
+    wall_g = (time.perf_counter() - t0) / replays
+    res = s.result(per_particle=False)
+    walls = []
+    for _ in range(5):
+        s.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.solve()
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t0)
+    s.close()
+    wall_e = sorted(walls)[len(walls) // 2]
+    log(f"small: replay {1e3 * wall_g:.3f} ms, enqueued {1e3 * wall_e:.3f} ms per solve")
+    return {"workload": "1 ellipsoid of 1024 points, 1 preshape x 512 contact points, 64^3 SDF, 32 Fibonacci "
+                        "particles, 30 iterations",
+            "replay_ms_per_solve": 1e3 * wall_g, "enqueued_ms_per_solve": 1e3 * wall_e,
+            "particle_iters_per_s": pb.k_tot * st.k_max / wall_g, "grasps_per_s": 1.0 / wall_g,
+            "replays": replays, "collision_free": int(res["best_free"][0])}
+
+
+def full_scan_leg(A, pb, st, log, iters=4):
+    """The forward NN without pruning (every object point compared with every
+    contact point) on the paper-scale workload: `iters` iterations from the
+    initial poses, HIP events around every launch."""
+    s = A.Solver(pb, st, timing=True, prune=False)
+    s.step(1)
+    s.result(per_particle=False)
+    s.reset()
+    s.step(iters)
+    s.result(per_particle=False)
+    ms, n, pr = s.kernel_time()
+    s.close()
+    r = nn_roofline(ms, n, pr)
+    log(f"full scan: {r['avg_launch_ms']:.3f} ms per launch, frac {r['frac']:.3f}")
+    return {"kernel": "k_nn_forward_full", "bound": "mfma", **r, "flop_per_pair": FLOP_PER_PAIR}
+
+
+def learned_leg(log, n_train, steps):
+    """Plain against learned-seeded AS-ICP at matched final cost, with the
+    network trained inside this run on grasps the solver finds."""
+    from paper_2412_08346_amd import proposal
+    t0 = time.perf_counter()
+    r = proposal.run_learned(n_train=n_train, steps=steps, log=log)
+    p, l, f = r["plain"], r["learned"], r["fibonacci_same_budget"]
+    pi_p = p["particles_per_preshape"] * p["iterations"]
+    pi_l = l["particles_per_preshape"] * l["iterations"]
+    return {"workload": f"{r['objects']} held-out random objects (superquadrics and box unions, 2k-8k points), 3 "
+                        "box-gripper preshapes x 4096 contact points",
+            "plain_grasps_per_s": p["grasps_per_s"], "learned_grasps_per_s": l["grasps_per_s"],
+            "grasp_rate_ratio": l["grasps_per_s"] / p["grasps_per_s"],
+            "particle_iters_per_grasp_ratio": pi_p / pi_l,
+            "median_cost_ratio": l["median_cost_ratio"], "matched_fraction": l["matched_fraction"],
+            "no_network_same_budget": {"median_cost_ratio": f["median_cost_ratio"],
+                                       "matched_fraction": f["matched_fraction"]},
+            "train_objects": r["train_objects"], "train_steps": r["train_steps"],
+            "leg_s": time.perf_counter() - t0, "detail": r}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,6 +197,11 @@ def main():
                          "instead of tuning")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch choices instead of timing them first")
+    ap.add_argument("--legs", default="batched,small,full,learned",
+                    help="extra legs of the default line (comma-separated: batched, small, full, learned; "
+                         "'none' for the paper-scale line alone)")
+    ap.add_argument("--learned-train", type=int, default=384, help="training objects of the learned leg")
+    ap.add_argument("--learned-steps", type=int, default=1500, help="Adam steps of the learned leg")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of MIB MiB (3 times): the reference "
                          "kernel that scales rocprofv3 FETCH_SIZE / WRITE_SIZE to bytes")
@@ -219,8 +341,20 @@ def main():
                      "launch": launch, "launch_choice_ms_per_solve": launch_ms},
         "best_cost_median": float(np.median(res["best_cost"])), "collision_free_objects": int(res["best_free"].sum()),
     }
+    log = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)
+    legs = [] if args.legs == "none" else args.legs.split(",")
+    if args.workload == "paper":
+        if "full" in legs:
+            line["full_scan"] = full_scan_leg(A, pb, st, log)
+        if "small" in legs:
+            line["small_replay"] = small_replay_leg(A, synth, log)
+        if "batched" in legs:
+            line["batched"] = batched_leg(A, synth, log)
+            log(f"batched: {line['batched']['particle_iters_per_s']:.3g} particle-iters/s")
+        if "learned" in legs:
+            line["learned_vs_plain"] = learned_leg(log, args.learned_train, args.learned_steps)
     if not args.no_cpu_baseline and args.workload == "paper":
-        print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
+        log("timing the CPU oracle sample")
         line["cpu_baseline"] = cpu_baseline(pb, st)
     print(json.dumps(line), flush=True)
 

@@ -146,9 +146,22 @@ def box_union_sdf(points: np.ndarray, boxes) -> np.ndarray:
     return out
 
 
+_GRID_CACHE: dict = {}
+
+
 def gripper_sdf_grid(gap: float, n: int, cell: float) -> Grid:
     """n^3 grid of the box gripper's signed distance, centred on the
-    gripper's bounding box; values computed in float64, stored float32."""
+    gripper's bounding box; values computed in float64, stored float32.
+    Grids are kept per (gap, n, cell) for the process; each call returns its
+    own copy of the values."""
+    key = (float(gap), int(n), float(cell))
+    if key not in _GRID_CACHE:
+        _GRID_CACHE[key] = _gripper_sdf_grid(gap, n, cell)
+    g = _GRID_CACHE[key]
+    return Grid(values=g.values.copy(), origin=g.origin.copy(), cell=g.cell)
+
+
+def _gripper_sdf_grid(gap: float, n: int, cell: float) -> Grid:
     boxes = gripper_boxes(gap)
     lo = np.min([c - h for c, h in boxes], axis=0)
     hi = np.max([c + h for c, h in boxes], axis=0)
@@ -276,6 +289,12 @@ def _rot_to_quat(Rm: np.ndarray) -> np.ndarray:
     return q if q[0] >= 0 else -q
 
 
+def _cross3(a, b) -> np.ndarray:
+    """Cross product of two 3-vectors (numpy's formula, without its per-call
+    overhead)."""
+    return np.array([a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]])
+
+
 def _look_at(u: np.ndarray, anchor: np.ndarray, tip: np.ndarray, dist: float,
              roll: float = 0.0):
     """Pose whose gripper +z axis points along -u (back at `anchor`), with the
@@ -284,9 +303,9 @@ def _look_at(u: np.ndarray, anchor: np.ndarray, tip: np.ndarray, dist: float,
     vertical) and then turned by `roll`.  Returns (t, q) in float64."""
     ez = -u
     w = np.array([0.0, 0.0, 1.0]) if abs(ez[2]) <= 0.9 else np.array([0.0, 1.0, 0.0])
-    ex = np.cross(w, ez)
+    ex = _cross3(w, ez)
     ex /= np.linalg.norm(ex)
-    ey = np.cross(ez, ex)
+    ey = _cross3(ez, ex)
     if roll != 0.0:
         ex, ey = math.cos(roll) * ex + math.sin(roll) * ey, -math.sin(roll) * ex + math.cos(roll) * ey
     Rm = np.stack([ex, ey, ez], axis=1)
