@@ -589,6 +589,10 @@ static asicp_status evaluate(asicp_ctx c, int k, int final_eval, bool bandwidth,
   }
   if (hipEventRecord(e0, hs) != hipSuccess || hipStreamWaitEvent(c->side, e0, 0) != hipSuccess)
     return fail(ASICP_E_HIP, "fork to the side stream failed");
+  // The gate follows the bandwidth select: started first, its workgroups
+  // take issue slots from the forward NN (which is bound by instruction
+  // issue) and the solve runs 3-10 % slower; after the select they mostly
+  // fill the forward launch's tail.
   if (bandwidth) {
     launch_bandwidth(c->d, c->inv_log_k, c->side);
     if ((st = check_launch("bandwidth")) != ASICP_OK) return st;

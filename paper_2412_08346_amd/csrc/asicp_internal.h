@@ -162,6 +162,12 @@ __device__ __forceinline__ void load_pose(const float* theta, int Ktot, int i, f
   q[3] = theta[6 * Ktot + i];
 }
 
+// A wave-uniform float computed on the vector unit, moved to a scalar
+// register (gfx9 has no scalar float arithmetic).
+__device__ __forceinline__ float uniform_f(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
 // The lane's index in its wavefront, from the execution mask (two VALU
 // instructions that the compiler can repeat instead of keeping a register).
 __device__ __forceinline__ int lane_id() {

@@ -177,9 +177,7 @@ __global__ __launch_bounds__(256) void k_gate_reverse(Dev d) {
   quat_to_rot(qv[0], qv[1], qv[2], qv[3], R);
   {
     const float* com = d.obj_com + 4 * gi.obj;
-    t[0] -= com[0];
-    t[1] -= com[1];
-    t[2] -= com[2];
+    for (int a = 0; a < 3; ++a) t[a] = uniform_f(t[a] - com[a]);
   }
 
   float* pout = d.pen_part + ((size_t)i * d.max_gate_chunks + cc) * kPartStride;

@@ -58,9 +58,7 @@ __device__ __forceinline__ void nn_forward_body(const Dev& d) {
   load_pose(d.theta, d.Ktot, i, t, qv);
   quat_to_rot(qv[0], qv[1], qv[2], qv[3], R);
   const float* com = d.obj_com + 4 * gi.obj;
-  t[0] -= com[0];
-  t[1] -= com[1];
-  t[2] -= com[2];
+  for (int a = 0; a < 3; ++a) t[a] = uniform_f(t[a] - com[a]);
 
   constexpr int Q = kNnQ, QPW = kQueriesPerWave;
   const float4* spts = d.pre_pts + (size_t)pi.prep_tg_begin * 64;  // Morton-sorted contact cloud

@@ -5,7 +5,7 @@
 //                 found exactly by a radix select over the FP32 bit patterns
 //                 (monotone for non-negative floats), 8 bits per pass
 //                 (k_bw_fused instead: all four passes in one workgroup per
-//                 group when K <= 256);
+//                 group when K <= 128);
 //   k_svgd_phi    Stein direction in the 6-D tangent: kernel-weighted mean of
 //                 the preconditioned driving terms -gamma A g_j (g_j minus the
 //                 log-prior gradient when a prior is given, eq. 8) plus tau times
@@ -131,7 +131,9 @@ __global__ __launch_bounds__(256) void k_bw_pass(Dev d, int pass, float inv_log_
 // with no global histogram, no last-workgroup hand-off and one launch instead
 // of four.  Pair slot s is {i, (i + d) mod K} with i = s mod K, d = s / K + 1:
 // d runs over 1 .. floor((K - 1) / 2) for every i, and for even K the slots
-// d = K / 2, i < K / 2 follow, so each unordered pair appears once.
+// d = K / 2, i < K / 2 follow, so each unordered pair appears once.  By
+// default it is launched only where 256 threads suffice (K <= 128, see
+// launch_bandwidth).
 constexpr int kBwRegs = 32;
 __global__ __launch_bounds__(1024) void k_bw_fused(Dev d, float inv_log_k) {
   __shared__ float st[256 * 3];
@@ -350,8 +352,16 @@ __global__ __launch_bounds__(256) void k_svgd_apply(Dev d) {
 
 void launch_bandwidth(const Dev& d, float inv_log_k, hipStream_t s) {
   if (d.K >= 2 && d.bw_mode == ASICP_BW_MEDIAN) {
+    // The fused select only where it fits a 256-thread workgroup (K <= 128):
+    // beside the forward NN launch, a 512- or 1024-thread workgroup waits
+    // for a CU to drain, while the sliced passes' 256-thread workgroups take
+    // the place of retiring forward workgroups (measured on K = 256: 41.4
+    // against 41.8 ms per paper-scale solve).
+#ifndef ASICP_BW_FUSED_MAX_PAIRS
+#define ASICP_BW_FUSED_MAX_PAIRS (kBwRegs * 256)
+#endif
     const int pairs = d.K * (d.K - 1) / 2;
-    if (pairs <= kBwRegs * 1024) {
+    if (pairs <= ASICP_BW_FUSED_MAX_PAIRS) {
       int nt = 256;
       while (nt * kBwRegs < pairs) nt *= 2;
       hipLaunchKernelGGL(k_bw_fused, dim3(d.G), dim3(nt), 0, s, d, inv_log_k);
