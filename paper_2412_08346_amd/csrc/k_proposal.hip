@@ -16,8 +16,8 @@
 //   d(a, g) = |t_a - t_g|^2 / 0.01 + (1 - (q_a . q_g)^2),
 //   L = (1/T) sum_g min_a d + (1/S) sum_a min_g d, averaged over preshapes and
 //   objects.  The max-pool routes each channel's gradient to one point, so
-//   the encoder's backward touches at most 256 points per object: it is a
-//   set of matrix-vector products, done in FP32 on the vector units.
+//   the encoder's backward touches at most 256 points per object: their
+//   products run on BF16 MFMA with FP32 accumulation (k_pn_point_bwd).
 // Every sum runs in a fixed order: no float atomics.
 #include <algorithm>
 #include <cmath>
@@ -267,62 +267,85 @@ __global__ __launch_bounds__(256) void k_pn_head_fwd(Net n, float* seeds, int Kt
 }
 
 // ---------------------------------------------------------------------------
-// set loss and dL/do: one thread per (object, preshape)
+// set loss and dL/do: one wave per (object, preshape).  The lanes split the
+// targets (nearest seed of each, lowest index on ties), then the seeds
+// (nearest target of each); each seed's gradient is accumulated by its own
+// lane in the order target 0 .. T-1, then its own nearest target, and the
+// loss is summed by lane 0 in the order targets, then seeds.
+constexpr int kLossMaxS = 1024 / 7;  // seeds per preshape (n_pre * n_seed * 7 <= 1024)
+constexpr int kLossMaxT = 4096;      // targets per preshape
 __global__ __launch_bounds__(64) void k_pn_loss(Net n, const float* tgt, float* lpart) {
-  const int j = blockIdx.x * 64 + threadIdx.x;
-  if (j >= n.n_obj * n.n_pre) return;
+  __shared__ float sd[kLossMaxS][8];  // seed: t (3, metres), q / |q| (4), 1 / |q|
+  __shared__ int bs_of[kLossMaxT];    // nearest seed of each target
+  __shared__ float bd_t[kLossMaxT], bd_s[kLossMaxS];
+  const int j = blockIdx.x, lane = threadIdx.x;
   const int o = j / n.n_pre, p = j - o * n.n_pre;
   const int S = n.n_seed, T = n.n_tgt, O = n.P.O;
   const float* a = n.out + (size_t)o * O + (size_t)p * S * 7;
   float* da = n.dout + (size_t)o * O + (size_t)p * S * 7;
   const float* tg = tgt + ((size_t)o * n.n_pre + p) * T * 7;
   const float cx = n.com[o * 4], cy = n.com[o * 4 + 1], cz = n.com[o * 4 + 2];
-  for (int i = 0; i < S * 7; ++i) da[i] = 0.f;
-  auto dist = [&](int s, int g, float* c_out) {
+  for (int s = lane; s < S; s += 64) {
     const float* r = a + s * 7;
-    const float* t = tg + g * 7;
-    const float dx = cx + kUnit * r[0] - t[0], dy = cy + kUnit * r[1] - t[1], dz = cz + kUnit * r[2] - t[2];
+    sd[s][0] = cx + kUnit * r[0];
+    sd[s][1] = cy + kUnit * r[1];
+    sd[s][2] = cz + kUnit * r[2];
     const float nq = sqrtf(r[3] * r[3] + r[4] * r[4] + r[5] * r[5] + r[6] * r[6]);
-    const float c = (r[3] * t[3] + r[4] * t[4] + r[5] * t[5] + r[6] * t[6]) / nq;
+    for (int e = 0; e < 4; ++e) sd[s][3 + e] = r[3 + e] / nq;
+    sd[s][7] = 1.f / nq;
+  }
+  __syncthreads();
+  // d(a, g) = |t_a - t_g|^2 / UNIT^2 + 1 - (q_a . q_g)^2 and q_a . q_g
+  auto dist = [&](int s, const float* t, float* c_out) {
+    const float dx = sd[s][0] - t[0], dy = sd[s][1] - t[1], dz = sd[s][2] - t[2];
+    const float c = sd[s][3] * t[3] + sd[s][4] * t[4] + sd[s][5] * t[5] + sd[s][6] * t[6];
     *c_out = c;
     return (dx * dx + dy * dy + dz * dz) / (kUnit * kUnit) + (1.f - c * c);
   };
-  // adds w * dd(s, g)/d(raw seed s)
-  auto grad = [&](int s, int g, float wgt) {
-    const float* r = a + s * 7;
+  float c;
+  for (int g = lane; g < T; g += 64) {
     const float* t = tg + g * 7;
-    float* d = da + s * 7;
-    const float dx = cx + kUnit * r[0] - t[0], dy = cy + kUnit * r[1] - t[1], dz = cz + kUnit * r[2] - t[2];
-    const float f = wgt * 2.f / kUnit;  // d/d raw t = 2 dt / UNIT^2 * UNIT
-    d[0] += f * dx; d[1] += f * dy; d[2] += f * dz;
-    const float nq = sqrtf(r[3] * r[3] + r[4] * r[4] + r[5] * r[5] + r[6] * r[6]);
-    float q[4] = {r[3] / nq, r[4] / nq, r[5] / nq, r[6] / nq};
-    const float c = q[0] * t[3] + q[1] * t[4] + q[2] * t[5] + q[3] * t[6];
-    const float k = -2.f * wgt * c / nq;
-    for (int e = 0; e < 4; ++e) d[3 + e] += k * (t[3 + e] - c * q[e]);
-  };
-  float L = 0.f, c;
-  for (int g = 0; g < T; ++g) {  // nearest seed of each target (lowest index)
     int bs = 0;
-    float bd = dist(0, g, &c);
+    float bd = dist(0, t, &c);
     for (int s = 1; s < S; ++s) {
-      const float dd = dist(s, g, &c);
+      const float dd = dist(s, t, &c);
       if (dd < bd) { bd = dd; bs = s; }
     }
-    L += bd / (float)T;
-    grad(bs, g, 1.f / (float)T / (float)n.n_pre);
+    bs_of[g] = bs;
+    bd_t[g] = bd;
   }
-  for (int s = 0; s < S; ++s) {  // nearest target of each seed
+  __syncthreads();
+  const float w_t = 1.f / (float)T / (float)n.n_pre, w_s = 1.f / (float)S / (float)n.n_pre;
+  for (int s = lane; s < S; s += 64) {
+    float d[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    // adds wgt * dd(s, g) / d(raw seed s)
+    auto grad = [&](const float* t, float wgt) {
+      const float dx = sd[s][0] - t[0], dy = sd[s][1] - t[1], dz = sd[s][2] - t[2];
+      const float f = wgt * 2.f / kUnit;  // d/d raw t = 2 dt / UNIT^2 * UNIT
+      d[0] += f * dx; d[1] += f * dy; d[2] += f * dz;
+      const float cc = sd[s][3] * t[3] + sd[s][4] * t[4] + sd[s][5] * t[5] + sd[s][6] * t[6];
+      const float k = -2.f * wgt * cc * sd[s][7];
+      for (int e = 0; e < 4; ++e) d[3 + e] += k * (t[3 + e] - cc * sd[s][3 + e]);
+    };
+    for (int g = 0; g < T; ++g)
+      if (bs_of[g] == s) grad(tg + g * 7, w_t);
     int bg = 0;
-    float bd = dist(s, 0, &c);
+    float bd = dist(s, tg, &c);
     for (int g = 1; g < T; ++g) {
-      const float dd = dist(s, g, &c);
+      const float dd = dist(s, tg + g * 7, &c);
       if (dd < bd) { bd = dd; bg = g; }
     }
-    L += bd / (float)S;
-    grad(s, bg, 1.f / (float)S / (float)n.n_pre);
+    grad(tg + bg * 7, w_s);
+    bd_s[s] = bd;
+    for (int e = 0; e < 7; ++e) da[s * 7 + e] = d[e];
   }
-  lpart[j] = L / (float)n.n_pre;
+  __syncthreads();
+  if (lane == 0) {
+    float L = 0.f;
+    for (int g = 0; g < T; ++g) L += bd_t[g] / (float)T;
+    for (int s = 0; s < S; ++s) L += bd_s[s] / (float)S;
+    lpart[j] = L / (float)n.n_pre;
+  }
 }
 
 // per object: loss over preshapes (fixed order)
@@ -416,22 +439,46 @@ __global__ __launch_bounds__(256) void k_pn_head_wgrad(Net n, float* grad) {
 
 // ---------------------------------------------------------------------------
 // encoder backward, one workgroup per object.  Channel c's gradient dg_c goes
-// to its argmax point p_c (where h3 = g_c > 0, so the relu passes it).  The
-// channels are sorted by point; each distinct point is processed in that
-// order by the whole workgroup: its forward up to h2 is recomputed (same
-// BF16 roundings as the forward), then dh2 = W3^T dz3, dz2, dh1 = W2^T dz2,
-// dz1, and the outer products into this object's gradient record.
+// to its argmax point p_c (where h3 = g_c > 0, so the relu passes it); the
+// distinct routed points (at most 256) form the rows of the products below,
+// processed in tiles of 64 rows:
+//   forward recompute   z1 (VALU, the forward's FMA order), h1 = bf16 relu(z1),
+//                       z2 = h1 W2^T + b2 (the forward's BF16 MFMA, so the
+//                       relu masks are the forward's bit for bit),
+//                       h2 = bf16 relu(z2);
+//   dW3 row c, db3 c    dg_c h2[p_c] (one point per channel: outer products);
+//   dh2                 sum over the row's channels of dg_c W3[c] (gather);
+//   dz2                 dh2 where z2 > 0, split into BF16 hi + lo parts
+//                       (|dz2 - hi - lo| <= 2^-17 |dz2|);
+//   dW2 += dz2^T h1     BF16 MFMA over the rows, hi and lo, FP32 accumulate
+//                       (kept in registers across the tiles);
+//   dh1 = dz2 W2        BF16 MFMA over the 128 channels, hi and lo;
+//   dz1                 dh1 where z1 > 0;  dW1 += dz1^T x, db1, db2 (VALU).
+// Every sum runs in a fixed order; the record of the object is written once.
+constexpr int kBwdRows = 64;  // routed points per tile
 __global__ __launch_bounds__(256) void k_pn_point_bwd(Net n) {
-  __shared__ unsigned int keyp[H3];   // (point << 8) | channel, sorted
+  __shared__ unsigned int keyp[H3];   // (point << 8) | channel, sorted; 0xFFFFFFFF = no gradient
   __shared__ float dgs[H3];
-  __shared__ float xp[3], z1[H1], a1f[H1], z2[H2], a2f[H2], dz2[H2], dz1[H1];
-  __shared__ float red[4][H2];
+  __shared__ int seg_row[H3];         // sorted position -> row (distinct point)
+  __shared__ int row_first[H3 + 1];   // row -> first sorted position of its channels
+  __shared__ int row_pt[H3];          // row -> point index in the object
+  __shared__ int n_rows;
+  __shared__ float xs[kBwdRows][3];
+  __shared__ unsigned short a1s[kBwdRows][H1 + 4];  // bf16 h1
+  __shared__ unsigned short dzh[kBwdRows][H2 + 2];  // dz2, bf16 hi part
+  __shared__ unsigned short dzl[kBwdRows][H2 + 2];  // dz2, bf16 lo part
+  // bf16 h2 of the tile, then (once dz2 is formed) dz1 as FP32
+  __shared__ __align__(16) unsigned char u2[kBwdRows * (H2 + 4) * 2];
+  unsigned short (*a2s)[H2 + 4] = reinterpret_cast<unsigned short (*)[H2 + 4]>(u2);
+  float (*dz1s)[H1 + 1] = reinterpret_cast<float (*)[H1 + 1]>(u2);
+  static_assert(kBwdRows * (H1 + 1) * 4 <= kBwdRows * (H2 + 4) * 2, "dz1 fits the h2 buffer");
+
   const int o = blockIdx.x, tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int row = lane & 15, kq = lane >> 4;
   const int a = n.off[o];
   float* part = n.part + (size_t)o * kEnc;
   // encoder record layout: W1, b1, W2, b2, W3, b3 (as in the parameters)
   const int oW1 = 0, ob1 = H1 * 3, oW2 = ob1 + H1, ob2 = oW2 + H2 * H1, oW3 = ob2 + H2, ob3 = oW3 + H3 * H2;
-  for (int i = tid; i < kEnc; i += 256) part[i] = 0.f;
   {
     const unsigned long long key = n.pool[(size_t)o * H3 + tid];
     const float gval = __uint_as_float((unsigned)(key >> 32));
@@ -440,6 +487,10 @@ __global__ __launch_bounds__(256) void k_pn_point_bwd(Net n) {
     const unsigned pt = 0xFFFFFFFFu - (unsigned)(key & 0xFFFFFFFFull);
     keyp[tid] = live ? ((pt << 8) | (unsigned)tid) : 0xFFFFFFFFu;
     dgs[tid] = dg;
+    if (!live) {  // channels without gradient: zero rows of dW3 and db3
+      for (int i = 0; i < H2; ++i) part[oW3 + tid * H2 + i] = 0.f;
+      part[ob3 + tid] = 0.f;
+    }
   }
   __syncthreads();
   // bitonic sort of the 256 keys (point major, channel minor)
@@ -454,82 +505,212 @@ __global__ __launch_bounds__(256) void k_pn_point_bwd(Net n) {
       __syncthreads();
     }
   }
-  int s0 = 0;
-  while (s0 < H3) {
-    const unsigned k0 = keyp[s0];
-    if (k0 == 0xFFFFFFFFu) break;  // uniform: every thread reads the same LDS word
-    const unsigned pt = k0 >> 8;
-    int s1 = s0 + 1;
-    while (s1 < H3 && (keyp[s1] >> 8) == pt) ++s1;
-    // recompute the point's forward up to h2
-    const int gi = a + (int)pt;
-    if (tid < 3) {
-      const float* src = tid == 0 ? n.x : (tid == 1 ? n.y : n.z);
-      xp[tid] = (src[gi] - n.com[o * 4 + tid]) / kUnit;
-    }
-    __syncthreads();
-    if (tid < H1) {
-      const float* W1 = n.prm + n.P.W1 + tid * 3;
-      float zz = n.prm[n.P.b1 + tid];
-      zz = __builtin_fmaf(W1[0], xp[0], zz);
-      zz = __builtin_fmaf(W1[1], xp[1], zz);
-      zz = __builtin_fmaf(W1[2], xp[2], zz);
-      z1[tid] = zz;
-      a1f[tid] = from_bf16(to_bf16(fmaxf(zz, 0.f)));
-    }
-    __syncthreads();
-    if (tid < H2) {
-      float acc = 0.f;
-      for (int k = 0; k < H1; ++k) acc = __builtin_fmaf(from_bf16(n.w2h[(size_t)tid * H1 + k]), a1f[k], acc);
-      z2[tid] = acc + n.prm[n.P.b2 + tid];
-      a2f[tid] = from_bf16(to_bf16(fmaxf(z2[tid], 0.f)));
-    }
-    __syncthreads();
-    // dW3 rows and db3 of this point's channels (each channel has one point)
-    for (int s = s0; s < s1; ++s) {
-      const int c = (int)(keyp[s] & 255u);
-      const float dg = dgs[c];
-      if (tid < H2) part[oW3 + c * H2 + tid] = dg * a2f[tid];
-      if (tid == 0) part[ob3 + c] = dg;
-    }
-    // dh2 = W3^T dz3 over the point's channels, the 4 waves split them
-    {
-      float acc0 = 0.f, acc1 = 0.f;
-      for (int s = s0 + w; s < s1; s += 4) {
-        const int c = (int)(keyp[s] & 255u);
-        const float dg = dgs[c];
-        acc0 = __builtin_fmaf(from_bf16(n.w3h[(size_t)c * H2 + lane]), dg, acc0);
-        acc1 = __builtin_fmaf(from_bf16(n.w3h[(size_t)c * H2 + 64 + lane]), dg, acc1);
+  // rows: one per distinct point, in point order (a prefix count of the
+  // positions that start a new point)
+  if (tid == 0) {
+    int r = -1;
+    unsigned prev = 0xFFFFFFFFu;
+    for (int s = 0; s < H3; ++s) {
+      const unsigned k = keyp[s];
+      if (k == 0xFFFFFFFFu) {
+        seg_row[s] = -1;
+        continue;
       }
-      red[w][lane] = acc0;
-      red[w][64 + lane] = acc1;
+      if ((k >> 8) != prev) {
+        ++r;
+        row_first[r] = s;
+        row_pt[r] = (int)(k >> 8);
+        prev = k >> 8;
+      }
+      seg_row[s] = r;
+    }
+    int end = 0;
+    while (end < H3 && keyp[end] != 0xFFFFFFFFu) ++end;
+    row_first[r + 1] = end;
+    n_rows = r + 1;
+  }
+  __syncthreads();
+  const int P = n_rows;
+  // dW2 accumulators: wave w owns output rows (channels of h2) 32w .. 32w+31
+  // as two 16-row tiles, times the four 16-column tiles of h1's channels
+  f4 acc2[2][4];
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 4; ++ni) acc2[mi][ni] = f4{0.f, 0.f, 0.f, 0.f};
+  float gW1[3] = {0.f, 0.f, 0.f}, gb1 = 0.f, gb2 = 0.f;  // threads < 64: h1 channel tid; gb2: tid & 127 (half tid >> 7)
+
+  for (int r0 = 0; r0 < P; r0 += kBwdRows) {
+    const int nr = min(kBwdRows, P - r0);
+    // x and h1 of the tile's rows (rows past the last point are zero)
+    if (tid < kBwdRows) {
+      for (int c = 0; c < 3; ++c) xs[tid][c] = 0.f;
+      if (tid < nr) {
+        const int gi = a + row_pt[r0 + tid];
+        xs[tid][0] = (n.x[gi] - n.com[o * 4 + 0]) / kUnit;
+        xs[tid][1] = (n.y[gi] - n.com[o * 4 + 1]) / kUnit;
+        xs[tid][2] = (n.z[gi] - n.com[o * 4 + 2]) / kUnit;
+      }
     }
     __syncthreads();
-    if (tid < H2) {
-      const float dh2 = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
-      dz2[tid] = z2[tid] > 0.f ? dh2 : 0.f;
+    for (int e = tid; e < kBwdRows * H1; e += 256) {
+      const int m = e / H1, c = e - m * H1;
+      unsigned short h = 0;
+      if (m < nr) {
+        const float* W1 = n.prm + n.P.W1 + c * 3;
+        float zz = n.prm[n.P.b1 + c];
+        zz = __builtin_fmaf(W1[0], xs[m][0], zz);
+        zz = __builtin_fmaf(W1[1], xs[m][1], zz);
+        zz = __builtin_fmaf(W1[2], xs[m][2], zz);
+        h = to_bf16(fmaxf(zz, 0.f));
+      }
+      a1s[m][c] = h;
     }
     __syncthreads();
+    // z2 = h1 W2^T + b2 and h2 = bf16 relu(z2): the forward's products;
+    // wave w takes output column tiles 2w, 2w+1
+    for (int nt = 2 * w; nt < 2 * w + 2; ++nt) {
+      for (int mt = 0; mt < kBwdRows / 16; ++mt) {
+        f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int k0 = 0; k0 < H1; k0 += 16) {
+          s4 av, bv;
+          const unsigned short* ap = &a1s[mt * 16 + row][k0 + 4 * kq];
+          const unsigned short* bp = n.w2h + (size_t)(nt * 16 + row) * H1 + k0 + 4 * kq;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) { av[j] = (short)ap[j]; bv[j] = (short)bp[j]; }
+          acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+        }
+        const int c = nt * 16 + row;
+        const float bias = n.prm[n.P.b2 + c];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) a2s[mt * 16 + 4 * kq + v][c] = to_bf16(fmaxf(acc[v] + bias, 0.f));
+      }
+    }
+    __syncthreads();
+    // dW3 rows and db3 of the tile's channels: two channels per pass
+    {
+      const int s_begin = row_first[r0], s_end = row_first[r0 + nr];
+      for (int s = s_begin + (tid >> 7); s < s_end; s += 2) {
+        const int c = (int)(keyp[s] & 255u);
+        const int rr = seg_row[s] - r0;
+        const int i = tid & 127;
+        part[oW3 + c * H2 + i] = dgs[c] * from_bf16(a2s[rr][i]);
+        if (i == 0) part[ob3 + c] = dgs[c];
+      }
+    }
+    // dz2 = (sum over the row's channels of dg_c W3[c]) where z2 > 0, as hi +
+    // lo BF16; thread tid owns channel tid & 127 of rows (tid >> 7) + 2j
+    {
+      const int i = tid & 127;
+      for (int m = tid >> 7; m < kBwdRows; m += 2) {
+        float dz = 0.f;
+        if (m < nr && from_bf16(a2s[m][i]) > 0.f) {  // z2 > 0
+          float dh = 0.f;
+          for (int s = row_first[r0 + m]; s < row_first[r0 + m + 1]; ++s) {
+            const int c = (int)(keyp[s] & 255u);
+            dh = __builtin_fmaf(from_bf16(n.w3h[(size_t)c * H2 + i]), dgs[c], dh);
+          }
+          dz = dh;
+        }
+        gb2 += dz;
+        const unsigned short hi = to_bf16(dz);
+        dzh[m][i] = hi;
+        dzl[m][i] = to_bf16(dz - from_bf16(hi));
+      }
+    }
+    __syncthreads();
+    // dW2 += dz2^T h1 over the tile's rows (K = 64 rows in 4 steps, hi and lo)
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi) {
+      const int ch = (2 * w + mi) * 16 + row;  // A row: channel of h2
+#pragma unroll
+      for (int k0 = 0; k0 < kBwdRows; k0 += 16) {
+        s4 ah, al;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          ah[j] = (short)dzh[k0 + 4 * kq + j][ch];
+          al[j] = (short)dzl[k0 + 4 * kq + j][ch];
+        }
+#pragma unroll
+        for (int ni = 0; ni < 4; ++ni) {
+          s4 bv;  // B column: channel of h1
+#pragma unroll
+          for (int j = 0; j < 4; ++j) bv[j] = (short)a1s[k0 + 4 * kq + j][ni * 16 + row];
+          acc2[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bv, acc2[mi][ni], 0, 0, 0);
+          acc2[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bv, acc2[mi][ni], 0, 0, 0);
+        }
+      }
+    }
+    // dh1 = dz2 W2 (K = 128 channels, hi and lo); wave w takes rows 16w ..
+    // 16w+15; dz1 = dh1 where z1 > 0 (h1 > 0), into the h2 buffer (h2 is
+    // no longer read)
+    {
+      f4 acc1[4];
+#pragma unroll
+      for (int ni = 0; ni < 4; ++ni) acc1[ni] = f4{0.f, 0.f, 0.f, 0.f};
+      const int m = w * 16 + row;
+#pragma unroll 2
+      for (int k0 = 0; k0 < H2; k0 += 16) {
+        s4 ah, al;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          ah[j] = (short)dzh[m][k0 + 4 * kq + j];
+          al[j] = (short)dzl[m][k0 + 4 * kq + j];
+        }
+#pragma unroll
+        for (int ni = 0; ni < 4; ++ni) {
+          s4 bv;  // B[i][k] = W2[i][k], column k = channel of h1
+#pragma unroll
+          for (int j = 0; j < 4; ++j) bv[j] = (short)n.w2h[(size_t)(k0 + 4 * kq + j) * H1 + ni * 16 + row];
+          acc1[ni] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bv, acc1[ni], 0, 0, 0);
+          acc1[ni] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bv, acc1[ni], 0, 0, 0);
+        }
+      }
+      __syncthreads();  // every wave is done with h2 before dz1 overwrites it
+#pragma unroll
+      for (int ni = 0; ni < 4; ++ni)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int mm = w * 16 + 4 * kq + v, k = ni * 16 + row;
+          dz1s[mm][k] = from_bf16(a1s[mm][k]) > 0.f ? acc1[ni][v] : 0.f;  // z1 > 0
+        }
+    }
+    __syncthreads();
+    // dW1 += dz1^T x, db1 += dz1 (thread < 64: channel tid, rows in order)
     if (tid < H1) {
-      float acc = 0.f;
-      for (int k = 0; k < H2; ++k) acc = __builtin_fmaf(from_bf16(n.w2h[(size_t)k * H1 + tid]), dz2[k], acc);
-      dz1[tid] = z1[tid] > 0.f ? acc : 0.f;
+      for (int mm = 0; mm < nr; ++mm) {
+        const float dz = dz1s[mm][tid];
+        gW1[0] = __builtin_fmaf(dz, xs[mm][0], gW1[0]);
+        gW1[1] = __builtin_fmaf(dz, xs[mm][1], gW1[1]);
+        gW1[2] = __builtin_fmaf(dz, xs[mm][2], gW1[2]);
+        gb1 += dz;
+      }
     }
+    __syncthreads();  // buffers are rewritten by the next tile
+  }
+  // the record: dW2 from the accumulators, D[4 kq + v][row] of each tile
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 4; ++ni)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = (2 * w + mi) * 16 + 4 * kq + v, k = ni * 16 + row;
+        part[oW2 + i * H1 + k] = acc2[mi][ni][v];
+      }
+  // db2: the two row halves in a fixed order
+  {
+    float* red = reinterpret_cast<float*>(u2);
+    red[tid] = gb2;
     __syncthreads();
-    // dW2 += dz2 (x) a1, db2 += dz2; dW1 += dz1 (x) x, db1 += dz1
-    for (int e = tid; e < H2 * H1; e += 256) {
-      const int i = e / H1, k = e - i * H1;
-      part[oW2 + e] += dz2[i] * a1f[k];
-    }
-    if (tid < H2) part[ob2 + tid] += dz2[tid];
-    if (tid < H1) {
-      part[oW1 + tid * 3 + 0] += dz1[tid] * xp[0];
-      part[oW1 + tid * 3 + 1] += dz1[tid] * xp[1];
-      part[oW1 + tid * 3 + 2] += dz1[tid] * xp[2];
-      part[ob1 + tid] += dz1[tid];
-    }
-    __syncthreads();
-    s0 = s1;
+    if (tid < H2) part[ob2 + tid] = red[tid] + red[tid + 128];
+  }
+  if (tid < H1) {
+    part[oW1 + tid * 3 + 0] = gW1[0];
+    part[oW1 + tid * 3 + 1] = gW1[1];
+    part[oW1 + tid * 3 + 2] = gW1[2];
+    part[ob1 + tid] = gb1;
   }
 }
 
@@ -788,7 +969,7 @@ asicp_status asicp_pn_loss_grad(const float* params, int32_t n_pre, int32_t n_se
     pn_forward(n, mc, nullptr, 0.f, hs);
     float* lpart = reinterpret_cast<float*>(static_cast<char*>(workspace) + pn_layout(n_obj, n_pre, n_seed).lpart);
     const int pairs = n_obj * n_pre;
-    hipLaunchKernelGGL(k_pn_loss, dim3((pairs + 63) / 64), dim3(64), 0, hs, n, targets, lpart);
+    hipLaunchKernelGGL(k_pn_loss, dim3(pairs), dim3(64), 0, hs, n, targets, lpart);
     hipLaunchKernelGGL(k_pn_loss_sum, dim3((n_obj + 63) / 64), dim3(64), 0, hs, n, lpart, loss);
     hipLaunchKernelGGL(k_pn_head_bwd, dim3(n_obj), dim3(256), 0, hs, n);
     const long long head_elems = (long long)HH * H3 + HH + (long long)HH * HH + HH + (long long)n.P.O * HH + n.P.O;
