@@ -166,7 +166,7 @@ def learned_leg(log, n_train, steps):
     p, l, f = r["plain"], r["learned"], r["fibonacci_same_budget"]
     pi_p = p["particles_per_preshape"] * p["iterations"]
     pi_l = l["particles_per_preshape"] * l["iterations"]
-    return {"workload": f"{r['objects']} held-out random objects (superquadrics and box unions, 2k-8k points), 3 "
+    return {"workload": f"{r['objects']} held-out random objects (superquadrics and box unions, 2k-16k points), 3 "
                         "box-gripper preshapes x 4096 contact points",
             "plain_grasps_per_s": p["grasps_per_s"], "learned_grasps_per_s": l["grasps_per_s"],
             "grasp_rate_ratio": l["grasps_per_s"] / p["grasps_per_s"],
@@ -200,8 +200,8 @@ def main():
     ap.add_argument("--legs", default="batched,small,full,learned",
                     help="extra legs of the default line (comma-separated: batched, small, full, learned; "
                          "'none' for the paper-scale line alone)")
-    ap.add_argument("--learned-train", type=int, default=384, help="training objects of the learned leg")
-    ap.add_argument("--learned-steps", type=int, default=1500, help="Adam steps of the learned leg")
+    ap.add_argument("--learned-train", type=int, default=768, help="training objects of the learned leg")
+    ap.add_argument("--learned-steps", type=int, default=3000, help="Adam steps of the learned leg")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of MIB MiB (3 times): the reference "
                          "kernel that scales rocprofv3 FETCH_SIZE / WRITE_SIZE to bytes")
@@ -224,7 +224,7 @@ def main():
         line = {"metric": METRIC, "value": r["learned"]["grasps_per_s"], "unit": "grasps/s (learned-seeded)",
                 "n_gpus": 1, "higher_is_better": True, "vs_baseline": None, "dtype": "f32",
                 "data": "synthetic", "config": {"workload": "64 held-out random objects (superquadrics and "
-                "box unions, 2k-8k points), 3 box-gripper preshapes x 4096 contact points; plain 256 Fibonacci "
+                "box unions, 2k-16k points), 3 box-gripper preshapes x 4096 contact points; plain 256 Fibonacci "
                 "particles x 100 annealed Stein iterations per preshape vs 32 learned seeds x 50 SGD-ICP "
                 "iterations"}, **r}
         print(json.dumps(line), flush=True)

@@ -230,7 +230,7 @@ def best_per_object(pb, r):
 
 def run_learned(n_train: int = 1024, n_eval: int = 64, steps: int = 3000, n_seed: int = 32,
                 seeded_iters: int = 50, seeded_k_stein: int = 0, retract: float = 0.03,
-                m_lo: int = 2048, m_hi: int = 8192,
+                m_lo: int = 2048, m_hi: int = 16384,
                 plain_k: int = 256, plain_iters: int = 100, n_targets: int = 16, seed: int = 0, log=None):
     """Self-supervised pipeline and the comparison at matched final cost.
 
