@@ -18,13 +18,12 @@ METRIC = "particle-iters/s & grasps/s at matched final cost: plain vs learned-se
 PEAK_FP32_MFMA = 157.3e12  # MI355X dense fp32 matrix peak, FLOP/s
 FLOP_PER_PAIR = 6          # 3 multiply-adds of |r|^2 - 2 r.s per (query, object point) pair
 # HBM bytes per launch of the forward-NN kernel on the paper-scale workload,
-# per launch choice, from two rocprofv3 --pmc passes: 2.000 x FETCH_SIZE +
-# 1.000 x WRITE_SIZE (KiB per dispatch, factors from a 256 MiB device copy),
-# averaged over the 101 launches of one solve
-# (profiles/nn_forward_counters_paper_scale.md).  Reported only while the
-# kernel's sources hash to the ones measured.
-NN_TRAFFIC = {"sha256": "a091dfb05068fcfd6e72993a41b78602c47ccf2cbc4a7bfa34a3c8d9d46d7a8c",
-              "bytes": {"0,0": 4880684, "0,1": 4894470, "1,0": 6295219, "1,1": 6295025}}  # launch "map,fine" -> bytes per launch
+# per launch choice ("xcd_map,fine,query_blocks,chunk_points"), from two
+# rocprofv3 --pmc passes: 2.000 x FETCH_SIZE + 1.000 x WRITE_SIZE (KiB per
+# dispatch, factors from a 256 MiB device copy), averaged over the launches
+# of one solve (profiles/nn_forward_counters_paper_scale.md).  Reported only
+# while the kernel's sources hash to the ones measured.
+NN_TRAFFIC = {"sha256": None, "bytes": {}}
 NN_SOURCES = ("k_nn_forward.hip", "nn_core.h", "asicp_internal.h")
 
 
@@ -36,7 +35,8 @@ def nn_traffic(workload, launch, brute):
             h.update(fh.read())
     if h.hexdigest() != NN_TRAFFIC["sha256"] or workload != "paper" or brute:
         return None
-    return NN_TRAFFIC["bytes"].get(f"{launch['xcd_map']},{launch['fine']}")
+    key = f"{launch['xcd_map']},{launch['fine']},{launch.get('query_blocks', 4)},{launch.get('chunk_points', 128)}"
+    return NN_TRAFFIC["bytes"].get(key)
 
 
 def cpu_baseline(pb, st, seconds=10.0):
@@ -192,9 +192,9 @@ def main():
                     help="plain against learned-seeded AS-ICP at matched final cost: trains the "
                          "proposal network on grasps the solver finds (a few minutes) and prints one "
                          "JSON line of the comparison instead of the throughput line")
-    ap.add_argument("--launch", default=None, metavar="MAP,FINE",
-                    help="use this launch choice (XCD placement 0/1, per-query chunk test 0/1) "
-                         "instead of tuning")
+    ap.add_argument("--launch", default=None, metavar="MAP,FINE[,QB,CP]",
+                    help="use this launch choice (XCD placement 0/1, per-query chunk test 0/1, query "
+                         "blocks per wave 1/2/4, points per chunk 64/128) instead of tuning")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch choices instead of timing them first")
     ap.add_argument("--legs", default="batched,small,full,learned",
@@ -270,17 +270,18 @@ def main():
     # outside the timed region) and the fastest is used for every timed solve
     solver.reset()
     if args.launch:
-        mp, fn = (int(v) for v in args.launch.split(","))
-        launch, launch_ms = {"xcd_map": mp, "fine": fn}, None
+        vals = [int(v) for v in args.launch.split(",")]
+        launch = dict(zip(("xcd_map", "fine", "query_blocks", "chunk_points"), vals))
+        launch_ms = None
     elif args.no_autotune:
         launch, launch_ms = solver.launch(), None
     else:
         launch_ms = []
-        for v in range(4):
+        for v in range(A.ASICP_LAUNCH_CHOICES):
             best = float("inf")
             for _ in range(2):
                 ctx = A.asicp_create(solver.problem, solver.config, solver._ws_ptr, solver.ws_bytes, sp)
-                A.asicp_set_launch(ctx, xcd_map=v >> 1, fine=v & 1)
+                A.asicp_set_launch(ctx, **A.launch_choice(v))
                 torch.cuda.synchronize()
                 a = time.perf_counter()
                 A.asicp_solve(ctx, sp)
@@ -289,9 +290,9 @@ def main():
                 A.asicp_destroy(ctx)
             launch_ms.append(1e3 * best)
         v = int(np.argmin(launch_ms))
-        launch = {"xcd_map": v >> 1, "fine": v & 1}
-        print(f"[bench] launch choice: {launch}; ms per solve, index 2 * xcd_map + fine: {launch_ms}",
-              file=sys.stderr, flush=True)
+        launch = A.launch_choice(v)
+        print(f"[bench] launch choice: {launch}; ms per solve by launch index: "
+              f"{[round(x, 2) for x in launch_ms]}", file=sys.stderr, flush=True)
     solver.close()
     ctxs = []
     torch.cuda.synchronize()

@@ -231,21 +231,33 @@ asicp_status asicp_pose_vjp(const float* grad, const float* gout, float* dtheta,
  * (ASICP_E_STATE); ASICP_FLAG_TIMING events are not recorded inside the graph. */
 asicp_status asicp_replay(asicp_ctx ctx, void* stream);
 
-/* Launch choices that change no result: how work is placed on the XCDs and
- * how much provably useless work the pruned nearest-neighbour search skips.
+/* Launch choices that change no result: how work is placed on the XCDs, how
+ * much provably useless work the pruned nearest-neighbour search skips, and
+ * the forward NN's shape (queries per wavefront, points per pruning chunk).
  * Every choice returns bit-identical outputs; only the speed differs. */
 typedef struct {
-  int32_t xcd_map;  /* 0: each XCD takes a contiguous range of the per-particle */
-                    /*    work (one object's data stays in one L2);              */
-                    /* 1: dispatch order (consecutive work on different XCDs,    */
-                    /*    which balances uneven work).  Default 1.               */
-  int32_t fine;     /* forward NN: test each candidate chunk against every      */
-                    /*    query's own bound (1) or only the query block's (0).   */
-                    /*    Default 1.                                             */
+  int32_t xcd_map;       /* 0: each XCD takes a contiguous range of the per-particle */
+                         /*    work (one object's data stays in one L2);              */
+                         /* 1: dispatch order (consecutive work on different XCDs,    */
+                         /*    which balances uneven work).  Default 1.               */
+  int32_t fine;          /* forward NN: test each candidate chunk against every      */
+                         /*    query's own bound (1) or only the query block's (0).   */
+                         /*    Default 1.                                             */
+  int32_t query_blocks;  /* forward NN: blocks of 16 contact points per wavefront,    */
+                         /*    1, 2 or 4 (fewer: more wavefronts for small problems). */
+                         /*    Default 4.                                             */
+  int32_t chunk_points;  /* forward NN: object points per pruning chunk, 64 or 128.   */
+                         /*    Default 128.                                           */
 } asicp_launch_t;
 
-/* Read or set the launch choices of a context (set: each field 0 or 1, else
- * ASICP_E_INVALID).  Setting them discards a captured asicp_replay graph. */
+/* Number of launch choices, and the index of one in asicp_autotune's ms_out:
+ * ((qi * 2 + (chunk_points == 128)) * 2 + xcd_map) * 2 + fine, with qi = 0, 1,
+ * 2 for query_blocks = 1, 2, 4. */
+#define ASICP_LAUNCH_CHOICES 24
+
+/* Read or set the launch choices of a context (set: xcd_map and fine 0 or 1,
+ * query_blocks 1, 2 or 4, chunk_points 64 or 128, else ASICP_E_INVALID).
+ * Setting them discards a captured asicp_replay graph. */
 asicp_status asicp_get_launch(asicp_ctx ctx, asicp_launch_t* out);
 asicp_status asicp_set_launch(asicp_ctx ctx, const asicp_launch_t* in);
 
@@ -254,12 +266,12 @@ asicp_status asicp_set_launch(asicp_ctx ctx, const asicp_launch_t* in);
  * runs the forward NN on `stream` beside the bandwidth select, in the Stein
  * phase, and the collision kernel on the context's side stream, as an
  * iteration does), keep the fastest and return it in `chosen` (may be
- * NULL); ms_out (host, may be NULL) receives the average time per
- * evaluation of each choice, index 2 * xcd_map + fine.  Synchronises
- * `stream`.  The solve's state is left as it was (tuning launches are not
- * counted by asicp_kernel_time);
- * a captured asicp_replay graph is discarded.  Results never depend on the
- * choice, so tuning cannot change what a solve returns. */
+ * NULL); ms_out (host, may be NULL, ASICP_LAUNCH_CHOICES floats) receives the
+ * average time per evaluation of each choice at the index given above.
+ * Synchronises `stream`.  The solve's state is left as it was (tuning
+ * launches are not counted by asicp_kernel_time); a captured asicp_replay
+ * graph is discarded.  Results never depend on the choice, so tuning cannot
+ * change what a solve returns. */
 asicp_status asicp_autotune(asicp_ctx ctx, int32_t reps, void* stream, asicp_launch_t* chosen,
                             float* ms_out);
 

@@ -62,7 +62,23 @@ class asicp_config(C.Structure):
 
 
 class asicp_launch_t(C.Structure):
-    _fields_ = [("xcd_map", C.c_int32), ("fine", C.c_int32)]
+    _fields_ = [("xcd_map", C.c_int32), ("fine", C.c_int32), ("query_blocks", C.c_int32),
+                ("chunk_points", C.c_int32)]
+
+
+ASICP_LAUNCH_CHOICES = 24
+
+
+def launch_index(xcd_map: int, fine: int, query_blocks: int = 4, chunk_points: int = 128) -> int:
+    """Index of a launch choice in asicp_autotune's timings (asicp.h)."""
+    qi = {1: 0, 2: 1, 4: 2}[int(query_blocks)]
+    return ((qi * 2 + (int(chunk_points) == 128)) * 2 + int(xcd_map)) * 2 + int(fine)
+
+
+def launch_choice(v: int) -> dict:
+    """The launch choice with index v (inverse of launch_index)."""
+    return {"xcd_map": (v >> 1) & 1, "fine": v & 1, "query_blocks": 1 << (v >> 3),
+            "chunk_points": 128 if (v >> 2) & 1 else 64}
 
 
 class asicp_result_t(C.Structure):
@@ -192,23 +208,29 @@ def asicp_kernel_time(ctx):
     return float(ms.value), int(n.value), float(pairs.value)
 
 
+def _launch_dict(out) -> dict:
+    return {"xcd_map": int(out.xcd_map), "fine": int(out.fine), "query_blocks": int(out.query_blocks),
+            "chunk_points": int(out.chunk_points)}
+
+
 def asicp_get_launch(ctx) -> dict:
     out = asicp_launch_t()
     _check(load().asicp_get_launch(ctx, C.byref(out)))
-    return {"xcd_map": int(out.xcd_map), "fine": int(out.fine)}
+    return _launch_dict(out)
 
 
-def asicp_set_launch(ctx, xcd_map: int, fine: int):
-    return _check(load().asicp_set_launch(ctx, C.byref(asicp_launch_t(int(xcd_map), int(fine)))))
+def asicp_set_launch(ctx, xcd_map: int, fine: int, query_blocks: int = 4, chunk_points: int = 128):
+    return _check(load().asicp_set_launch(
+        ctx, C.byref(asicp_launch_t(int(xcd_map), int(fine), int(query_blocks), int(chunk_points)))))
 
 
 def asicp_autotune(ctx, reps: int, stream: int):
     """Time every launch choice; returns (chosen dict, ms per evaluation of
-    each choice indexed 2 * xcd_map + fine)."""
+    each choice, indexed as launch_index)."""
     out = asicp_launch_t()
-    ms = (C.c_float * 4)()
+    ms = (C.c_float * ASICP_LAUNCH_CHOICES)()
     _check(load().asicp_autotune(ctx, int(reps), C.c_void_p(stream), C.byref(out), ms))
-    return {"xcd_map": int(out.xcd_map), "fine": int(out.fine)}, [float(v) for v in ms]
+    return _launch_dict(out), [float(v) for v in ms]
 
 
 def asicp_destroy(ctx):
@@ -403,9 +425,10 @@ class Solver:
     def launch(self) -> dict:
         return asicp_get_launch(self.ctx)
 
-    def set_launch(self, xcd_map: int, fine: int):
-        asicp_set_launch(self.ctx, xcd_map, fine)
-        self._launch = {"xcd_map": int(xcd_map), "fine": int(fine)}
+    def set_launch(self, xcd_map: int, fine: int, query_blocks: int = 4, chunk_points: int = 128):
+        asicp_set_launch(self.ctx, xcd_map, fine, query_blocks, chunk_points)
+        self._launch = {"xcd_map": int(xcd_map), "fine": int(fine), "query_blocks": int(query_blocks),
+                        "chunk_points": int(chunk_points)}
 
     def autotune(self, reps: int = 3, stream=None):
         chosen, ms = asicp_autotune(self.ctx, reps, self._stream(stream))

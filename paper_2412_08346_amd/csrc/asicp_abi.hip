@@ -43,7 +43,8 @@ constexpr int kMaxPoints = 1 << 22;   // per object / collision cloud / preshape
 constexpr int kMaxGroups = 1 << 16;
 
 struct Layout {
-  size_t groups, objs, pres, obj_prep, pre_prep, obj_pts, pre_pts, obj_perm, pre_perm, obj_box, pre_box, col_box;
+  size_t groups, objs, pres, obj_prep, pre_prep, obj_pts, pre_pts, obj_perm, pre_perm, obj_box, obj_box1, pre_box,
+      col_box;
   size_t sort_keys, wave_pairs, obj_com, pre_const, col_pts, col_perm, obj_prep_mb, batch_mark, prior;
   size_t theta, cost, col_cost, prev_cost, ncol, converged, grad, grad_ct, grad_col, phi, h, bw_hist, bw_state;
   size_t nn_part, col_part, pen_part, best, best_theta, flags, dbg_nn, dbg_rev;
@@ -60,7 +61,7 @@ struct Shape {
   int max_m, max_m_pad;
   bool minibatch;
   bool prior;
-  long long total_waves, total_gate_wgs;
+  long long total_waves[kNumQ], total_gate_wgs;  // forward waves per query-block count
   bool debug;
   bool timing;
 };
@@ -84,7 +85,8 @@ Layout layout_of(const Shape& s) {
   L.pre_pts = bump(c, (size_t)s.pre_tg * 64 * 16);
   L.obj_perm = bump(c, (size_t)s.obj_tg * 64 * 4);
   L.pre_perm = bump(c, (size_t)s.pre_tg * 64 * 4);
-  L.obj_box = bump(c, (size_t)s.obj_tg / kChunkTG * 32);
+  L.obj_box = bump(c, (size_t)s.obj_tg / 2 * 32);
+  L.obj_box1 = bump(c, (size_t)s.obj_tg * 32);
   L.pre_box = bump(c, (size_t)s.pre_tg / kChunkTG * 32);
   L.col_box = bump(c, 32 * (size_t)(s.gate_chunks > 0 ? s.gate_chunks : 1));
   L.sort_keys = bump(c, (size_t)s.sort_keys * 8);
@@ -93,7 +95,7 @@ Layout layout_of(const Shape& s) {
   L.batch_mark = s.minibatch ? bump(c, (size_t)s.r_total) : 0;
   L.prior = s.prior ? bump(c, 48 * (size_t)s.G) : 0;
   L.col_perm = bump(c, (size_t)(s.c_total > 0 ? s.c_total : 1) * 4);
-  L.wave_pairs = s.timing ? bump(c, 8 * (size_t)s.total_waves) : 0;
+  L.wave_pairs = s.timing ? bump(c, 8 * (size_t)s.total_waves[0]) : 0;
   L.obj_com = bump(c, 16 * (size_t)s.n_obj);
   L.pre_const = bump(c, 32 * (size_t)s.n_pre);
   L.theta = bump(c, 4 * 7 * K);
@@ -190,7 +192,7 @@ asicp_status validate(const asicp_problem* pb, const asicp_config* cfg, Shape& s
     s.pre_tg += (int)((n + kPadPoints - 1) / kPadPoints) * (kPadPoints / 64);
     s.sort_keys += pow2_at_least((long long)n);
     s.n_max = std::max(s.n_max, (int)n);
-    s.max_waves_pp = std::max(s.max_waves_pp, (int)((n + kQueriesPerWave - 1) / kQueriesPerWave));
+    s.max_waves_pp = std::max(s.max_waves_pp, (int)((n + 15) / 16));  // 1 block of 16 queries per wave
     const asicp_sdf& g = pb->sdf[p];
     if (!g.values) return fail(ASICP_E_INVALID, "SDF values of preshape " + std::to_string(p) + " are NULL");
     if (g.nx < 2 || g.ny < 2 || g.nz < 2 || (long long)g.nx * g.ny * g.nz > (1ll << 30))
@@ -200,16 +202,17 @@ asicp_status validate(const asicp_problem* pb, const asicp_config* cfg, Shape& s
       return fail(ASICP_E_INVALID, "SDF origin must be finite");
   }
   if ((long long)pb->s_off[s.n_pre] > (1ll << 30)) return fail(ASICP_E_INVALID, "contact clouds too large");
-  s.total_waves = 0;
+  for (int qi = 0; qi < kNumQ; ++qi) s.total_waves[qi] = 0;
   s.total_gate_wgs = 0;
   for (int o = 0; o < s.n_obj; ++o)
     for (int p = 0; p < s.n_pre; ++p) {
       const long long n = (long long)pb->s_off[p + 1] - pb->s_off[p];
       const long long mc = (long long)pb->c_off[o + 1] - pb->c_off[o];
-      s.total_waves += (long long)s.K * ((n + kQueriesPerWave - 1) / kQueriesPerWave);
+      for (int qi = 0; qi < kNumQ; ++qi)
+        s.total_waves[qi] += (long long)s.K * ((n + 16 * q_blocks(qi) - 1) / (16 * q_blocks(qi)));
       s.total_gate_wgs += (long long)s.K * ((mc + kGateChunk - 1) / kGateChunk);
     }
-  if (s.total_waves > (1ll << 30) || s.total_gate_wgs > (1ll << 30))
+  if (s.total_waves[0] > (1ll << 30) || s.total_gate_wgs > (1ll << 30))
     return fail(ASICP_E_INVALID, "problem too large for one launch");
   if (cfg->k_max < 1) return fail(ASICP_E_INVALID, "k_max must be >= 1");
   if (cfg->k_stein < 0 || cfg->k_stein > cfg->k_max) return fail(ASICP_E_INVALID, "k_stein must be in 0..k_max");
@@ -387,7 +390,7 @@ asicp_status asicp_create(const asicp_problem* pb, const asicp_config* cfg, void
       pi.n = pb->s_off[p + 1] - pb->s_off[p];
       pi.prep_tg_begin = tg;
       pi.ntg = ((pi.n + kPadPoints - 1) / kPadPoints) * (kPadPoints / 64);
-      pi.waves = (pi.n + kQueriesPerWave - 1) / kQueriesPerWave;
+      for (int qi = 0; qi < kNumQ; ++qi) pi.waves[qi] = (pi.n + 16 * q_blocks(qi) - 1) / (16 * q_blocks(qi));
       pi.key_off = (int32_t)key_off;
       key_off += pow2_at_least(pi.n);
       tg += pi.ntg;
@@ -402,15 +405,15 @@ asicp_status asicp_create(const asicp_problem* pb, const asicp_config* cfg, void
         pi.neg_hi[ax] = -1;
       }
     }
-    int wave_off = 0, gate_off = 0;
+    int wave_off[kNumQ] = {0, 0, 0}, gate_off = 0;
     for (int o = 0; o < s.n_obj; ++o)
       for (int p = 0; p < s.n_pre; ++p) {
         GroupInfo& gi = groups[o * s.n_pre + p];
         gi.obj = o;
         gi.pre = p;
-        gi.wave_off = wave_off;
+        for (int qi = 0; qi < kNumQ; ++qi) gi.wave_off[qi] = wave_off[qi];
         gi.gate_off = gate_off;
-        wave_off += s.K * pres[p].waves;
+        for (int qi = 0; qi < kNumQ; ++qi) wave_off[qi] += s.K * pres[p].waves[qi];
         gate_off += s.K * objs[o].gate_chunks;
       }
 
@@ -424,7 +427,7 @@ asicp_status asicp_create(const asicp_problem* pb, const asicp_config* cfg, void
     d.objs = reinterpret_cast<const ObjInfo*>(ws + L.objs);
     d.pres = reinterpret_cast<const PreInfo*>(ws + L.pres);
     d.n_obj = s.n_obj; d.n_pre = s.n_pre; d.K = s.K; d.G = s.G; d.Ktot = s.Ktot;
-    d.total_waves = (int)s.total_waves;
+    for (int qi = 0; qi < kNumQ; ++qi) d.total_waves[qi] = (int)s.total_waves[qi];
     d.total_gate_wgs = (int)s.total_gate_wgs;
     d.max_waves_pp = s.max_waves_pp;
     d.max_gate_chunks = s.max_gate_chunks > 0 ? s.max_gate_chunks : 1;
@@ -437,6 +440,7 @@ asicp_status asicp_create(const asicp_problem* pb, const asicp_config* cfg, void
     d.obj_perm = reinterpret_cast<int32_t*>(ws + L.obj_perm);
     d.pre_perm = reinterpret_cast<int32_t*>(ws + L.pre_perm);
     d.obj_box = reinterpret_cast<float*>(ws + L.obj_box);
+    d.obj_box1 = reinterpret_cast<float*>(ws + L.obj_box1);
     d.pre_box = reinterpret_cast<float*>(ws + L.pre_box);
     d.col_box = reinterpret_cast<float*>(ws + L.col_box);
     d.sort_keys = reinterpret_cast<unsigned long long*>(ws + L.sort_keys);
@@ -486,6 +490,8 @@ asicp_status asicp_create(const asicp_problem* pb, const asicp_config* cfg, void
     d.prior = s.prior ? reinterpret_cast<const float*>(ws + L.prior) : nullptr;
     d.xcd_map = 1;  // launch defaults (asicp_set_launch / asicp_autotune change them)
     d.fine = 1;
+    d.nn_qi = 2;    // 4 blocks of 16 queries per forward wave
+    d.nn_ch = 2;    // 128-point pruning chunks
     std::vector<float> prior_words;
     if (s.prior) {
       prior_words.assign(12 * (size_t)s.G, 0.f);
@@ -813,7 +819,7 @@ asicp_status asicp_kernel_time(asicp_ctx c, double* total_ms, int32_t* launches,
       tot += ms;
     }
     if (nn_pairs) {  // one slot per forward wave (no shared counter to contend for)
-      std::vector<unsigned long long> per((size_t)c->d.total_waves, 0ull);
+      std::vector<unsigned long long> per((size_t)c->d.total_waves[0], 0ull);
       if (c->n_timed > 0 && hipMemcpy(per.data(), c->d.wave_pairs, 8 * per.size(), hipMemcpyDeviceToHost) != hipSuccess)
         return fail(ASICP_E_HIP, "reading the pair counts failed");
       double cnt = 0.0;
@@ -826,12 +832,26 @@ asicp_status asicp_kernel_time(asicp_ctx c, double* total_ms, int32_t* launches,
   });
 }
 
+static void launch_of(const Dev& d, asicp_launch_t* out) {
+  out->xcd_map = d.xcd_map;
+  out->fine = d.fine;
+  out->query_blocks = q_blocks(d.nn_qi);
+  out->chunk_points = 64 * d.nn_ch;
+}
+
+// The launch choice with index v (the order of asicp_autotune's ms_out).
+static void choice_of(int v, Dev& d) {
+  d.fine = v & 1;
+  d.xcd_map = (v >> 1) & 1;
+  d.nn_ch = ((v >> 2) & 1) ? 2 : 1;
+  d.nn_qi = v >> 3;
+}
+
 asicp_status asicp_get_launch(asicp_ctx c, asicp_launch_t* out) {
   return guarded([&]() -> asicp_status {
     g_err.clear();
     if (!c || !out) return fail(ASICP_E_INVALID, "NULL argument");
-    out->xcd_map = c->d.xcd_map;
-    out->fine = c->d.fine;
+    launch_of(c->d, out);
     return ASICP_OK;
   });
 }
@@ -847,8 +867,14 @@ asicp_status asicp_set_launch(asicp_ctx c, const asicp_launch_t* in) {
     if (!c || !in) return fail(ASICP_E_INVALID, "NULL argument");
     if ((in->xcd_map != 0 && in->xcd_map != 1) || (in->fine != 0 && in->fine != 1))
       return fail(ASICP_E_INVALID, "xcd_map and fine must be 0 or 1");
+    if (in->query_blocks != 1 && in->query_blocks != 2 && in->query_blocks != 4)
+      return fail(ASICP_E_INVALID, "query_blocks must be 1, 2 or 4");
+    if (in->chunk_points != 64 && in->chunk_points != 128)
+      return fail(ASICP_E_INVALID, "chunk_points must be 64 or 128");
     c->d.xcd_map = in->xcd_map;
     c->d.fine = in->fine;
+    c->d.nn_qi = in->query_blocks == 1 ? 0 : (in->query_blocks == 2 ? 1 : 2);
+    c->d.nn_ch = in->chunk_points / 64;
     drop_graph(c);
     return ASICP_OK;
   });
@@ -883,13 +909,12 @@ asicp_status asicp_autotune(asicp_ctx c, int32_t reps, void* stream, asicp_launc
     // phase) and the collision kernel while the forward NN runs on `stream`,
     // and joins; how the three share the GPU depends on the choice.
     const bool bandwidth = c->k < c->cfg.k_stein;
-    float ev_ms[4] = {0, 0, 0, 0};
+    float ev_ms[ASICP_LAUNCH_CHOICES] = {};
     bool ok = true, streams_ok = true;
-    for (int v = 0; v < 4 && ok; ++v) {  // v = 2 * xcd_map + fine
+    for (int v = 0; v < ASICP_LAUNCH_CHOICES && ok; ++v) {
       Dev dv = c->d;
       dv.wave_pairs = nullptr;  // tuning launches are not counted
-      dv.xcd_map = v >> 1;
-      dv.fine = v & 1;
+      choice_of(v, dv);
       ok = timed([&] {
         streams_ok = streams_ok && hipEventRecord(c->fork_ev, hs) == hipSuccess &&
                      hipStreamWaitEvent(c->side, c->fork_ev, 0) == hipSuccess;
@@ -905,18 +930,15 @@ asicp_status asicp_autotune(asicp_ctx c, int32_t reps, void* stream, asicp_launc
     if (!ok || !streams_ok) return fail(ASICP_E_HIP, "timing a launch variant failed");
     const asicp_status st = check_launch("autotune");
     if (st != ASICP_OK) return st;
-    int bestv = 2 * c->d.xcd_map + c->d.fine;  // keep the current choice unless another is faster
-    for (int v = 0; v < 4; ++v) {
+    // keep the current choice unless another is faster
+    int bestv = ((c->d.nn_qi * 2 + (c->d.nn_ch == 2)) * 2 + c->d.xcd_map) * 2 + c->d.fine;
+    for (int v = 0; v < ASICP_LAUNCH_CHOICES; ++v) {
       if (ev_ms[v] < ev_ms[bestv]) bestv = v;
       if (ms_out) ms_out[v] = ev_ms[v] / (float)reps;
     }
-    c->d.xcd_map = bestv >> 1;
-    c->d.fine = bestv & 1;
+    choice_of(bestv, c->d);
     drop_graph(c);
-    if (chosen) {
-      chosen->xcd_map = c->d.xcd_map;
-      chosen->fine = c->d.fine;
-    }
+    if (chosen) launch_of(c->d, chosen);
     return ASICP_OK;
   });
 }

@@ -10,11 +10,12 @@ namespace asicp {
 
 constexpr int kWave = 64;          // CDNA wavefront
 constexpr int kTileGroup = 64;     // points per MFMA-ready tile group (4 tiles of 16)
-// Query blocks of 16 per forward-NN wavefront (tuning knob, 1..4) and an
-// optional waves-per-SIMD occupancy request for that kernel (0: compiler's).
-#ifndef ASICP_NN_Q
-#define ASICP_NN_Q 4
-#endif
+// Forward-NN launch shapes, chosen per context at run time (asicp_set_launch,
+// asicp_autotune): 1, 2 or 4 blocks of 16 queries per wavefront (index qi =
+// 0, 1, 2: 1 << qi blocks) and pruning chunks of 1 or 2 tile groups.  A
+// waves-per-SIMD occupancy request for the pruned kernels (0: compiler's).
+constexpr int kNumQ = 3;
+__host__ __device__ constexpr int q_blocks(int qi) { return 1 << qi; }
 #ifndef ASICP_NN_WPE
 #define ASICP_NN_WPE 6
 #endif
@@ -22,12 +23,6 @@ constexpr int kTileGroup = 64;     // points per MFMA-ready tile group (4 tiles 
 #ifndef ASICP_NN_REFRESH
 #define ASICP_NN_REFRESH 4
 #endif
-// Tile groups (64 points each) per pruning chunk: 1 or 2.
-#ifndef ASICP_NN_CHUNK_TG
-#define ASICP_NN_CHUNK_TG 2
-#endif
-constexpr int kNnQ = ASICP_NN_Q;
-constexpr int kQueriesPerWave = 16 * kNnQ;
 constexpr int kGateChunk = 2048;   // collision points per gate workgroup (8 per thread)
 constexpr int kPartStride = 8;     // floats per partial-sum record
 constexpr int kBwSlices = 32;      // workgroups per group in each bandwidth pass
@@ -36,8 +31,8 @@ constexpr float kDummyNorm = 1.0e30f;  // |r|^2 of padding points: never a neare
 // Per-group descriptor (group = (object, preshape)).
 struct GroupInfo {
   int32_t obj, pre;
-  int32_t wave_off;   // first forward-NN wave of this group
-  int32_t gate_off;   // first gate workgroup of this group
+  int32_t gate_off;            // first gate workgroup of this group
+  int32_t wave_off[kNumQ];     // first forward-NN wave of this group, per query-block count
 };
 
 // Per-object descriptor.
@@ -56,7 +51,7 @@ struct ObjInfo {
 struct PreInfo {
   int32_t s_begin, n;      // offset into S inputs, point count
   int32_t prep_tg_begin, ntg;
-  int32_t waves;           // forward-NN waves per particle: ceil(n / 64)
+  int32_t waves[kNumQ];    // forward-NN waves per particle: ceil(n / (16 q_blocks(qi)))
   int32_t nx, ny, nz;
   const float* sdf;
   float ox, oy, oz, cell, inv_cell;
@@ -74,8 +69,8 @@ struct Dev {
   const ObjInfo* objs;
   const PreInfo* pres;
   int32_t n_obj, n_pre, K, G, Ktot;
-  int32_t total_waves, total_gate_wgs;
-  int32_t max_waves_pp, max_gate_chunks;  // partial-record strides
+  int32_t total_waves[kNumQ], total_gate_wgs;  // forward waves per query-block count
+  int32_t max_waves_pp, max_gate_chunks;  // partial-record strides (max_waves_pp at 1 block per wave)
   int32_t n_max, mc_max;
   int32_t max_m, max_m_pad;  // largest object cloud, and padded to whole tile groups
   // clouds in Morton order (index = prep_tg_begin*64 + k): MFMA-ready float4
@@ -89,13 +84,14 @@ struct Dev {
   float4* pre_pts;
   int32_t* obj_perm;
   int32_t* pre_perm;
-  float* obj_box;
+  float* obj_box;   // per chunk of 2 tile groups (128 points)
+  float* obj_box1;  // per tile group (64 points): the forward NN's 64-point chunks
   float* pre_box;
   float* col_box;  // [gate chunks][8]: box of each kGateChunk points of the sorted collision clouds
   float4* col_pts;    // collision clouds in Morton order (offsets as the input's)
   int32_t* col_perm;
   unsigned long long* sort_keys;
-  unsigned long long* wave_pairs;  // [total_waves] distances evaluated per forward wave,
+  unsigned long long* wave_pairs;  // [total_waves[0]] distances evaluated per forward wave,
                                    //   summed over launches (ASICP_FLAG_TIMING only, else NULL)
   int32_t prune;                 // skip object chunks that cannot hold a nearest neighbour
   float* obj_com;   // [n_obj][4]: centroid xyz, largest |r - centroid|^2
@@ -136,6 +132,8 @@ struct Dev {
   // launch choices that change no result (ASICP launch options)
   int32_t xcd_map;          // 0: contiguous work per XCD, 1: dispatch order
   int32_t fine;             // forward NN: per-query chunk test
+  int32_t nn_qi;            // forward NN: 1 << nn_qi blocks of 16 queries per wave
+  int32_t nn_ch;            // forward NN: tile groups per pruning chunk (1 or 2)
 };
 
 typedef float f4v __attribute__((ext_vector_type(4)));
@@ -281,6 +279,30 @@ __device__ __forceinline__ float wave_sum8(const float a[8]) {
   v += dppf<kDppXor2>(v);
   v += dppf<kDppXor1>(v);
   return v;
+}
+
+// Eight sums over each row of 16 lanes at once, in a fixed order (the same
+// for every row, whatever the other rows hold): values k and k + 4 are folded
+// across the row's halves (lane l with 15 - l), then across quarter rows
+// (l with 7 - l), then lane pairs (l with l ^ 1) and (l with l ^ 2).
+// Afterwards lane 4m + j (j = 0, 1) of each row holds the row's total of
+// value 2m + j.
+__device__ __forceinline__ float row_sum8(const float a[8]) {
+  const int l = lane_id() & 15;
+  float b[4], c[2];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const float keep = l < 8 ? a[k] : a[k + 4], send = l < 8 ? a[k + 4] : a[k];
+    b[k] = keep + dppf<kDppMirror>(send);
+  }
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const float keep = (l & 7) < 4 ? b[k] : b[k + 2], send = (l & 7) < 4 ? b[k + 2] : b[k];
+    c[k] = keep + dppf<kDppHalfMirror>(send);
+  }
+  const float keep = (l & 1) ? c[1] : c[0], send = (l & 1) ? c[0] : c[1];
+  const float d = keep + dppf<kDppXor1>(send);
+  return d + dppf<kDppXor2>(d);
 }
 
 // Sum over the 64 lanes of a wave in a fixed order; every lane gets the total.

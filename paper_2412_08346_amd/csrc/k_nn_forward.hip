@@ -5,9 +5,12 @@
 // One wavefront = one particle x 16*Q contact points (consecutive in the
 // Morton-sorted contact cloud, so spatially close), matched against the object
 // cloud of its group with the MFMA core.  By default object chunks that
-// provably cannot hold any of the wave's nearest neighbours are skipped.
-// Partial sums per wavefront: [sum |e|^2, sum e (3), sum s' x e (3),
-// points], e = s' - r_nn, s' relative to the object's centroid (the
+// provably cannot hold any of the wave's nearest neighbours are skipped.  Q
+// (1, 2 or 4 blocks of 16 queries) and the chunk size CH (1 or 2 tile groups
+// of 64 points) are launch choices: every combination returns the same
+// nearest neighbours and partial sums.
+// Partial sums per block of 16 contact points: [sum |e|^2, sum e (3), sum
+// s' x e (3), points], e = s' - r_nn, s' relative to the object's centroid (the
 // finaliser turns the moment into sum (R s) x e = sum s' x e - (t - CoM) x
 // sum e, so no pose value stays live through the scan).
 #include "nn_core.h"
@@ -31,25 +34,29 @@ __device__ __forceinline__ int xcd_logical(int b, int nwg) {
 #define NN_OCCUPANCY
 #endif
 
-template <bool PRUNE, int MAP, bool FINE>
+template <int Q, int CH, bool PRUNE, int MAP, bool FINE>
 __device__ __forceinline__ void nn_forward_body(const Dev& d) {
-  const int nwg = (d.total_waves + 3) >> 2;
+  constexpr int QI = Q == 1 ? 0 : (Q == 2 ? 1 : 2);
+  static_assert(q_blocks(QI) == Q, "1, 2 or 4 query blocks per wave");
+  const int total_waves = d.total_waves[QI];
+  const int nwg = (total_waves + 3) >> 2;
   const int logical = xcd_logical<MAP>(blockIdx.x, nwg);
   if (logical >= nwg) return;
   const int wave = __builtin_amdgcn_readfirstlane(logical * 4 + (int)(threadIdx.x >> 6));
-  if (wave >= d.total_waves) return;
+  if (wave >= total_waves) return;
   const int lane = lane_id();
 
   int lo = 0, hi = d.G - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (d.groups[mid].wave_off <= wave) lo = mid; else hi = mid - 1;
+    if (d.groups[mid].wave_off[QI] <= wave) lo = mid; else hi = mid - 1;
   }
   const GroupInfo gi = d.groups[lo];
   const PreInfo& pi = d.pres[gi.pre];
   const ObjInfo& oi = d.objs[gi.obj];
-  const int local = wave - gi.wave_off;
-  const int pj = local / pi.waves, chunk = local - pj * pi.waves;
+  const int local = wave - gi.wave_off[QI];
+  const int pw = pi.waves[QI];
+  const int pj = local / pw, chunk = local - pj * pw;
   const int i = lo * d.K + pj;
 
   // the pose relative to the object's centroid: the object cloud is stored
@@ -60,7 +67,7 @@ __device__ __forceinline__ void nn_forward_body(const Dev& d) {
   const float* com = d.obj_com + 4 * gi.obj;
   for (int a = 0; a < 3; ++a) t[a] = uniform_f(t[a] - com[a]);
 
-  constexpr int Q = kNnQ, QPW = kQueriesPerWave;
+  constexpr int QPW = 16 * Q;
   const float4* spts = d.pre_pts + (size_t)pi.prep_tg_begin * 64;  // Morton-sorted contact cloud
   const int comp = lane >> 4, j = lane & 15;
   float bq[Q], qc[3 * Q];
@@ -84,10 +91,12 @@ __device__ __forceinline__ void nn_forward_body(const Dev& d) {
     int vq[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) vq[q] = max(0, min(16, pi.n - (chunk * QPW + q * 16)));
-    pairs = nn_scan_pruned<Q, true, FINE>(prep, oi.ntg, oi.m, d.obj_box + (size_t)oi.prep_tg_begin / kChunkTG * 8,
-                                          bq, nullptr, qc, vq, com[3], idx, d.flags + 1);
+    const float* box = CH == 1 ? d.obj_box1 + (size_t)oi.prep_tg_begin * 8
+                               : d.obj_box + (size_t)oi.prep_tg_begin / 2 * 8;
+    pairs = nn_scan_pruned<Q, true, FINE, CH>(prep, oi.ntg, oi.m, box, bq, nullptr, qc, vq, com[3], idx,
+                                              d.flags + 1);
   } else {
-    nn_scan<Q>(prep, oi.ntg, bq, qc, idx, d.flags + 1);
+    nn_scan<Q, CH>(prep, oi.ntg, bq, qc, idx, d.flags + 1);
     pairs = (long long)oi.m * min(QPW, pi.n - chunk * QPW);
   }
 
@@ -126,9 +135,14 @@ __device__ __forceinline__ void nn_forward_body(const Dev& d) {
       d.dbg_nn[(size_t)i * d.n_max + n_orig] = d.obj_perm[(size_t)oi.prep_tg_begin * 64 + my];
     }
   }
+  // one record per block of 16 contact points (a row of lanes), summed in
+  // the same order whatever the launch shape, so every launch choice gives
+  // the same records
   const float sums[8] = {e2, ex, ey, ez, mx, my_, mz, cnt};
-  const float tot = wave_sum8(sums);  // lane 8k holds sums[k]
-  if ((lane & 7) == 0) d.nn_part[((size_t)i * d.max_waves_pp + chunk) * kPartStride + (lane >> 3)] = tot;
+  const float tot = row_sum8(sums);  // lane 4m + j of row r: total of sums[2m + j] over block r
+  const int blk16 = chunk * Q + comp;
+  if (comp < Q && blk16 < pi.waves[0] && (lane & 2) == 0)
+    d.nn_part[((size_t)i * d.max_waves_pp + blk16) * kPartStride + (((lane & 15) >> 2) << 1 | (lane & 1))] = tot;
   // the wave's own slot: launches are ordered on the stream, so a plain
   // read-modify-write accumulates over them without contention
   if (lane == 0 && d.wave_pairs) d.wave_pairs[wave] += (unsigned long long)pairs;
@@ -137,30 +151,47 @@ __device__ __forceinline__ void nn_forward_body(const Dev& d) {
 // The pruned scan keeps fewer registers live per wavefront and gains from
 // more wavefronts per SIMD to hide its per-chunk loads.  The full scan folds
 // one tile group's MFMA results at a time, which fits 3 wavefronts per SIMD
-// (168 registers; 4 would spill heavily).
-template <int MAP, bool FINE>
+// at 4 query blocks (168 registers; 4 would spill heavily); it visits every
+// chunk in index order, so its chunk is always 2 tile groups.
+template <int Q, int CH, int MAP, bool FINE>
 __global__ __launch_bounds__(256) NN_OCCUPANCY void k_nn_forward(Dev d) {
-  nn_forward_body<true, MAP, FINE>(d);
+  nn_forward_body<Q, CH, true, MAP, FINE>(d);
 }
-template <int MAP>
+template <int Q, int MAP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_nn_forward_full(Dev d) {
-  nn_forward_body<false, MAP, false>(d);
+  nn_forward_body<Q, 2, false, MAP, false>(d);
+}
+
+template <int Q, int CH>
+static void launch_pruned(const Dev& d, dim3 g, dim3 b, hipStream_t s) {
+  if (d.xcd_map) {
+    if (d.fine) hipLaunchKernelGGL((k_nn_forward<Q, CH, 1, true>), g, b, 0, s, d);
+    else hipLaunchKernelGGL((k_nn_forward<Q, CH, 1, false>), g, b, 0, s, d);
+  } else {
+    if (d.fine) hipLaunchKernelGGL((k_nn_forward<Q, CH, 0, true>), g, b, 0, s, d);
+    else hipLaunchKernelGGL((k_nn_forward<Q, CH, 0, false>), g, b, 0, s, d);
+  }
+}
+
+template <int Q>
+static void launch_shape(const Dev& d, dim3 g, dim3 b, hipStream_t s) {
+  if (!d.prune) {
+    if (d.xcd_map) hipLaunchKernelGGL((k_nn_forward_full<Q, 1>), g, b, 0, s, d);
+    else hipLaunchKernelGGL((k_nn_forward_full<Q, 0>), g, b, 0, s, d);
+  } else if (d.nn_ch == 1) {
+    launch_pruned<Q, 1>(d, g, b, s);
+  } else {
+    launch_pruned<Q, 2>(d, g, b, s);
+  }
 }
 
 void launch_nn_forward(const Dev& d, hipStream_t s) {
-  const int nwg = (d.total_waves + 3) / 4;
+  const int nwg = (d.total_waves[d.nn_qi] + 3) / 4;
   const int grid = ((nwg + 7) / 8) * 8;
   const dim3 g(grid), b(256);
-  if (!d.prune) {
-    if (d.xcd_map) hipLaunchKernelGGL(k_nn_forward_full<1>, g, b, 0, s, d);
-    else hipLaunchKernelGGL(k_nn_forward_full<0>, g, b, 0, s, d);
-  } else if (d.xcd_map) {
-    if (d.fine) hipLaunchKernelGGL((k_nn_forward<1, true>), g, b, 0, s, d);
-    else hipLaunchKernelGGL((k_nn_forward<1, false>), g, b, 0, s, d);
-  } else {
-    if (d.fine) hipLaunchKernelGGL((k_nn_forward<0, true>), g, b, 0, s, d);
-    else hipLaunchKernelGGL((k_nn_forward<0, false>), g, b, 0, s, d);
-  }
+  if (d.nn_qi == 0) launch_shape<1>(d, g, b, s);
+  else if (d.nn_qi == 1) launch_shape<2>(d, g, b, s);
+  else launch_shape<4>(d, g, b, s);
 }
 
 }  // namespace asicp

@@ -52,7 +52,8 @@ __global__ __launch_bounds__(256) void k_finalize(Dev d, int k, int final_eval) 
 
   float s[7] = {0, 0, 0, 0, 0, 0, 0};
   const float* np = d.nn_part + (size_t)i * d.max_waves_pp * kPartStride;
-  for (int c = lane; c < pi.waves; c += 64)
+  const int blocks = pi.waves[0];  // one record per 16 contact points
+  for (int c = lane; c < blocks; c += 64)
 #pragma unroll
     for (int a = 0; a < 7; ++a) s[a] += np[c * kPartStride + a];
   float cs[8] = {0, 0, 0, 0, 0, 0, 0, 0};

@@ -263,22 +263,27 @@ __global__ __launch_bounds__(1024) void k_sort_cloud(Dev d) {
     }
   }
   __syncthreads();
-  // chunk boxes (kChunkPts points per chunk; an all-padding chunk gets an
-  // empty box)
-  const int nch = ntg / kChunkTG;
-  for (int c = tid; c < nch; c += 1024) {
-    float bb[6] = {__builtin_inff(), __builtin_inff(), __builtin_inff(),
-                   -__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
-    const int k1 = min(n, (c + 1) * kChunkPts);
-    for (int k = c * kChunkPts; k < k1; ++k) {
-      const float4 p = pts[base + k];
-      bb[0] = fminf(bb[0], p.x); bb[1] = fminf(bb[1], p.y); bb[2] = fminf(bb[2], p.z);
-      bb[3] = fmaxf(bb[3], p.x); bb[4] = fmaxf(bb[4], p.y); bb[5] = fmaxf(bb[5], p.z);
+  // chunk boxes (an all-padding chunk gets an empty box): every 128 points
+  // (2 tile groups), and for an object cloud also every 64 points (the
+  // forward NN's pruning chunk is a launch choice)
+  auto chunk_boxes = [&](int tgs, float* out) {
+    const int pts_per = 64 * tgs, nch = ntg / tgs;
+    for (int c = tid; c < nch; c += 1024) {
+      float bb[6] = {__builtin_inff(), __builtin_inff(), __builtin_inff(),
+                     -__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
+      const int k1 = min(n, (c + 1) * pts_per);
+      for (int k = c * pts_per; k < k1; ++k) {
+        const float4 p = pts[base + k];
+        bb[0] = fminf(bb[0], p.x); bb[1] = fminf(bb[1], p.y); bb[2] = fminf(bb[2], p.z);
+        bb[3] = fmaxf(bb[3], p.x); bb[4] = fmaxf(bb[4], p.y); bb[5] = fmaxf(bb[5], p.z);
+      }
+      float* o = out + ((size_t)tg0 / tgs + c) * 8;
+      o[0] = bb[0]; o[1] = bb[1]; o[2] = bb[2]; o[3] = 0.f;
+      o[4] = bb[3]; o[5] = bb[4]; o[6] = bb[5]; o[7] = 0.f;
     }
-    float* o = box + ((size_t)tg0 / kChunkTG + c) * 8;
-    o[0] = bb[0]; o[1] = bb[1]; o[2] = bb[2]; o[3] = 0.f;
-    o[4] = bb[3]; o[5] = bb[4]; o[6] = bb[5]; o[7] = 0.f;
-  }
+  };
+  chunk_boxes(kChunkTG, box);
+  if (kind == 0) chunk_boxes(1, d.obj_box1);
 }
 
 // Box of negative SDF nodes per preshape (grid: n_pre x 64 workgroups).
@@ -320,7 +325,7 @@ __global__ __launch_bounds__(256) void k_setup_state(Dev d, const float* theta0,
   for (int w = i; w < d.G * 256; w += gridDim.x * 256) d.bw_hist[w] = 0u;
   if (i < 4) d.flags[i] = 0;
   if (d.wave_pairs)
-    for (int w = i; w < d.total_waves; w += gridDim.x * 256) d.wave_pairs[w] = 0ull;
+    for (int w = i; w < d.total_waves[0]; w += gridDim.x * 256) d.wave_pairs[w] = 0ull;
   if (i >= d.Ktot) return;
   const int K = d.Ktot;
   for (int a = 0; a < 7; ++a) d.theta[a * K + i] = theta0[a * K + i];

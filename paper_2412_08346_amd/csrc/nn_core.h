@@ -62,12 +62,13 @@ __device__ __forceinline__ float4 load_tg(__amdgpu_buffer_rsrc_t r, int tg, unsi
   return f;
 }
 
-// Chunk = kChunkTG tile groups (64 or 128 points), the unit of spatial
-// pruning; prepared clouds are padded to a multiple of 256 points, a whole
-// number of chunk pairs, so the full scan's loop runs without a tail.
-constexpr int kChunkTG = ASICP_NN_CHUNK_TG;
-static_assert(kChunkTG == 1 || kChunkTG == 2, "a chunk is one or two tile groups");
-constexpr int kChunkPts = 64 * kChunkTG;
+// Chunk = CH tile groups (CH = 1 or 2: 64 or 128 points), the unit of
+// spatial pruning; the scans below take CH as a template argument (the
+// forward NN's is a launch choice; the contact clouds of the reverse NN use
+// kChunkTG).  Prepared clouds are padded to a multiple of 256 points, a
+// whole number of chunk pairs for either size, so the full scan's loop runs
+// without a tail.
+constexpr int kChunkTG = 2;
 constexpr int kPadPoints = 256;
 
 // Fold the 16 distances a lane holds for one query and one tile group into
@@ -97,7 +98,7 @@ __device__ __forceinline__ void tile_group(const float4& a, const float* b, floa
   }
 }
 
-// Fold one chunk (kChunkTG tile groups) into each lane's running minimum.  The
+// Fold one chunk (CH tile groups) into each lane's running minimum.  The
 // chunk's own minimum is folded first, so that the chunk recorded with the
 // running minimum is the lowest-index chunk holding it whatever order the
 // chunks are visited in: a chunk with a smaller value replaces it, one with
@@ -106,14 +107,14 @@ __device__ __forceinline__ void tile_group(const float4& a, const float* b, floa
 // smaller, which selects the same chunk, and keeps one tile group's MFMA
 // results live at a time (fewer registers, so more wavefronts per SIMD hide
 // the matrix-core latency).
-template <int Q, bool ASCENDING = false>
-__device__ __forceinline__ void chunk_step(const float4 (&a)[kChunkTG], const float* b, float* best, int* bch,
+template <int Q, int CH, bool ASCENDING = false>
+__device__ __forceinline__ void chunk_step(const float4 (&a)[CH], const float* b, float* best, int* bch,
                                            int c, const bool* need = nullptr) {
   float m[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) m[q] = __builtin_inff();
 #pragma unroll
-  for (int t = 0; t < kChunkTG; ++t) {
+  for (int t = 0; t < CH; ++t) {
     if (ASCENDING && t) __builtin_amdgcn_sched_barrier(0);
     tile_group<Q>(a[t], b, m, need);
   }
@@ -137,14 +138,14 @@ __device__ __forceinline__ void chunk_step(const float4 (&a)[kChunkTG], const fl
 // performs.
 //
 // With BATCH, when one lane group wins (the usual case), the query's four
-// lanes test that group's 4 rows in all 4 kChunkTG tiles of the chunk: lane
-// group g takes tiles g kChunkTG .. g kChunkTG + kChunkTG - 1 (sub-tiles of
+// lanes test that group's 4 rows in all 4 CH tiles of the chunk: lane
+// group g takes tiles g CH .. g CH + CH - 1 (sub-tiles of
 // one tile group, adjacent in the prepared cloud), so 16 buffer loads with
 // immediate offsets fetch all operands at once; qc holds the lane's query
 // (x, y, z per block) from the caller.  Otherwise (or on ties between lane
 // groups, which test all 16 rows) the lanes split the tiles and test row by
 // row, reading the query from the B operand.
-template <int Q, bool BATCH>
+template <int Q, bool BATCH, int CH>
 __device__ __forceinline__ void nn_rescan(const float4* __restrict__ prep, __amdgpu_buffer_rsrc_t rs,
                                           const float* b, const float* qc, const float* best,
                                           const int* bch, int* idx, int32_t* miss) {
@@ -164,25 +165,25 @@ __device__ __forceinline__ void nn_rescan(const float4* __restrict__ prep, __amd
     if (cmin != 0x7fffffff) {
       if (BATCH && ng == 1) {
         const float s0 = qc[3 * q], s1 = qc[3 * q + 1], s2 = qc[3 * q + 2];
-        const int t0 = grp * kChunkTG;  // first tile of the lane group within the chunk
+        const int t0 = grp * CH;  // first tile of the lane group within the chunk
         const int tgi = t0 >> 2, u0 = t0 & 3, r0 = 4 * gw;
-        const unsigned voff = 4u * (unsigned)((cmin * kChunkTG + tgi) * 256 + r0 * 4 + u0);
-        float a[4][4][kChunkTG];  // [component][row][sub-tile]
+        const unsigned voff = 4u * (unsigned)((cmin * CH + tgi) * 256 + r0 * 4 + u0);
+        float a[4][4][CH];  // [component][row][sub-tile]
 #pragma unroll
         for (int k = 0; k < 4; ++k)
 #pragma unroll
           for (int ii = 0; ii < 4; ++ii) {
-            if (kChunkTG == 2) {
+            if (CH == 2) {
               const float2 v = load_f2(rs, voff + 16u * (unsigned)(k * 16 + ii));
               a[k][ii][0] = v.x;
-              a[k][ii][kChunkTG - 1] = v.y;
+              a[k][ii][CH - 1] = v.y;
             } else {
               a[k][ii][0] = load_f1(rs, voff + 16u * (unsigned)(k * 16 + ii));
             }
           }
-        const int tbase = (cmin * kChunkTG * 4 + t0) * 16 + r0;
+        const int tbase = (cmin * CH * 4 + t0) * 16 + r0;
 #pragma unroll
-        for (int u = kChunkTG - 1; u >= 0; --u)
+        for (int u = CH - 1; u >= 0; --u)
 #pragma unroll
           for (int ii = 3; ii >= 0; --ii) {  // the lowest index is tested last, so it wins
             float acc = __builtin_fmaf(a[0][ii][u], s0, 0.0f);
@@ -197,16 +198,16 @@ __device__ __forceinline__ void nn_rescan(const float4* __restrict__ prep, __amd
         const float s2 = __shfl(b[q], j + 32, 64);
         const float s3 = __shfl(b[q], j + 48, 64);
         const int r0 = (ng > 1) ? 0 : 4 * gw, r1 = (ng > 1) ? 16 : 4 * gw + 4;
-        for (int tt = 0; tt < kChunkTG && cand == 0x7fffffff; ++tt) {
+        for (int tt = 0; tt < CH && cand == 0x7fffffff; ++tt) {
           const int t = grp + 4 * tt;  // tile within the chunk: tile group t/4, sub-tile t%4
-          const float* base = pf + (size_t)(cmin * kChunkTG + (t >> 2)) * 256 + (t & 3);
+          const float* base = pf + (size_t)(cmin * CH + (t >> 2)) * 256 + (t & 3);
           for (int i = r0; i < r1; ++i) {
             float acc = __builtin_fmaf(base[(0 * 16 + i) * 4], s0, 0.0f);
             acc = __builtin_fmaf(base[(1 * 16 + i) * 4], s1, acc);
             acc = __builtin_fmaf(base[(2 * 16 + i) * 4], s2, acc);
             acc = __builtin_fmaf(base[(3 * 16 + i) * 4], s3, acc);
             if (acc == vmin) {
-              cand = ((cmin * kChunkTG + (t >> 2)) * 4 + (t & 3)) * 16 + i;
+              cand = ((cmin * CH + (t >> 2)) * 4 + (t & 3)) * 16 + i;
               break;
             }
           }
@@ -230,7 +231,7 @@ __device__ __forceinline__ void nn_rescan(const float4* __restrict__ prep, __amd
 // with the smallest FP32 value.  A query whose minimum cannot be re-found
 // (only possible with non-finite inputs) gets index 0 and sets *miss.
 // qc[3q + a] = component a of the lane's query (l % 16) of block q.
-template <int Q>
+template <int Q, int CH>
 __device__ __forceinline__ void nn_scan(const float4* __restrict__ prep, int ntg, const float* bq,
                                         const float* qc, int* idx, int32_t* miss) {
   const int lane = lane_id();
@@ -242,23 +243,23 @@ __device__ __forceinline__ void nn_scan(const float4* __restrict__ prep, int ntg
     best[q] = __builtin_inff();
     bch[q] = 0;
   }
-  const int nch = ntg / kChunkTG;  // even
+  const int nch = ntg / CH;  // even
   const unsigned lo = 16u * (unsigned)lane;
   const __amdgpu_buffer_rsrc_t rs = cloud_rsrc(prep, ntg);
-  float4 x[kChunkTG], y[kChunkTG];
+  float4 x[CH], y[CH];
 #pragma unroll
-  for (int t = 0; t < kChunkTG; ++t) x[t] = load_tg(rs, t, lo);
+  for (int t = 0; t < CH; ++t) x[t] = load_tg(rs, t, lo);
   for (int c = 0; c < nch; c += 2) {
 #pragma unroll
-    for (int t = 0; t < kChunkTG; ++t) y[t] = load_tg(rs, (c + 1) * kChunkTG + t, lo);
-    chunk_step<Q, true>(x, b, best, bch, c);
+    for (int t = 0; t < CH; ++t) y[t] = load_tg(rs, (c + 1) * CH + t, lo);
+    chunk_step<Q, CH, true>(x, b, best, bch, c);
     if (c + 2 < nch) {
 #pragma unroll
-      for (int t = 0; t < kChunkTG; ++t) x[t] = load_tg(rs, (c + 2) * kChunkTG + t, lo);
+      for (int t = 0; t < CH; ++t) x[t] = load_tg(rs, (c + 2) * CH + t, lo);
     }
-    chunk_step<Q, true>(y, b, best, bch, c + 1);
+    chunk_step<Q, CH, true>(y, b, best, bch, c + 1);
   }
-  nn_rescan<Q, true>(prep, rs, b, qc, best, bch, idx, miss);
+  nn_rescan<Q, true, CH>(prep, rs, b, qc, best, bch, idx, miss);
 }
 
 // Q non-negative floats packed as FP16 pairs with rounding toward zero, so an
@@ -342,7 +343,7 @@ __device__ __forceinline__ float point_box2(const float* p, const float* bx) {
 // 5e-7 (r2max + |s|^2) (the rounding of the fused chain |r|^2 - 2 r.s is
 // at most a few units of 2^-24 times |r|^2 + 2 |r| |s| <= 2 (|r|^2 + |s|^2)),
 // plus 1e-7 (squared length units).
-template <int Q, bool BATCH_RESCAN, bool FINE>
+template <int Q, bool BATCH_RESCAN, bool FINE, int CH>
 __device__ __forceinline__ long long nn_scan_pruned(const float4* __restrict__ prep, int ntg, int m,
                                                     const float* __restrict__ box, const float* bq,
                                                     const float* snorm, const float* qc, const int* vq,
@@ -364,7 +365,7 @@ __device__ __forceinline__ long long nn_scan_pruned(const float4* __restrict__ p
       qhi[q][a] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(hi), 16 * a));
     }
   }
-  const int nch = ntg / kChunkTG;
+  const int nch = ntg / CH;
   const unsigned lo = 16u * (unsigned)lane;
   const __amdgpu_buffer_rsrc_t rs = cloud_rsrc(prep, ntg);
   // qb[q]: the lane's query's current best squared distance (block q), with
@@ -427,11 +428,11 @@ __device__ __forceinline__ long long nn_scan_pruned(const float4* __restrict__ p
   for (int q = 0; q < Q; ++q) vqu[q] = __builtin_amdgcn_readfirstlane(vq[q]);
   long long pairs = 0;
   {
-    const int pts = max(0, min(kChunkPts, mu - kChunkPts * c0));
-    float4 x0[kChunkTG];
+    const int pts = max(0, min((64 * CH), mu - (64 * CH) * c0));
+    float4 x0[CH];
 #pragma unroll
-    for (int t = 0; t < kChunkTG; ++t) x0[t] = load_tg(rs, c0 * kChunkTG + t, lo);
-    chunk_step<Q>(x0, b, best, bch, c0);
+    for (int t = 0; t < CH; ++t) x0[t] = load_tg(rs, c0 * CH + t, lo);
+    chunk_step<Q, CH>(x0, b, best, bch, c0);
 #pragma unroll
     for (int q = 0; q < Q; ++q) pairs += (long long)(pts * vqu[q]);
   }
@@ -484,17 +485,17 @@ __device__ __forceinline__ long long nn_scan_pruned(const float4* __restrict__ p
     // One step compares chunk cl (held in cur) and loads the next candidate
     // into nxt while it does; two steps per iteration swap the roles of the
     // register pairs, so no copy is made between them.
-    float4 x[kChunkTG], y[kChunkTG];
-    auto fetch = [&](float4 (&dst)[kChunkTG], int l) {
+    float4 x[CH], y[CH];
+    auto fetch = [&](float4 (&dst)[CH], int l) {
 #pragma unroll
-      for (int t = 0; t < kChunkTG; ++t) dst[t] = load_tg(rs, (blk + l) * kChunkTG + t, lo);
+      for (int t = 0; t < CH; ++t) dst[t] = load_tg(rs, (blk + l) * CH + t, lo);
     };
     fetch(x, cl);
-    auto step = [&](const float4 (&cur)[kChunkTG], float4 (&nxt)[kChunkTG]) {
+    auto step = [&](const float4 (&cur)[CH], float4 (&nxt)[CH]) {
       const int cc = blk + cl;
       int nl = pick();
       if (nl >= 0) fetch(nxt, nl);
-      const int pts = max(0, min(kChunkPts, mu - kChunkPts * cc));
+      const int pts = max(0, min((64 * CH), mu - (64 * CH) * cc));
       // block q is compared only if chunk cc is still in its mask (a scalar
       // bit test) and, with FINE, some query of the block may improve
       bool need[Q];
@@ -505,7 +506,7 @@ __device__ __forceinline__ long long nn_scan_pruned(const float4* __restrict__ p
         if (FINE && need[q]) need[q] = __ballot(point_box2(qc + 3 * q, bx) <= qb[q]) != 0ull;
         pairs += need[q] ? (long long)(pts * vqu[q]) : 0ll;
       }
-      chunk_step<Q>(cur, b, best, bch, cc, need);
+      chunk_step<Q, CH>(cur, b, best, bch, cc, need);
       if (++since == ASICP_NN_REFRESH) {
         since = 0;
         refresh();
@@ -537,7 +538,7 @@ __device__ __forceinline__ long long nn_scan_pruned(const float4* __restrict__ p
       step(y, x);
     }
   }
-  nn_rescan<Q, BATCH_RESCAN>(prep, rs, b, qc, best, bch, idx, miss);
+  nn_rescan<Q, BATCH_RESCAN, CH>(prep, rs, b, qc, best, bch, idx, miss);
   return pairs;
 }
 

@@ -172,3 +172,17 @@ def test_launch_calls_reject_null_and_bad_values():
     assert L.asicp_get_launch(None, C.byref(out)) == A.ASICP_E_INVALID
     assert L.asicp_set_launch(None, C.byref(out)) == A.ASICP_E_INVALID
     assert L.asicp_autotune(None, 3, None, None, None) == A.ASICP_E_INVALID
+
+
+def test_launch_choice_index_matches_the_header():
+    """The binding's launch-choice index (the order of asicp_autotune's
+    timings) is a bijection onto 0 .. ASICP_LAUNCH_CHOICES - 1."""
+    text = open(os.path.join(ROOT, "include", "asicp.h")).read()
+    n = int(re.search(r"#define ASICP_LAUNCH_CHOICES (\d+)", text).group(1))
+    assert n == A.ASICP_LAUNCH_CHOICES == 24
+    seen = set()
+    for v in range(n):
+        ch = A.launch_choice(v)
+        assert A.launch_index(**ch) == v
+        seen.add(tuple(sorted(ch.items())))
+    assert len(seen) == n

@@ -32,14 +32,15 @@ def test_traffic_record_follows_the_kernel_source():
     # the record is reported only for the kernel source it was measured on;
     # after a change to that source the traffic is null until re-measured
     same = h.hexdigest() == bench.NN_TRAFFIC["sha256"]
-    assert set(bench.NN_TRAFFIC["bytes"]) == {"0,0", "0,1", "1,0", "1,1"}
-    for mp in (0, 1):
-        for fn in (0, 1):
-            b = bench.nn_traffic("paper", {"xcd_map": mp, "fine": fn}, False)
-            assert b == (bench.NN_TRAFFIC["bytes"][f"{mp},{fn}"] if same else None)
-            # other workloads and the full scan were not measured: null
-            assert bench.nn_traffic("batched", {"xcd_map": mp, "fine": fn}, False) is None
-            assert bench.nn_traffic("paper", {"xcd_map": mp, "fine": fn}, True) is None
+    import paper_2412_08346_amd as A
+    for v in range(A.ASICP_LAUNCH_CHOICES):
+        ch = A.launch_choice(v)
+        key = f"{ch['xcd_map']},{ch['fine']},{ch['query_blocks']},{ch['chunk_points']}"
+        b = bench.nn_traffic("paper", ch, False)
+        assert b == (bench.NN_TRAFFIC["bytes"].get(key) if same else None)
+        # other workloads and the full scan were not measured: null
+        assert bench.nn_traffic("batched", ch, False) is None
+        assert bench.nn_traffic("paper", ch, True) is None
 
 
 def test_more_than_one_gpu_exits_with_a_message():

@@ -343,11 +343,12 @@ def test_exact_ties_give_one_valid_nearest_point_for_every_launch():
     d_ref = ((sp - R[ref]) ** 2).sum(-1)
     first = None
     for prune in (True, False):
-        for xcd_map, fine in ((0, 0), (0, 1), (1, 0), (1, 1)):
-            if not prune and fine:
-                continue
+        for v in range(A.ASICP_LAUNCH_CHOICES):
+            ch = A.launch_choice(v)
+            if not prune and (ch["fine"] or ch["chunk_points"] == 64):
+                continue  # the full scan has neither test
             sol = A.Solver(pb, st, debug=True, theta0=th, prune=prune)
-            sol.set_launch(xcd_map, fine)
+            sol.set_launch(**ch)
             sol.step(1)
             g = sol.result()
             sol.close()
@@ -355,7 +356,7 @@ def test_exact_ties_give_one_valid_nearest_point_for_every_launch():
             assert ((got >= 0) & (got < len(obj))).all()
             d_got = ((sp - R[got]) ** 2).sum(-1)
             mirror = int((got != ref).sum())
-            say(f"[ties] prune={prune} launch=({xcd_map},{fine}): other copy for {mirror} of {got.size}")
+            say(f"[ties] prune={prune} launch={ch}: other copy for {mirror} of {got.size}")
             assert np.array_equal(d_got, d_ref), "not a nearest point"
             if first is None:
                 first = got
@@ -853,7 +854,7 @@ def _run(pb, st, launch=None, tune=False, steps=3):
     s = A.Solver(pb, st, debug=True)
     chosen = None
     if launch is not None:
-        s.set_launch(*launch)
+        s.set_launch(**launch)
     if tune:
         chosen, ms = s.autotune(reps=2)
         say("[parity] autotune", chosen, ms)
@@ -874,15 +875,31 @@ def test_launch_choices_are_bit_identical(wl):
         pb, st = synth.workload_paper_scale()
     else:
         pb, st = synth.workload_batched(n_obj=8, K=32, m_lo=1024, m_hi=8192, grid_n=64)
-    ref, _ = _run(pb, st, launch=(0, 0))
-    for launch in ((0, 1), (1, 0), (1, 1)):
+    A, torch = _gpu()
+    ref, _ = _run(pb, st, launch=A.launch_choice(0))
+    for v in range(1, A.ASICP_LAUNCH_CHOICES):
+        launch = A.launch_choice(v)
         r, _ = _run(pb, st, launch=launch)
         for key in ("theta", "cost", "ncol", "grad", "nn_idx", "rev_idx", "h"):
             assert np.array_equal(np.asarray(r[key]), np.asarray(ref[key])), (launch, key)
     r, chosen = _run(pb, st, tune=True)
-    assert chosen["xcd_map"] in (0, 1) and chosen["fine"] in (0, 1)
+    assert A.launch_index(**chosen) in range(A.ASICP_LAUNCH_CHOICES)
     for key in ("theta", "cost", "ncol", "grad", "nn_idx", "rev_idx", "h"):
         assert np.array_equal(np.asarray(r[key]), np.asarray(ref[key])), ("tuned", key)
+
+
+def test_launch_choices_rejected_on_the_host():
+    A, torch = _gpu()
+    pb, st = synth.workload_small(k_max=2)
+    s = A.Solver(pb, st)
+    assert s.launch() == {"xcd_map": 1, "fine": 1, "query_blocks": 4, "chunk_points": 128}
+    for bad in (dict(xcd_map=2, fine=0), dict(xcd_map=0, fine=0, query_blocks=3),
+                dict(xcd_map=0, fine=0, chunk_points=96)):
+        with pytest.raises(A.AsicpError) as e:
+            s.set_launch(**bad)
+        assert e.value.status == A.ASICP_E_INVALID
+    assert s.launch() == {"xcd_map": 1, "fine": 1, "query_blocks": 4, "chunk_points": 128}
+    s.close()
 
 
 def test_autotune_leaves_the_pair_counter():
