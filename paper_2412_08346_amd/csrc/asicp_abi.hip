@@ -98,7 +98,7 @@ Layout layout_of(const Shape& s) {
   L.wave_pairs = s.timing ? bump(c, 8 * (size_t)s.total_waves[0]) : 0;
   L.obj_com = bump(c, 16 * (size_t)s.n_obj);
   L.pre_const = bump(c, 32 * (size_t)s.n_pre);
-  L.theta = bump(c, 4 * 7 * K);
+  L.theta = bump(c, 2 * 4 * 7 * K);  // two pose buffers (Stein update: read one, write the other)
   L.cost = bump(c, 4 * K);
   L.col_cost = bump(c, 4 * K);
   L.prev_cost = bump(c, 4 * K);
@@ -451,6 +451,7 @@ asicp_status asicp_create(const asicp_problem* pb, const asicp_config* cfg, void
     d.obj_com = reinterpret_cast<float*>(ws + L.obj_com);
     d.pre_const = reinterpret_cast<float*>(ws + L.pre_const);
     d.theta = reinterpret_cast<float*>(ws + L.theta);
+    d.theta_next = d.theta + 7 * (size_t)s.Ktot;
     d.cost = reinterpret_cast<float*>(ws + L.cost);
     d.col_cost = reinterpret_cast<float*>(ws + L.col_cost);
     d.prev_cost = reinterpret_cast<float*>(ws + L.prev_cost);
@@ -624,7 +625,13 @@ static asicp_status iterate(asicp_ctx c, int k, hipStream_t hs) {
   if (st != ASICP_OK || !stein) return st;
   float gamma, tau;
   schedule_of(c->cfg, k, &gamma, &tau);
-  launch_stein(c->d, gamma, tau, hs);
+  // the update reads every pose of a group from one buffer and writes the
+  // next poses to the other, which becomes the current one
+  Dev& d = c->d;
+  float* next = d.theta_next;
+  launch_stein(d, gamma, tau, hs);
+  d.theta_next = d.theta;
+  d.theta = next;
   return check_launch("svgd");
 }
 

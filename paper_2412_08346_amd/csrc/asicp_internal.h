@@ -97,7 +97,9 @@ struct Dev {
   float* obj_com;   // [n_obj][4]: centroid xyz, largest |r - centroid|^2
   float* pre_const; // [n_pre][8]: tcp xyz, rho2, a_t, a_w, largest |s|^2, -
   // state
-  float* theta;     // [7][Ktot]
+  float* theta;     // [7][Ktot] current poses: one of two buffers (the Stein
+                    //   update writes the other, which then becomes current)
+  float* theta_next;  // the Stein update's output buffer (set per launch)
   float* cost;
   float* col_cost;
   float* prev_cost;

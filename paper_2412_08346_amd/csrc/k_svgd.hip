@@ -1,5 +1,5 @@
 // k_svgd.hip -- annealed Stein ICP update of each (object, preshape) group
-// (eqs. (6)-(11)), in six launches:
+// (eqs. (6)-(11)), in two to five launches:
 //   k_bw_pass     x4: h of the RBF kernel (eq. 9), the lower median of
 //                 |t_i - t_j|^2 over pairs i < j divided by ln K and floored,
 //                 found exactly by a radix select over the FP32 bit patterns
@@ -12,9 +12,11 @@
 //                 the kernel gradient with respect to particle j (translation
 //                 part scaled by h/2); 16 particles per workgroup, 16 lanes
 //                 per particle;
-//   k_svgd_apply  t += eta phi_t, q <- canon(normalize(Exp(eta phi_w) (x) q)).
-// Every phi is computed from the poses of the same iteration: poses are only
-// written by the last launch.
+//                 the same launch applies t += eta phi_t, q <-
+//                 canon(normalize(Exp(eta phi_w) (x) q)), writing the next
+//                 poses to the second pose buffer.
+// Every phi is computed from the poses of the same iteration: they are read
+// from one buffer and the updated poses written to the other.
 #include "asicp_internal.h"
 
 namespace asicp {
@@ -313,20 +315,22 @@ __global__ __launch_bounds__(256) void k_svgd_phi(Dev d, float gamma, float tau)
     acc[a] += dppf<kDppHalfMirror>(acc[a]);
     acc[a] += dppf<kDppMirror>(acc[a]);
   }
-  if (ii < K && part == 0) {
-    const float invK = 1.0f / (float)K;
-    for (int a = 0; a < 6; ++a) d.phi[a * Kt + base + ii] = acc[a] * invK;
+  if (!(ii < K && part == 0)) return;
+  const float invK = 1.0f / (float)K;
+  float ph[6];
+  for (int a = 0; a < 6; ++a) {
+    ph[a] = acc[a] * invK;
+    d.phi[a * Kt + base + ii] = ph[a];
   }
-}
-
-__global__ __launch_bounds__(256) void k_svgd_apply(Dev d) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= d.Ktot) return;
-  const int Kt = d.Ktot;
+  // the update of eqs. (7), (3): t += eta phi_t, q <- canon(normalize(Exp(eta
+  // phi_w) (x) q)), written to the other pose buffer (every workgroup of the
+  // group reads the poses of this iteration from the current one)
+  const int i = base + ii;
   const float e = d.eta;
   float t[3], q[4];
-  load_pose(d.theta, Kt, i, t, q);
-  const float wx = e * d.phi[3 * Kt + i], wy = e * d.phi[4 * Kt + i], wz = e * d.phi[5 * Kt + i];
+  for (int a = 0; a < 3; ++a) t[a] = st[3 * ii + a];
+  for (int a = 0; a < 4; ++a) q[a] = sq[4 * ii + a];
+  const float wx = e * ph[3], wy = e * ph[4], wz = e * ph[5];
   const float th = sqrtf(wx * wx + wy * wy + wz * wz);
   float ew = 1.f, ex = 0.f, ey = 0.f, ez = 0.f;
   if (th > 0.f) {
@@ -341,13 +345,14 @@ __global__ __launch_bounds__(256) void k_svgd_apply(Dev d) {
   const float nz = ew * q[3] + q[0] * ez + (ex * q[2] - ey * q[1]);
   const float nrm = sqrtf(nw * nw + nx * nx + ny * ny + nz * nz);
   const float inv = ((nw < 0.f) ? -1.f : 1.f) / nrm;
-  d.theta[0 * Kt + i] = t[0] + e * d.phi[0 * Kt + i];
-  d.theta[1 * Kt + i] = t[1] + e * d.phi[1 * Kt + i];
-  d.theta[2 * Kt + i] = t[2] + e * d.phi[2 * Kt + i];
-  d.theta[3 * Kt + i] = nw * inv;
-  d.theta[4 * Kt + i] = nx * inv;
-  d.theta[5 * Kt + i] = ny * inv;
-  d.theta[6 * Kt + i] = nz * inv;
+  float* out = d.theta_next;
+  out[0 * Kt + i] = t[0] + e * ph[0];
+  out[1 * Kt + i] = t[1] + e * ph[1];
+  out[2 * Kt + i] = t[2] + e * ph[2];
+  out[3 * Kt + i] = nw * inv;
+  out[4 * Kt + i] = nx * inv;
+  out[5 * Kt + i] = ny * inv;
+  out[6 * Kt + i] = nz * inv;
 }
 
 void launch_bandwidth(const Dev& d, float inv_log_k, hipStream_t s) {
@@ -376,7 +381,6 @@ void launch_bandwidth(const Dev& d, float inv_log_k, hipStream_t s) {
 
 void launch_stein(const Dev& d, float gamma, float tau, hipStream_t s) {
   hipLaunchKernelGGL(k_svgd_phi, dim3(d.G, (d.K + kPhiPer - 1) / kPhiPer), dim3(256), 0, s, d, gamma, tau);
-  hipLaunchKernelGGL(k_svgd_apply, dim3((d.Ktot + 255) / 256), dim3(256), 0, s, d);
 }
 
 }  // namespace asicp
