@@ -23,7 +23,8 @@ FLOP_PER_PAIR = 6          # 3 multiply-adds of |r|^2 - 2 r.s per (query, object
 # dispatch, factors from a 256 MiB device copy), averaged over the launches
 # of one solve (profiles/nn_forward_counters_paper_scale.md).  Reported only
 # while the kernel's sources hash to the ones measured.
-NN_TRAFFIC = {"sha256": None, "bytes": {}}
+NN_TRAFFIC = {"sha256": "247fcb5766a155e7af7e84711e1333df36cddfa893c9f7cd38e3aec3dc1feecd",
+              "bytes": {"1,1,4,128": 14205703}}  # 5933712 fetched + 8271991 written
 NN_SOURCES = ("k_nn_forward.hip", "nn_core.h", "asicp_internal.h")
 
 
@@ -96,10 +97,23 @@ def batched_leg(A, synth, log, solves=2):
         nn = [nn[0] + ms, nn[1] + n, nn[2] + pr]
     res = s.result(per_particle=False)
     s.close()
+    # the same solve as one captured HIP graph (asicp_replay), timed by wall
+    # clock over whole replays (no per-kernel events inside a graph)
+    g = A.Solver(pb, st)
+    g.set_launch(**launch)
+    g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.replay()
+    torch.cuda.synchronize()
+    wall_graph = time.perf_counter() - t0
+    g.result(per_particle=False)
+    g.close()
     wall = float(np.median(walls))
     out = {"workload": "64 objects (superquadrics and unions of 1-3 boxes, 2k-32k points, log-uniform) x 3 "
                        "box-gripper preshapes x 4096 contact points x 128 Fibonacci particles, 100 iterations, "
                        "one launch per kernel for all objects",
+           "replay_ms_per_solve": 1e3 * wall_graph,
            "particle_iters_per_s": pb.k_tot * st.k_max / wall, "grasps_per_s": pb.n_obj / wall,
            "ms_per_solve": 1e3 * wall, "solves": solves, "launch": launch,
            "collision_free_objects": int(res["best_free"].sum()),

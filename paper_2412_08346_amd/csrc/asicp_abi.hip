@@ -594,24 +594,35 @@ static asicp_status evaluate(asicp_ctx c, int k, int final_eval, bool bandwidth,
     e0 = c->ev[2 * c->n_timed];
     e1 = c->ev[2 * c->n_timed + 1];
   }
-  if (hipEventRecord(e0, hs) != hipSuccess || hipStreamWaitEvent(c->side, e0, 0) != hipSuccess)
-    return fail(ASICP_E_HIP, "fork to the side stream failed");
-  // The gate follows the bandwidth select: started first, its workgroups
-  // take issue slots from the forward NN (which is bound by instruction
-  // issue) and the solve runs 3-10 % slower; after the select they mostly
-  // fill the forward launch's tail.
+  if (hipEventRecord(e0, hs) != hipSuccess) return fail(ASICP_E_HIP, "hipEventRecord failed");
+#ifndef ASICP_NN_FIRST
+#define ASICP_NN_FIRST 1
+#endif
+  // The forward NN is enqueued before the side stream's work (the side
+  // stream still waits only for e0): a captured graph then runs the two
+  // branches concurrently.  The gate follows the bandwidth select: started
+  // first, its workgroups take issue slots from the forward NN (which is
+  // bound by instruction issue) and the solve runs 3-10 % slower; after the
+  // select they mostly fill the forward launch's tail.
+  auto forward = [&]() -> asicp_status {
+    launch_nn_forward(c->d, hs);
+    asicp_status s2 = check_launch("nn_forward");
+    if (s2 != ASICP_OK) return s2;
+    if (timing) {
+      if (hipEventRecord(e1, hs) != hipSuccess) return fail(ASICP_E_HIP, "hipEventRecord failed");
+      ++c->n_timed;
+    }
+    return ASICP_OK;
+  };
+  if (ASICP_NN_FIRST && (st = forward()) != ASICP_OK) return st;
+  if (hipStreamWaitEvent(c->side, e0, 0) != hipSuccess) return fail(ASICP_E_HIP, "fork to the side stream failed");
   if (bandwidth) {
     launch_bandwidth(c->d, c->inv_log_k, c->side);
     if ((st = check_launch("bandwidth")) != ASICP_OK) return st;
   }
   launch_gate_reverse(c->d, c->side);
   if ((st = check_launch("gate_reverse")) != ASICP_OK) return st;
-  launch_nn_forward(c->d, hs);
-  if ((st = check_launch("nn_forward")) != ASICP_OK) return st;
-  if (timing) {
-    if (hipEventRecord(e1, hs) != hipSuccess) return fail(ASICP_E_HIP, "hipEventRecord failed");
-    ++c->n_timed;
-  }
+  if (!ASICP_NN_FIRST && (st = forward()) != ASICP_OK) return st;
   if (hipEventRecord(c->join_ev, c->side) != hipSuccess || hipStreamWaitEvent(hs, c->join_ev, 0) != hipSuccess)
     return fail(ASICP_E_HIP, "join of the side stream failed");
   launch_finalize(c->d, k, final_eval, hs);
