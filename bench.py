@@ -85,7 +85,8 @@ def batched_leg(A, synth, log, solves=2):
     s.solve()
     s.result(per_particle=False)
     log(f"batched: workload ready (Ktot={pb.k_tot}), launch {launch}")
-    walls, nn = [], [0.0, 0, 0.0]
+    walls = []
+    before = s.kernel_time()  # the records accumulate over the context's solves
     for _ in range(solves):
         s.reset()
         torch.cuda.synchronize()
@@ -93,8 +94,7 @@ def batched_leg(A, synth, log, solves=2):
         s.solve()
         torch.cuda.synchronize()
         walls.append(time.perf_counter() - t0)
-        ms, n, pr = s.kernel_time()
-        nn = [nn[0] + ms, nn[1] + n, nn[2] + pr]
+    nn = [a - b for a, b in zip(s.kernel_time(), before)]
     res = s.result(per_particle=False)
     s.close()
     # the same solve as one captured HIP graph (asicp_replay), timed by wall
@@ -161,10 +161,11 @@ def full_scan_leg(A, pb, st, log, iters=4):
     s = A.Solver(pb, st, timing=True, prune=False)
     s.step(1)
     s.result(per_particle=False)
+    before = s.kernel_time()  # the warm-up launch is not counted
     s.reset()
     s.step(iters)
     s.result(per_particle=False)
-    ms, n, pr = s.kernel_time()
+    ms, n, pr = [a - b for a, b in zip(s.kernel_time(), before)]
     s.close()
     r = nn_roofline(ms, n, pr)
     log(f"full scan: {r['avg_launch_ms']:.3f} ms per launch, frac {r['frac']:.3f}")
@@ -266,10 +267,9 @@ def main():
     solver = A.Solver(pb, st, timing=True, prune=not args.brute)
     print(f"[bench] workload ready: Ktot={pb.k_tot} objects={pb.n_obj} points={pb.R.shape[0]} "
           f"k_max={st.k_max}", file=sys.stderr, flush=True)
-    # one step = one whole solve: a fresh context on the resident inputs and
-    # workspace (set-up), the iterations, the final evaluation and the
-    # selection, all enqueued on one stream; contexts are kept until the
-    # timed region ends so that reading their kernel timings never stalls it
+    # one step = one whole solve on the resident inputs and workspace: the
+    # set-up, the iterations, the final evaluation and the selection, all
+    # enqueued on one stream
     sp = torch.cuda.current_stream().cuda_stream
     for w in range(args.warmup):
         solver.reset()
@@ -307,25 +307,24 @@ def main():
         launch = A.launch_choice(v)
         print(f"[bench] launch choice: {launch}; ms per solve by launch index: "
               f"{[round(x, 2) for x in launch_ms]}", file=sys.stderr, flush=True)
+    # one context for the timed solves: each step re-runs the set-up from the
+    # resident inputs (asicp_reset) and the whole solve; one context keeps one
+    # side stream (contexts created per step spread their side streams over
+    # the hardware queues, and those sharing the main stream's queue lose the
+    # overlap)
     solver.close()
-    ctxs = []
+    ctx = A.asicp_create(solver.problem, solver.config, solver._ws_ptr, solver.ws_bytes, sp)
+    A.asicp_set_launch(ctx, **launch)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(args.steps):
-        ctx = A.asicp_create(solver.problem, solver.config, solver._ws_ptr, solver.ws_bytes, sp)
-        A.asicp_set_launch(ctx, **launch)
+        A.asicp_reset(ctx, sp)
         A.asicp_solve(ctx, sp)
-        ctxs.append(ctx)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    nn_ms, nn_n, nn_pairs = 0.0, 0, 0.0
-    for ctx in ctxs:
-        ms, n, pr = A.asicp_kernel_time(ctx)
-        nn_ms, nn_n, nn_pairs = nn_ms + ms, nn_n + n, nn_pairs + pr
-    solver.ctx = ctxs[-1]
+    nn_ms, nn_n, nn_pairs = A.asicp_kernel_time(ctx)
+    solver.ctx = ctx
     res = solver.result(per_particle=False)
-    for ctx in ctxs[:-1]:
-        A.asicp_destroy(ctx)
     solver.close()
     wall = t1 - t0
     ms_per_step = 1e3 * wall / args.steps

@@ -188,6 +188,14 @@ asicp_status asicp_workspace_bytes(const asicp_problem* pb, const asicp_config* 
 asicp_status asicp_create(const asicp_problem* pb, const asicp_config* cfg, void* workspace,
                           size_t workspace_bytes, void* stream, asicp_ctx* out);
 
+/* Enqueue the set-up again from the borrowed inputs (which the caller may
+ * have rewritten in place: a new object of the same size, new initial
+ * particles) and return the context to the state asicp_create left it in:
+ * the next iteration is k_start, no final evaluation.  Launch choices and
+ * timing records are kept.  Reusing one context this way keeps its side
+ * stream and avoids creating contexts per solve. */
+asicp_status asicp_reset(asicp_ctx ctx, void* stream);
+
 /* Enqueue n_iters iterations of Algorithm 1 (n_iters >= 0).  Running past
  * k_max, or stepping after the final evaluation, is ASICP_E_STATE. */
 asicp_status asicp_step(asicp_ctx ctx, int32_t n_iters, void* stream);

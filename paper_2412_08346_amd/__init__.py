@@ -27,7 +27,7 @@ EXPORTS = ("asicp_workspace_bytes", "asicp_create", "asicp_step", "asicp_solve",
            "asicp_set_launch", "asicp_autotune", "asicp_destroy", "asicp_last_error",
            "asicp_pn_param_count", "asicp_pn_workspace_bytes", "asicp_pn_forward",
            "asicp_pn_loss_grad", "asicp_pn_adam", "asicp_pn_last_error", "asicp_pn_forward_noalloc",
-           "asicp_pose_vjp")
+           "asicp_pose_vjp", "asicp_reset")
 ASICP_GRAD_TANGENT, ASICP_GRAD_POSE = 0, 1
 
 
@@ -106,6 +106,8 @@ def load():
         L.asicp_workspace_bytes.restype = i32
         L.asicp_create.argtypes = [vp, vp, vp, C.c_size_t, vp, C.POINTER(vp)]
         L.asicp_create.restype = i32
+        L.asicp_reset.argtypes = [vp, vp]
+        L.asicp_reset.restype = i32
         L.asicp_step.argtypes = [vp, i32, vp]
         L.asicp_step.restype = i32
         L.asicp_solve.argtypes = [vp, vp]
@@ -170,6 +172,10 @@ def asicp_create(pb, cfg, workspace_ptr: int, workspace_bytes: int, stream: int)
     _check(load().asicp_create(C.byref(pb), C.byref(cfg), C.c_void_p(workspace_ptr), workspace_bytes,
                                C.c_void_p(stream), C.byref(ctx)))
     return ctx
+
+
+def asicp_reset(ctx, stream: int):
+    return _check(load().asicp_reset(ctx, C.c_void_p(stream)))
 
 
 def asicp_step(ctx, n_iters: int, stream: int):
@@ -359,12 +365,10 @@ class Solver:
         return int(stream)
 
     def reset(self, stream=None):
-        """Destroy the context and create a fresh one on the same device
-        arrays and workspace (runs the set-up kernels again)."""
-        self.close()
-        self.ctx = asicp_create(self.problem, self.config, self._ws_ptr, self.ws_bytes, self._stream(stream))
-        if getattr(self, "_launch", None) is not None:  # keep a chosen or tuned launch
-            asicp_set_launch(self.ctx, **self._launch)
+        """Start the solve again from the initial poses on the same context
+        (asicp_reset: the set-up kernels run again; the launch choice, the
+        captured graph and the timing records are kept)."""
+        asicp_reset(self.ctx, self._stream(stream))
 
     def step(self, n: int = 1, stream=None):
         asicp_step(self.ctx, n, self._stream(stream))

@@ -317,6 +317,7 @@ struct asicp_ctx_s {
   const float* prev_cost0;
   const int32_t* converged0;
   hipGraphExec_t graph;         // whole-solve graph of asicp_replay
+  float* graph_theta[2];        // the pose buffers (current, next) the graph ends with
   hipStream_t cap_stream;       // private stream the graph is captured on
   bool capturing;               // no timing events inside a captured graph
   // Side stream of an evaluation: the bandwidth select and the collision
@@ -646,6 +647,28 @@ static asicp_status iterate(asicp_ctx c, int k, hipStream_t hs) {
   return check_launch("svgd");
 }
 
+asicp_status asicp_reset(asicp_ctx c, void* stream) {
+  return guarded([&]() -> asicp_status {
+    g_err.clear();
+    if (!c) return fail(ASICP_E_INVALID, "ctx is NULL");
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    (void)hipGetLastError();
+    Dev ds = c->d;
+    ds.wave_pairs = nullptr;  // the pair counts of the timing records are kept
+    launch_setup(ds, c->theta0, c->prev_cost0, c->converged0, hs);
+    asicp_status st = check_launch("setup");
+    if (st != ASICP_OK) return st;
+    if (c->d.dbg_nn) {
+      if (hipMemsetAsync(c->d.dbg_nn, 0xff, 4 * (size_t)c->d.Ktot * c->d.n_max, hs) != hipSuccess ||
+          hipMemsetAsync(c->d.dbg_rev, 0xff, 4 * (size_t)c->d.Ktot * c->d.mc_max, hs) != hipSuccess)
+        return fail(ASICP_E_HIP, "debug buffer clear failed");
+    }
+    c->k = c->k_start;
+    c->final_done = false;
+    return ASICP_OK;
+  });
+}
+
 asicp_status asicp_step(asicp_ctx c, int32_t n_iters, void* stream) {
   return guarded([&]() -> asicp_status {
     g_err.clear();
@@ -753,6 +776,8 @@ asicp_status asicp_replay(asicp_ctx c, void* stream) {
         return st;
       }
       if (e != hipSuccess || !g) return fail(ASICP_E_HIP, "hipStreamEndCapture failed");
+      c->graph_theta[0] = c->d.theta;
+      c->graph_theta[1] = c->d.theta_next;
       const hipError_t ei = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
       (void)hipGraphDestroy(g);
       if (ei != hipSuccess) {
@@ -761,6 +786,10 @@ asicp_status asicp_replay(asicp_ctx c, void* stream) {
       }
     }
     if (hipGraphLaunch(c->graph, hs) != hipSuccess) return fail(ASICP_E_HIP, "hipGraphLaunch failed");
+    // the double-buffered poses: an eager solve since the capture (after
+    // asicp_reset) may have left the other buffer current
+    c->d.theta = c->graph_theta[0];
+    c->d.theta_next = c->graph_theta[1];
     c->k = c->cfg.k_max;
     c->final_done = true;
     return ASICP_OK;

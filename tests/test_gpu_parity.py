@@ -849,6 +849,46 @@ def test_timing_hook_counts_launches():
     s.close()
 
 
+
+def test_reset_repeats_the_solve_exactly():
+    """asicp_reset starts the solve again on the same context: a second solve
+    returns bitwise what the first did, the timing records accumulate over
+    both, and a captured graph replayed after an eager solve (an odd number
+    of iterations, so the double-buffered poses end on the other buffer)
+    still reads back its own final poses."""
+    A, torch = _gpu()
+    pb, st = synth.workload_small(k_max=5)
+    keys = ("theta", "cost", "ncol", "grad", "h", "best_theta", "best_particle")
+    s = A.Solver(pb, st, timing=True)
+    s.solve()
+    first = s.result()
+    t1 = s.kernel_time()
+    s.reset()
+    s.solve()
+    second = s.result()
+    t2 = s.kernel_time()
+    for key in keys:
+        assert np.array_equal(np.asarray(first[key]), np.asarray(second[key])), key
+    assert t2[1] == 2 * t1[1] and t2[2] == 2 * t1[2]
+    s.close()
+    g = A.Solver(pb, st)
+    g.replay()
+    rep = g.result()
+    g.reset()
+    g.step(2)
+    part = g.result()
+    assert part["iterations_done"] == 2
+    g.solve()
+    eager = g.result()
+    g.replay()
+    rep2 = g.result()
+    g.close()
+    for key in keys:
+        assert np.array_equal(np.asarray(rep[key]), np.asarray(first[key])), ("replay", key)
+        assert np.array_equal(np.asarray(eager[key]), np.asarray(first[key])), ("eager after replay", key)
+        assert np.array_equal(np.asarray(rep2[key]), np.asarray(first[key])), ("replay after eager", key)
+    assert not np.array_equal(np.asarray(part["theta"]), np.asarray(first["theta"]))
+
 def _run(pb, st, launch=None, tune=False, steps=3):
     A, torch = _gpu()
     s = A.Solver(pb, st, debug=True)
