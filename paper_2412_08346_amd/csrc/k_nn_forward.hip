@@ -9,7 +9,7 @@
 // (1, 2 or 4 blocks of 16 queries) and the chunk size CH (1 or 2 tile groups
 // of 64 points) are launch choices: every combination returns the same
 // nearest neighbours and partial sums.
-// Partial sums per block of 16 contact points: [sum |e|^2, sum e (3), sum
+// Partial sums per wavefront: [sum |e|^2, sum e (3), sum
 // s' x e (3), points], e = s' - r_nn, s' relative to the object's centroid (the
 // finaliser turns the moment into sum (R s) x e = sum s' x e - (t - CoM) x
 // sum e, so no pose value stays live through the scan).
@@ -135,14 +135,22 @@ __device__ __forceinline__ void nn_forward_body(const Dev& d) {
       d.dbg_nn[(size_t)i * d.n_max + n_orig] = d.obj_perm[(size_t)oi.prep_tg_begin * 64 + my];
     }
   }
-  // one record per block of 16 contact points (a row of lanes), summed in
-  // the same order whatever the launch shape, so every launch choice gives
-  // the same records
+  // one record per wave: each block of 16 contact points (a row of lanes) is
+  // summed by a fixed tree, then blocks are added in pairs and pairs of
+  // pairs, the same partial tree the finaliser completes for smaller waves,
+  // so every launch choice gives the same totals
   const float sums[8] = {e2, ex, ey, ez, mx, my_, mz, cnt};
-  const float tot = row_sum8(sums);  // lane 4m + j of row r: total of sums[2m + j] over block r
-  const int blk16 = chunk * Q + comp;
-  if (comp < Q && blk16 < pi.waves[0] && (lane & 2) == 0)
-    d.nn_part[((size_t)i * d.max_waves_pp + blk16) * kPartStride + (((lane & 15) >> 2) << 1 | (lane & 1))] = tot;
+  float tot = row_sum8(sums);  // lane 4m + j of row r: total of sums[2m + j] over block r
+  if (Q >= 2) {
+    const RowPair a = swap16(tot);
+    tot = a.even + a.odd;
+  }
+  if (Q == 4) {
+    const RowPair b = swap32(tot);
+    tot = b.even + b.odd;
+  }
+  if (lane < 16 && (lane & 2) == 0)
+    d.nn_part[((size_t)i * d.max_waves_pp + chunk) * kPartStride + ((lane >> 2) << 1 | (lane & 1))] = tot;
   // the wave's own slot: launches are ordered on the stream, so a plain
   // read-modify-write accumulates over them without contention
   if (lane == 0 && d.wave_pairs) d.wave_pairs[wave] += (unsigned long long)pairs;

@@ -50,12 +50,36 @@ __global__ __launch_bounds__(256) void k_finalize(Dev d, int k, int final_eval) 
   const PreInfo& pi = d.pres[gi.pre];
   const ObjInfo& oi = d.objs[gi.obj];
 
+  // the forward records: one per 16 * 2^qi contact points (one per wave of
+  // the forward launch).  Each group of 64 points is completed to the same
+  // tree, (b0 + b1) + (b2 + b3) over its blocks of 16, whatever qi is; blocks
+  // past the cloud's end count as +0, as they do inside a wave
   float s[7] = {0, 0, 0, 0, 0, 0, 0};
   const float* np = d.nn_part + (size_t)i * d.max_waves_pp * kPartStride;
-  const int blocks = pi.waves[0];  // one record per 16 contact points
-  for (int c = lane; c < blocks; c += 64)
+  const int qi = d.nn_qi, nrec = pi.waves[qi], groups = pi.waves[2];
+  for (int c = lane; c < groups; c += 64) {
+    if (qi == 2) {
 #pragma unroll
-    for (int a = 0; a < 7; ++a) s[a] += np[c * kPartStride + a];
+      for (int a = 0; a < 7; ++a) s[a] += np[c * kPartStride + a];
+    } else if (qi == 1) {
+      const bool h = 2 * c + 1 < nrec;
+#pragma unroll
+      for (int a = 0; a < 7; ++a) {
+        const float r0 = np[2 * c * kPartStride + a], r1 = h ? np[(2 * c + 1) * kPartStride + a] : 0.f;
+        s[a] += r0 + r1;
+      }
+    } else {
+      float r[4][7];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const bool h = 4 * c + b < nrec;
+#pragma unroll
+        for (int a = 0; a < 7; ++a) r[b][a] = h ? np[(4 * c + b) * kPartStride + a] : 0.f;
+      }
+#pragma unroll
+      for (int a = 0; a < 7; ++a) s[a] += (r[0][a] + r[1][a]) + (r[2][a] + r[3][a]);
+    }
+  }
   float cs[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   const float* cp = d.col_part + (size_t)i * d.max_gate_chunks * kPartStride;
   for (int c = lane; c < oi.gate_chunks; c += 64)
