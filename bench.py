@@ -56,10 +56,29 @@ def cpu_baseline(pb, st, seconds=10.0):
         th, pc, cv = r["theta"], r["prev_cost"], r["converged"]
         iters += 1
     dt = time.perf_counter() - t0
-    return {"value": pb.k_tot * iters / dt, "unit": "particle-iters/s", "cores": oracle.threads(),
-            "kind": "oracle",
-            "sample": f"{iters} iteration(s) of all {pb.k_tot} particles of the same workload "
-                      f"(FP64, {dt:.1f} s)"}
+    out = {"value": pb.k_tot * iters / dt, "unit": "particle-iters/s", "cores": oracle.threads(),
+           "kind": "oracle",
+           "sample": f"{iters} iteration(s) of all {pb.k_tot} particles of the same workload "
+                     f"(FP64, {dt:.1f} s)"}
+    # one core: one iteration of the first (object, preshape) group, the same
+    # per-particle work (an iteration couples only the particles of a group)
+    from paper_2412_08346_amd import synth
+    sub = synth.Problem(R=pb.R, r_off=pb.r_off[:2], C=pb.C, c_off=pb.c_off[:2],
+                        S=pb.S[pb.s_off[0]:pb.s_off[1]], s_off=np.array([0, pb.s_off[1] - pb.s_off[0]], np.int32),
+                        grids=pb.grids[:1], theta0=np.ascontiguousarray(pb.theta0[:, :pb.K]), K=pb.K)
+    n_threads = oracle.threads()
+    oracle.set_threads(1)
+    try:
+        o1 = oracle.Oracle(sub, st)
+        t0 = time.perf_counter()
+        o1.step(0, sub.theta0.astype(np.float64))
+        dt1 = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(n_threads)
+    out["one_core"] = {"value": sub.k_tot / dt1, "unit": "particle-iters/s", "cores": 1,
+                       "sample": f"1 iteration of the {sub.k_tot} particles of one (object, preshape) group "
+                                 f"(FP64, {dt1:.1f} s)"}
+    return out
 
 
 def nn_roofline(ms, n, pairs):

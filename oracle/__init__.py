@@ -96,6 +96,8 @@ def lib():
         L.or_log_prior.argtypes = [vp, vp, vp]
         L.or_log_prior.restype = f64
         L.or_threads.restype = i32
+        L.or_set_threads.argtypes = [i32]
+        L.or_set_threads.restype = None
         _lib = L
     return _lib
 
@@ -106,6 +108,11 @@ def _p(a):
 
 def threads() -> int:
     return int(lib().or_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of the parallel loops from now on (results do not depend on it)."""
+    lib().or_set_threads(int(n))
 
 
 # ---------------------------------------------------------------------------

@@ -30,6 +30,16 @@ int32_t or_threads(void) {
 #endif
 }
 
+/* Threads used by the parallel loops from now on (at least 1); results do not
+ * depend on it. */
+void or_set_threads(int32_t n) {
+#ifdef _OPENMP
+  omp_set_num_threads(n > 0 ? (int)n : 1);
+#else
+  (void)n;
+#endif
+}
+
 /* Rotation matrix of the unit quaternion q = (w, x, y, z) (Sec. III-A: R is
  * parametrised by theta^{4:7}); row-major. */
 void or_quat_to_rot(const double q[4], double Rm[9]) {

@@ -123,6 +123,7 @@ int32_t or_solve(const or_problem* pb, const or_config* cfg, int32_t k_start, in
 void or_select(const or_problem* pb, const double* cost, const int32_t* ncol, int32_t* best_idx,
                int32_t* best_free);
 int32_t or_threads(void);
+void or_set_threads(int32_t n);
 
 #ifdef __cplusplus
 }
