@@ -16,9 +16,12 @@ import bench  # noqa: E402
 def test_cpu_baseline_fields_and_bounded_sample():
     pb, st = synth.workload_small(k_max=6)
     cb = bench.cpu_baseline(pb, st, seconds=0.0)  # one whole iteration
-    assert set(cb) == {"value", "unit", "cores", "kind", "sample"}
+    assert set(cb) == {"value", "unit", "cores", "kind", "sample", "one_core"}
     assert cb["kind"] == "oracle" and cb["unit"] == "particle-iters/s"
     assert cb["cores"] == oracle.threads() and cb["value"] > 0
+    one = cb["one_core"]
+    assert one["cores"] == 1 and one["value"] > 0 and one["unit"] == "particle-iters/s"
+    assert one["sample"].startswith(f"1 iteration of the {pb.K} particles of one")
     assert cb["sample"].startswith(f"1 iteration(s) of all {pb.k_tot} particles")
     cb = bench.cpu_baseline(pb, st, seconds=1e9)  # capped by k_max
     assert cb["sample"].startswith(f"{st.k_max} iteration(s)")
