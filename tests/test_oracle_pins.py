@@ -705,6 +705,18 @@ def test_result_independent_of_thread_count():
         env = dict(os.environ, OMP_NUM_THREADS=nt, PYTHONPATH=root)
         outs.append(subprocess.check_output([sys.executable, "-c", code], env=env, cwd=root))
     assert outs[0] == outs[1]
+    # the same through the in-process setter the CPU baseline's one-core sample uses
+    pb, st = synth.workload_small(k_max=2)
+    n = oracle.threads()
+    try:
+        oracle.set_threads(1)
+        assert oracle.threads() == 1
+        one = oracle.Oracle(pb, st).solve()
+    finally:
+        oracle.set_threads(n)
+    assert oracle.threads() == n
+    many = oracle.Oracle(pb, st).solve()
+    assert np.array_equal(one["theta"], many["theta"]) and np.array_equal(one["cost"], many["cost"])
 
 
 # ---------------------------------------------------------------------------
