@@ -70,7 +70,11 @@ __device__ __forceinline__ void nn_forward_body(const Dev& d) {
   constexpr int QPW = 16 * Q;
   const float4* spts = d.pre_pts + (size_t)pi.prep_tg_begin * 64;  // Morton-sorted contact cloud
   const int comp = lane >> 4, j = lane & 15;
-  float bq[Q], qc[3 * Q];
+  // bq: the B operand (row a = component a of the block's 16 queries, row 3
+  // = 1); own: the lane's own query, number j of block min(comp, Q - 1); the
+  // full scan's re-scan also keeps every block's query (qc)
+  const int qo = min(comp, Q - 1);
+  float bq[Q], own[3], qc[PRUNE ? 1 : 3 * Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     int n = chunk * QPW + q * 16 + j;
@@ -80,9 +84,16 @@ __device__ __forceinline__ void nn_forward_body(const Dev& d) {
     const float py = R[3] * s.x + R[4] * s.y + R[5] * s.z + t[1];
     const float pz = R[6] * s.x + R[7] * s.y + R[8] * s.z + t[2];
     bq[q] = comp == 0 ? px : comp == 1 ? py : comp == 2 ? pz : 1.0f;
-    qc[3 * q] = px;
-    qc[3 * q + 1] = py;
-    qc[3 * q + 2] = pz;
+    if (!PRUNE) {
+      qc[3 * q] = px;
+      qc[3 * q + 1] = py;
+      qc[3 * q + 2] = pz;
+    }
+    if (q == 0 || q == qo) {
+      own[0] = px;
+      own[1] = py;
+      own[2] = pz;
+    }
   }
   int idx[Q];
   const float4* prep = (d.minibatch ? d.obj_prep_mb : d.obj_prep) + (size_t)oi.prep_tg_begin * 64;
@@ -93,7 +104,7 @@ __device__ __forceinline__ void nn_forward_body(const Dev& d) {
     for (int q = 0; q < Q; ++q) vq[q] = max(0, min(16, pi.n - (chunk * QPW + q * 16)));
     const float* box = CH == 1 ? d.obj_box1 + (size_t)oi.prep_tg_begin * 8
                                : d.obj_box + (size_t)oi.prep_tg_begin / 2 * 8;
-    pairs = nn_scan_pruned<Q, true, FINE, CH>(prep, oi.ntg, oi.m, box, bq, nullptr, qc, vq, com[3], idx,
+    pairs = nn_scan_pruned<Q, true, FINE, CH>(prep, oi.ntg, oi.m, box, bq, nullptr, own, vq, com[3], idx,
                                               d.flags + 1);
   } else {
     nn_scan<Q, CH>(prep, oi.ntg, bq, qc, idx, d.flags + 1);
@@ -112,15 +123,8 @@ __device__ __forceinline__ void nn_forward_body(const Dev& d) {
       atomicOr(d.flags + 1, 2);
       my = oi.m - 1;
     }
-    // the lane's transformed contact point s' is its query of block comp
-    float px = qc[0], py = qc[1], pz = qc[2];
-#pragma unroll
-    for (int q = 1; q < Q; ++q)
-      if (comp == q) {
-        px = qc[3 * q];
-        py = qc[3 * q + 1];
-        pz = qc[3 * q + 2];
-      }
+    // the lane's transformed contact point s' is its own query (block comp)
+    const float px = own[0], py = own[1], pz = own[2];
     const float4 r = d.obj_pts[(size_t)oi.prep_tg_begin * 64 + my];
     ex = px - r.x;
     ey = py - r.y;

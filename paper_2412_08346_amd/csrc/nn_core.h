@@ -142,7 +142,8 @@ __device__ __forceinline__ void chunk_step(const float4 (&a)[CH], const float* b
 // group g takes tiles g CH .. g CH + CH - 1 (sub-tiles of
 // one tile group, adjacent in the prepared cloud), so 16 buffer loads with
 // immediate offsets fetch all operands at once; qc holds the lane's query
-// (x, y, z per block) from the caller.  Otherwise (or on ties between lane
+// (x, y, z per block) from the caller, or is null (then the query is read
+// from the B operand's rows).  Otherwise (or on ties between lane
 // groups, which test all 16 rows) the lanes split the tiles and test row by
 // row, reading the query from the B operand.
 template <int Q, bool BATCH, int CH>
@@ -164,7 +165,11 @@ __device__ __forceinline__ void nn_rescan(const float4* __restrict__ prep, __amd
     int cand = 0x7fffffff;
     if (cmin != 0x7fffffff) {
       if (BATCH && ng == 1) {
-        const float s0 = qc[3 * q], s1 = qc[3 * q + 1], s2 = qc[3 * q + 2];
+        // the lane's query (x, y, z): kept by the caller, or gathered from
+        // rows 0-2 of the B operand
+        const float s0 = qc ? qc[3 * q] : __shfl(b[q], j, 64);
+        const float s1 = qc ? qc[3 * q + 1] : __shfl(b[q], j + 16, 64);
+        const float s2 = qc ? qc[3 * q + 2] : __shfl(b[q], j + 32, 64);
         const int t0 = grp * CH;  // first tile of the lane group within the chunk
         const int tgi = t0 >> 2, u0 = t0 & 3, r0 = 4 * gw;
         const unsigned voff = 4u * (unsigned)((cmin * CH + tgi) * 256 + r0 * 4 + u0);
@@ -329,13 +334,18 @@ __device__ __forceinline__ float point_box2(const float* p, const float* bx) {
 // queries takes a candidate chunk only while the box-to-box lower bound is
 // within the block's bound (refreshed every ASICP_NN_REFRESH chunks) and,
 // with FINE, only if some query's point-to-box distance is within that
-// query's own best (qc holds the lane's query).  None of these tests can drop
+// query's own best.  None of these tests can drop
 // a chunk holding a value equal to a final minimum, and the chunk record of
 // chunk_step does not depend on the visiting order, so the results do not
 // depend on them.
 // snorm[q] = |s|^2 of the lane's query in block q (turns the reduced value
-// |r|^2 - 2 r.s into a squared distance; with BATCH_RESCAN it is computed
-// from qc instead and snorm may be null); box = the cloud's chunk boxes;
+// |r|^2 - 2 r.s into a squared distance).  With OWN the lane instead owns one
+// query, number (l % 16) of block min(l / 16, Q - 1), whose coordinates the
+// caller passes in own[3]: the bounds and the per-query chunk test are then
+// computed once per lane for all blocks at once (one lane per query rather
+// than four copies of each block), |s|^2 comes from own, snorm may be null,
+// and the re-scan reads the queries from the B operand.  box = the cloud's
+// chunk boxes;
 // m = real points of the cloud; vq[q] = real queries of block q; r2max = the
 // largest |r|^2 of the cloud.  Returns the number of (query, point) distances
 // evaluated (wave-uniform).  Every bound carries a slack for the FP32
@@ -343,12 +353,14 @@ __device__ __forceinline__ float point_box2(const float* p, const float* bx) {
 // 5e-7 (r2max + |s|^2) (the rounding of the fused chain |r|^2 - 2 r.s is
 // at most a few units of 2^-24 times |r|^2 + 2 |r| |s| <= 2 (|r|^2 + |s|^2)),
 // plus 1e-7 (squared length units).
-template <int Q, bool BATCH_RESCAN, bool FINE, int CH>
+template <int Q, bool OWN, bool FINE, int CH>
 __device__ __forceinline__ long long nn_scan_pruned(const float4* __restrict__ prep, int ntg, int m,
                                                     const float* __restrict__ box, const float* bq,
-                                                    const float* snorm, const float* qc, const int* vq,
+                                                    const float* snorm, const float* own, const int* vq,
                                                     float r2max, int* idx, int32_t* miss) {
+  static_assert(OWN || !FINE, "the per-query chunk test needs the lane's own query");
   const int lane = lane_id();
+  const int qo = min(lane >> 4, Q - 1);  // with OWN: the block of the lane's own query
   float b[Q], best[Q];
   int bch[Q];
   float qlo[Q][3], qhi[Q][3];
@@ -368,24 +380,36 @@ __device__ __forceinline__ long long nn_scan_pruned(const float4* __restrict__ p
   const int nch = ntg / CH;
   const unsigned lo = 16u * (unsigned)lane;
   const __amdgpu_buffer_rsrc_t rs = cloud_rsrc(prep, ntg);
-  // qb[q]: the lane's query's current best squared distance (block q), with
-  // slack; ub[q]: the largest of them over the block
-  float ub[Q], qb[Q], ubmax;
+  // qbo (OWN): the lane's own query's current best squared distance, with
+  // slack; ub[q]: the largest such bound over block q's queries
+  float ub[Q], qbo = 0.0f, ubmax;
   auto refresh = [&]() {
+    if (OWN) {
+      float mn = rows_min(best[0]);
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      float sn = snorm ? snorm[q] : 0.0f;
-      if (BATCH_RESCAN) {
-        // |s|^2 from the query's coordinates, recomputed here rather than
-        // kept in registers through the scan (the empty constraints keep the
-        // compiler from hoisting it out of the loop)
-        float x = qc[3 * q], y = qc[3 * q + 1], z = qc[3 * q + 2];
-        __asm__("" : "+v"(x), "+v"(y), "+v"(z));
-        sn = __builtin_fmaf(z, z, __builtin_fmaf(y, y, x * x));
+      for (int q = 1; q < Q; ++q) {
+        const float v = rows_min(best[q]);
+        mn = qo == q ? v : mn;
       }
-      qb[q] = __builtin_fmaf(rows_min(best[q]) + sn, 1.0001f, __builtin_fmaf(5e-7f, r2max + sn, 1e-7f));
-      // every row holds the same 16 queries, so the row maximum is uniform
-      ub[q] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(row_max(qb[q]))));
+      // |s|^2 from the query's coordinates, recomputed here rather than kept
+      // in a register through the scan (the empty constraints keep the
+      // compiler from hoisting it out of the loop)
+      float x = own[0], y = own[1], z = own[2];
+      __asm__("" : "+v"(x), "+v"(y), "+v"(z));
+      const float sn = __builtin_fmaf(z, z, __builtin_fmaf(y, y, x * x));
+      qbo = __builtin_fmaf(mn + sn, 1.0001f, __builtin_fmaf(5e-7f, r2max + sn, 1e-7f));
+      // row q holds block q's queries
+      const float rm = row_max(qbo);
+#pragma unroll
+      for (int q = 0; q < Q; ++q) ub[q] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(rm), 16 * q));
+    } else {
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const float sn = snorm[q];
+        const float qb = __builtin_fmaf(rows_min(best[q]) + sn, 1.0001f, __builtin_fmaf(5e-7f, r2max + sn, 1e-7f));
+        // every row holds the same 16 queries, so the row maximum is uniform
+        ub[q] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(row_max(qb))));
+      }
     }
     ubmax = ub[0];
 #pragma unroll
@@ -498,14 +522,20 @@ __device__ __forceinline__ long long nn_scan_pruned(const float4* __restrict__ p
       const int pts = max(0, min((64 * CH), mu - (64 * CH) * cc));
       // block q is compared only if chunk cc is still in its mask (a scalar
       // bit test) and, with FINE, some query of the block may improve
-      bool need[Q];
-      const float* bx = box + (size_t)cc * 8;
+      bool need[Q], any = false;
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
         need[q] = (mq[q] >> cl) & 1ull;
-        if (FINE && need[q]) need[q] = __ballot(point_box2(qc + 3 * q, bx) <= qb[q]) != 0ull;
-        pairs += need[q] ? (long long)(pts * vqu[q]) : 0ll;
+        any = any || need[q];
       }
+      if (FINE && any) {
+        // one test per lane's own query; bits 16q .. 16q + 15 are block q's
+        const unsigned long long fm = __ballot(point_box2(own, box + (size_t)cc * 8) <= qbo);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) need[q] = need[q] && ((fm >> (16 * q)) & 0xffffull) != 0ull;
+      }
+#pragma unroll
+      for (int q = 0; q < Q; ++q) pairs += need[q] ? (long long)(pts * vqu[q]) : 0ll;
       chunk_step<Q, CH>(cur, b, best, bch, cc, need);
       if (++since == ASICP_NN_REFRESH) {
         since = 0;
@@ -538,7 +568,7 @@ __device__ __forceinline__ long long nn_scan_pruned(const float4* __restrict__ p
       step(y, x);
     }
   }
-  nn_rescan<Q, BATCH_RESCAN, CH>(prep, rs, b, qc, best, bch, idx, miss);
+  nn_rescan<Q, OWN, CH>(prep, rs, b, nullptr, best, bch, idx, miss);
   return pairs;
 }
 
