@@ -175,9 +175,11 @@ def small_replay_leg(A, synth, log, replays=50):
 
 def full_scan_leg(A, pb, st, log, iters=4):
     """The forward NN without pruning (every object point compared with every
-    contact point) on the paper-scale workload: `iters` iterations from the
-    initial poses, HIP events around every launch."""
+    contact point) on the paper-scale workload: the launch choice of the
+    library's tuner, `iters` iterations from the initial poses, HIP events
+    around every launch."""
     s = A.Solver(pb, st, timing=True, prune=False)
+    launch, _ = s.autotune(reps=2)  # query blocks per wave and XCD placement
     s.step(1)
     s.result(per_particle=False)
     before = s.kernel_time()  # the warm-up launch is not counted
@@ -188,7 +190,8 @@ def full_scan_leg(A, pb, st, log, iters=4):
     s.close()
     r = nn_roofline(ms, n, pr)
     log(f"full scan: {r['avg_launch_ms']:.3f} ms per launch, frac {r['frac']:.3f}")
-    return {"kernel": "k_nn_forward_full", "bound": "mfma", **r, "flop_per_pair": FLOP_PER_PAIR}
+    return {"kernel": "k_nn_forward_full", "bound": "mfma", **r, "flop_per_pair": FLOP_PER_PAIR,
+            "launch": {"xcd_map": launch["xcd_map"], "query_blocks": launch["query_blocks"]}}
 
 
 def learned_leg(log, n_train, steps):

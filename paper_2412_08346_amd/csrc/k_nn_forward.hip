@@ -71,10 +71,9 @@ __device__ __forceinline__ void nn_forward_body(const Dev& d) {
   const float4* spts = d.pre_pts + (size_t)pi.prep_tg_begin * 64;  // Morton-sorted contact cloud
   const int comp = lane >> 4, j = lane & 15;
   // bq: the B operand (row a = component a of the block's 16 queries, row 3
-  // = 1); own: the lane's own query, number j of block min(comp, Q - 1); the
-  // full scan's re-scan also keeps every block's query (qc)
+  // = 1); own: the lane's own query, number j of block min(comp, Q - 1)
   const int qo = min(comp, Q - 1);
-  float bq[Q], own[3], qc[PRUNE ? 1 : 3 * Q];
+  float bq[Q], own[3];
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     int n = chunk * QPW + q * 16 + j;
@@ -84,11 +83,6 @@ __device__ __forceinline__ void nn_forward_body(const Dev& d) {
     const float py = R[3] * s.x + R[4] * s.y + R[5] * s.z + t[1];
     const float pz = R[6] * s.x + R[7] * s.y + R[8] * s.z + t[2];
     bq[q] = comp == 0 ? px : comp == 1 ? py : comp == 2 ? pz : 1.0f;
-    if (!PRUNE) {
-      qc[3 * q] = px;
-      qc[3 * q + 1] = py;
-      qc[3 * q + 2] = pz;
-    }
     if (q == 0 || q == qo) {
       own[0] = px;
       own[1] = py;
@@ -107,7 +101,7 @@ __device__ __forceinline__ void nn_forward_body(const Dev& d) {
     pairs = nn_scan_pruned<Q, true, FINE, CH>(prep, oi.ntg, oi.m, box, bq, nullptr, own, vq, com[3], idx,
                                               d.flags + 1);
   } else {
-    nn_scan<Q, CH>(prep, oi.ntg, bq, qc, idx, d.flags + 1);
+    nn_scan<Q, CH>(prep, oi.ntg, bq, nullptr, idx, d.flags + 1);
     pairs = (long long)oi.m * min(QPW, pi.n - chunk * QPW);
   }
 

@@ -235,7 +235,8 @@ __device__ __forceinline__ void nn_rescan(const float4* __restrict__ prep, __amd
 // point for query (l % 16) of block q: the lowest index among the candidates
 // with the smallest FP32 value.  A query whose minimum cannot be re-found
 // (only possible with non-finite inputs) gets index 0 and sets *miss.
-// qc[3q + a] = component a of the lane's query (l % 16) of block q.
+// qc[3q + a] = component a of the lane's query (l % 16) of block q, or null
+// (the re-scan then reads the queries from the B operand).
 template <int Q, int CH>
 __device__ __forceinline__ void nn_scan(const float4* __restrict__ prep, int ntg, const float* bq,
                                         const float* qc, int* idx, int32_t* miss) {
