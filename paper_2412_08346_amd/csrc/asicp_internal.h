@@ -91,6 +91,7 @@ struct Dev {
   float4* col_pts;    // collision clouds in Morton order (offsets as the input's)
   int32_t* col_perm;
   unsigned long long* sort_keys;
+  float* kd_box;      // per object tile group: the set-up's k-d build scratch (16 floats)
   unsigned long long* wave_pairs;  // [total_waves[0]] distances evaluated per forward wave,
                                    //   summed over launches (ASICP_FLAG_TIMING only, else NULL)
   int32_t prune;                 // skip object chunks that cannot hold a nearest neighbour

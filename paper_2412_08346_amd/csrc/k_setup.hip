@@ -108,12 +108,131 @@ __device__ __forceinline__ unsigned int spread10(unsigned int v) {
   return v;
 }
 
+// Clouds of up to this many (power-of-two padded) points are sorted in LDS.
+constexpr int kLdsKeys = 8192;
+
+// Ascending bitonic sort of npow2 (a power of two) keys, in LDS or global
+// memory, by one workgroup of 1024 threads.
+__device__ void bitonic_sort(unsigned long long* keys, int npow2, int tid) {
+  for (int size = 2; size <= npow2; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int t = tid; t < (npow2 >> 1); t += 1024) {
+        const int i = 2 * stride * (t / stride) + (t % stride);
+        const int j = i + stride;
+        const bool asc = (i & size) == 0;
+        const unsigned long long a = keys[i], c = keys[j];
+        if ((a > c) == asc) {
+          keys[i] = c;
+          keys[j] = a;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// The k-d layout of an object cloud: leaves of 64 points (one tile group);
+// a part of L >= 3 leaves splits after 2 round(L / 4) leaves (an even
+// number, so every aligned pair of leaves, a 128-point pruning chunk, is one
+// subtree), a part of 2 leaves into its two leaves.  On return [a, b) are the
+// leaves of the part holding leaf lf after `level` splits.
+__device__ __forceinline__ void kd_part(int nleaf, int level, int lf, int& a, int& b) {
+  a = 0;
+  b = nleaf;
+  for (int l = 0; l < level && b - a > 1; ++l) {
+    const int L = b - a;
+    const int m = a + (L > 2 ? 2 * ((L + 2) >> 2) : 1);
+    if (lf < m) b = m; else a = m;
+  }
+}
+
+// Orders an object cloud's n points as the leaves of a k-d tree: each part
+// is sorted along the longest axis of its bounding box and split at the
+// leaf boundary above (the two halves of a median split, rounded to whole
+// leaves).  Chunks of 64 or 128 consecutive points then have tight boxes,
+// which the exact chunk pruning of the nearest-neighbour scans depends on
+// (space-filling-curve orders leave some chunks spanning a jump of the
+// curve).  One level per pass: every point's key becomes (first leaf of its
+// part, 16-bit position along the part's axis, original index), and one sort
+// orders all parts at once.  Ties fall to the original index, so the order
+// is deterministic.  kb: 16 floats of scratch per leaf.
+__device__ void kd_leaf_order(unsigned long long* keys, int n, int npow2, const float* sx, const float* sy,
+                              const float* sz, float* kb, int* s_split, int tid) {
+  const int nleaf = (n + 63) >> 6;
+  const int w = tid >> 6, lane = tid & 63;
+  for (int k = tid; k < npow2; k += 1024) keys[k] = k < n ? (unsigned long long)k : ~0ull;
+  __syncthreads();
+  for (int level = 0;; ++level) {
+    // the box of every leaf in the current order, one wavefront per leaf
+    for (int lf = w; lf < nleaf; lf += 16) {
+      const int pos = lf * 64 + lane;
+      float v[6] = {__builtin_inff(), __builtin_inff(), __builtin_inff(),
+                    -__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
+      if (pos < n) {
+        const int o = (int)(keys[pos] & 0xffffffffull);
+        v[0] = v[3] = sx[o];
+        v[1] = v[4] = sy[o];
+        v[2] = v[5] = sz[o];
+      }
+      for (int off = 32; off >= 1; off >>= 1) {
+        for (int a = 0; a < 3; ++a) v[a] = fminf(v[a], __shfl_xor(v[a], off, 64));
+        for (int a = 3; a < 6; ++a) v[a] = fmaxf(v[a], __shfl_xor(v[a], off, 64));
+      }
+      if (lane < 6) kb[(size_t)lf * 16 + lane] = v[lane];
+    }
+    if (tid == 0) *s_split = 0;
+    __syncthreads();
+    // every part that still splits: its box from its leaves, the longest
+    // axis and the quantisation along it, kept in the part's first leaf
+    for (int lf = tid; lf < nleaf; lf += 1024) {
+      int a, b;
+      kd_part(nleaf, level, lf, a, b);
+      if (lf != a || b - a < 2) continue;
+      float lo[3], hi[3];
+      for (int c = 0; c < 3; ++c) {
+        lo[c] = kb[(size_t)a * 16 + c];
+        hi[c] = kb[(size_t)a * 16 + 3 + c];
+      }
+      for (int l = a + 1; l < b; ++l)
+        for (int c = 0; c < 3; ++c) {
+          lo[c] = fminf(lo[c], kb[(size_t)l * 16 + c]);
+          hi[c] = fmaxf(hi[c], kb[(size_t)l * 16 + 3 + c]);
+        }
+      int ax = 0;
+      for (int c = 1; c < 3; ++c)
+        if (hi[c] - lo[c] > hi[ax] - lo[ax]) ax = c;
+      const float ext = hi[ax] - lo[ax];
+      kb[(size_t)a * 16 + 8] = __int_as_float(ax);
+      kb[(size_t)a * 16 + 9] = lo[ax];
+      kb[(size_t)a * 16 + 10] = ext > 0.f ? 65535.0f / ext : 0.f;
+      *s_split = 1;
+    }
+    __syncthreads();
+    if (*s_split == 0) break;  // every part is one leaf
+    for (int pos = tid; pos < n; pos += 1024) {
+      const int o = (int)(keys[pos] & 0xffffffffull);
+      int a, b;
+      kd_part(nleaf, level, pos >> 6, a, b);
+      unsigned int q = 0;
+      if (b - a >= 2) {
+        const int ax = __float_as_int(kb[(size_t)a * 16 + 8]);
+        const float x = ax == 0 ? sx[o] : (ax == 1 ? sy[o] : sz[o]);
+        q = (unsigned int)fminf(fmaxf((x - kb[(size_t)a * 16 + 9]) * kb[(size_t)a * 16 + 10], 0.f), 65535.f);
+      }
+      keys[pos] = ((unsigned long long)a << 48) | ((unsigned long long)q << 32) | (unsigned int)o;
+    }
+    __syncthreads();
+    bitonic_sort(keys, npow2, tid);
+  }
+}
+
 // One workgroup (1024 threads) per cloud: blocks [0, n_obj) sort object
 // clouds, blocks [n_obj, n_obj + n_pre) contact clouds, the last n_obj blocks
 // collision clouds (object and collision clouds relative to the object's
-// centroid).  Points are ordered by the Morton code of their position
-// in the cloud's bounding box (ties by original index: the keys are unique,
-// so the order is deterministic), then written as MFMA-ready float4, plain
+// centroid).  Object clouds are put in k-d leaf order (kd_leaf_order),
+// contact and collision clouds in the order of the Morton code of their
+// position in the cloud's bounding box (ties by original index: the keys are
+// unique, so either order is deterministic); then written as MFMA-ready float4, plain
 // float4, the original index, and one bounding box per pruning chunk; a
 // collision cloud gets a plain copy, the original index and one box per
 // kGateChunk points (one gate workgroup's share).  Padding points carry
@@ -182,37 +301,29 @@ __global__ __launch_bounds__(1024) void k_sort_cloud(Dev d) {
     const float ext = s_box[3 + a] - s_box[a];
     scale[a] = ext > 0.f ? 1023.0f / ext : 0.f;
   }
-  // keys, padded to a power of two with the largest key
+  // keys, padded to a power of two with the largest key; in LDS when they
+  // fit, else in the workspace
   int npow2 = 2;
   while (npow2 < n) npow2 <<= 1;
-  unsigned long long* keys = d.sort_keys + key_off;
-  for (int k = tid; k < npow2; k += 1024) {
-    unsigned long long key = ~0ull;
-    if (k < n) {
-      const unsigned int qx = (unsigned int)fminf(fmaxf((sx[k] - s_box[0]) * scale[0], 0.f), 1023.f);
-      const unsigned int qy = (unsigned int)fminf(fmaxf((sy[k] - s_box[1]) * scale[1], 0.f), 1023.f);
-      const unsigned int qz = (unsigned int)fminf(fmaxf((sz[k] - s_box[2]) * scale[2], 0.f), 1023.f);
-      const unsigned int code = spread10(qx) | (spread10(qy) << 1) | (spread10(qz) << 2);
-      key = ((unsigned long long)code << 32) | (unsigned int)k;
-    }
-    keys[k] = key;
-  }
-  __syncthreads();
-  // bitonic sort, ascending
-  for (int size = 2; size <= npow2; size <<= 1) {
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int t = tid; t < (npow2 >> 1); t += 1024) {
-        const int i = 2 * stride * (t / stride) + (t % stride);
-        const int j = i + stride;
-        const bool asc = (i & size) == 0;
-        const unsigned long long a = keys[i], c = keys[j];
-        if ((a > c) == asc) {
-          keys[i] = c;
-          keys[j] = a;
-        }
+  __shared__ unsigned long long lkeys[kLdsKeys];
+  unsigned long long* keys = npow2 <= kLdsKeys ? lkeys : d.sort_keys + key_off;
+  if (kind == 0) {
+    __shared__ int s_split;
+    kd_leaf_order(keys, n, npow2, sx, sy, sz, d.kd_box + (size_t)tg0 * 16, &s_split, tid);
+  } else {
+    for (int k = tid; k < npow2; k += 1024) {
+      unsigned long long key = ~0ull;
+      if (k < n) {
+        const unsigned int qx = (unsigned int)fminf(fmaxf((sx[k] - s_box[0]) * scale[0], 0.f), 1023.f);
+        const unsigned int qy = (unsigned int)fminf(fmaxf((sy[k] - s_box[1]) * scale[1], 0.f), 1023.f);
+        const unsigned int qz = (unsigned int)fminf(fmaxf((sz[k] - s_box[2]) * scale[2], 0.f), 1023.f);
+        const unsigned int code = spread10(qx) | (spread10(qy) << 1) | (spread10(qz) << 2);
+        key = ((unsigned long long)code << 32) | (unsigned int)k;
       }
-      __syncthreads();
+      keys[k] = key;
     }
+    __syncthreads();
+    bitonic_sort(keys, npow2, tid);
   }
   // emit the sorted copies
   if (kind == 2) {
