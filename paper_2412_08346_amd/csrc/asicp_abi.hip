@@ -87,7 +87,7 @@ Layout layout_of(const Shape& s) {
   L.pre_perm = bump(c, (size_t)s.pre_tg * 64 * 4);
   L.obj_box = bump(c, (size_t)s.obj_tg / 2 * 32);
   L.obj_box1 = bump(c, (size_t)s.obj_tg * 32);
-  L.kd_box = bump(c, (size_t)s.obj_tg * 64);
+  L.kd_box = bump(c, 64 * ((size_t)s.obj_tg + 4 * (size_t)s.pre_tg + (size_t)(kGateChunk / 64) * (size_t)s.gate_chunks));
   L.pre_box = bump(c, (size_t)s.pre_tg / kChunkTG * 32);
   L.col_box = bump(c, 32 * (size_t)(s.gate_chunks > 0 ? s.gate_chunks : 1));
   L.sort_keys = bump(c, (size_t)s.sort_keys * 8);
@@ -444,6 +444,8 @@ asicp_status asicp_create(const asicp_problem* pb, const asicp_config* cfg, void
     d.obj_box = reinterpret_cast<float*>(ws + L.obj_box);
     d.obj_box1 = reinterpret_cast<float*>(ws + L.obj_box1);
     d.kd_box = reinterpret_cast<float*>(ws + L.kd_box);
+    d.kd_pre_off = s.obj_tg;
+    d.kd_col_off = s.obj_tg + 4 * s.pre_tg;
     d.pre_box = reinterpret_cast<float*>(ws + L.pre_box);
     d.col_box = reinterpret_cast<float*>(ws + L.col_box);
     d.sort_keys = reinterpret_cast<unsigned long long*>(ws + L.sort_keys);

@@ -91,7 +91,10 @@ struct Dev {
   float4* col_pts;    // collision clouds in Morton order (offsets as the input's)
   int32_t* col_perm;
   unsigned long long* sort_keys;
-  float* kd_box;      // per object tile group: the set-up's k-d build scratch (16 floats)
+  float* kd_box;      // the set-up's k-d build scratch, 16 floats per leaf: object clouds
+                     //   per tile group, then contact clouds from kd_pre_off (4 per tile
+                     //   group), then collision clouds from kd_col_off (32 per gate chunk)
+  int32_t kd_pre_off, kd_col_off;
   unsigned long long* wave_pairs;  // [total_waves[0]] distances evaluated per forward wave,
                                    //   summed over launches (ASICP_FLAG_TIMING only, else NULL)
   int32_t prune;                 // skip object chunks that cannot hold a nearest neighbour

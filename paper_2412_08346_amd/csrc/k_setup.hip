@@ -98,28 +98,24 @@ __global__ __launch_bounds__(256) void k_setup_pre(Dev d) {
   }
 }
 
-// 10-bit Morton interleave of one axis
-__device__ __forceinline__ unsigned int spread10(unsigned int v) {
-  v &= 1023u;
-  v = (v | (v << 16)) & 0x030000FFu;
-  v = (v | (v << 8)) & 0x0300F00Fu;
-  v = (v | (v << 4)) & 0x030C30C3u;
-  v = (v | (v << 2)) & 0x09249249u;
-  return v;
-}
-
-// Clouds of up to this many (power-of-two padded) points are sorted in LDS.
+// Clouds of up to this many (power-of-two padded) points, and of up to
+// kLdsLeaves k-d leaves, are ordered in LDS.
 constexpr int kLdsKeys = 8192;
+constexpr int kLdsLeaves = 512;
+// A sort key ends in the point's original index (clouds hold < 2^22 points).
+constexpr unsigned long long kOrigMask = (1ull << 22) - 1;
 
 // Ascending bitonic sort of npow2 (a power of two) keys, in LDS or global
-// memory, by one workgroup of 1024 threads.
-__device__ void bitonic_sort(unsigned long long* keys, int npow2, int tid) {
-  for (int size = 2; size <= npow2; size <<= 1) {
+// memory, by one workgroup of 1024 threads (inlined, so that LDS arrays are
+// addressed as LDS).  With seg < npow2 (a power of two) each aligned block of
+// seg keys is sorted on its own (fewer stages: the blocks need no merging).
+__device__ __forceinline__ void bitonic_sort(unsigned long long* keys, int npow2, int tid, int seg) {
+  for (int size = 2; size <= seg; size <<= 1) {
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
       for (int t = tid; t < (npow2 >> 1); t += 1024) {
-        const int i = 2 * stride * (t / stride) + (t % stride);
+        const int i = ((t & ~(stride - 1)) << 1) | (t & (stride - 1));  // stride is a power of two
         const int j = i + stride;
-        const bool asc = (i & size) == 0;
+        const bool asc = size == seg || (i & size) == 0;
         const unsigned long long a = keys[i], c = keys[j];
         if ((a > c) == asc) {
           keys[i] = c;
@@ -131,115 +127,128 @@ __device__ void bitonic_sort(unsigned long long* keys, int npow2, int tid) {
   }
 }
 
-// The k-d layout of an object cloud: leaves of 64 points (one tile group);
-// a part of L >= 3 leaves splits after 2 round(L / 4) leaves (an even
-// number, so every aligned pair of leaves, a 128-point pruning chunk, is one
-// subtree), a part of 2 leaves into its two leaves.  On return [a, b) are the
+// The k-d layout of a cloud: leaves of `unit` points; a part of L >= 2
+// leaves splits after A max(1, round(L / 2A)) leaves, A the largest power of
+// two below L capped at `cap`, so every aligned block of cap leaves (and of
+// every power of two below it) is one subtree.  On return [a, b) are the
 // leaves of the part holding leaf lf after `level` splits.
-__device__ __forceinline__ void kd_part(int nleaf, int level, int lf, int& a, int& b) {
+__device__ __forceinline__ void kd_part(int nleaf, int cap, int level, int lf, int& a, int& b) {
   a = 0;
   b = nleaf;
   for (int l = 0; l < level && b - a > 1; ++l) {
     const int L = b - a;
-    const int m = a + (L > 2 ? 2 * ((L + 2) >> 2) : 1);
+    int sh = 0;  // A = 2^sh
+    while ((2 << sh) < L && (1 << sh) < cap) ++sh;
+    const int m = a + (max(1, (L + (1 << sh)) >> (sh + 1)) << sh);
     if (lf < m) b = m; else a = m;
   }
 }
 
-// Orders an object cloud's n points as the leaves of a k-d tree: each part
-// is sorted along the longest axis of its bounding box and split at the
-// leaf boundary above (the two halves of a median split, rounded to whole
-// leaves).  Chunks of 64 or 128 consecutive points then have tight boxes,
-// which the exact chunk pruning of the nearest-neighbour scans depends on
-// (space-filling-curve orders leave some chunks spanning a jump of the
-// curve).  One level per pass: every point's key becomes (first leaf of its
-// part, 16-bit position along the part's axis, original index), and one sort
-// orders all parts at once.  Ties fall to the original index, so the order
-// is deterministic.  kb: 16 floats of scratch per leaf.
-__device__ void kd_leaf_order(unsigned long long* keys, int n, int npow2, const float* sx, const float* sy,
-                              const float* sz, float* kb, int* s_split, int tid) {
-  const int nleaf = (n + 63) >> 6;
+// Orders a cloud's n points as the leaves of a k-d tree: each part is sorted
+// along the longest axis of its bounding box and split at the leaf boundary
+// above (the halves of a median split, rounded to whole aligned leaves).
+// Consecutive runs of points (pruning chunks, query blocks, gate workgroups)
+// then have tight boxes, which the exact pruning of the scans depends on
+// (space-filling-curve orders leave some runs spanning a jump of the curve).
+// One level per pass: every point's key becomes (first leaf of its part,
+// 16-bit position along the part's axis, original index), and one sort
+// orders all parts at once; ties fall to the original index, so the order is
+// deterministic.  unit: points per leaf (16 or 64); kb: 16 floats of scratch
+// per leaf.  Inlined, so that LDS arrays passed in are addressed as LDS.
+__device__ __forceinline__ void kd_leaf_order(unsigned long long* keys, int n, int npow2, int unit, int cap,
+                                              const float* sx, const float* sy, const float* sz, float* kb,
+                                              int* s_split, int tid) {
+  const int ush = unit == 16 ? 4 : 6;  // unit is 16 or 64
+  const int nleaf = (n + unit - 1) >> ush;
   const int w = tid >> 6, lane = tid & 63;
   for (int k = tid; k < npow2; k += 1024) keys[k] = k < n ? (unsigned long long)k : ~0ull;
   __syncthreads();
   for (int level = 0;; ++level) {
-    // the box of every leaf in the current order, one wavefront per leaf
-    for (int lf = w; lf < nleaf; lf += 16) {
-      const int pos = lf * 64 + lane;
+    // the box of every leaf in the current order: a wavefront covers 64
+    // consecutive points, 64 / unit leaves
+    for (int base = w * 64; base < nleaf * unit; base += 16 * 64) {
+      const int pos = base + lane;
       float v[6] = {__builtin_inff(), __builtin_inff(), __builtin_inff(),
                     -__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
       if (pos < n) {
-        const int o = (int)(keys[pos] & 0xffffffffull);
+        const int o = (int)(keys[pos] & kOrigMask);
         v[0] = v[3] = sx[o];
         v[1] = v[4] = sy[o];
         v[2] = v[5] = sz[o];
       }
-      for (int off = 32; off >= 1; off >>= 1) {
+      for (int off = unit >> 1; off >= 1; off >>= 1) {
         for (int a = 0; a < 3; ++a) v[a] = fminf(v[a], __shfl_xor(v[a], off, 64));
         for (int a = 3; a < 6; ++a) v[a] = fmaxf(v[a], __shfl_xor(v[a], off, 64));
       }
-      if (lane < 6) kb[(size_t)lf * 16 + lane] = v[lane];
+      if ((lane & (unit - 1)) == 0 && (pos >> ush) < nleaf)
+        for (int a = 0; a < 6; ++a) kb[(size_t)(pos >> ush) * 16 + a] = v[a];
     }
     if (tid == 0) *s_split = 0;
     __syncthreads();
-    // every part that still splits: its box from its leaves, the longest
-    // axis and the quantisation along it, kept in the part's first leaf
-    for (int lf = tid; lf < nleaf; lf += 1024) {
+    // every part that still splits: its box from its leaves (one wavefront
+    // per part), the longest axis and the quantisation along it, kept in the
+    // part's first leaf
+    for (int lf = w; lf < nleaf; lf += 16) {
       int a, b;
-      kd_part(nleaf, level, lf, a, b);
-      if (lf != a || b - a < 2) continue;
-      float lo[3], hi[3];
-      for (int c = 0; c < 3; ++c) {
-        lo[c] = kb[(size_t)a * 16 + c];
-        hi[c] = kb[(size_t)a * 16 + 3 + c];
+      kd_part(nleaf, cap, level, lf, a, b);
+      if (lf != a || b - a < 2) continue;  // uniform over the wavefront
+      float v[6] = {__builtin_inff(), __builtin_inff(), __builtin_inff(),
+                    -__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
+      for (int l = a + lane; l < b; l += 64) {
+        for (int c = 0; c < 3; ++c) v[c] = fminf(v[c], kb[(size_t)l * 16 + c]);
+        for (int c = 3; c < 6; ++c) v[c] = fmaxf(v[c], kb[(size_t)l * 16 + c]);
       }
-      for (int l = a + 1; l < b; ++l)
-        for (int c = 0; c < 3; ++c) {
-          lo[c] = fminf(lo[c], kb[(size_t)l * 16 + c]);
-          hi[c] = fmaxf(hi[c], kb[(size_t)l * 16 + 3 + c]);
-        }
-      int ax = 0;
-      for (int c = 1; c < 3; ++c)
-        if (hi[c] - lo[c] > hi[ax] - lo[ax]) ax = c;
-      const float ext = hi[ax] - lo[ax];
-      kb[(size_t)a * 16 + 8] = __int_as_float(ax);
-      kb[(size_t)a * 16 + 9] = lo[ax];
-      kb[(size_t)a * 16 + 10] = ext > 0.f ? 65535.0f / ext : 0.f;
-      *s_split = 1;
+      for (int off = 32; off >= 1; off >>= 1) {
+        for (int c = 0; c < 3; ++c) v[c] = fminf(v[c], __shfl_xor(v[c], off, 64));
+        for (int c = 3; c < 6; ++c) v[c] = fmaxf(v[c], __shfl_xor(v[c], off, 64));
+      }
+      if (lane == 0) {
+        int ax = 0;
+        for (int c = 1; c < 3; ++c)
+          if (v[3 + c] - v[c] > v[3 + ax] - v[ax]) ax = c;
+        const float ext = v[3 + ax] - v[ax];
+        kb[(size_t)a * 16 + 8] = __int_as_float(ax);
+        kb[(size_t)a * 16 + 9] = v[ax];
+        kb[(size_t)a * 16 + 10] = ext > 0.f ? 65535.0f / ext : 0.f;
+        *s_split = 1;
+      }
     }
     __syncthreads();
     if (*s_split == 0) break;  // every part is one leaf
     for (int pos = tid; pos < n; pos += 1024) {
-      const int o = (int)(keys[pos] & 0xffffffffull);
+      const int o = (int)(keys[pos] & kOrigMask);
       int a, b;
-      kd_part(nleaf, level, pos >> 6, a, b);
+      kd_part(nleaf, cap, level, pos >> ush, a, b);
       unsigned int q = 0;
       if (b - a >= 2) {
         const int ax = __float_as_int(kb[(size_t)a * 16 + 8]);
         const float x = ax == 0 ? sx[o] : (ax == 1 ? sy[o] : sz[o]);
         q = (unsigned int)fminf(fmaxf((x - kb[(size_t)a * 16 + 9]) * kb[(size_t)a * 16 + 10], 0.f), 65535.f);
       }
-      keys[pos] = ((unsigned long long)a << 48) | ((unsigned long long)q << 32) | (unsigned int)o;
+      // part (< 2^18 leaves) | position (16 bits) | original index (< 2^22)
+      keys[pos] = ((unsigned long long)a << 38) | ((unsigned long long)q << 22) | (unsigned int)o;
     }
     __syncthreads();
-    bitonic_sort(keys, npow2, tid);
+    // a cloud of a power-of-two number of whole leaves splits into aligned
+    // halves, so at this level every part is an aligned block of n >> level
+    // points and sorts on its own
+    const bool halves = n == npow2 && (nleaf & (nleaf - 1)) == 0;
+    bitonic_sort(keys, npow2, tid, halves ? (npow2 >> level) : npow2);
   }
 }
 
 // One workgroup (1024 threads) per cloud: blocks [0, n_obj) sort object
 // clouds, blocks [n_obj, n_obj + n_pre) contact clouds, the last n_obj blocks
 // collision clouds (object and collision clouds relative to the object's
-// centroid).  Object clouds are put in k-d leaf order (kd_leaf_order),
-// contact and collision clouds in the order of the Morton code of their
-// position in the cloud's bounding box (ties by original index: the keys are
-// unique, so either order is deterministic); then written as MFMA-ready float4, plain
+// centroid).  Points are put in k-d leaf order (kd_leaf_order; ties by
+// original index, so the order is deterministic), then written as
+// MFMA-ready float4, plain
 // float4, the original index, and one bounding box per pruning chunk; a
 // collision cloud gets a plain copy, the original index and one box per
 // kGateChunk points (one gate workgroup's share).  Padding points carry
 // |r|^2 = 1e30.
 __global__ __launch_bounds__(1024) void k_sort_cloud(Dev d) {
   __shared__ float sb[1024][6];
-  __shared__ float s_box[6];
   const int tid = threadIdx.x;
   // kind 0: object cloud, 1: contact cloud, 2: collision cloud (no MFMA copy)
   const int kind = blockIdx.x < d.n_obj ? 0 : (blockIdx.x < d.n_obj + d.n_pre ? 1 : 2);
@@ -277,58 +286,34 @@ __global__ __launch_bounds__(1024) void k_sort_cloud(Dev d) {
     base = (size_t)oi.c_begin;
   }
   if (n == 0) return;  // uniform: an empty collision cloud
-  // bounding box
-  float b[6] = {__builtin_inff(), __builtin_inff(), __builtin_inff(),
-                -__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
-  for (int k = tid; k < n; k += 1024) {
-    const float x = sx[k], y = sy[k], z = sz[k];
-    b[0] = fminf(b[0], x); b[1] = fminf(b[1], y); b[2] = fminf(b[2], z);
-    b[3] = fmaxf(b[3], x); b[4] = fmaxf(b[4], y); b[5] = fmaxf(b[5], z);
-  }
-  for (int a = 0; a < 6; ++a) sb[tid][a] = b[a];
-  __syncthreads();
-  for (int off = 512; off >= 1; off >>= 1) {
-    if (tid < off) {
-      for (int a = 0; a < 3; ++a) sb[tid][a] = fminf(sb[tid][a], sb[tid + off][a]);
-      for (int a = 3; a < 6; ++a) sb[tid][a] = fmaxf(sb[tid][a], sb[tid + off][a]);
-    }
-    __syncthreads();
-  }
-  if (tid < 6) s_box[tid] = sb[0][tid];
-  __syncthreads();
-  float scale[3];
-  for (int a = 0; a < 3; ++a) {
-    const float ext = s_box[3 + a] - s_box[a];
-    scale[a] = ext > 0.f ? 1023.0f / ext : 0.f;
-  }
-  // keys, padded to a power of two with the largest key; in LDS when they
-  // fit, else in the workspace
+  // keys, padded to a power of two with the largest key, and the k-d
+  // scratch: in LDS when they fit, else in the workspace
   int npow2 = 2;
   while (npow2 < n) npow2 <<= 1;
   __shared__ unsigned long long lkeys[kLdsKeys];
-  unsigned long long* keys = npow2 <= kLdsKeys ? lkeys : d.sort_keys + key_off;
-  if (kind == 0) {
-    __shared__ int s_split;
-    kd_leaf_order(keys, n, npow2, sx, sy, sz, d.kd_box + (size_t)tg0 * 16, &s_split, tid);
+  __shared__ float lkb[kLdsLeaves * 16];
+  __shared__ int s_split;
+  // k-d leaf order: object clouds in 64-point leaves (pruning chunks of 64
+  // and 128 points are subtrees), contact clouds in 16-point leaves (query
+  // blocks of 16 to 64 points and the reverse scan's 128-point chunks are
+  // subtrees), collision clouds in 64-point leaves within aligned blocks of
+  // kGateChunk points (one gate workgroup's share)
+  const int unit = kind == 1 ? 16 : 64;
+  const int cap = kind == 2 ? kGateChunk / 64 : 128 / unit;
+  const bool lds = npow2 <= kLdsKeys && (n + unit - 1) / unit <= kLdsLeaves;  // uniform
+  unsigned long long* keys = lds ? lkeys : d.sort_keys + key_off;
+  if (lds) {
+    kd_leaf_order(lkeys, n, npow2, unit, cap, sx, sy, sz, lkb, &s_split, tid);
   } else {
-    for (int k = tid; k < npow2; k += 1024) {
-      unsigned long long key = ~0ull;
-      if (k < n) {
-        const unsigned int qx = (unsigned int)fminf(fmaxf((sx[k] - s_box[0]) * scale[0], 0.f), 1023.f);
-        const unsigned int qy = (unsigned int)fminf(fmaxf((sy[k] - s_box[1]) * scale[1], 0.f), 1023.f);
-        const unsigned int qz = (unsigned int)fminf(fmaxf((sz[k] - s_box[2]) * scale[2], 0.f), 1023.f);
-        const unsigned int code = spread10(qx) | (spread10(qy) << 1) | (spread10(qz) << 2);
-        key = ((unsigned long long)code << 32) | (unsigned int)k;
-      }
-      keys[k] = key;
-    }
-    __syncthreads();
-    bitonic_sort(keys, npow2, tid);
+    float* kb = d.kd_box + 16 * (kind == 0 ? (size_t)tg0
+                                 : kind == 1 ? (size_t)d.kd_pre_off + (size_t)tg0 * 4
+                                             : (size_t)d.kd_col_off + (size_t)d.objs[blockIdx.x - d.n_obj - d.n_pre].gbox_begin * (kGateChunk / 64));
+    kd_leaf_order(d.sort_keys + key_off, n, npow2, unit, cap, sx, sy, sz, kb, &s_split, tid);
   }
   // emit the sorted copies
   if (kind == 2) {
     for (int k = tid; k < n; k += 1024) {
-      const int orig = (int)(keys[k] & 0xffffffffull);
+      const int orig = (int)(keys[k] & kOrigMask);
       pts[base + k] = make_float4(sx[orig] - c0, sy[orig] - c1, sz[orig] - c2, 0.f);
       perm[base + k] = orig;
     }
@@ -339,7 +324,7 @@ __global__ __launch_bounds__(1024) void k_sort_cloud(Dev d) {
       float e[6] = {__builtin_inff(), __builtin_inff(), __builtin_inff(),
                     -__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
       for (int k = c * kGateChunk + tid; k < min(n, (c + 1) * kGateChunk); k += 1024) {
-        const int orig = (int)(keys[k] & 0xffffffffull);
+        const int orig = (int)(keys[k] & kOrigMask);
         const float x = sx[orig] - c0, y = sy[orig] - c1, z = sz[orig] - c2;
         e[0] = fminf(e[0], x); e[1] = fminf(e[1], y); e[2] = fminf(e[2], z);
         e[3] = fmaxf(e[3], x); e[4] = fmaxf(e[4], y); e[5] = fmaxf(e[5], z);
@@ -362,7 +347,7 @@ __global__ __launch_bounds__(1024) void k_sort_cloud(Dev d) {
   for (int k = tid; k < ntg * 64; k += 1024) {
     const size_t g = base + k;
     if (k < n) {
-      const int orig = (int)(keys[k] & 0xffffffffull);
+      const int orig = (int)(keys[k] & kOrigMask);
       const float x = sx[orig] - c0, y = sy[orig] - c1, z = sz[orig] - c2;
       prep_store(pf, k, -2.f * x, -2.f * y, -2.f * z, __builtin_fmaf(z, z, __builtin_fmaf(y, y, x * x)));
       pts[g] = make_float4(x, y, z, 0.f);
