@@ -22,10 +22,11 @@ FLOP_PER_PAIR = 6          # 3 multiply-adds of |r|^2 - 2 r.s per (query, object
 # rocprofv3 --pmc passes: 2.000 x FETCH_SIZE + 1.000 x WRITE_SIZE (KiB per
 # dispatch, factors from a 256 MiB device copy), averaged over the launches
 # of one solve (profiles/nn_forward_counters_paper_scale.md).  Reported only
-# while the kernel's sources hash to the ones measured.
-NN_TRAFFIC = {"sha256": "dfcdf49f9511357301aba5d3c082c55e6f36a96b692ae4f23503a797d0cef959",
-              "bytes": {"1,1,4,128": 6299859}}  # 4333648 fetched + 1966211 written
-NN_SOURCES = ("k_nn_forward.hip", "nn_core.h", "asicp_internal.h")
+# while the kernel's sources, and the set-up that orders the clouds it scans,
+# hash to the ones measured.
+NN_TRAFFIC = {"sha256": "2eace4bd008cc881a9ac6318fba7a26944f14fa284ee4a6451e7b56204d2dea8",
+              "bytes": {"0,1,4,64": 4775370, "0,1,4,128": 4841047, "1,1,4,64": 6256100, "1,1,4,128": 6276009}}
+NN_SOURCES = ("k_nn_forward.hip", "nn_core.h", "asicp_internal.h", "k_setup.hip")
 
 
 def nn_traffic(workload, launch, brute):

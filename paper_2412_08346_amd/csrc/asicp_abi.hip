@@ -621,12 +621,21 @@ static asicp_status evaluate(asicp_ctx c, int k, int final_eval, bool bandwidth,
   };
   if (ASICP_NN_FIRST && (st = forward()) != ASICP_OK) return st;
   if (hipStreamWaitEvent(c->side, e0, 0) != hipSuccess) return fail(ASICP_E_HIP, "fork to the side stream failed");
+#ifndef ASICP_GATE_FIRST
+#define ASICP_GATE_FIRST 0
+#endif
+  if (ASICP_GATE_FIRST) {
+    launch_gate_reverse(c->d, c->side);
+    if ((st = check_launch("gate_reverse")) != ASICP_OK) return st;
+  }
   if (bandwidth) {
     launch_bandwidth(c->d, c->inv_log_k, c->side);
     if ((st = check_launch("bandwidth")) != ASICP_OK) return st;
   }
-  launch_gate_reverse(c->d, c->side);
-  if ((st = check_launch("gate_reverse")) != ASICP_OK) return st;
+  if (!ASICP_GATE_FIRST) {
+    launch_gate_reverse(c->d, c->side);
+    if ((st = check_launch("gate_reverse")) != ASICP_OK) return st;
+  }
   if (!ASICP_NN_FIRST && (st = forward()) != ASICP_OK) return st;
   if (hipEventRecord(c->join_ev, c->side) != hipSuccess || hipStreamWaitEvent(hs, c->join_ev, 0) != hipSuccess)
     return fail(ASICP_E_HIP, "join of the side stream failed");

@@ -73,7 +73,7 @@ struct Dev {
   int32_t max_waves_pp, max_gate_chunks;  // partial-record strides (max_waves_pp at 1 block per wave)
   int32_t n_max, mc_max;
   int32_t max_m, max_m_pad;  // largest object cloud, and padded to whole tile groups
-  // clouds in Morton order (index = prep_tg_begin*64 + k): MFMA-ready float4
+  // clouds in k-d leaf order (index = prep_tg_begin*64 + k): MFMA-ready float4
   // (A-operand order), plain float4 (x, y, z, 0), original index (-1 for
   // padding), and one bounding box per pruning chunk of kChunkTG tile groups
   // (lo xyz, -, hi xyz, -).  Object and collision clouds are stored relative
@@ -88,7 +88,7 @@ struct Dev {
   float* obj_box1;  // per tile group (64 points): the forward NN's 64-point chunks
   float* pre_box;
   float* col_box;  // [gate chunks][8]: box of each kGateChunk points of the sorted collision clouds
-  float4* col_pts;    // collision clouds in Morton order (offsets as the input's)
+  float4* col_pts;    // collision clouds in k-d leaf order (offsets as the input's)
   int32_t* col_perm;
   unsigned long long* sort_keys;
   float* kd_box;      // the set-up's k-d build scratch, 16 floats per leaf: object clouds

@@ -13,7 +13,7 @@
 // Trilinear weights are non-negative, so a point can only collide inside a
 // cell with a negative corner: the box of such cells (from the negative SDF
 // nodes) culls whole workgroups (the transformed box of the workgroup's own
-// 2048 points, compact because the cloud is Morton sorted) and single points
+// 2048 points, compact because the cloud is in k-d leaf order) and single points
 // without reading the grid.  Both tests are exact.
 #include "nn_core.h"
 
@@ -124,7 +124,7 @@ __device__ __forceinline__ bool box_may_collide(const PreInfo& pi, const float* 
 }
 
 // Reverse NN of Q blocks of colliding points (gripper frame) against the
-// Morton-sorted contact cloud, skipping contact chunks that cannot hold a
+// k-d ordered contact cloud, skipping contact chunks that cannot hold a
 // nearest point (same exact result as scanning them all).
 template <int Q>
 __device__ __forceinline__ void rev_scan(const Dev& d, const PreInfo& pi, int gi_pre, const float* bq, int* idx) {
@@ -182,7 +182,7 @@ __global__ __launch_bounds__(256) void k_gate_reverse(Dev d) {
 
   float* pout = d.pen_part + ((size_t)i * d.max_gate_chunks + cc) * kPartStride;
   // the box of this workgroup's 2048 points (spatially compact: the cloud is
-  // Morton sorted), not of the whole cloud, so most far chunks stop here
+  // k-d ordered), not of the whole cloud, so most far chunks stop here
   if (!box_may_collide(pi, d.col_box + (size_t)(oi.gbox_begin + cc) * 8, R, t)) {
     if (tid < kPartStride) {
       out[tid] = 0.f;
@@ -197,7 +197,7 @@ __global__ __launch_bounds__(256) void k_gate_reverse(Dev d) {
   }
 
   // gate: thread tid owns points cc*2048 + r*256 + tid, r = 0..7, of the
-  // Morton-sorted collision cloud (so colliding points come out clustered)
+  // k-d ordered collision cloud (so colliding points come out clustered)
   unsigned int bits = 0u;
   float px[kPerThread], py[kPerThread], pz[kPerThread];
   // penetration sums (gripper frame): phi^2, -2 phi grad, 2 phi grad x c'
@@ -249,7 +249,7 @@ __global__ __launch_bounds__(256) void k_gate_reverse(Dev d) {
       else if (d.dbg_rev) d.dbg_rev[(size_t)i * d.mc_max + d.col_perm[oi.c_begin + m]] = -1;
     }
   }
-  // compaction in the cloud's (Morton) order, point m = cc*2048 + r*256 + tid:
+  // compaction in the cloud's (k-d) order, point m = cc*2048 + r*256 + tid:
   // slot r's ballot ranks the lane within its wave, and the per-slot wave
   // counts place the wave, so a block of 16 consecutive colliding points is
   // spatially compact and the reverse scan's chunk bounds stay tight
@@ -328,7 +328,7 @@ __global__ __launch_bounds__(256) void k_gate_reverse(Dev d) {
         atomicOr(d.flags + 1, 4);
         my_idx = pi.n - 1;
       }
-      const float4 sp = d.pre_pts[(size_t)pi.prep_tg_begin * 64 + my_idx];  // Morton-sorted copy
+      const float4 sp = d.pre_pts[(size_t)pi.prep_tg_begin * 64 + my_idx];  // k-d ordered copy
       const float sx = sp.x, sy = sp.y, sz = sp.z;
       const float dx = sx - lx[p], dy = sy - ly[p], dz = sz - lz[p];
       e2 += dx * dx + dy * dy + dz * dz;

@@ -3,7 +3,7 @@
 // object cloud by eq. (1), accumulate the terms of eqs. (14), (16), (17)).
 //
 // One wavefront = one particle x 16*Q contact points (consecutive in the
-// Morton-sorted contact cloud, so spatially close), matched against the object
+// k-d ordered contact cloud, so spatially close), matched against the object
 // cloud of its group with the MFMA core.  By default object chunks that
 // provably cannot hold any of the wave's nearest neighbours are skipped.  Q
 // (1, 2 or 4 blocks of 16 queries) and the chunk size CH (1 or 2 tile groups
@@ -68,7 +68,7 @@ __device__ __forceinline__ void nn_forward_body(const Dev& d) {
   for (int a = 0; a < 3; ++a) t[a] = uniform_f(t[a] - com[a]);
 
   constexpr int QPW = 16 * Q;
-  const float4* spts = d.pre_pts + (size_t)pi.prep_tg_begin * 64;  // Morton-sorted contact cloud
+  const float4* spts = d.pre_pts + (size_t)pi.prep_tg_begin * 64;  // k-d ordered contact cloud
   const int comp = lane >> 4, j = lane & 15;
   // bq: the B operand (row a = component a of the block's 16 queries, row 3
   // = 1); own: the lane's own query, number j of block min(comp, Q - 1)

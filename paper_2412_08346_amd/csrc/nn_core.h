@@ -326,7 +326,7 @@ __device__ __forceinline__ float point_box2(const float* p, const float* bx) {
 // As nn_scan, but a chunk is only compared with a block of 16 queries if the
 // chunk's box can hold a point nearer than the block's current worst bound:
 // exact (the same nearest distances as scanning everything).  Queries must be
-// spatially coherent for this to pay (contact clouds are Morton sorted).
+// spatially coherent for this to pay (contact clouds are in k-d leaf order).
 //
 // The chunk nearest to the wave's query box is scanned first; the other
 // candidates follow nearest first (smallest box-to-box lower bound over the

@@ -310,11 +310,11 @@ def test_bandwidth_on_both_sides_of_one_workgroup(K):
 
 def test_exact_ties_give_one_valid_nearest_point_for_every_launch():
     """A mirror-symmetric object seen from its mirror plane: every query's two
-    nearest points (a point and its mirror image, 1024 indices apart and far
-    apart in the Morton order) have bit-identical squared distances, in FP32 as
+    nearest points (a point and its mirror image, 1024 indices apart in the
+    input) have bit-identical squared distances, in FP32 as
     in FP64, so eq. (1) has two minimisers.  The oracle takes the lowest
     original index (the first copy); the GPU takes the lowest index of the
-    prepared (Morton-sorted) cloud, which is the other copy as often as not.
+    prepared (k-d ordered) cloud, which is the other copy as often as not.
     Both are valid: the GPU's point must lie at exactly the oracle's minimal
     distance, and every launch choice, pruned or not, must return the same
     index whatever order it visits the chunks in."""
