@@ -43,7 +43,7 @@ constexpr int kMaxPoints = 1 << 22;   // per object / collision cloud / preshape
 constexpr int kMaxGroups = 1 << 16;
 
 struct Layout {
-  size_t groups, objs, pres, obj_prep, pre_prep, obj_pts, pre_pts, obj_perm, pre_perm, obj_box, obj_box1, kd_box, pre_box,
+  size_t groups, objs, pres, obj_prep, pre_prep, obj_pts, pre_pts, obj_perm, pre_perm, obj_box, obj_box1, obj_blk, obj_blk1, kd_box, pre_box,
       col_box;
   size_t sort_keys, wave_pairs, obj_com, pre_const, col_pts, col_perm, obj_prep_mb, batch_mark, prior;
   size_t theta, cost, col_cost, prev_cost, ncol, converged, grad, grad_ct, grad_col, phi, h, bw_hist, bw_state;
@@ -87,6 +87,8 @@ Layout layout_of(const Shape& s) {
   L.pre_perm = bump(c, (size_t)s.pre_tg * 64 * 4);
   L.obj_box = bump(c, (size_t)s.obj_tg / 2 * 32);
   L.obj_box1 = bump(c, (size_t)s.obj_tg * 32);
+  L.obj_blk = bump(c, (size_t)s.obj_tg / 4 * 32);  // ceil(chunks / 64) <= tile groups / 4 per object
+  L.obj_blk1 = bump(c, (size_t)s.obj_tg / 4 * 32);
   L.kd_box = bump(c, 64 * ((size_t)s.obj_tg + 4 * (size_t)s.pre_tg + (size_t)(kGateChunk / 64) * (size_t)s.gate_chunks));
   L.pre_box = bump(c, (size_t)s.pre_tg / kChunkTG * 32);
   L.col_box = bump(c, 32 * (size_t)(s.gate_chunks > 0 ? s.gate_chunks : 1));
@@ -443,6 +445,8 @@ asicp_status asicp_create(const asicp_problem* pb, const asicp_config* cfg, void
     d.pre_perm = reinterpret_cast<int32_t*>(ws + L.pre_perm);
     d.obj_box = reinterpret_cast<float*>(ws + L.obj_box);
     d.obj_box1 = reinterpret_cast<float*>(ws + L.obj_box1);
+    d.obj_blk = reinterpret_cast<float*>(ws + L.obj_blk);
+    d.obj_blk1 = reinterpret_cast<float*>(ws + L.obj_blk1);
     d.kd_box = reinterpret_cast<float*>(ws + L.kd_box);
     d.kd_pre_off = s.obj_tg;
     d.kd_col_off = s.obj_tg + 4 * s.pre_tg;

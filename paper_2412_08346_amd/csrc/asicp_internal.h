@@ -17,7 +17,7 @@ constexpr int kTileGroup = 64;     // points per MFMA-ready tile group (4 tiles 
 constexpr int kNumQ = 3;
 __host__ __device__ constexpr int q_blocks(int qi) { return 1 << qi; }
 #ifndef ASICP_NN_WPE
-#define ASICP_NN_WPE 6
+#define ASICP_NN_WPE 7
 #endif
 // Candidate chunks compared between refreshes of the pruning bound.
 #ifndef ASICP_NN_REFRESH
@@ -86,6 +86,8 @@ struct Dev {
   int32_t* pre_perm;
   float* obj_box;   // per chunk of 2 tile groups (128 points)
   float* obj_box1;  // per tile group (64 points): the forward NN's 64-point chunks
+  float* obj_blk;   // per block of 64 chunks of obj_box (a k-d subtree), at prep_tg_begin / 4 + b
+  float* obj_blk1;  // the same for the 64-point chunks of obj_box1
   float* pre_box;
   float* col_box;  // [gate chunks][8]: box of each kGateChunk points of the sorted collision clouds
   float4* col_pts;    // collision clouds in k-d leaf order (offsets as the input's)

@@ -141,7 +141,7 @@ __device__ __forceinline__ void rev_scan(const Dev& d, const PreInfo& pi, int gi
     vq[q] = 16;
   }
   nn_scan_pruned<Q, false, false, kChunkTG>(d.pre_prep + (size_t)pi.prep_tg_begin * 64, pi.ntg, pi.n,
-                                  d.pre_box + (size_t)pi.prep_tg_begin / kChunkTG * 8, bq, snorm, nullptr, vq,
+                                  d.pre_box + (size_t)pi.prep_tg_begin / kChunkTG * 8, nullptr, bq, snorm, nullptr, vq,
                                   d.pre_const[8 * gi_pre + 6], idx, d.flags + 1);
 }
 

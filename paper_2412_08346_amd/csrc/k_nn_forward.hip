@@ -98,7 +98,8 @@ __device__ __forceinline__ void nn_forward_body(const Dev& d) {
     for (int q = 0; q < Q; ++q) vq[q] = max(0, min(16, pi.n - (chunk * QPW + q * 16)));
     const float* box = CH == 1 ? d.obj_box1 + (size_t)oi.prep_tg_begin * 8
                                : d.obj_box + (size_t)oi.prep_tg_begin / 2 * 8;
-    pairs = nn_scan_pruned<Q, true, FINE, CH>(prep, oi.ntg, oi.m, box, bq, nullptr, own, vq, com[3], idx,
+    const float* blk = (CH == 1 ? d.obj_blk1 : d.obj_blk) + (size_t)oi.prep_tg_begin / 4 * 8;
+    pairs = nn_scan_pruned<Q, true, FINE, CH>(prep, oi.ntg, oi.m, box, blk, bq, nullptr, own, vq, com[3], idx,
                                               d.flags + 1);
   } else {
     nn_scan<Q, CH>(prep, oi.ntg, bq, nullptr, idx, d.flags + 1);

@@ -363,23 +363,53 @@ __global__ __launch_bounds__(1024) void k_sort_cloud(Dev d) {
   // (2 tile groups), and for an object cloud also every 64 points (the
   // forward NN's pruning chunk is a launch choice)
   auto chunk_boxes = [&](int tgs, float* out) {
-    const int pts_per = 64 * tgs, nch = ntg / tgs;
-    for (int c = tid; c < nch; c += 1024) {
+    // one wavefront per chunk, a lane per point
+    const int pts_per = 64 * tgs, nch = ntg / tgs, w = tid >> 6, lane = tid & 63;
+    for (int c = w; c < nch; c += 16) {
       float bb[6] = {__builtin_inff(), __builtin_inff(), __builtin_inff(),
                      -__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
       const int k1 = min(n, (c + 1) * pts_per);
-      for (int k = c * pts_per; k < k1; ++k) {
+      for (int k = c * pts_per + lane; k < k1; k += 64) {
         const float4 p = pts[base + k];
         bb[0] = fminf(bb[0], p.x); bb[1] = fminf(bb[1], p.y); bb[2] = fminf(bb[2], p.z);
         bb[3] = fmaxf(bb[3], p.x); bb[4] = fmaxf(bb[4], p.y); bb[5] = fmaxf(bb[5], p.z);
       }
+      for (int off = 32; off >= 1; off >>= 1) {
+        for (int a = 0; a < 3; ++a) bb[a] = fminf(bb[a], __shfl_xor(bb[a], off, 64));
+        for (int a = 3; a < 6; ++a) bb[a] = fmaxf(bb[a], __shfl_xor(bb[a], off, 64));
+      }
       float* o = out + ((size_t)tg0 / tgs + c) * 8;
-      o[0] = bb[0]; o[1] = bb[1]; o[2] = bb[2]; o[3] = 0.f;
-      o[4] = bb[3]; o[5] = bb[4]; o[6] = bb[5]; o[7] = 0.f;
+      if (lane < 8) o[lane] = lane == 3 || lane == 7 ? 0.f : bb[lane < 3 ? lane : lane - 1];
     }
   };
   chunk_boxes(kChunkTG, box);
-  if (kind == 0) chunk_boxes(1, d.obj_box1);
+  if (kind == 0) {
+    chunk_boxes(1, d.obj_box1);
+    __syncthreads();  // the chunk boxes are read back below
+    // the box of every block of 64 chunks (a k-d subtree): one wavefront per
+    // block, a lane per chunk; lets a scan skip a whole block with one test
+    auto block_boxes = [&](const float* cb, int nch, float* out) {
+      const int w = tid >> 6, lane = tid & 63;
+      for (int b = w; b * 64 < nch; b += 16) {
+        const int c = b * 64 + lane;
+        float v[6] = {__builtin_inff(), __builtin_inff(), __builtin_inff(),
+                      -__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
+        if (c < nch) {
+          for (int a = 0; a < 3; ++a) {
+            v[a] = cb[(size_t)c * 8 + a];
+            v[3 + a] = cb[(size_t)c * 8 + 4 + a];
+          }
+        }
+        for (int off = 32; off >= 1; off >>= 1) {
+          for (int a = 0; a < 3; ++a) v[a] = fminf(v[a], __shfl_xor(v[a], off, 64));
+          for (int a = 3; a < 6; ++a) v[a] = fmaxf(v[a], __shfl_xor(v[a], off, 64));
+        }
+        if (lane < 8) out[(size_t)b * 8 + lane] = lane == 3 || lane == 7 ? 0.f : v[lane < 3 ? lane : lane - 1];
+      }
+    };
+    block_boxes(box + (size_t)tg0 / kChunkTG * 8, ntg / kChunkTG, d.obj_blk + (size_t)tg0 / 4 * 8);
+    block_boxes(d.obj_box1 + (size_t)tg0 * 8, ntg, d.obj_blk1 + (size_t)tg0 / 4 * 8);
+  }
 }
 
 // Box of negative SDF nodes per preshape (grid: n_pre x 64 workgroups).

@@ -347,6 +347,7 @@ __device__ __forceinline__ float point_box2(const float* p, const float* bx) {
 // than four copies of each block), |s|^2 comes from own, snorm may be null,
 // and the re-scan reads the queries from the B operand.  box = the cloud's
 // chunk boxes;
+// blk_box = the box of every block of 64 chunks, or null (no block test);
 // m = real points of the cloud; vq[q] = real queries of block q; r2max = the
 // largest |r|^2 of the cloud.  Returns the number of (query, point) distances
 // evaluated (wave-uniform).  Every bound carries a slack for the FP32
@@ -356,7 +357,8 @@ __device__ __forceinline__ float point_box2(const float* p, const float* bx) {
 // plus 1e-7 (squared length units).
 template <int Q, bool OWN, bool FINE, int CH>
 __device__ __forceinline__ long long nn_scan_pruned(const float4* __restrict__ prep, int ntg, int m,
-                                                    const float* __restrict__ box, const float* bq,
+                                                    const float* __restrict__ box,
+                                                    const float* __restrict__ blk_box, const float* bq,
                                                     const float* snorm, const float* own, const int* vq,
                                                     float r2max, int* idx, int32_t* miss) {
   static_assert(OWN || !FINE, "the per-query chunk test needs the lane's own query");
@@ -442,6 +444,14 @@ __device__ __forceinline__ long long nn_scan_pruned(const float4* __restrict__ p
       cbest = c;
     }
   }
+  // lane b: the lower bound between the union box and block b's box (the
+  // first 64 blocks of 64 chunks; later blocks are not tested)
+  float blk_gap = 0.0f;
+  if (blk_box && nch > 64 && lane < ((nch + 63) >> 6)) {
+    float bb[8];
+    load_box(box_rsrc(blk_box, (nch + 63) >> 6), lane, bb);
+    blk_gap = box_gap2(bb, ulo, uhi);
+  }
   const unsigned gmin = wave_min_u(gbest);
   const int c0 = __builtin_amdgcn_readfirstlane(
       min((int)wave_min_u(gbest == gmin ? (unsigned)cbest : 0x7fffffffu), nch - 1));  // same in every lane
@@ -464,6 +474,12 @@ __device__ __forceinline__ long long nn_scan_pruned(const float4* __restrict__ p
   refresh();
   int since = 0;
   for (int blk = 0; blk < nch; blk += 64) {
+    // the whole block of 64 chunks is skipped when its box is beyond every
+    // block's bound: each chunk box lies in the block box and each block of
+    // queries in the union box, so no chunk of it could be a candidate
+    if (blk_box && nch > 64 && blk < 64 * 64 &&
+        __int_as_float(__builtin_amdgcn_readlane(__float_as_int(blk_gap), blk >> 6)) > ubmax)
+      continue;
     const int c = blk + lane;
     // lb(q): lower bound of the squared distance between block q's queries
     // and the lane's chunk, kept as FP16 pairs rounded toward zero (still
