@@ -44,7 +44,7 @@ constexpr int kMaxGroups = 1 << 16;
 
 struct Layout {
   size_t groups, objs, pres, obj_prep, pre_prep, obj_pts, pre_pts, obj_perm, pre_perm, obj_box, obj_box1, obj_blk, obj_blk1, kd_box, pre_box,
-      col_box;
+      col_box, col_leaf_box;
   size_t sort_keys, wave_pairs, obj_com, pre_const, col_pts, col_perm, obj_prep_mb, batch_mark, prior;
   size_t theta, cost, col_cost, prev_cost, ncol, converged, grad, grad_ct, grad_col, phi, h, bw_hist, bw_state;
   size_t nn_part, col_part, pen_part, best, best_theta, flags, dbg_nn, dbg_rev;
@@ -92,6 +92,7 @@ Layout layout_of(const Shape& s) {
   L.kd_box = bump(c, 64 * ((size_t)s.obj_tg + 4 * (size_t)s.pre_tg + (size_t)(kGateChunk / 64) * (size_t)s.gate_chunks));
   L.pre_box = bump(c, (size_t)s.pre_tg / kChunkTG * 32);
   L.col_box = bump(c, 32 * (size_t)(s.gate_chunks > 0 ? s.gate_chunks : 1));
+  L.col_leaf_box = bump(c, 32 * (size_t)(kGateChunk / 64) * (size_t)(s.gate_chunks > 0 ? s.gate_chunks : 1));
   L.sort_keys = bump(c, (size_t)s.sort_keys * 8);
   L.col_pts = bump(c, (size_t)(s.c_total > 0 ? s.c_total : 1) * 16);
   L.obj_prep_mb = s.minibatch ? bump(c, (size_t)s.obj_tg * 64 * 16) : 0;
@@ -452,6 +453,7 @@ asicp_status asicp_create(const asicp_problem* pb, const asicp_config* cfg, void
     d.kd_col_off = s.obj_tg + 4 * s.pre_tg;
     d.pre_box = reinterpret_cast<float*>(ws + L.pre_box);
     d.col_box = reinterpret_cast<float*>(ws + L.col_box);
+    d.col_leaf_box = reinterpret_cast<float*>(ws + L.col_leaf_box);
     d.sort_keys = reinterpret_cast<unsigned long long*>(ws + L.sort_keys);
     d.col_pts = reinterpret_cast<float4*>(ws + L.col_pts);
     d.col_perm = reinterpret_cast<int32_t*>(ws + L.col_perm);

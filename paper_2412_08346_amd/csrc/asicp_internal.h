@@ -90,6 +90,7 @@ struct Dev {
   float* obj_blk1;  // the same for the 64-point chunks of obj_box1
   float* pre_box;
   float* col_box;  // [gate chunks][8]: box of each kGateChunk points of the sorted collision clouds
+  float* col_leaf_box;  // [gate chunks][kGateChunk / 64][8]: box of each 64-point leaf of them
   float4* col_pts;    // collision clouds in k-d leaf order (offsets as the input's)
   int32_t* col_perm;
   unsigned long long* sort_keys;

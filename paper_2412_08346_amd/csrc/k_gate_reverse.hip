@@ -123,6 +123,32 @@ __device__ __forceinline__ bool box_may_collide(const PreInfo& pi, const float* 
   return true;
 }
 
+// The same test for one 64-point leaf, per lane: the leaf box moved into the
+// gripper frame as centre R^T (c - t) and half extents |R^T| e (the box of
+// its rotated corners, in fewer operations), with the same margin.  An empty
+// leaf (lo > hi) never collides.
+__device__ __forceinline__ bool leaf_may_collide(const PreInfo& pi, const float* bx, const float R[9],
+                                                 const float t[3]) {
+  if (!(bx[0] <= bx[4] && bx[1] <= bx[5] && bx[2] <= bx[6])) return false;
+  const float cx = 0.5f * (bx[0] + bx[4]) - t[0], cy = 0.5f * (bx[1] + bx[5]) - t[1],
+              cz = 0.5f * (bx[2] + bx[6]) - t[2];
+  const float ex = 0.5f * (bx[4] - bx[0]), ey = 0.5f * (bx[5] - bx[1]), ez = 0.5f * (bx[6] - bx[2]);
+  const float c[3] = {R[0] * cx + R[3] * cy + R[6] * cz, R[1] * cx + R[4] * cy + R[7] * cz,
+                      R[2] * cx + R[5] * cy + R[8] * cz};
+  const float e[3] = {fabsf(R[0]) * ex + fabsf(R[3]) * ey + fabsf(R[6]) * ez,
+                      fabsf(R[1]) * ex + fabsf(R[4]) * ey + fabsf(R[7]) * ez,
+                      fabsf(R[2]) * ex + fabsf(R[5]) * ey + fabsf(R[8]) * ez};
+  const float o[3] = {pi.ox, pi.oy, pi.oz};
+  const float margin = 1e-5f;
+  bool ok = true;
+  for (int a = 0; a < 3; ++a) {
+    const float b0 = o[a] + (float)(pi.neg_lo[a] - 1) * pi.cell - margin;
+    const float b1 = o[a] + (float)(pi.neg_hi[a] + 1) * pi.cell + margin;
+    ok = ok && c[a] + e[a] >= b0 && c[a] - e[a] <= b1;
+  }
+  return ok;
+}
+
 // Reverse NN of Q blocks of colliding points (gripper frame) against the
 // k-d ordered contact cloud, skipping contact chunks that cannot hold a
 // nearest point (same exact result as scanning them all).
@@ -197,7 +223,18 @@ __global__ __launch_bounds__(256) void k_gate_reverse(Dev d) {
   }
 
   // gate: thread tid owns points cc*2048 + r*256 + tid, r = 0..7, of the
-  // k-d ordered collision cloud (so colliding points come out clustered)
+  // k-d ordered collision cloud (so colliding points come out clustered).
+  // In round r the wave's 64 points are one 64-point leaf (r * 4 + w of the
+  // chunk); lane r tests that leaf's box, and rounds whose leaf cannot reach
+  // a negative cell load no point (bit r of lmask, uniform over the wave)
+  unsigned int lmask;
+  {
+    bool ok = false;
+    if (lane < kPerThread)
+      ok = leaf_may_collide(pi, d.col_leaf_box + (((size_t)oi.gbox_begin + cc) * (kGateChunk / 64) + lane * 4 + w) * 8,
+                            R, t);
+    lmask = (unsigned int)__ballot(ok);
+  }
   unsigned int bits = 0u;
   float px[kPerThread], py[kPerThread], pz[kPerThread];
   // penetration sums (gripper frame): phi^2, -2 phi grad, 2 phi grad x c'
@@ -208,6 +245,8 @@ __global__ __launch_bounds__(256) void k_gate_reverse(Dev d) {
   // so their memory latencies overlap
 #pragma unroll
   for (int r = 0; r < kPerThread; ++r) {
+    px[r] = py[r] = pz[r] = 0.f;
+    if (!((lmask >> r) & 1u)) continue;
     const int m = cc * kGateChunk + r * 256 + tid;
     const float4 c = d.col_pts[oi.c_begin + max(0, min(m, oi.mc - 1))];
     const float dx = c.x - t[0];
@@ -226,7 +265,8 @@ __global__ __launch_bounds__(256) void k_gate_reverse(Dev d) {
     for (int u = 0; u < kGateBatch; ++u) {
       const int r = r0 + u;
       off[u] = 0;
-      cand[u] = cc * kGateChunk + r * 256 + tid < oi.mc && sdf_cell(pi, px[r], py[r], pz[r], off[u], fr[u]);
+      cand[u] = ((lmask >> r) & 1u) && cc * kGateChunk + r * 256 + tid < oi.mc &&
+                sdf_cell(pi, px[r], py[r], pz[r], off[u], fr[u]);
       if (cand[u]) sdf_corners(pi, off[u], v[u]);
     }
 #pragma unroll

@@ -248,7 +248,6 @@ __device__ __forceinline__ void kd_leaf_order(unsigned long long* keys, int n, i
 // kGateChunk points (one gate workgroup's share).  Padding points carry
 // |r|^2 = 1e30.
 __global__ __launch_bounds__(1024) void k_sort_cloud(Dev d) {
-  __shared__ float sb[1024][6];
   const int tid = threadIdx.x;
   // kind 0: object cloud, 1: contact cloud, 2: collision cloud (no MFMA copy)
   const int kind = blockIdx.x < d.n_obj ? 0 : (blockIdx.x < d.n_obj + d.n_pre ? 1 : 2);
@@ -320,26 +319,44 @@ __global__ __launch_bounds__(1024) void k_sort_cloud(Dev d) {
     // the box of every kGateChunk consecutive sorted points (one gate
     // workgroup's share), read back from the unsorted inputs
     const ObjInfo& oi = d.objs[blockIdx.x - d.n_obj - d.n_pre];
-    for (int c = 0; c < oi.gate_chunks; ++c) {
+    __syncthreads();  // the sorted points are read back below
+    // the box of every 64-point leaf (one wavefront per leaf, a lane per
+    // point), then of every kGateChunk points (one gate workgroup's share,
+    // 32 leaves: one wavefront per chunk, a lane per leaf)
+    const int w = tid >> 6, lane = tid & 63, nleaf = (n + 63) >> 6;
+    float* leaf = d.col_leaf_box + (size_t)oi.gbox_begin * (kGateChunk / 64) * 8;
+    for (int lf = w; lf < oi.gate_chunks * (kGateChunk / 64); lf += 16) {
       float e[6] = {__builtin_inff(), __builtin_inff(), __builtin_inff(),
                     -__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
-      for (int k = c * kGateChunk + tid; k < min(n, (c + 1) * kGateChunk); k += 1024) {
-        const int orig = (int)(keys[k] & kOrigMask);
-        const float x = sx[orig] - c0, y = sy[orig] - c1, z = sz[orig] - c2;
-        e[0] = fminf(e[0], x); e[1] = fminf(e[1], y); e[2] = fminf(e[2], z);
-        e[3] = fmaxf(e[3], x); e[4] = fmaxf(e[4], y); e[5] = fmaxf(e[5], z);
+      const int k = lf * 64 + lane;
+      if (lf < nleaf && k < n) {
+        const float4 p = pts[base + k];
+        e[0] = e[3] = p.x;
+        e[1] = e[4] = p.y;
+        e[2] = e[5] = p.z;
       }
-      __syncthreads();  // sb is reused
-      for (int a = 0; a < 6; ++a) sb[tid][a] = e[a];
-      __syncthreads();
-      for (int off = 512; off >= 1; off >>= 1) {
-        if (tid < off) {
-          for (int a = 0; a < 3; ++a) sb[tid][a] = fminf(sb[tid][a], sb[tid + off][a]);
-          for (int a = 3; a < 6; ++a) sb[tid][a] = fmaxf(sb[tid][a], sb[tid + off][a]);
+      for (int off = 32; off >= 1; off >>= 1) {
+        for (int a = 0; a < 3; ++a) e[a] = fminf(e[a], __shfl_xor(e[a], off, 64));
+        for (int a = 3; a < 6; ++a) e[a] = fmaxf(e[a], __shfl_xor(e[a], off, 64));
+      }
+      if (lane < 8) leaf[(size_t)lf * 8 + lane] = lane == 3 || lane == 7 ? 0.f : e[lane < 3 ? lane : lane - 1];
+    }
+    __syncthreads();
+    for (int c = w; c < oi.gate_chunks; c += 16) {
+      float e[6] = {__builtin_inff(), __builtin_inff(), __builtin_inff(),
+                    -__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
+      if (lane < kGateChunk / 64) {
+        const float* lb = leaf + ((size_t)c * (kGateChunk / 64) + lane) * 8;
+        for (int a = 0; a < 3; ++a) {
+          e[a] = lb[a];
+          e[3 + a] = lb[4 + a];
         }
-        __syncthreads();
       }
-      if (tid < 8) d.col_box[(size_t)(oi.gbox_begin + c) * 8 + tid] = tid == 3 || tid == 7 ? 0.f : sb[0][tid < 3 ? tid : tid - 1];
+      for (int off = 32; off >= 1; off >>= 1) {
+        for (int a = 0; a < 3; ++a) e[a] = fminf(e[a], __shfl_xor(e[a], off, 64));
+        for (int a = 3; a < 6; ++a) e[a] = fmaxf(e[a], __shfl_xor(e[a], off, 64));
+      }
+      if (lane < 8) d.col_box[(size_t)(oi.gbox_begin + c) * 8 + lane] = lane == 3 || lane == 7 ? 0.f : e[lane < 3 ? lane : lane - 1];
     }
     return;
   }
