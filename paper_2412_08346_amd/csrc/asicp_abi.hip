@@ -40,6 +40,9 @@ asicp_status guarded(F&& body) noexcept {
 }
 
 constexpr int kMaxPoints = 1 << 22;   // per object / collision cloud / preshape
+// In a captured graph, forward launches of at most this many wavefronts (well
+// below the 7168 the GPU holds at once) run the gate on a branch of its own.
+constexpr long long kConcurrentGateWaves = 2048;
 constexpr int kMaxGroups = 1 << 16;
 
 struct Layout {
@@ -328,7 +331,11 @@ struct asicp_ctx_s {
   // gate depend only on the poses, so they run beside the forward NN launch
   // (fork after the caller's preceding work, join before the finaliser).
   hipStream_t side;
-  hipEvent_t fork_ev, join_ev;
+  hipStream_t side2;            // the gate's branch in a captured graph of a small problem
+                                //   (created with the capture stream and kept with the graph:
+                                //   releasing it after the capture slowed replays, 1.53 against
+                                //   1.21 ms per small solve)
+  hipEvent_t fork_ev, join_ev, join2_ev;
 };
 
 extern "C" {
@@ -548,12 +555,13 @@ asicp_status asicp_create(const asicp_problem* pb, const asicp_config* cfg, void
     c->final_done = false;
     c->inv_log_k = s.K >= 2 ? (float)(1.0 / std::log((double)s.K)) : 1.0f;
     c->n_timed = 0;
-    c->side = nullptr;
-    c->fork_ev = c->join_ev = nullptr;
+    c->side = c->side2 = nullptr;
+    c->fork_ev = c->join_ev = c->join2_ev = nullptr;
     // default priority, like every stream here
     if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->join2_ev, hipEventDisableTiming) != hipSuccess) {
       asicp_destroy(c);
       return fail(ASICP_E_HIP, "creating the side stream or its events failed");
     }
@@ -627,24 +635,38 @@ static asicp_status evaluate(asicp_ctx c, int k, int final_eval, bool bandwidth,
   };
   if (ASICP_NN_FIRST && (st = forward()) != ASICP_OK) return st;
   if (hipStreamWaitEvent(c->side, e0, 0) != hipSuccess) return fail(ASICP_E_HIP, "fork to the side stream failed");
+  // In a captured graph, a forward launch too small to fill the GPU leaves
+  // room for the gate beside the bandwidth select: then the gate gets a
+  // branch of its own (a second side stream; on a small problem the
+  // select-then-gate chain was the replayed iteration's critical path).  A
+  // large forward launch is slowed by gate workgroups started early, so there
+  // the gate follows the select; enqueued kernel by kernel, a third stream's
+  // dependencies cost more than they save (small workload: 2.50 against
+  // 1.50 ms per solve; replayed: 1.22 against 1.38 ms).
+  const bool split = c->capturing && c->side2 && (long long)c->d.total_waves[c->d.nn_qi] <= kConcurrentGateWaves;
+  if (split && hipStreamWaitEvent(c->side2, e0, 0) != hipSuccess)
+    return fail(ASICP_E_HIP, "fork to the second side stream failed");
+  hipStream_t gate_stream = split ? c->side2 : c->side;
 #ifndef ASICP_GATE_FIRST
 #define ASICP_GATE_FIRST 0
 #endif
-  if (ASICP_GATE_FIRST) {
-    launch_gate_reverse(c->d, c->side);
+  if (ASICP_GATE_FIRST || split) {
+    launch_gate_reverse(c->d, gate_stream);
     if ((st = check_launch("gate_reverse")) != ASICP_OK) return st;
   }
   if (bandwidth) {
     launch_bandwidth(c->d, c->inv_log_k, c->side);
     if ((st = check_launch("bandwidth")) != ASICP_OK) return st;
   }
-  if (!ASICP_GATE_FIRST) {
-    launch_gate_reverse(c->d, c->side);
+  if (!ASICP_GATE_FIRST && !split) {
+    launch_gate_reverse(c->d, gate_stream);
     if ((st = check_launch("gate_reverse")) != ASICP_OK) return st;
   }
   if (!ASICP_NN_FIRST && (st = forward()) != ASICP_OK) return st;
   if (hipEventRecord(c->join_ev, c->side) != hipSuccess || hipStreamWaitEvent(hs, c->join_ev, 0) != hipSuccess)
     return fail(ASICP_E_HIP, "join of the side stream failed");
+  if (split && (hipEventRecord(c->join2_ev, c->side2) != hipSuccess || hipStreamWaitEvent(hs, c->join2_ev, 0) != hipSuccess))
+    return fail(ASICP_E_HIP, "join of the second side stream failed");
   launch_finalize(c->d, k, final_eval, hs);
   return check_launch("finalize");
 }
@@ -777,6 +799,10 @@ asicp_status asicp_replay(asicp_ctx c, void* stream) {
       // priority.
       if (!c->cap_stream && hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
         c->cap_stream = nullptr;
+        return fail(ASICP_E_HIP, "hipStreamCreateWithFlags failed");
+      }
+      if (!c->side2 && hipStreamCreateWithFlags(&c->side2, hipStreamNonBlocking) != hipSuccess) {
+        c->side2 = nullptr;
         return fail(ASICP_E_HIP, "hipStreamCreateWithFlags failed");
       }
       hipStream_t cs = c->cap_stream;
@@ -1014,8 +1040,10 @@ void asicp_destroy(asicp_ctx c) {
   if (c->graph) (void)hipGraphExecDestroy(c->graph);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   if (c->side) (void)hipStreamDestroy(c->side);
+  if (c->side2) (void)hipStreamDestroy(c->side2);
   if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
   if (c->join_ev) (void)hipEventDestroy(c->join_ev);
+  if (c->join2_ev) (void)hipEventDestroy(c->join2_ev);
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   delete c;
 }
