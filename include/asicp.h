@@ -232,9 +232,9 @@ asicp_status asicp_pose_vjp(const float* grad, const float* gout, float* dtheta,
  * borrowed inputs (which the caller may have rewritten in place: a new object
  * of the same size, new initial particles), iterations k_start .. k_max-1,
  * the final evaluation and the selection.  The graph is captured on the first
- * call (on a private stream; `stream` may be the null stream) and replayed
- * after, so repeated solves
- * pay no per-kernel launch cost.  Afterwards the context is in the state
+ * call (on private streams kept with the graph; `stream` may be the null
+ * stream) and replayed after, so repeated solves pay no per-kernel launch
+ * cost.  Afterwards the context is in the state
  * asicp_solve leaves it in.  Not available with ASICP_FLAG_DEBUG
  * (ASICP_E_STATE); ASICP_FLAG_TIMING events are not recorded inside the graph. */
 asicp_status asicp_replay(asicp_ctx ctx, void* stream);
