@@ -109,14 +109,15 @@ constexpr unsigned long long kOrigMask = (1ull << 22) - 1;
 // memory, by one workgroup of 1024 threads (inlined, so that LDS arrays are
 // addressed as LDS).  With seg < npow2 (a power of two) each aligned block of
 // seg keys is sorted on its own (fewer stages: the blocks need no merging).
-__device__ __forceinline__ void bitonic_sort(unsigned long long* keys, int npow2, int tid, int seg) {
+template <typename K>
+__device__ __forceinline__ void bitonic_sort(K* keys, int npow2, int tid, int seg) {
   for (int size = 2; size <= seg; size <<= 1) {
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
       for (int t = tid; t < (npow2 >> 1); t += 1024) {
         const int i = ((t & ~(stride - 1)) << 1) | (t & (stride - 1));  // stride is a power of two
         const int j = i + stride;
         const bool asc = size == seg || (i & size) == 0;
-        const unsigned long long a = keys[i], c = keys[j];
+        const K a = keys[i], c = keys[j];
         if ((a > c) == asc) {
           keys[i] = c;
           keys[j] = a;
@@ -155,13 +156,18 @@ __device__ __forceinline__ void kd_part(int nleaf, int cap, int level, int lf, i
 // orders all parts at once; ties fall to the original index, so the order is
 // deterministic.  unit: points per leaf (16 or 64); kb: 16 floats of scratch
 // per leaf.  Inlined, so that LDS arrays passed in are addressed as LDS.
-__device__ __forceinline__ void kd_leaf_order(unsigned long long* keys, int n, int npow2, int unit, int cap,
-                                              const float* sx, const float* sy, const float* sz, float* kb,
-                                              int* s_split, int tid) {
+template <typename K>
+__device__ __forceinline__ void kd_leaf_order(K* keys, int n, int npow2, int unit, int cap, const float* sx,
+                                              const float* sy, const float* sz, float* kb, int* s_split, int tid) {
+  // 64-bit keys: (first leaf of the part, 16-bit position, original index);
+  // 32-bit keys, when every part is an aligned block sorted on its own (the
+  // part is implied by the position): (10-bit position, original index)
+  constexpr bool k32 = sizeof(K) == 4;
+  constexpr float kQ = k32 ? 1023.0f : 65535.0f;
   const int ush = unit == 16 ? 4 : 6;  // unit is 16 or 64
   const int nleaf = (n + unit - 1) >> ush;
   const int w = tid >> 6, lane = tid & 63;
-  for (int k = tid; k < npow2; k += 1024) keys[k] = k < n ? (unsigned long long)k : ~0ull;
+  for (int k = tid; k < npow2; k += 1024) keys[k] = k < n ? (K)k : (K)~0ull;
   __syncthreads();
   for (int level = 0;; ++level) {
     // the box of every leaf in the current order: a wavefront covers 64
@@ -209,7 +215,7 @@ __device__ __forceinline__ void kd_leaf_order(unsigned long long* keys, int n, i
         const float ext = v[3 + ax] - v[ax];
         kb[(size_t)a * 16 + 8] = __int_as_float(ax);
         kb[(size_t)a * 16 + 9] = v[ax];
-        kb[(size_t)a * 16 + 10] = ext > 0.f ? 65535.0f / ext : 0.f;
+        kb[(size_t)a * 16 + 10] = ext > 0.f ? kQ / ext : 0.f;
         *s_split = 1;
       }
     }
@@ -223,10 +229,12 @@ __device__ __forceinline__ void kd_leaf_order(unsigned long long* keys, int n, i
       if (b - a >= 2) {
         const int ax = __float_as_int(kb[(size_t)a * 16 + 8]);
         const float x = ax == 0 ? sx[o] : (ax == 1 ? sy[o] : sz[o]);
-        q = (unsigned int)fminf(fmaxf((x - kb[(size_t)a * 16 + 9]) * kb[(size_t)a * 16 + 10], 0.f), 65535.f);
+        q = (unsigned int)fminf(fmaxf((x - kb[(size_t)a * 16 + 9]) * kb[(size_t)a * 16 + 10], 0.f), kQ);
       }
-      // part (< 2^18 leaves) | position (16 bits) | original index (< 2^22)
-      keys[pos] = ((unsigned long long)a << 38) | ((unsigned long long)q << 22) | (unsigned int)o;
+      if (k32)  // position (10 bits) | original index (< 2^22)
+        keys[pos] = (K)((q << 22) | (unsigned int)o);
+      else      // part (< 2^18 leaves) | position (16 bits) | original index (< 2^22)
+        keys[pos] = (K)(((unsigned long long)a << 38) | ((unsigned long long)q << 22) | (unsigned int)o);
     }
     __syncthreads();
     // a cloud of a power-of-two number of whole leaves splits into aligned
@@ -301,7 +309,19 @@ __global__ __launch_bounds__(1024) void k_sort_cloud(Dev d) {
   const int cap = kind == 2 ? kGateChunk / 64 : 128 / unit;
   const bool lds = npow2 <= kLdsKeys && (n + unit - 1) / unit <= kLdsLeaves;  // uniform
   unsigned long long* keys = lds ? lkeys : d.sort_keys + key_off;
-  if (lds) {
+  const bool halves = n == npow2 && (((n + unit - 1) / unit) & ((n + unit - 1) / unit - 1)) == 0;
+  if (lds && halves) {
+    // 32-bit keys in the first half of lkeys, widened to the 64-bit keys the
+    // code below reads
+    unsigned int* k32 = reinterpret_cast<unsigned int*>(lkeys);
+    kd_leaf_order(k32, n, npow2, unit, cap, sx, sy, sz, lkb, &s_split, tid);
+    unsigned int v[kLdsKeys / 1024];
+    for (int r = 0; r < kLdsKeys / 1024; ++r) v[r] = tid + r * 1024 < npow2 ? k32[tid + r * 1024] : 0u;
+    __syncthreads();
+    for (int r = 0; r < kLdsKeys / 1024; ++r)
+      if (tid + r * 1024 < npow2) lkeys[tid + r * 1024] = v[r] == ~0u ? ~0ull : (unsigned long long)(v[r] & kOrigMask);
+    __syncthreads();
+  } else if (lds) {
     kd_leaf_order(lkeys, n, npow2, unit, cap, sx, sy, sz, lkb, &s_split, tid);
   } else {
     float* kb = d.kd_box + 16 * (kind == 0 ? (size_t)tg0
