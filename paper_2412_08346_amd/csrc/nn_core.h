@@ -118,15 +118,29 @@ __device__ __forceinline__ void chunk_step(const float4 (&a)[CH], const float* b
     if (ASCENDING && t) __builtin_amdgcn_sched_barrier(0);
     tile_group<Q>(a[t], b, m, need);
   }
+  // A block the chunk was not compared with keeps m = +inf, and its running
+  // minimum is finite (the first chunk is compared with every block), so the
+  // updates below leave it as it is.
+  if (ASCENDING) {
 #pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    if (need && !need[q]) continue;  // wave-uniform
-    if (ASCENDING)
-      bch[q] = m[q] < best[q] ? c : bch[q];
-    else
-      bch[q] = (m[q] < best[q] || (m[q] == best[q] && c < bch[q])) ? c : bch[q];
-    best[q] = fminf(best[q], m[q]);
+    for (int q = 0; q < Q; ++q) bch[q] = m[q] < best[q] ? c : bch[q];
+  } else {
+    // A chunk value equal to the running minimum (a tie across chunks) is
+    // rare: one wave-wide test, and only then the lower-index rule
+    bool tie = false;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) tie = tie || m[q] == best[q];
+    if (__ballot(tie) != 0ull) {
+#pragma unroll
+      for (int q = 0; q < Q; ++q)
+        bch[q] = (m[q] < best[q] || (m[q] == best[q] && c < bch[q])) ? c : bch[q];
+    } else {
+#pragma unroll
+      for (int q = 0; q < Q; ++q) bch[q] = m[q] < best[q] ? c : bch[q];
+    }
   }
+#pragma unroll
+  for (int q = 0; q < Q; ++q) best[q] = fminf(best[q], m[q]);
 }
 
 // Re-find the index of each query's minimum.  Each lane group owns rows
