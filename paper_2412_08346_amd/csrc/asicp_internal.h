@@ -25,6 +25,7 @@ __host__ __device__ constexpr int q_blocks(int qi) { return 1 << qi; }
 #endif
 constexpr int kGateChunk = 2048;   // collision points per gate workgroup (8 per thread)
 constexpr int kPartStride = 8;     // floats per partial-sum record
+constexpr int kBrick = 4;          // cells per brick edge of the SDF cull table
 constexpr int kBwSlices = 32;      // workgroups per group in each bandwidth pass
 constexpr float kDummyNorm = 1.0e30f;  // |r|^2 of padding points: never a nearest neighbour
 
@@ -58,6 +59,15 @@ struct PreInfo {
   int32_t neg_lo[3];       // per axis: lowest / highest node index with a
   int32_t neg_hi[3];       //   negative value (set on the device at set-up)
   int32_t key_off;         // offset of this cloud's sort keys (uint64) in the scratch
+  // Cull tables of the grid (written on the device at set-up):
+  // cell_bits: bit (x % 32) of word ((z (ny - 1) + y) cbw + x / 32) is set when
+  //   cell (x, y, z) (nodes x..x+1, y..y+1, z..z+1) has a negative node;
+  // brick_sum: over bricks of kBrick^3 cells, entry (z (bny + 1) + y) (bnx + 1) + x
+  //   counts the bricks (bx < x, by < y, bz < z) holding such a cell.
+  const uint32_t* cell_bits;
+  const int32_t* brick_sum;
+  int32_t cbw, bnx, bny, bnz;
+  int32_t sdf_done;        // set-up workgroups finished on the tables (0 between set-ups)
 };
 
 // Everything a kernel needs, passed by value.
@@ -98,6 +108,7 @@ struct Dev {
                      //   per tile group, then contact clouds from kd_pre_off (4 per tile
                      //   group), then collision clouds from kd_col_off (32 per gate chunk)
   int32_t kd_pre_off, kd_col_off;
+  int32_t sdf_blocks;  // set-up workgroups per preshape building the SDF cull tables
   unsigned long long* wave_pairs;  // [total_waves[0]] distances evaluated per forward wave,
                                    //   summed over launches (ASICP_FLAG_TIMING only, else NULL)
   int32_t prune;                 // skip object chunks that cannot hold a nearest neighbour

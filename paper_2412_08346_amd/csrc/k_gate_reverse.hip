@@ -53,6 +53,7 @@ __device__ __forceinline__ bool sdf_cell(const PreInfo& pi, float px, float py, 
   if (ix < pi.neg_lo[0] - 1 || ix > pi.neg_hi[0] || iy < pi.neg_lo[1] - 1 || iy > pi.neg_hi[1] ||
       iz < pi.neg_lo[2] - 1 || iz > pi.neg_hi[2])
     return false;
+  if (!((pi.cell_bits[((long long)iz * (pi.ny - 1) + iy) * pi.cbw + (ix >> 5)] >> (ix & 31)) & 1u)) return false;
   f[0] = ux - (float)ix;
   f[1] = uy - (float)iy;
   f[2] = uz - (float)iz;
@@ -94,41 +95,17 @@ __device__ __forceinline__ float sdf_interp(const float v[8], const float f[3], 
 }
 
 // Can any point of a box of collision points (lo = bx[0..2], hi = bx[4..6])
-// reach a cell with a negative corner?  Box corners are moved into the
-// gripper frame; a 10 um margin covers the rounding of the per-point
-// transform.
+// reach a cell with a negative node?  The box is moved into the gripper frame
+// as centre R^T (c - t) and half extents |R^T| e (the box of its rotated
+// corners), widened by 10 um for the rounding of the per-point transform; it
+// must meet the box of cells next to negative nodes, and the bricks its cells
+// fall in must hold such a cell (8 entries of the brick counts).  A point's
+// cell index is a monotone function of its coordinate, so the cells of the
+// points lie in the range computed from the box's bounds.  An empty box
+// (lo > hi) never collides.
 __device__ __forceinline__ bool box_may_collide(const PreInfo& pi, const float* bx, const float R[9],
                                                 const float t[3]) {
   if (pi.neg_hi[0] < 0) return false;  // no negative node at all
-  float lo[3] = {__builtin_inff(), __builtin_inff(), __builtin_inff()};
-  float hi[3] = {-__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
-  for (int c = 0; c < 8; ++c) {
-    const float dx = ((c & 1) ? bx[4] : bx[0]) - t[0];
-    const float dy = ((c & 2) ? bx[5] : bx[1]) - t[1];
-    const float dz = ((c & 4) ? bx[6] : bx[2]) - t[2];
-    const float p[3] = {R[0] * dx + R[3] * dy + R[6] * dz, R[1] * dx + R[4] * dy + R[7] * dz,
-                        R[2] * dx + R[5] * dy + R[8] * dz};
-    for (int a = 0; a < 3; ++a) {
-      lo[a] = fminf(lo[a], p[a]);
-      hi[a] = fmaxf(hi[a], p[a]);
-    }
-  }
-  const float o[3] = {pi.ox, pi.oy, pi.oz};
-  const float margin = 1e-5f;
-  for (int a = 0; a < 3; ++a) {
-    const float b0 = o[a] + (float)(pi.neg_lo[a] - 1) * pi.cell - margin;
-    const float b1 = o[a] + (float)(pi.neg_hi[a] + 1) * pi.cell + margin;
-    if (!(hi[a] >= b0 && lo[a] <= b1)) return false;
-  }
-  return true;
-}
-
-// The same test for one 64-point leaf, per lane: the leaf box moved into the
-// gripper frame as centre R^T (c - t) and half extents |R^T| e (the box of
-// its rotated corners, in fewer operations), with the same margin.  An empty
-// leaf (lo > hi) never collides.
-__device__ __forceinline__ bool leaf_may_collide(const PreInfo& pi, const float* bx, const float R[9],
-                                                 const float t[3]) {
   if (!(bx[0] <= bx[4] && bx[1] <= bx[5] && bx[2] <= bx[6])) return false;
   const float cx = 0.5f * (bx[0] + bx[4]) - t[0], cy = 0.5f * (bx[1] + bx[5]) - t[1],
               cz = 0.5f * (bx[2] + bx[6]) - t[2];
@@ -139,14 +116,30 @@ __device__ __forceinline__ bool leaf_may_collide(const PreInfo& pi, const float*
                       fabsf(R[1]) * ex + fabsf(R[4]) * ey + fabsf(R[7]) * ez,
                       fabsf(R[2]) * ex + fabsf(R[5]) * ey + fabsf(R[8]) * ez};
   const float o[3] = {pi.ox, pi.oy, pi.oz};
+  const int n[3] = {pi.nx, pi.ny, pi.nz};
   const float margin = 1e-5f;
-  bool ok = true;
+  int b0[3], b1[3];
   for (int a = 0; a < 3; ++a) {
-    const float b0 = o[a] + (float)(pi.neg_lo[a] - 1) * pi.cell - margin;
-    const float b1 = o[a] + (float)(pi.neg_hi[a] + 1) * pi.cell + margin;
-    ok = ok && c[a] + e[a] >= b0 && c[a] - e[a] <= b1;
+    const float lo = c[a] - e[a] - margin, hi = c[a] + e[a] + margin;
+    const float g0 = o[a] + (float)(pi.neg_lo[a] - 1) * pi.cell - margin;
+    const float g1 = o[a] + (float)(pi.neg_hi[a] + 1) * pi.cell + margin;
+    if (!(hi >= g0 && lo <= g1)) return false;
+    // cells of the points, as the per-point lookup computes them (outside
+    // the node box no point collides)
+    const float u0 = (lo - o[a]) * pi.inv_cell, u1 = (hi - o[a]) * pi.inv_cell;
+    if (!(u1 >= 0.f && u0 <= (float)(n[a] - 1))) return false;
+    const int i0 = u0 > 0.f ? (int)fminf(floorf(u0), (float)(n[a] - 2)) : 0;
+    const int i1 = (int)fminf(floorf(u1), (float)(n[a] - 2));
+    b0[a] = i0 / kBrick;
+    b1[a] = i1 / kBrick + 1;
   }
-  return ok;
+  const long long ex1 = pi.bnx + 1, pl = ex1 * (pi.bny + 1);
+  auto at = [&](int x, int y, int z) { return pi.brick_sum[(long long)z * pl + (long long)y * ex1 + x]; };
+  const int cnt = (at(b1[0], b1[1], b1[2]) - at(b0[0], b1[1], b1[2]) - at(b1[0], b0[1], b1[2]) -
+                   at(b1[0], b1[1], b0[2])) +
+                  (at(b0[0], b0[1], b1[2]) + at(b0[0], b1[1], b0[2]) + at(b1[0], b0[1], b0[2]) -
+                   at(b0[0], b0[1], b0[2]));
+  return cnt > 0;
 }
 
 // Reverse NN of Q blocks of colliding points (gripper frame) against the
@@ -231,7 +224,7 @@ __global__ __launch_bounds__(256) void k_gate_reverse(Dev d) {
   {
     bool ok = false;
     if (lane < kPerThread)
-      ok = leaf_may_collide(pi, d.col_leaf_box + (((size_t)oi.gbox_begin + cc) * (kGateChunk / 64) + lane * 4 + w) * 8,
+      ok = box_may_collide(pi, d.col_leaf_box + (((size_t)oi.gbox_begin + cc) * (kGateChunk / 64) + lane * 4 + w) * 8,
                             R, t);
     lmask = (unsigned int)__ballot(ok);
   }

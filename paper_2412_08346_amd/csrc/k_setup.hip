@@ -245,6 +245,116 @@ __device__ __forceinline__ void kd_leaf_order(K* keys, int n, int npow2, int uni
   }
 }
 
+// SDF cull tables of preshape p, built by workgroup j of d.sdf_blocks (1024
+// threads each) beside the cloud sorts: the box of negative nodes, one bit
+// per cell telling whether any of its 8 nodes is negative (a trilinear value
+// is a convex combination of the cell's node values, so only such a cell can
+// give a negative value), and, from the last of the workgroups to finish,
+// the 3-D prefix counts of bricks of kBrick^3 cells holding such a cell (the
+// number of them in any box of bricks from 8 entries).
+__device__ void sdf_tables(const Dev& d, int p, int j) {
+  __shared__ int s_last;
+  PreInfo* pi = const_cast<PreInfo*>(d.pres) + p;
+  const int nx = pi->nx, ny = pi->ny, nz = pi->nz;
+  const float* v = pi->sdf;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const long long stride = (long long)d.sdf_blocks * 1024;
+  // box of the negative nodes
+  {
+    const long long total = (long long)nx * ny * nz;
+    int lo[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, hi[3] = {-1, -1, -1};
+    for (long long idx = (long long)j * 1024 + tid; idx < total; idx += stride) {
+      if (v[idx] < 0.f) {
+        const int x = (int)(idx % nx), y = (int)((idx / nx) % ny), z = (int)(idx / ((long long)nx * ny));
+        lo[0] = min(lo[0], x); lo[1] = min(lo[1], y); lo[2] = min(lo[2], z);
+        hi[0] = max(hi[0], x); hi[1] = max(hi[1], y); hi[2] = max(hi[2], z);
+      }
+    }
+    for (int a = 0; a < 3; ++a) {
+      for (int off = 32; off >= 1; off >>= 1) {
+        lo[a] = min(lo[a], __shfl_xor(lo[a], off, 64));
+        hi[a] = max(hi[a], __shfl_xor(hi[a], off, 64));
+      }
+    }
+    if (lane == 0) {
+      for (int a = 0; a < 3; ++a) {
+        if (lo[a] != 0x7fffffff) atomicMin(&pi->neg_lo[a], lo[a]);
+        if (hi[a] != -1) atomicMax(&pi->neg_hi[a], hi[a]);
+      }
+    }
+  }
+  // cell bits: slot s is bit s % 32 of word s / 32; the 64 slots of a wave
+  // are two whole words (the loop bound is uniform over the wave)
+  const int cbw = pi->cbw;
+  uint32_t* bits = const_cast<uint32_t*>(pi->cell_bits);
+  const long long nwords = (long long)(nz - 1) * (ny - 1) * cbw;
+  const long long sy = nx, sz = (long long)nx * ny;
+  for (long long s0 = (long long)j * 1024 + (tid & ~63); s0 < 32 * nwords; s0 += stride) {
+    const long long w = (s0 + lane) >> 5;
+    bool neg = false;
+    if (w < nwords) {
+      const int x = (int)(w % cbw) * 32 + (lane & 31);
+      const long long row = w / cbw;
+      const int y = (int)(row % (ny - 1)), z = (int)(row / (ny - 1));
+      if (x < nx - 1) {
+        const float* g = v + (long long)z * sz + (long long)y * sy + x;
+        neg = g[0] < 0.f || g[1] < 0.f || g[sy] < 0.f || g[sy + 1] < 0.f || g[sz] < 0.f || g[sz + 1] < 0.f ||
+              g[sz + sy] < 0.f || g[sz + sy + 1] < 0.f;
+      }
+    }
+    const unsigned long long b = __ballot(neg);
+    if ((lane & 31) == 0 && w < nwords) bits[w] = (uint32_t)(b >> (lane & 32));
+  }
+  // the last workgroup to finish builds the brick counts
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) s_last = atomicAdd(&pi->sdf_done, 1) == d.sdf_blocks - 1;
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  const int bnx = pi->bnx, bny = pi->bny, bnz = pi->bnz;
+  const int ex = bnx + 1, ey = bny + 1;
+  const long long plane = (long long)ex * ey, ntot = plane * (bnz + 1);
+  int* S = const_cast<int*>(pi->brick_sum);
+  for (long long e = tid; e < ntot; e += 1024) {
+    const int x = (int)(e % ex), y = (int)((e / ex) % ey), z = (int)(e / plane);
+    unsigned int f = 0u;
+    if (x > 0 && y > 0 && z > 0) {
+      // cells kBrick (x - 1) .. + kBrick - 1 lie in one word (kBrick divides 32)
+      const int c0 = kBrick * (x - 1);
+      const int wx = c0 >> 5, sh = c0 & 31;
+      const int zl = min(kBrick * z, nz - 1), yl = min(kBrick * y, ny - 1);
+      for (int zz = kBrick * (z - 1); zz < zl; ++zz)
+        for (int yy = kBrick * (y - 1); yy < yl; ++yy) {
+          // written by other workgroups: read past this one's caches
+          const uint32_t word = __hip_atomic_load(bits + ((long long)zz * (ny - 1) + yy) * cbw + wx,
+                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          f |= (word >> sh) & ((1u << kBrick) - 1u);
+        }
+    }
+    S[e] = f != 0u ? 1 : 0;
+  }
+  __syncthreads();
+  for (long long l = tid; l < plane / ex * (bnz + 1); l += 1024) {  // along x: lines (y, z)
+    int* r = S + l * ex;
+    int acc = 0;
+    for (int x = 0; x < ex; ++x) r[x] = (acc += r[x]);
+  }
+  __syncthreads();
+  for (long long l = tid; l < (long long)ex * (bnz + 1); l += 1024) {  // along y: lines (x, z)
+    int* r = S + (l / ex) * plane + (l % ex);
+    int acc = 0;
+    for (int y = 0; y < ey; ++y) r[(long long)y * ex] = (acc += r[(long long)y * ex]);
+  }
+  __syncthreads();
+  for (long long l = tid; l < plane; l += 1024) {  // along z: lines (x, y)
+    int* r = S + l;
+    int acc = 0;
+    for (int z = 0; z <= bnz; ++z) r[z * plane] = (acc += r[z * plane]);
+  }
+  if (tid == 0) pi->sdf_done = 0;  // ready for the next set-up
+}
+
 // One workgroup (1024 threads) per cloud: blocks [0, n_obj) sort object
 // clouds, blocks [n_obj, n_obj + n_pre) contact clouds, the last n_obj blocks
 // collision clouds (object and collision clouds relative to the object's
@@ -257,6 +367,11 @@ __device__ __forceinline__ void kd_leaf_order(K* keys, int n, int npow2, int uni
 // |r|^2 = 1e30.
 __global__ __launch_bounds__(1024) void k_sort_cloud(Dev d) {
   const int tid = threadIdx.x;
+  if ((int)blockIdx.x >= 2 * d.n_obj + d.n_pre) {  // uniform: an SDF table workgroup
+    const int b = (int)blockIdx.x - 2 * d.n_obj - d.n_pre;
+    sdf_tables(d, b / d.sdf_blocks, b % d.sdf_blocks);
+    return;
+  }
   // kind 0: object cloud, 1: contact cloud, 2: collision cloud (no MFMA copy)
   const int kind = blockIdx.x < d.n_obj ? 0 : (blockIdx.x < d.n_obj + d.n_pre ? 1 : 2);
   const float *sx, *sy, *sz;
@@ -449,35 +564,6 @@ __global__ __launch_bounds__(1024) void k_sort_cloud(Dev d) {
   }
 }
 
-// Box of negative SDF nodes per preshape (grid: n_pre x 64 workgroups).
-__global__ __launch_bounds__(256) void k_sdf_bounds(Dev d) {
-  const int p = blockIdx.y;
-  PreInfo* pi = const_cast<PreInfo*>(d.pres) + p;
-  const int nx = pi->nx, ny = pi->ny, nz = pi->nz;
-  const float* v = pi->sdf;
-  const long long total = (long long)nx * ny * nz;
-  int lo[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, hi[3] = {-1, -1, -1};
-  for (long long idx = (long long)blockIdx.x * 256 + threadIdx.x; idx < total; idx += (long long)gridDim.x * 256) {
-    if (v[idx] < 0.f) {
-      const int x = (int)(idx % nx), y = (int)((idx / nx) % ny), z = (int)(idx / ((long long)nx * ny));
-      lo[0] = min(lo[0], x); lo[1] = min(lo[1], y); lo[2] = min(lo[2], z);
-      hi[0] = max(hi[0], x); hi[1] = max(hi[1], y); hi[2] = max(hi[2], z);
-    }
-  }
-  for (int a = 0; a < 3; ++a) {
-    for (int off = 32; off >= 1; off >>= 1) {
-      lo[a] = min(lo[a], __shfl_xor(lo[a], off, 64));
-      hi[a] = max(hi[a], __shfl_xor(hi[a], off, 64));
-    }
-  }
-  if ((threadIdx.x & 63) == 0) {
-    for (int a = 0; a < 3; ++a) {
-      if (lo[a] != 0x7fffffff) atomicMin(&pi->neg_lo[a], lo[a]);
-      if (hi[a] != -1) atomicMax(&pi->neg_hi[a], hi[a]);
-    }
-  }
-}
-
 __global__ __launch_bounds__(256) void k_setup_state(Dev d, const float* theta0, const float* prev0,
                                                      const int32_t* conv0) {
   const int i = blockIdx.x * 256 + threadIdx.x;
@@ -532,8 +618,8 @@ void launch_setup(const Dev& d, const float* theta0, const float* prev_cost0,
                   const int32_t* converged0, hipStream_t s) {
   hipLaunchKernelGGL(k_setup_obj, dim3(d.n_obj), dim3(256), 0, s, d);
   hipLaunchKernelGGL(k_setup_pre, dim3(d.n_pre), dim3(256), 0, s, d);
-  hipLaunchKernelGGL(k_sdf_bounds, dim3(64, d.n_pre), dim3(256), 0, s, d);
-  hipLaunchKernelGGL(k_sort_cloud, dim3(2 * d.n_obj + d.n_pre), dim3(1024), 0, s, d);
+  // the cloud sorts (one workgroup per cloud) and, beside them, the SDF tables
+  hipLaunchKernelGGL(k_sort_cloud, dim3(2 * d.n_obj + d.n_pre + d.n_pre * d.sdf_blocks), dim3(1024), 0, s, d);
   const int n = d.Ktot > d.G ? d.Ktot : d.G;
   hipLaunchKernelGGL(k_setup_state, dim3((n + 255) / 256), dim3(256), 0, s, d,
                      theta0, prev_cost0, converged0);
