@@ -47,7 +47,7 @@ constexpr int kMaxGroups = 1 << 16;
 
 struct Layout {
   size_t groups, objs, pres, obj_prep, pre_prep, obj_pts, pre_pts, obj_perm, pre_perm, obj_box, obj_box1, obj_blk, obj_blk1, kd_box, pre_box,
-      col_box, col_leaf_box, sdf_bits, sdf_sum;
+      col_box, col_leaf_box, sdf_bits, sdf_sum, sdf_flag;
   size_t sort_keys, wave_pairs, obj_com, pre_const, col_pts, col_perm, obj_prep_mb, batch_mark, prior;
   size_t theta, cost, col_cost, prev_cost, ncol, converged, grad, grad_ct, grad_col, phi, h, bw_hist, bw_state;
   size_t nn_part, col_part, pen_part, best, best_theta, flags, dbg_nn, dbg_rev;
@@ -59,7 +59,7 @@ struct Shape {
   int obj_tg, pre_tg, max_waves_pp, max_gate_chunks, n_max, mc_max;
   long long gate_chunks;  // over all objects
   long long sort_keys;  // total power-of-two padded cloud sizes
-  long long sdf_words, sdf_bricks;  // SDF cull tables over all preshapes (32-bit words)
+  long long sdf_words, sdf_bricks, sdf_flags;  // SDF cull tables over all preshapes (32-bit words)
   int sdf_blocks;       // set-up workgroups per preshape building them
   long long c_total;    // collision points over all objects
   long long r_total;    // object points over all objects
@@ -101,6 +101,7 @@ Layout layout_of(const Shape& s) {
   L.sort_keys = bump(c, (size_t)s.sort_keys * 8);
   L.sdf_bits = bump(c, 4 * (size_t)s.sdf_words);
   L.sdf_sum = bump(c, 4 * (size_t)s.sdf_bricks);
+  L.sdf_flag = bump(c, 4 * (size_t)s.sdf_flags);
   L.col_pts = bump(c, (size_t)(s.c_total > 0 ? s.c_total : 1) * 16);
   L.obj_prep_mb = s.minibatch ? bump(c, (size_t)s.obj_tg * 64 * 16) : 0;
   L.batch_mark = s.minibatch ? bump(c, (size_t)s.r_total) : 0;
@@ -166,7 +167,7 @@ asicp_status validate(const asicp_problem* pb, const asicp_config* cfg, Shape& s
   s.Ktot = (int)ktot;
   s.obj_tg = s.pre_tg = 0;
   s.sort_keys = 0;
-  s.sdf_words = s.sdf_bricks = 0;
+  s.sdf_words = s.sdf_bricks = s.sdf_flags = 0;
   long long max_cells = 0;
   s.n_max = s.mc_max = 0;
   s.max_waves_pp = 0;
@@ -216,10 +217,13 @@ asicp_status validate(const asicp_problem* pb, const asicp_config* cfg, Shape& s
     s.sdf_words += (long long)(g.nz - 1) * (g.ny - 1) * ((g.nx - 1 + 31) / 32);
     s.sdf_bricks += (long long)((g.nx - 1 + kBrick - 1) / kBrick + 1) * ((g.ny - 1 + kBrick - 1) / kBrick + 1) *
                     ((g.nz - 1 + kBrick - 1) / kBrick + 1);
+    s.sdf_flags += (long long)((g.nx - 1 + kBrick - 1) / kBrick) * ((g.ny - 1 + kBrick - 1) / kBrick) *
+                   ((g.nz - 1 + kBrick - 1) / kBrick);
     max_cells = std::max(max_cells, (long long)(g.nz - 1) * (g.ny - 1) * (g.nx - 1));
   }
-  // one set-up workgroup (1024 threads) per 32 cells per thread, at most 64 per preshape
-  s.sdf_blocks = (int)std::min<long long>(64, std::max<long long>(1, (max_cells + 32767) / 32768));
+  // one set-up workgroup (1024 threads) per 16 cells per thread, at most 64
+  // per preshape (each takes a CU beside the sorts)
+  s.sdf_blocks = (int)std::min<long long>(64, std::max<long long>(1, (max_cells + 16383) / 16384));
   if ((long long)pb->s_off[s.n_pre] > (1ll << 30)) return fail(ASICP_E_INVALID, "contact clouds too large");
   for (int qi = 0; qi < kNumQ; ++qi) s.total_waves[qi] = 0;
   s.total_gate_wgs = 0;
@@ -407,8 +411,8 @@ asicp_status asicp_create(const asicp_problem* pb, const asicp_config* cfg, void
       tg += oi.ntg;
     }
     tg = 0;
-    std::vector<long long> bits_off(s.n_pre), sum_off(s.n_pre);
-    long long bits_at = 0, sum_at = 0;
+    std::vector<long long> bits_off(s.n_pre), sum_off(s.n_pre), flag_off(s.n_pre);
+    long long bits_at = 0, sum_at = 0, flag_at = 0;
     for (int p = 0; p < s.n_pre; ++p) {
       PreInfo& pi = pres[p];
       std::memset(&pi, 0, sizeof pi);
@@ -438,6 +442,8 @@ asicp_status asicp_create(const asicp_problem* pb, const asicp_config* cfg, void
       sum_off[p] = sum_at;
       bits_at += (long long)(g.nz - 1) * (g.ny - 1) * pi.cbw;
       sum_at += (long long)(pi.bnx + 1) * (pi.bny + 1) * (pi.bnz + 1);
+      flag_off[p] = flag_at;
+      flag_at += (long long)pi.bnx * pi.bny * pi.bnz;
     }
     int wave_off[kNumQ] = {0, 0, 0}, gate_off = 0;
     for (int o = 0; o < s.n_obj; ++o)
@@ -487,6 +493,7 @@ asicp_status asicp_create(const asicp_problem* pb, const asicp_config* cfg, void
     for (int p = 0; p < s.n_pre; ++p) {
       pres[p].cell_bits = reinterpret_cast<const uint32_t*>(ws + L.sdf_bits) + bits_off[p];
       pres[p].brick_sum = reinterpret_cast<const int32_t*>(ws + L.sdf_sum) + sum_off[p];
+      pres[p].brick_flag = reinterpret_cast<int32_t*>(ws + L.sdf_flag) + flag_off[p];
     }
     d.sort_keys = reinterpret_cast<unsigned long long*>(ws + L.sort_keys);
     d.col_pts = reinterpret_cast<float4*>(ws + L.col_pts);
@@ -559,6 +566,8 @@ asicp_status asicp_create(const asicp_problem* pb, const asicp_config* cfg, void
     upload_words(ws + L.pres, pres.data(), sizeof(PreInfo) * pres.size(), hs);
     if (s.prior) upload_words(ws + L.prior, prior_words.data(), 4 * prior_words.size(), hs);
     if ((st = check_launch("table upload")) != ASICP_OK) return st;
+    zero_words(ws + L.sdf_flag, s.sdf_flags, hs);  // the brick flags start at zero; each set-up leaves them so
+    if ((st = check_launch("flag clear")) != ASICP_OK) return st;
     launch_setup(d, pb->theta0, pb->prev_cost, pb->converged, hs);
     if ((st = check_launch("setup")) != ASICP_OK) return st;
     if (s.debug) {

@@ -63,9 +63,11 @@ struct PreInfo {
   // cell_bits: bit (x % 32) of word ((z (ny - 1) + y) cbw + x / 32) is set when
   //   cell (x, y, z) (nodes x..x+1, y..y+1, z..z+1) has a negative node;
   // brick_sum: over bricks of kBrick^3 cells, entry (z (bny + 1) + y) (bnx + 1) + x
-  //   counts the bricks (bx < x, by < y, bz < z) holding such a cell.
+  //   counts the bricks (bx < x, by < y, bz < z) holding such a cell;
+  // brick_flag: per brick (z bny + y) bnx + x, set-up scratch, zero between set-ups.
   const uint32_t* cell_bits;
   const int32_t* brick_sum;
+  int32_t* brick_flag;
   int32_t cbw, bnx, bny, bnz;
   int32_t sdf_done;        // set-up workgroups finished on the tables (0 between set-ups)
 };
@@ -338,6 +340,7 @@ __device__ __forceinline__ float wave_sum(float v) {
 }
 
 // Launchers (host side), one per kernel family.
+void zero_words(void* dst, long long n, hipStream_t s);  // n 32-bit words, a fill kernel
 void launch_setup(const Dev& d, const float* theta0, const float* prev_cost0,
                   const int32_t* converged0, hipStream_t s);
 void launch_nn_forward(const Dev& d, hipStream_t s);

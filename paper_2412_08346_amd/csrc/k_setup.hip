@@ -246,12 +246,14 @@ __device__ __forceinline__ void kd_leaf_order(K* keys, int n, int npow2, int uni
 }
 
 // SDF cull tables of preshape p, built by workgroup j of d.sdf_blocks (1024
-// threads each) beside the cloud sorts: the box of negative nodes, one bit
-// per cell telling whether any of its 8 nodes is negative (a trilinear value
-// is a convex combination of the cell's node values, so only such a cell can
-// give a negative value), and, from the last of the workgroups to finish,
-// the 3-D prefix counts of bricks of kBrick^3 cells holding such a cell (the
-// number of them in any box of bricks from 8 entries).
+// threads each) beside the cloud sorts, in one pass over the cells (each
+// node is a corner of some cell): one bit per cell telling whether any of its
+// 8 nodes is negative (a trilinear value is a convex combination of the
+// cell's node values, so only such a cell can give a negative value), the
+// box of the negative nodes, and a flag per brick of kBrick^3 cells holding
+// such a cell.  The last workgroup to finish turns the flags into 3-D prefix
+// counts (the number of such bricks in any box of bricks from 8 entries)
+// and clears them for the next set-up.
 __device__ void sdf_tables(const Dev& d, int p, int j) {
   __shared__ int s_last;
   PreInfo* pi = const_cast<PreInfo*>(d.pres) + p;
@@ -259,36 +261,14 @@ __device__ void sdf_tables(const Dev& d, int p, int j) {
   const float* v = pi->sdf;
   const int tid = threadIdx.x, lane = tid & 63;
   const long long stride = (long long)d.sdf_blocks * 1024;
-  // box of the negative nodes
-  {
-    const long long total = (long long)nx * ny * nz;
-    int lo[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, hi[3] = {-1, -1, -1};
-    for (long long idx = (long long)j * 1024 + tid; idx < total; idx += stride) {
-      if (v[idx] < 0.f) {
-        const int x = (int)(idx % nx), y = (int)((idx / nx) % ny), z = (int)(idx / ((long long)nx * ny));
-        lo[0] = min(lo[0], x); lo[1] = min(lo[1], y); lo[2] = min(lo[2], z);
-        hi[0] = max(hi[0], x); hi[1] = max(hi[1], y); hi[2] = max(hi[2], z);
-      }
-    }
-    for (int a = 0; a < 3; ++a) {
-      for (int off = 32; off >= 1; off >>= 1) {
-        lo[a] = min(lo[a], __shfl_xor(lo[a], off, 64));
-        hi[a] = max(hi[a], __shfl_xor(hi[a], off, 64));
-      }
-    }
-    if (lane == 0) {
-      for (int a = 0; a < 3; ++a) {
-        if (lo[a] != 0x7fffffff) atomicMin(&pi->neg_lo[a], lo[a]);
-        if (hi[a] != -1) atomicMax(&pi->neg_hi[a], hi[a]);
-      }
-    }
-  }
-  // cell bits: slot s is bit s % 32 of word s / 32; the 64 slots of a wave
-  // are two whole words (the loop bound is uniform over the wave)
-  const int cbw = pi->cbw;
+  const int cbw = pi->cbw, bnx = pi->bnx, bny = pi->bny, bnz = pi->bnz;
   uint32_t* bits = const_cast<uint32_t*>(pi->cell_bits);
+  int* F = pi->brick_flag;
   const long long nwords = (long long)(nz - 1) * (ny - 1) * cbw;
   const long long sy = nx, sz = (long long)nx * ny;
+  int lo[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, hi[3] = {-1, -1, -1};
+  // slot s is bit s % 32 of word s / 32; the 64 slots of a wave are two
+  // whole words (the loop bound is uniform over the wave)
   for (long long s0 = (long long)j * 1024 + (tid & ~63); s0 < 32 * nwords; s0 += stride) {
     const long long w = (s0 + lane) >> 5;
     bool neg = false;
@@ -298,60 +278,87 @@ __device__ void sdf_tables(const Dev& d, int p, int j) {
       const int y = (int)(row % (ny - 1)), z = (int)(row / (ny - 1));
       if (x < nx - 1) {
         const float* g = v + (long long)z * sz + (long long)y * sy + x;
-        neg = g[0] < 0.f || g[1] < 0.f || g[sy] < 0.f || g[sy + 1] < 0.f || g[sz] < 0.f || g[sz + 1] < 0.f ||
-              g[sz + sy] < 0.f || g[sz + sy + 1] < 0.f;
+        // n[4 dz + 2 dy + dx]: node (x + dx, y + dy, z + dz) is negative
+        const bool n0 = g[0] < 0.f, n1 = g[1] < 0.f, n2 = g[sy] < 0.f, n3 = g[sy + 1] < 0.f;
+        const bool n4 = g[sz] < 0.f, n5 = g[sz + 1] < 0.f, n6 = g[sz + sy] < 0.f, n7 = g[sz + sy + 1] < 0.f;
+        neg = n0 || n1 || n2 || n3 || n4 || n5 || n6 || n7;
+        if (neg) {
+          // the cell's negative corners: per axis the lower coordinate if
+          // one of them lies on the lower face, the upper one likewise
+          lo[0] = min(lo[0], (n0 || n2 || n4 || n6) ? x : x + 1);
+          hi[0] = max(hi[0], (n1 || n3 || n5 || n7) ? x + 1 : x);
+          lo[1] = min(lo[1], (n0 || n1 || n4 || n5) ? y : y + 1);
+          hi[1] = max(hi[1], (n2 || n3 || n6 || n7) ? y + 1 : y);
+          lo[2] = min(lo[2], (n0 || n1 || n2 || n3) ? z : z + 1);
+          hi[2] = max(hi[2], (n4 || n5 || n6 || n7) ? z + 1 : z);
+          // every writer stores the same value
+          F[((long long)(z / kBrick) * bny + y / kBrick) * bnx + x / kBrick] = 1;
+        }
       }
     }
     const unsigned long long b = __ballot(neg);
     if ((lane & 31) == 0 && w < nwords) bits[w] = (uint32_t)(b >> (lane & 32));
   }
-  // the last workgroup to finish builds the brick counts
+  for (int a = 0; a < 3; ++a) {
+    for (int off = 32; off >= 1; off >>= 1) {
+      lo[a] = min(lo[a], __shfl_xor(lo[a], off, 64));
+      hi[a] = max(hi[a], __shfl_xor(hi[a], off, 64));
+    }
+  }
+  if (lane == 0) {
+    for (int a = 0; a < 3; ++a) {
+      if (lo[a] != 0x7fffffff) atomicMin(&pi->neg_lo[a], lo[a]);
+      if (hi[a] != -1) atomicMax(&pi->neg_hi[a], hi[a]);
+    }
+  }
+  // the last workgroup to finish: prefix counts from the flags (written by
+  // other workgroups, so read, and the table written and re-read, with
+  // device-scope atomics, 8 entries of a line in flight at a time)
   __threadfence();
   __syncthreads();
   if (tid == 0) s_last = atomicAdd(&pi->sdf_done, 1) == d.sdf_blocks - 1;
   __syncthreads();
   if (!s_last) return;
   __threadfence();
-  const int bnx = pi->bnx, bny = pi->bny, bnz = pi->bnz;
   const int ex = bnx + 1, ey = bny + 1;
-  const long long plane = (long long)ex * ey, ntot = plane * (bnz + 1);
+  const long long plane = (long long)ex * ey;
   int* S = const_cast<int*>(pi->brick_sum);
-  for (long long e = tid; e < ntot; e += 1024) {
-    const int x = (int)(e % ex), y = (int)((e / ex) % ey), z = (int)(e / plane);
-    unsigned int f = 0u;
-    if (x > 0 && y > 0 && z > 0) {
-      // cells kBrick (x - 1) .. + kBrick - 1 lie in one word (kBrick divides 32)
-      const int c0 = kBrick * (x - 1);
-      const int wx = c0 >> 5, sh = c0 & 31;
-      const int zl = min(kBrick * z, nz - 1), yl = min(kBrick * y, ny - 1);
-      for (int zz = kBrick * (z - 1); zz < zl; ++zz)
-        for (int yy = kBrick * (y - 1); yy < yl; ++yy) {
-          // written by other workgroups: read past this one's caches
-          const uint32_t word = __hip_atomic_load(bits + ((long long)zz * (ny - 1) + yy) * cbw + wx,
-                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          f |= (word >> sh) & ((1u << kBrick) - 1u);
+  // src (null: zeros) holds len - 1 values; dst gets 0 and their running sums
+  auto scan_line = [&](int* src, long long sstep, int* dst, long long dstep, int len, bool clear) {
+    int acc = 0;
+    __hip_atomic_store(dst, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int x0 = 0; x0 < len - 1; x0 += 8) {
+      int val[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        val[u] = (src && x0 + u < len - 1)
+                     ? __hip_atomic_load(src + (x0 + u) * sstep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                     : 0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        acc += val[u];
+        if (x0 + u < len - 1) {
+          __hip_atomic_store(dst + (x0 + u + 1) * dstep, acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (clear) __hip_atomic_store(src + (x0 + u) * sstep, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
+      }
     }
-    S[e] = f != 0u ? 1 : 0;
+  };
+  // along x: S line (y', z') from flag line (y' - 1, z' - 1); lines with
+  // y' = 0 or z' = 0 are zero
+  for (long long l = tid; l < (long long)ey * (bnz + 1); l += 1024) {
+    const int yy = (int)(l % ey), zz = (int)(l / ey);
+    int* src = (yy > 0 && zz > 0) ? F + ((long long)(zz - 1) * bny + (yy - 1)) * bnx : nullptr;
+    scan_line(src, 1, S + l * ex, 1, ex, src != nullptr);
   }
   __syncthreads();
-  for (long long l = tid; l < plane / ex * (bnz + 1); l += 1024) {  // along x: lines (y, z)
-    int* r = S + l * ex;
-    int acc = 0;
-    for (int x = 0; x < ex; ++x) r[x] = (acc += r[x]);
-  }
-  __syncthreads();
-  for (long long l = tid; l < (long long)ex * (bnz + 1); l += 1024) {  // along y: lines (x, z)
+  // along y and z, in place (entry 0 of each line is already 0)
+  for (long long l = tid; l < (long long)ex * (bnz + 1); l += 1024) {
     int* r = S + (l / ex) * plane + (l % ex);
-    int acc = 0;
-    for (int y = 0; y < ey; ++y) r[(long long)y * ex] = (acc += r[(long long)y * ex]);
+    scan_line(r + ex, ex, r, ex, ey, false);
   }
   __syncthreads();
-  for (long long l = tid; l < plane; l += 1024) {  // along z: lines (x, y)
-    int* r = S + l;
-    int acc = 0;
-    for (int z = 0; z <= bnz; ++z) r[z * plane] = (acc += r[z * plane]);
-  }
+  for (long long l = tid; l < plane; l += 1024) scan_line(S + l + plane, plane, S + l, plane, bnz + 1, false);
   if (tid == 0) pi->sdf_done = 0;  // ready for the next set-up
 }
 
@@ -600,6 +607,19 @@ struct UploadChunk {
 
 __global__ void k_upload(uint32_t* dst, UploadChunk c) {
   for (int w = threadIdx.x; w < c.nwords; w += blockDim.x) dst[w] = c.words[w];
+}
+
+__global__ void k_zero_words(uint32_t* dst, long long n) {
+  for (long long w = (long long)blockIdx.x * 256 + threadIdx.x; w < n; w += (long long)gridDim.x * 256) dst[w] = 0u;
+}
+
+// A fill kernel rather than a memset node, so that a captured stream gets
+// an ordinary kernel.
+void zero_words(void* dst, long long n, hipStream_t s) {
+  if (n <= 0) return;
+  const long long blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(k_zero_words, dim3((unsigned)(blocks < 1024 ? blocks : 1024)), dim3(256), 0, s,
+                     static_cast<uint32_t*>(dst), n);
 }
 
 void upload_words(void* dst, const void* src, size_t bytes, hipStream_t s) {

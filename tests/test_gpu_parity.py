@@ -4,6 +4,7 @@ Teacher forcing: the oracle runs its own trajectory; its pose at iteration k,
 rounded to float32, is the input of one step on both sides.  No input and no
 expected value comes from the HIP path.
 """
+import dataclasses
 import math
 import sys
 
@@ -888,6 +889,39 @@ def test_reset_repeats_the_solve_exactly():
         assert np.array_equal(np.asarray(eager[key]), np.asarray(first[key])), ("eager after replay", key)
         assert np.array_equal(np.asarray(rep2[key]), np.asarray(first[key])), ("replay after eager", key)
     assert not np.array_equal(np.asarray(part["theta"]), np.asarray(first["theta"]))
+
+def test_reset_reads_a_rewritten_sdf():
+    """The set-up rebuilds the SDF cull tables from the borrowed grid: after
+    the grid is rewritten in place (a gripper inflated by 3 cm, then the
+    original again), asicp_reset and a solve return bitwise what a fresh
+    context on that grid returns, and collisions do occur on the inflated
+    grid."""
+    A, torch = _gpu()
+    pb, st = synth.workload_small(k_max=8)
+    keys = ("theta", "cost", "col_cost", "ncol", "grad", "best_theta", "best_particle")
+    fat = dataclasses.replace(pb.grids[0], values=(pb.grids[0].values - np.float32(0.03)).astype(np.float32))
+    pb_fat = dataclasses.replace(pb, grids=[fat])
+
+    def fresh(problem):
+        f = A.Solver(problem, st)
+        f.solve()
+        r = f.result()
+        f.close()
+        return r
+
+    ref_thin, ref_fat = fresh(pb), fresh(pb_fat)
+    assert int(np.sum(ref_fat["ncol"])) > int(np.sum(ref_thin["ncol"]))
+    s = A.Solver(pb, st)
+    grid = s._keep["grids"][0]
+    for values, ref, name in ((fat.values, ref_fat, "inflated"), (pb.grids[0].values, ref_thin, "original")):
+        grid.copy_(torch.as_tensor(values).to(grid.device))
+        s.reset()
+        s.solve()
+        r = s.result()
+        for key in keys:
+            assert np.array_equal(np.asarray(r[key]), np.asarray(ref[key])), (name, key)
+    s.close()
+
 
 def _run(pb, st, launch=None, tune=False, steps=3):
     A, torch = _gpu()
