@@ -131,18 +131,15 @@ __device__ __forceinline__ void bitonic_sort(K* keys, int npow2, int tid, int se
 // The k-d layout of a cloud: leaves of `unit` points; a part of L >= 2
 // leaves splits after A max(1, round(L / 2A)) leaves, A the largest power of
 // two below L capped at `cap`, so every aligned block of cap leaves (and of
-// every power of two below it) is one subtree.  On return [a, b) are the
-// leaves of the part holding leaf lf after `level` splits.
-__device__ __forceinline__ void kd_part(int nleaf, int cap, int level, int lf, int& a, int& b) {
-  a = 0;
-  b = nleaf;
-  for (int l = 0; l < level && b - a > 1; ++l) {
-    const int L = b - a;
-    int sh = 0;  // A = 2^sh
-    while ((2 << sh) < L && (1 << sh) < cap) ++sh;
-    const int m = a + (max(1, (L + (1 << sh)) >> (sh + 1)) << sh);
-    if (lf < m) b = m; else a = m;
-  }
+// every power of two below it) is one subtree.  One split: [a, b), the
+// leaves of the part holding leaf lf, becomes the half holding lf.
+__device__ __forceinline__ void kd_split(int cap, int lf, int& a, int& b) {
+  const int L = b - a;
+  if (L <= 1) return;
+  int sh = 0;  // A = 2^sh
+  while ((2 << sh) < L && (1 << sh) < cap) ++sh;
+  const int m = a + (max(1, (L + (1 << sh)) >> (sh + 1)) << sh);
+  if (lf < m) b = m; else a = m;
 }
 
 // Orders a cloud's n points as the leaves of a k-d tree: each part is sorted
@@ -155,7 +152,10 @@ __device__ __forceinline__ void kd_part(int nleaf, int cap, int level, int lf, i
 // 16-bit position along the part's axis, original index), and one sort
 // orders all parts at once; ties fall to the original index, so the order is
 // deterministic.  unit: points per leaf (16 or 64); kb: 16 floats of scratch
-// per leaf.  Inlined, so that LDS arrays passed in are addressed as LDS.
+// per leaf (its box, the part's axis and quantisation in the part's first
+// leaf, and the bounds [a, b) of the leaf's current part, updated by one
+// split per level).  Inlined, so that LDS arrays passed in are addressed as
+// LDS.
 template <typename K>
 __device__ __forceinline__ void kd_leaf_order(K* keys, int n, int npow2, int unit, int cap, const float* sx,
                                               const float* sy, const float* sz, float* kb, int* s_split, int tid) {
@@ -167,27 +167,49 @@ __device__ __forceinline__ void kd_leaf_order(K* keys, int n, int npow2, int uni
   const int ush = unit == 16 ? 4 : 6;  // unit is 16 or 64
   const int nleaf = (n + unit - 1) >> ush;
   const int w = tid >> 6, lane = tid & 63;
+  // the part of leaf l: [kb[16 l + 12], kb[16 l + 13]) (integers)
+  auto part_of = [&](int l, int& a, int& b) {
+    a = __float_as_int(kb[(size_t)l * 16 + 12]);
+    b = __float_as_int(kb[(size_t)l * 16 + 13]);
+  };
   for (int k = tid; k < npow2; k += 1024) keys[k] = k < n ? (K)k : (K)~0ull;
+  for (int l = tid; l < nleaf; l += 1024) {
+    kb[(size_t)l * 16 + 12] = __int_as_float(0);
+    kb[(size_t)l * 16 + 13] = __int_as_float(nleaf);
+  }
   __syncthreads();
   for (int level = 0;; ++level) {
     // the box of every leaf in the current order: a wavefront covers 64
-    // consecutive points, 64 / unit leaves
-    for (int base = w * 64; base < nleaf * unit; base += 16 * 64) {
-      const int pos = base + lane;
-      float v[6] = {__builtin_inff(), __builtin_inff(), __builtin_inff(),
-                    -__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
-      if (pos < n) {
-        const int o = (int)(keys[pos] & kOrigMask);
-        v[0] = v[3] = sx[o];
-        v[1] = v[4] = sy[o];
-        v[2] = v[5] = sz[o];
+    // consecutive points, 64 / unit leaves, kBoxBatch runs of them with their
+    // point reads in flight together
+    constexpr int kBoxBatch = 4;
+    for (int base0 = w * 64; base0 < nleaf * unit; base0 += kBoxBatch * 16 * 64) {
+      float p[kBoxBatch][3];
+#pragma unroll
+      for (int u = 0; u < kBoxBatch; ++u) {
+        const int pos = base0 + u * 16 * 64 + lane;
+        p[u][0] = p[u][1] = p[u][2] = 0.f;
+        if (pos < n) {
+          const int o = (int)(keys[pos] & kOrigMask);
+          p[u][0] = sx[o];
+          p[u][1] = sy[o];
+          p[u][2] = sz[o];
+        }
       }
-      for (int off = unit >> 1; off >= 1; off >>= 1) {
-        for (int a = 0; a < 3; ++a) v[a] = fminf(v[a], __shfl_xor(v[a], off, 64));
-        for (int a = 3; a < 6; ++a) v[a] = fmaxf(v[a], __shfl_xor(v[a], off, 64));
+#pragma unroll
+      for (int u = 0; u < kBoxBatch; ++u) {
+        if (base0 + u * 16 * 64 >= nleaf * unit) break;  // uniform over the wavefront
+        const int pos = base0 + u * 16 * 64 + lane;
+        const bool in = pos < n;
+        float v[6] = {in ? p[u][0] : __builtin_inff(), in ? p[u][1] : __builtin_inff(), in ? p[u][2] : __builtin_inff(),
+                      in ? p[u][0] : -__builtin_inff(), in ? p[u][1] : -__builtin_inff(), in ? p[u][2] : -__builtin_inff()};
+        for (int off = unit >> 1; off >= 1; off >>= 1) {
+          for (int a = 0; a < 3; ++a) v[a] = fminf(v[a], __shfl_xor(v[a], off, 64));
+          for (int a = 3; a < 6; ++a) v[a] = fmaxf(v[a], __shfl_xor(v[a], off, 64));
+        }
+        if ((lane & (unit - 1)) == 0 && (pos >> ush) < nleaf)
+          for (int a = 0; a < 6; ++a) kb[(size_t)(pos >> ush) * 16 + a] = v[a];
       }
-      if ((lane & (unit - 1)) == 0 && (pos >> ush) < nleaf)
-        for (int a = 0; a < 6; ++a) kb[(size_t)(pos >> ush) * 16 + a] = v[a];
     }
     if (tid == 0) *s_split = 0;
     __syncthreads();
@@ -196,7 +218,7 @@ __device__ __forceinline__ void kd_leaf_order(K* keys, int n, int npow2, int uni
     // part's first leaf
     for (int lf = w; lf < nleaf; lf += 16) {
       int a, b;
-      kd_part(nleaf, cap, level, lf, a, b);
+      part_of(lf, a, b);
       if (lf != a || b - a < 2) continue;  // uniform over the wavefront
       float v[6] = {__builtin_inff(), __builtin_inff(), __builtin_inff(),
                     -__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
@@ -221,22 +243,50 @@ __device__ __forceinline__ void kd_leaf_order(K* keys, int n, int npow2, int uni
     }
     __syncthreads();
     if (*s_split == 0) break;  // every part is one leaf
-    for (int pos = tid; pos < n; pos += 1024) {
-      const int o = (int)(keys[pos] & kOrigMask);
-      int a, b;
-      kd_part(nleaf, cap, level, pos >> ush, a, b);
-      unsigned int q = 0;
-      if (b - a >= 2) {
-        const int ax = __float_as_int(kb[(size_t)a * 16 + 8]);
-        const float x = ax == 0 ? sx[o] : (ax == 1 ? sy[o] : sz[o]);
-        q = (unsigned int)fminf(fmaxf((x - kb[(size_t)a * 16 + 9]) * kb[(size_t)a * 16 + 10], 0.f), kQ);
+    // new keys, kKeyBatch points per thread with their coordinate reads in
+    // flight together
+    constexpr int kKeyBatch = 4;
+    for (int pos0 = tid; pos0 < n; pos0 += kKeyBatch * 1024) {
+      int o[kKeyBatch], a[kKeyBatch], b[kKeyBatch];
+      float x[kKeyBatch];
+#pragma unroll
+      for (int u = 0; u < kKeyBatch; ++u) {
+        const int pos = pos0 + u * 1024;
+        o[u] = 0;
+        a[u] = b[u] = 0;
+        x[u] = 0.f;
+        if (pos < n) {
+          o[u] = (int)(keys[pos] & kOrigMask);
+          part_of(pos >> ush, a[u], b[u]);
+          if (b[u] - a[u] >= 2) {
+            const int ax = __float_as_int(kb[(size_t)a[u] * 16 + 8]);
+            x[u] = (ax == 0 ? sx : (ax == 1 ? sy : sz))[o[u]];
+          }
+        }
       }
-      if (k32)  // position (10 bits) | original index (< 2^22)
-        keys[pos] = (K)((q << 22) | (unsigned int)o);
-      else      // part (< 2^18 leaves) | position (16 bits) | original index (< 2^22)
-        keys[pos] = (K)(((unsigned long long)a << 38) | ((unsigned long long)q << 22) | (unsigned int)o);
+#pragma unroll
+      for (int u = 0; u < kKeyBatch; ++u) {
+        const int pos = pos0 + u * 1024;
+        if (pos >= n) continue;
+        unsigned int q = 0;
+        if (b[u] - a[u] >= 2)
+          q = (unsigned int)fminf(fmaxf((x[u] - kb[(size_t)a[u] * 16 + 9]) * kb[(size_t)a[u] * 16 + 10], 0.f), kQ);
+        if (k32)  // position (10 bits) | original index (< 2^22)
+          keys[pos] = (K)((q << 22) | (unsigned int)o[u]);
+        else      // part (< 2^18 leaves) | position (16 bits) | original index (< 2^22)
+          keys[pos] = (K)(((unsigned long long)a[u] << 38) | ((unsigned long long)q << 22) | (unsigned int)o[u]);
+      }
     }
     __syncthreads();
+    // each leaf's part for the next level: the half of the current one
+    // holding it (read above only, so no barrier is needed before the sort)
+    for (int l = tid; l < nleaf; l += 1024) {
+      int a, b;
+      part_of(l, a, b);
+      kd_split(cap, l, a, b);
+      kb[(size_t)l * 16 + 12] = __int_as_float(a);
+      kb[(size_t)l * 16 + 13] = __int_as_float(b);
+    }
     // a cloud of a power-of-two number of whole leaves splits into aligned
     // halves, so at this level every part is an aligned block of n >> level
     // points and sorts on its own

@@ -520,6 +520,33 @@ def test_ragged_sizes_and_edges():
     compare_step(pb, st, pulled_in(pb, 0.7), 4, label="K=1 SGD")
 
 
+@pytest.mark.parametrize("case", ["cropped", "no_negative_node", "all_negative"])
+def test_sdf_grid_shapes_and_degenerate_grids(case):
+    """The collision gate's cull tables (one bit per cell, prefix counts of
+    4^3-cell bricks) on grids that a cubic grid would not exercise: a grid
+    cropped to 63 x 40 x 37 nodes (per axis a different cell count, none a
+    multiple of 4 or 32, cutting through the fingers), a grid without any
+    negative node (nothing collides) and one with every node negative (every
+    collision point inside the grid collides).  One teacher-forced step
+    against the oracle, poses pulled in so that the gripper meets the
+    object."""
+    pb, st = synth.workload_small(k_max=8)
+    g = pb.grids[0]
+    if case == "cropped":
+        x0, y0, z0 = 1, 7, 3
+        vals = np.ascontiguousarray(g.values[z0:z0 + 37, y0:y0 + 40, x0:x0 + 63])
+        origin = (g.origin + np.float32(g.cell) * np.array([x0, y0, z0], np.float32)).astype(np.float32)
+        grid = synth.Grid(values=vals, origin=origin, cell=g.cell)
+    elif case == "no_negative_node":
+        grid = synth.Grid(values=(np.abs(g.values) + np.float32(1e-3)).astype(np.float32), origin=g.origin, cell=g.cell)
+    else:
+        grid = synth.Grid(values=(-np.abs(g.values) - np.float32(1e-3)).astype(np.float32), origin=g.origin, cell=g.cell)
+    pb = dataclasses.replace(pb, grids=[grid])
+    for k, frac in [(0, 0.6), (2, 0.8)]:
+        out = compare_step(pb, st, pulled_in(pb, frac), k, label=f"sdf {case} k={k}")
+        say(f"[parity] sdf {case} k={k}", out)
+
+
 @pytest.mark.parametrize("offset", [(1.0, -0.7, 0.5), (-3.0, 2.5, 4.0)])
 def test_scene_away_from_the_origin(offset):
     """The whole scene -- object and collision clouds and every pose -- moved
