@@ -48,7 +48,7 @@ constexpr int kMaxGroups = 1 << 16;
 struct Layout {
   size_t groups, objs, pres, obj_prep, pre_prep, obj_pts, pre_pts, obj_perm, pre_perm, obj_box, obj_box1, obj_blk, obj_blk1, kd_box, pre_box,
       col_box, col_leaf_box, sdf_bits, sdf_sum, sdf_flag;
-  size_t sort_keys, wave_pairs, obj_com, pre_const, col_pts, col_perm, obj_prep_mb, batch_mark, prior;
+  size_t gate_wg, sort_keys, wave_pairs, obj_com, pre_const, col_pts, col_perm, obj_prep_mb, batch_mark, prior;
   size_t theta, cost, col_cost, prev_cost, ncol, converged, grad, grad_ct, grad_col, phi, h, bw_hist, bw_state;
   size_t nn_part, col_part, pen_part, best, best_theta, flags, dbg_nn, dbg_rev;
   size_t total;
@@ -99,6 +99,7 @@ Layout layout_of(const Shape& s) {
   L.col_box = bump(c, 32 * (size_t)(s.gate_chunks > 0 ? s.gate_chunks : 1));
   L.col_leaf_box = bump(c, 32 * (size_t)(kGateChunk / 64) * (size_t)(s.gate_chunks > 0 ? s.gate_chunks : 1));
   L.sort_keys = bump(c, (size_t)s.sort_keys * 8);
+  L.gate_wg = bump(c, sizeof(GateWG) * (size_t)(s.total_gate_wgs > 0 ? s.total_gate_wgs : 1));
   L.sdf_bits = bump(c, 4 * (size_t)s.sdf_words);
   L.sdf_sum = bump(c, 4 * (size_t)s.sdf_bricks);
   L.sdf_flag = bump(c, 4 * (size_t)s.sdf_flags);
@@ -490,6 +491,7 @@ asicp_status asicp_create(const asicp_problem* pb, const asicp_config* cfg, void
     d.col_box = reinterpret_cast<float*>(ws + L.col_box);
     d.col_leaf_box = reinterpret_cast<float*>(ws + L.col_leaf_box);
     d.sdf_blocks = s.sdf_blocks;
+    d.gate_wg = reinterpret_cast<GateWG*>(ws + L.gate_wg);
     for (int p = 0; p < s.n_pre; ++p) {
       pres[p].cell_bits = reinterpret_cast<const uint32_t*>(ws + L.sdf_bits) + bits_off[p];
       pres[p].brick_sum = reinterpret_cast<const int32_t*>(ws + L.sdf_sum) + sum_off[p];

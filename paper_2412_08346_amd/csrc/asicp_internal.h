@@ -29,6 +29,13 @@ constexpr int kBrick = 4;          // cells per brick edge of the SDF cull table
 constexpr int kBwSlices = 32;      // workgroups per group in each bandwidth pass
 constexpr float kDummyNorm = 1.0e30f;  // |r|^2 of padding points: never a nearest neighbour
 
+// Per gate workgroup: its group, particle, chunk of the collision cloud and
+// that chunk's box (written at set-up, so a workgroup finds its work with
+// one read).
+struct GateWG {
+  int32_t g, i, cc, box;
+};
+
 // Per-group descriptor (group = (object, preshape)).
 struct GroupInfo {
   int32_t obj, pre;
@@ -111,6 +118,7 @@ struct Dev {
                      //   group), then collision clouds from kd_col_off (32 per gate chunk)
   int32_t kd_pre_off, kd_col_off;
   int32_t sdf_blocks;  // set-up workgroups per preshape building the SDF cull tables
+  GateWG* gate_wg;     // [total_gate_wgs]
   unsigned long long* wave_pairs;  // [total_waves[0]] distances evaluated per forward wave,
                                    //   summed over launches (ASICP_FLAG_TIMING only, else NULL)
   int32_t prune;                 // skip object chunks that cannot hold a nearest neighbour

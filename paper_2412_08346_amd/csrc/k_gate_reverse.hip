@@ -176,17 +176,11 @@ __global__ __launch_bounds__(256) void k_gate_reverse(Dev d) {
   if (logical >= nwg) return;  // uniform over the workgroup
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
 
-  int lo = 0, hi = d.G - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (d.groups[mid].gate_off <= logical) lo = mid; else hi = mid - 1;
-  }
-  const GroupInfo gi = d.groups[lo];
+  const GateWG gw = d.gate_wg[logical];
+  const GroupInfo gi = d.groups[gw.g];
   const PreInfo& pi = d.pres[gi.pre];
   const ObjInfo& oi = d.objs[gi.obj];
-  const int local = logical - gi.gate_off;
-  const int pj = local / oi.gate_chunks, cc = local - pj * oi.gate_chunks;
-  const int i = lo * d.K + pj;
+  const int cc = gw.cc, i = gw.i;
   float* out = d.col_part + ((size_t)i * d.max_gate_chunks + cc) * kPartStride;
 
   // the pose relative to the object's centroid, like the stored collision
@@ -202,7 +196,7 @@ __global__ __launch_bounds__(256) void k_gate_reverse(Dev d) {
   float* pout = d.pen_part + ((size_t)i * d.max_gate_chunks + cc) * kPartStride;
   // the box of this workgroup's 2048 points (spatially compact: the cloud is
   // k-d ordered), not of the whole cloud, so most far chunks stop here
-  if (!box_may_collide(pi, d.col_box + (size_t)(oi.gbox_begin + cc) * 8, R, t)) {
+  if (!box_may_collide(pi, d.col_box + (size_t)gw.box * 8, R, t)) {
     if (tid < kPartStride) {
       out[tid] = 0.f;
       pout[tid] = 0.f;

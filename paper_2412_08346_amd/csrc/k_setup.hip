@@ -708,6 +708,19 @@ __global__ __launch_bounds__(256) void k_setup_state(Dev d, const float* theta0,
     for (int a = 0; a < 4; ++a) d.bw_state[4 * i + a] = 0u;
   }
   for (int w = i; w < d.G * 256; w += gridDim.x * 256) d.bw_hist[w] = 0u;
+  // the work of every gate workgroup (its group by a search over the groups'
+  // first workgroups)
+  for (int w = i; w < d.total_gate_wgs; w += gridDim.x * 256) {
+    int lo = 0, hi = d.G - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (d.groups[mid].gate_off <= w) lo = mid; else hi = mid - 1;
+    }
+    const ObjInfo& oi = d.objs[d.groups[lo].obj];
+    const int local = w - d.groups[lo].gate_off;
+    const int pj = local / oi.gate_chunks, cc = local - pj * oi.gate_chunks;
+    d.gate_wg[w] = GateWG{lo, lo * d.K + pj, cc, oi.gbox_begin + cc};
+  }
   if (i < 4) d.flags[i] = 0;
   if (d.wave_pairs)
     for (int w = i; w < d.total_waves[0]; w += gridDim.x * 256) d.wave_pairs[w] = 0ull;
