@@ -11,10 +11,12 @@
 // frame: [sum |s - c'|^2, sum (s - c') (3), sum s x (s - c') (3), count].
 //
 // Trilinear weights are non-negative, so a point can only collide inside a
-// cell with a negative corner: the box of such cells (from the negative SDF
-// nodes) culls whole workgroups (the transformed box of the workgroup's own
-// 2048 points, compact because the cloud is in k-d leaf order) and single points
-// without reading the grid.  Both tests are exact.
+// cell with a negative corner.  Without reading the grid, whole workgroups
+// (the transformed box of the workgroup's own 2048 points, compact because
+// the cloud is in k-d leaf order) and 64-point leaves are culled by the box
+// of negative nodes and the brick counts of the set-up's SDF tables, and
+// single points by their cell's bit.  Every test is exact.  A workgroup finds
+// its particle and chunk in the set-up's table of gate workgroups.
 #include "nn_core.h"
 
 namespace asicp {
