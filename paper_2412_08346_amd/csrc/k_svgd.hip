@@ -10,7 +10,7 @@
 //                 the preconditioned driving terms -gamma A g_j (g_j minus the
 //                 log-prior gradient when a prior is given, eq. 8) plus tau times
 //                 the kernel gradient with respect to particle j (translation
-//                 part scaled by h/2); 16 particles per workgroup, 16 lanes
+//                 part scaled by h/2); 4 particles per workgroup, 64 lanes
 //                 per particle;
 //                 the same launch applies t += eta phi_t, q <-
 //                 canon(normalize(Exp(eta phi_w) (x) q)), writing the next
@@ -250,7 +250,7 @@ __device__ __forceinline__ void log_prior_grad(const float* pr, const float* t, 
   gp[5] = c * (q[0] * mz - mw * q[3] - (mx * q[2] - my * q[1]));
 }
 
-constexpr int kPhiLanes = 16;              // lanes per particle (one row of a wave)
+constexpr int kPhiLanes = 64;              // lanes per particle (one wavefront)
 constexpr int kPhiPer = 256 / kPhiLanes;   // particles per workgroup
 __global__ __launch_bounds__(256) void k_svgd_phi(Dev d, float gamma, float tau) {
   __shared__ float st[kMaxK * 3];
@@ -307,14 +307,9 @@ __global__ __launch_bounds__(256) void k_svgd_phi(Dev d, float gamma, float tau)
       acc[5] += wdw * (-ga_w * gj[5]) + tau * wrw * 0.5f * vz;
     }
   }
-  // sum over the particle's 16 lanes (one row): every lane gets the total
+  // sum over the particle's wavefront (a fixed tree): every lane gets the total
 #pragma unroll
-  for (int a = 0; a < 6; ++a) {
-    acc[a] += dppf<kDppXor1>(acc[a]);
-    acc[a] += dppf<kDppXor2>(acc[a]);
-    acc[a] += dppf<kDppHalfMirror>(acc[a]);
-    acc[a] += dppf<kDppMirror>(acc[a]);
-  }
+  for (int a = 0; a < 6; ++a) acc[a] = wave_sum(acc[a]);
   if (!(ii < K && part == 0)) return;
   const float invK = 1.0f / (float)K;
   float ph[6];
