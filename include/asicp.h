@@ -244,10 +244,12 @@ asicp_status asicp_replay(asicp_ctx ctx, void* stream);
  * the forward NN's shape (queries per wavefront, points per pruning chunk).
  * Every choice returns bit-identical outputs; only the speed differs. */
 typedef struct {
-  int32_t xcd_map;       /* 0: each XCD takes a contiguous range of the per-particle */
-                         /*    work (one object's data stays in one L2);              */
-                         /* 1: dispatch order (consecutive work on different XCDs,    */
-                         /*    which balances uneven work).  Default 1.               */
+  int32_t xcd_map;       /* 0: forward NN: whole particles' work dealt round-robin   */
+                         /*    over the XCDs (each particle in one L2, every XCD a    */
+                         /*    mix of near and far particles); collision gate: each   */
+                         /*    XCD takes a contiguous range of its work;              */
+                         /* 1: dispatch order (consecutive work on different XCDs).   */
+                         /*    Default 1.                                             */
   int32_t fine;          /* forward NN: test each candidate chunk against every      */
                          /*    query's own bound (1) or only the query block's (0).   */
                          /*    Default 1.                                             */

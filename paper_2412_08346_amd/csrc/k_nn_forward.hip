@@ -17,15 +17,20 @@
 
 namespace asicp {
 
-// Hardware places workgroup b on XCD b % 8.  MAP 0 gives each XCD a
-// contiguous range of logical workgroups (one object's data stays in one L2);
-// MAP 1 keeps the dispatch order (consecutive work on different XCDs, which
-// balances uneven work).  Neither changes any result.
+// Hardware places workgroup b on XCD b % 8.  MAP 0 deals units of `unit`
+// consecutive logical workgroups (one particle's forward work) round-robin
+// over the XCDs: each particle's workgroups run in one L2 and every XCD gets
+// a mix of near and far particles (workgroups past the last whole round of 8
+// units keep their index, so the map is a bijection for any count).  MAP 1
+// keeps the dispatch order (a particle's consecutive workgroups on different
+// XCDs).  Neither changes any result.
 template <int MAP>
-__device__ __forceinline__ int xcd_logical(int b, int nwg) {
+__device__ __forceinline__ int xcd_logical(int b, int nwg, int unit) {
   if (MAP == 1) return b;
-  const int per = (nwg + 7) >> 3;
-  return (b & 7) * per + (b >> 3);
+  const int full = nwg / (8 * unit) * (8 * unit);
+  if (b >= full) return b;
+  const int s = b >> 3;
+  return ((s / unit) * 8 + (b & 7)) * unit + s % unit;
 }
 
 #if ASICP_NN_WPE > 0
@@ -40,7 +45,8 @@ __device__ __forceinline__ void nn_forward_body(const Dev& d) {
   static_assert(q_blocks(QI) == Q, "1, 2 or 4 query blocks per wave");
   const int total_waves = d.total_waves[QI];
   const int nwg = (total_waves + 3) >> 2;
-  const int logical = xcd_logical<MAP>(blockIdx.x, nwg);
+  const int unit = max(1, (d.pres[0].waves[QI] + 3) >> 2);  // workgroups per particle (first preshape)
+  const int logical = xcd_logical<MAP>(blockIdx.x, nwg, unit);
   if (logical >= nwg) return;
   const int wave = __builtin_amdgcn_readfirstlane(logical * 4 + (int)(threadIdx.x >> 6));
   if (wave >= total_waves) return;
