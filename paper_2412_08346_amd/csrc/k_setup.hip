@@ -2,8 +2,9 @@
 // preprocessing): centre of mass of each object cloud (its centroid), tool
 // centre point of each contact cloud (its centroid, Sec. IV-B), the
 // Gauss-Newton diagonal preconditioner of eq. (3), spatially sorted MFMA-ready
-// copies of the clouds with per-chunk bounding boxes, the box of negative SDF
-// nodes, and the initial particle state.  Sums run in FP64 over a fixed order
+// copies of the clouds with per-chunk bounding boxes, the SDF cull tables (box
+// of negative nodes, cell bits, brick counts), the table of gate workgroups,
+// and the initial particle state.  Sums run in FP64 over a fixed order
 // (strided per thread, then a fixed tree).
 #include "nn_core.h"
 
